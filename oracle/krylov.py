@@ -1,0 +1,198 @@
+"""PCG, Armijo line search and the Gauss-Newton outer iteration (FP64, CPU).
+
+Paper: Section "Inexact Newton-Krylov Method" (PCG with the spectral
+preconditioner, the inexact termination rule e:termination-criterion-ksm with
+forcing eta_k = min(0.5, sqrt(||g_k|| / ||g_0||)), at most n inner iterations),
+Algorithm a:outer-iteration, the Armijo backtracking line search of Section
+"Numerical Optimization", the stopping rules e:stopping-criteria /
+e:converged, the CFL guard of Section "Parameter Selection" (halve s_k until
+the CFL condition holds, before the line search), and beta continuation
+(divide beta by ten per level, warm start).
+
+Readings where the paper is silent:
+* PCG is the textbook preconditioned CG with x0 = 0 and Euclidean inner products
+  (the h_d weight cancels in every ratio). It also stops on non-positive
+  curvature <p, H p> <= 0.
+* Armijo: alpha starts at 1, sufficient decrease J(v + a s) <= J(v) + c1 a <g, s>_h
+  with c1 = 1e-4, alpha halved at most 20 times, then failure is reported.
+* Convergence studies use ||g_k||_inf <= gtol * ||g_0||_inf ("relative change of
+  the gradient of three orders", gtol = 1e-3) or the paper's full rule
+  ((C1 and C2 and C3) or C4 or C5) with tau_J.
+* Continuation: a list of beta levels solved in turn, each warm-started from
+  the previous level's solution, each with its own relative-gradient rule.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Callable, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import reduced as rd
+from .timebasis import velocity_at
+
+
+def pcg(apply_H: Callable[[np.ndarray], np.ndarray],
+        apply_Pinv: Callable[[np.ndarray], np.ndarray],
+        rhs: np.ndarray, rtol: float, maxit: int) -> Tuple[np.ndarray, int, float, bool]:
+    """Solve H x = rhs from x0 = 0; stop when ||r||_2 <= rtol ||rhs||_2.
+
+    Returns (x, iterations, ||r||/||rhs||, converged).
+    """
+    x = np.zeros_like(rhs)
+    r = rhs.copy()
+    nb = float(np.sqrt(np.sum(rhs * rhs)))
+    if nb == 0.0:
+        return x, 0, 0.0, True
+    tol = rtol * nb
+    z = apply_Pinv(r)
+    p = z.copy()
+    rz = float(np.sum(r * z))
+    it = 0
+    rn = nb
+    while it < maxit:
+        if rn <= tol:
+            return x, it, rn / nb, True
+        Hp = apply_H(p)
+        pHp = float(np.sum(p * Hp))
+        if pHp <= 0.0:
+            break
+        alpha = rz / pHp
+        x = x + alpha * p
+        r = r - alpha * Hp
+        it += 1
+        rn = float(np.sqrt(np.sum(r * r)))
+        if rn <= tol:
+            return x, it, rn / nb, True
+        z = apply_Pinv(r)
+        rz_new = float(np.sum(r * z))
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return x, it, rn / nb, rn <= tol
+
+
+def cfl_number(vl: np.ndarray, nt: int) -> float:
+    """h_t * max over t_j and i of ||v^i(t_j)||_inf / h_x^i (Section "Numerical Discretization")."""
+    d = vl.shape[1]
+    shape = vl.shape[2:]
+    h = 1.0 / nt
+    best = 0.0
+    if vl.shape[0] == 1:
+        times = [0.0]
+    else:
+        times = [j * h for j in range(nt + 1)]
+    for t in times:
+        v = velocity_at(vl, t)
+        for i in range(d):
+            hx = 2.0 * math.pi / shape[i]
+            best = max(best, float(np.abs(v[i]).max()) / hx)
+    return h * best
+
+
+def armijo(P: rd.Problem, vl: np.ndarray, J: float, g: np.ndarray, s: np.ndarray,
+           c1: float = 1e-4, max_halvings: int = 20) -> Tuple[float, bool, int]:
+    """Backtracking from alpha = 1; returns (alpha, success, trial count)."""
+    slope = P.inner(g, s)
+    alpha = 1.0
+    for trial in range(max_halvings + 1):
+        Jt, _, _ = rd.objective(P, vl + alpha * s)
+        if Jt <= J + c1 * alpha * slope:
+            return alpha, True, trial + 1
+        alpha *= 0.5
+    return 0.0, False, max_halvings + 1
+
+
+@dataclass
+class SolveReport:
+    iterations: int = 0
+    cg_iterations: List[int] = field(default_factory=list)
+    alphas: List[float] = field(default_factory=list)
+    J: List[float] = field(default_factory=list)
+    gnorm_inf: List[float] = field(default_factory=list)
+    n_pde: int = 0
+    matvecs: int = 0
+    converged: bool = False
+    line_search_failed: bool = False
+    reason: str = ""
+
+
+def gauss_newton(P: rd.Problem, v0: Optional[np.ndarray] = None, gtol: float = 1e-3,
+                 max_outer: int = 50, rule: str = "relgrad", tau_J: float = 1e-3,
+                 cfl_max: Optional[float] = None, pcg_maxit: Optional[int] = None
+                 ) -> Tuple[np.ndarray, SolveReport, rd.State]:
+    """Algorithm a:outer-iteration with GN-PCG search directions."""
+    vl = np.zeros(P.vshape()) if v0 is None else v0.copy()
+    n = int(np.prod(P.vshape()))
+    maxit = n if pcg_maxit is None else pcg_maxit
+    rep = SolveReport()
+    S = rd.objective_gradient(P, vl)
+    rep.n_pde += 2
+    J0 = S.J
+    g0_2 = float(np.sqrt(np.sum(S.g * S.g)))
+    g0_inf = float(np.abs(S.g).max())
+    rep.J.append(S.J)
+    rep.gnorm_inf.append(g0_inf)
+    J_prev: Optional[float] = None
+    v_prev: Optional[np.ndarray] = None
+    k = 0
+    while True:
+        ginf = float(np.abs(S.g).max())
+        if rule == "relgrad":
+            if ginf <= gtol * g0_inf or g0_inf == 0.0:
+                rep.converged, rep.reason = True, "relative gradient"
+                break
+        else:
+            eps = np.finfo(np.float64).eps
+            c4 = ginf < 1e3 * eps
+            if k > 0:
+                c1 = (J_prev - S.J) < tau_J * (1.0 + J0)
+                c2 = float(np.abs(v_prev - vl).max()) < math.sqrt(tau_J) * (1.0 + float(np.abs(vl).max()))
+                c3 = ginf < tau_J ** (1.0 / 3.0) * (1.0 + J0)
+                if (c1 and c2 and c3) or c4:
+                    rep.converged, rep.reason = True, "C1-C3/C4"
+                    break
+            elif c4:
+                rep.converged, rep.reason = True, "C4"
+                break
+        if k >= max_outer:
+            rep.reason = "max outer iterations"
+            break
+        g2 = float(np.sqrt(np.sum(S.g * S.g)))
+        eta = min(0.5, math.sqrt(g2 / g0_2))
+        s, its, _, _ = pcg(lambda w: rd.hessian_matvec(P, S, w), lambda r: rd.precond(P, r),
+                           -S.g, eta, maxit)
+        rep.cg_iterations.append(its)
+        rep.matvecs += its
+        rep.n_pde += 2 * its
+        if cfl_max is not None:
+            while cfl_number(vl + s, P.nt) > cfl_max:
+                s = 0.5 * s
+        alpha, ok, trials = armijo(P, vl, S.J, S.g, s)
+        rep.n_pde += trials
+        if not ok:
+            rep.line_search_failed, rep.reason = True, "line search failed"
+            break
+        rep.alphas.append(alpha)
+        J_prev, v_prev = S.J, vl
+        vl = vl + alpha * s
+        S = rd.objective_gradient(P, vl)
+        rep.n_pde += 2
+        rep.J.append(S.J)
+        rep.gnorm_inf.append(float(np.abs(S.g).max()))
+        k += 1
+    rep.iterations = k
+    return vl, rep, S
+
+
+def continuation(P: rd.Problem, betas: Sequence[float], gtol: float = 1e-3,
+                 max_outer: int = 50, cfl_max: Optional[float] = None
+                 ) -> Tuple[np.ndarray, List[SolveReport]]:
+    """Solve for each beta in turn, warm-starting from the previous level."""
+    vl = np.zeros(P.vshape())
+    reports = []
+    for b in betas:
+        Pb = rd.Problem(P.mT, P.mR, P.nt, P.nc, P.reg, P.gamma, b)
+        vl, rep, _ = gauss_newton(Pb, vl, gtol=gtol, max_outer=max_outer, cfl_max=cfl_max)
+        reports.append(rep)
+    return vl, reports

@@ -1,0 +1,144 @@
+"""Pins of the oracle's PCG, line search, GN driver and deformation gradient."""
+import numpy as np
+import pytest
+
+from oracle import defgrad as dg
+from oracle import krylov as kr
+from oracle import reduced as rd
+from oracle import spectral as sp
+from oracle import transport as tr
+import synth
+
+
+def small_problem(shape=(8, 8), nt=4, nc=1, reg=1, gamma=0, beta=1e-2):
+    mT = synth.smooth_image(shape, 5, 8.0)
+    vstar = synth.bandlimited_velocity(shape, 77, 3, 0.8, divfree=bool(gamma), nc=nc)
+    mR = tr.forward_only(mT, vstar, nt)
+    return rd.Problem(mT, mR, nt, nc, reg, gamma, beta), vstar
+
+
+@pytest.mark.parametrize("reg", [1, 2])
+def test_pcg_matches_dense_solve(reg):
+    P, vstar = small_problem(reg=reg)
+    S = rd.objective_gradient(P, 0.5 * vstar)
+    n = int(np.prod(P.vshape()))
+    cols = []
+    for i in range(n):
+        e = np.zeros(n)
+        e[i] = 1.0
+        cols.append(rd.hessian_matvec(P, S, e.reshape(P.vshape())).reshape(-1))
+    H = np.stack(cols, axis=1)
+    assert np.all(np.linalg.eigvalsh(0.5 * (H + H.T)) > 0)
+    rhs = -S.g
+    x_ref = np.linalg.solve(H, rhs.reshape(-1)).reshape(P.vshape())
+    x, its, relres, ok = kr.pcg(lambda w: rd.hessian_matvec(P, S, w), lambda r: rd.precond(P, r),
+                                rhs, 1e-12, n)
+    assert ok and its <= n
+    assert np.abs(x - x_ref).max() <= 1e-9 * np.abs(x_ref).max()
+
+
+def test_pcg_identity_preconditioner_on_spd_matrix_converges_in_n_steps():
+    rng = np.random.default_rng(0)
+    B = rng.standard_normal((12, 12))
+    H = B @ B.T + 12 * np.eye(12)
+    b = rng.standard_normal(12)
+    x, its, relres, ok = kr.pcg(lambda w: H @ w, lambda r: r, b, 1e-13, 12)
+    assert ok and its <= 12
+    assert np.abs(H @ x - b).max() < 1e-10
+
+
+def test_pcg_zero_rhs_and_forcing_stop():
+    H = np.diag(np.arange(1.0, 11.0))
+    x, its, relres, ok = kr.pcg(lambda w: H @ w, lambda r: r, np.zeros(10), 0.5, 10)
+    assert its == 0 and ok and not x.any()
+    x, its, relres, ok = kr.pcg(lambda w: H @ w, lambda r: r, np.ones(10), 0.5, 10)
+    assert ok and relres <= 0.5 and its < 10
+
+
+def test_armijo_rejects_ascent_direction():
+    P, vstar = small_problem()
+    v = np.zeros(P.vshape())
+    S = rd.objective_gradient(P, v)
+    alpha, ok, trials = kr.armijo(P, v, S.J, S.g, S.g.copy())
+    assert not ok and alpha == 0.0 and trials == 21
+
+
+def test_gauss_newton_converges_with_full_steps():
+    """GN-PCG rows of the paper's convergence tables: a handful of outer iterations
+    (4 to 13 there) with every full step accepted."""
+    P, vstar = small_problem(shape=(16, 16), nt=8, reg=2, beta=1e-1)
+    v, rep, S = kr.gauss_newton(P, gtol=1e-3, max_outer=20)
+    assert rep.converged
+    assert rep.iterations <= 10
+    assert all(a == 1.0 for a in rep.alphas)
+    assert rep.J[-1] < rep.J[0]
+
+
+def test_gauss_newton_reduces_mismatch_and_counts_pde_solves():
+    P, vstar = small_problem(shape=(16, 16), nt=8, reg=1, beta=1e-3)
+    v, rep, S = kr.gauss_newton(P, gtol=1e-3, max_outer=20)
+    assert rep.converged
+    mis0 = np.sum((P.mR - P.mT) ** 2)
+    assert S.J_dist / (0.5 * P.hd * mis0) < 0.05
+    # 2 PDE solves per gradient, 2 per matvec, 1 per line-search trial (one trial per
+    # iteration when every full step is accepted)
+    assert all(a == 1.0 for a in rep.alphas)
+    assert rep.n_pde == 2 * (rep.iterations + 1) + 2 * rep.matvecs + rep.iterations
+
+
+def test_stokes_driver_keeps_velocity_divergence_free():
+    P, vstar = small_problem(shape=(16, 16), nt=8, reg=2, gamma=1, beta=1e-2)
+    v, rep, S = kr.gauss_newton(P, gtol=1e-3, max_outer=10)
+    assert rep.converged
+    assert np.abs(sp.div(v[0])).max() < 1e-10 * max(1.0, np.abs(v).max())
+
+
+def test_cfl_guard_halves_steps():
+    v = np.zeros((1, 2, 16, 16))
+    v[0, 0] = 1.0
+    assert kr.cfl_number(v, 16) == pytest.approx(16 / (2 * np.pi) / 16)
+
+
+def test_continuation_warm_starts():
+    P, _ = small_problem(shape=(16, 16), nt=8, reg=2, beta=1e-3)
+    v, reps = kr.continuation(P, [1e-1, 1e-2, 1e-3])
+    assert len(reps) == 3 and all(r.converged for r in reps)
+
+
+def test_deformation_gradient_constant_velocity_is_identity():
+    v = np.zeros((1, 2, 16, 16))
+    v[0, 0], v[0, 1] = 0.4, -0.9
+    F = dg.deformation_gradient(v, 6)
+    assert np.abs(F[0, 0] - 1).max() < 1e-14 and np.abs(F[1, 1] - 1).max() < 1e-14
+    assert np.abs(F[0, 1]).max() < 1e-14 and np.abs(F[1, 0]).max() < 1e-14
+
+
+@pytest.mark.parametrize("shape", [(32, 32), (16, 16, 16)])
+def test_det_divergence_free_is_one_to_second_order(shape):
+    v = synth.bandlimited_velocity(shape, 12, 3, 0.8, divfree=True)
+    errs = []
+    for nt in (8, 16):
+        _, (mn, mx, mean, std) = dg.det_stats(v, nt)
+        errs.append(max(abs(mn - 1), abs(mx - 1)))
+    assert errs[1] < 1e-3
+    assert 3.0 < errs[0] / errs[1] < 5.0
+
+
+def test_det_compressible_matches_jacobi_transport():
+    """d/dt J + v . grad J = (div v) J with J(0) = 1 (Jacobi's formula), Heun in time."""
+    shape = (32, 32)
+    v = synth.c0_velocity(shape, 0.6)
+    vv = v[0]
+    dv = sp.div(vv)
+    res = []
+    for nt in (16, 32):
+        h = 1.0 / nt
+        J = np.ones(shape)
+        for _ in range(nt):
+            r1 = -np.sum(vv * sp.grad(J), axis=0) + dv * J
+            Js = J + h * r1
+            r2 = -np.sum(vv * sp.grad(Js), axis=0) + dv * Js
+            J = J + 0.5 * h * (r1 + r2)
+        det1, _ = dg.det_stats(v, nt)
+        res.append(np.abs(det1 - J).max())
+    assert res[1] < 1e-3 and res[0] / res[1] > 3.0
