@@ -1,0 +1,185 @@
+/*
+ * nkreg.h -- C ABI of the MI355X (gfx950) Gauss-Newton-Krylov registration library.
+ *
+ * The library solves the optimal-control formulation of diffeomorphic image
+ * registration of Mang & Biros, "An inexact Newton-Krylov algorithm for
+ * constrained diffeomorphic image registration" (arXiv 1408.6299):
+ *
+ *   minimise over v:  J[v] = 1/2 ||m_R - m_1||^2_{L2} + beta/2 sum_l <v_l, A v_l>
+ *   subject to        dt m + grad m . v = 0,  m(0) = m_T,  gamma div v = 0,
+ *
+ * on the periodic box [0, 2 pi)^d, d in {2, 3} (objective e:objective with the
+ * quadratic regulariser e:quadratic-regularization, constraint e:constraint).
+ * Space is Fourier pseudospectral, time is RK2 (Heun) with h_t = 1/nt, and v
+ * is expanded in time in nc Chebyshev coefficients (e:expansion).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Pointers named d_* are DEVICE pointers (hipMalloc'd memory, e.g. torch
+ *   tensors) owned by the caller. The library reads them during the call (or,
+ *   for asynchronous calls, before the stream reaches the call's end) and never
+ *   frees or keeps them. Pointers named h_* are host pointers.
+ * - Element type of every field is float if config.precision == 32 and double
+ *   if 64. Fields are contiguous, row-major, last axis fastest, axis 0 = x1.
+ *   A scalar field has n = N1*N2(*N3) values; x_j = 2 pi j / N_i.
+ *   A velocity (coefficients) has layout [nc][d][N1][N2](N3).
+ * - Gradients and Hessian products are the nodal values of the L2-Riesz
+ *   representative: dJ[w] = h_d * sum(g * w), h_d = prod(2 pi / N_i). This is
+ *   the scaling of the paper's Table t:eigenvalues.
+ * - All host scalars are double. Reductions are always accumulated in FP64.
+ * - Calls run on the stream given to nkreg_create. Calls returning host scalars
+ *   synchronise that stream; the others are asynchronous.
+ * - A handle is not thread-safe. No exception crosses the ABI.
+ * - The library owns its workspace (trajectory, spectra, Krylov vectors), which
+ *   it allocates in nkreg_create and frees in nkreg_destroy.
+ */
+#ifndef NKREG_H
+#define NKREG_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NKREG_OK = 0,
+  NKREG_EINVAL = -1,     /* bad argument value (beta <= 0, d not 2/3, reg not 1/2, null pointer) */
+  NKREG_ESHAPE = -2,     /* grid size not a power of two in [8, 512], or sizes inconsistent */
+  NKREG_ENOMEM = -3,     /* device allocation failed */
+  NKREG_EHIP = -4,       /* a HIP runtime call failed */
+  NKREG_ESTATE = -5,     /* call order: Hessian matvec / PCG without a prior gradient */
+  NKREG_ENONFINITE = -6, /* a reduction produced NaN or Inf */
+  NKREG_ECFL = -7,       /* the velocity violates the CFL bound config.cfl_max */
+  NKREG_ENOCONV = -8,    /* PCG / Newton reached its iteration limit (outputs still written) */
+  NKREG_ENOTIMPL = -9    /* feature not available for this configuration */
+} nkreg_status;
+
+typedef struct {
+  int dim;              /* d: 2 or 3 */
+  int n[3];             /* N1, N2, N3 (N3 ignored for d = 2); powers of two in [8, 512] */
+  int nt;               /* RK2 time steps, h_t = 1/nt */
+  int nc;               /* Chebyshev coefficients in time, 1..16 (1 = stationary) */
+  int reg;              /* 1: H1 seminorm, A = -Lap;  2: H2 seminorm, A = Lap^2 */
+  int incompressible;   /* gamma: 1 applies the Leray projection K to body forces */
+  double beta;          /* regularisation weight, > 0 */
+  int precision;        /* 32 or 64: element type of fields and FFTs */
+  int checkpoint_every; /* 0: keep the full state trajectory (the only mode in this version) */
+  double cfl_max;       /* CFL bound checked by nkreg_objective_gradient; <= 0 disables */
+} nkreg_config;
+
+typedef struct nkreg_problem nkreg_problem;
+
+/* Options of the outer iteration (Algorithm a:outer-iteration). */
+typedef struct {
+  int max_outer;        /* n_opt (e:stopping-criteria C5) */
+  double gtol;          /* relative gradient rule ||g_k||_inf <= gtol ||g_0||_inf; <= 0: use C1-C5 */
+  double tau_J;         /* tolerance of C1-C3 */
+  int pcg_maxit;        /* cap on PCG iterations per Newton step; <= 0: n (system size) */
+  int cfl_guard;        /* 1: halve the step until h_t max|v^i|/h_x^i <= cfl_max before the line search */
+  int verbose;          /* 1: print one line per outer iteration to stderr */
+} nkreg_solve_opts;
+
+/* What the outer iteration did (quantities of interest, Table t:quantities-of-interest). */
+typedef struct {
+  int iterations;       /* outer iterations k* */
+  int cg_iterations;    /* total PCG iterations (= Hessian matvecs) */
+  int n_pde;            /* hyperbolic PDE solves: 2 per gradient, 2 per matvec, 1 per line-search trial */
+  int line_search_failed;
+  int converged;
+  double J0, J;         /* objective at v = v0 and at the end */
+  double J_dist, J_reg; /* data term and regulariser at the end */
+  double gnorm0_inf, gnorm_inf;
+  double seconds;       /* wall-clock of the whole solve */
+} nkreg_solve_report;
+
+/* Library version string, e.g. "nkreg 1.0 gfx950". */
+const char* nkreg_version(void);
+/* Human-readable text of a status code. */
+const char* nkreg_status_string(int status);
+/* Text of the last error on this thread (HIP error names etc.). */
+const char* nkreg_last_error(void);
+
+/* Create a problem handle on a HIP stream (NULL = the null stream). Allocates
+ * the workspace. Errors: EINVAL, ESHAPE, ENOMEM, EHIP. */
+int nkreg_create(const nkreg_config* cfg, void* hip_stream, nkreg_problem** out);
+/* Free the handle and its workspace. NULL is accepted. */
+int nkreg_destroy(nkreg_problem* p);
+/* Change beta (continuation; Section "Parameter Selection"). Keeps the cached state. */
+int nkreg_set_beta(nkreg_problem* p, double beta);
+
+/* Copy the template m_T and reference m_R (each n values) into the handle. */
+int nkreg_set_images(nkreg_problem* p, const void* d_mT, const void* d_mR);
+
+/* State equation e:first-order-forward: Heun from m(0) = m_T under velocity
+ * coefficients d_v; writes m_1 (n values) to d_m1 (may be NULL) and caches the
+ * trajectory (grad m^j and grad m*_j) for later adjoint / Hessian calls. */
+int nkreg_forward(nkreg_problem* p, const void* d_v, void* d_m1);
+
+/* Objective and reduced gradient at d_v: forward solve, adjoint solve
+ * (e:first-order-adjoint, lambda(1) = m_R - m_1) and
+ * g = beta A v + K[f] (e:eliminated-control; K only if incompressible), f the
+ * time-integrated body force lambda grad m. Writes g to d_g (nc*d*n values,
+ * may be NULL) and J, J_dist, J_reg to host doubles (may be NULL). Caches the
+ * state for nkreg_hessian_matvec / nkreg_pcg. Synchronises.
+ * Errors: ECFL (velocity above cfl_max), ENONFINITE. */
+int nkreg_objective_gradient(nkreg_problem* p, const void* d_v, double* h_J, double* h_J_dist,
+                             double* h_J_reg, void* d_g);
+
+/* Objective only (one forward solve); does not touch the cached state. Synchronises. */
+int nkreg_objective(nkreg_problem* p, const void* d_v, double* h_J, double* h_J_dist,
+                    double* h_J_reg);
+
+/* Gauss-Newton reduced Hessian matvec at the cached state (Algorithm
+ * a:hessian-matvec with the GN approximation e:gauss-newton, eliminated form
+ * e:eliminated-icontrol): incremental state forward, incremental adjoint
+ * backward, H vt = beta A vt + K[f~]. d_vt and d_Hvt hold nc*d*n values and may
+ * not alias. Errors: ESTATE if no gradient has been computed since create or
+ * the last set_images. Asynchronous. */
+int nkreg_hessian_matvec(nkreg_problem* p, const void* d_vt, void* d_Hvt);
+
+/* Spectral preconditioner (beta A)^-1 with the zero mode unscaled (Section
+ * "Inversion: Regularization Operators"). Asynchronous. */
+int nkreg_precond_apply(nkreg_problem* p, const void* d_r, void* d_z);
+
+/* Apply the Leray projection K (e:eliminated-control) to nc*d*n values. Asynchronous. */
+int nkreg_project(nkreg_problem* p, const void* d_f, void* d_out);
+
+/* PCG on H s = rhs at the cached state, x0 = 0, stop when
+ * ||r||_2 <= rtol ||rhs||_2 (e:termination-criterion-ksm), at most maxit
+ * iterations (<= 0: n). Writes s, the iteration count and ||r||/||rhs||.
+ * Returns ENOCONV (with s written) if maxit is reached. Synchronises. */
+int nkreg_pcg(nkreg_problem* p, const void* d_rhs, void* d_s, double rtol, int maxit,
+              int* h_iters, double* h_relres);
+
+/* Deformation gradient e:def-grad under d_v, computed in FP64 whatever the
+ * problem precision; writes det F_1 (n doubles) to d_detF (may be NULL) and
+ * (min, max, mean, population std) to h_stats[4]. Synchronises. */
+int nkreg_det_grad_y(nkreg_problem* p, const void* d_v, void* d_detF, double* h_stats);
+
+/* Gauss-Newton-Krylov outer iteration (Algorithm a:outer-iteration) from the
+ * velocity in d_v (overwritten with the solution). Synchronises. */
+int nkreg_newton_solve(nkreg_problem* p, void* d_v, const nkreg_solve_opts* opts,
+                       nkreg_solve_report* report);
+
+/* Building blocks exposed for testing the spectral machinery. */
+/* d_g (d*n) = spectral gradient of the scalar field d_u (n). */
+int nkreg_gradient(nkreg_problem* p, const void* d_u, void* d_g);
+/* d_s (n) = spectral divergence of the vector field d_w (d*n). */
+int nkreg_divergence(nkreg_problem* p, const void* d_w, void* d_s);
+/* d_out = A d_x (nc*d*n values, A = -Lap or Lap^2 per component). */
+int nkreg_apply_reg(nkreg_problem* p, const void* d_x, void* d_out);
+
+/* Host reductions in FP64 over cnt elements of the problem's precision. */
+int nkreg_dot(nkreg_problem* p, const void* d_a, const void* d_b, long long cnt, double* h_out);
+
+/* Batched Gauss-Newton matvecs over independent problems of uneven sizes
+ * (each a handle created with nkreg_create on the same stream and with a
+ * cached state). One call applies H_i to vt_i for every item i. */
+typedef struct nkreg_batch nkreg_batch;
+int nkreg_batch_create(int count, nkreg_problem* const* items, nkreg_batch** out);
+int nkreg_batch_destroy(nkreg_batch* b);
+int nkreg_batch_hessian_matvec(nkreg_batch* b, const void* const* d_vt, void* const* d_Hvt);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NKREG_H */

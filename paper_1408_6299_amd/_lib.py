@@ -1,0 +1,94 @@
+"""ctypes declarations of the C ABI in include/nkreg.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, Structure, c_char_p, c_double, c_int, c_longlong, c_void_p
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnkreg.so")
+
+OK, EINVAL, ESHAPE, ENOMEM, EHIP, ESTATE, ENONFINITE, ECFL, ENOCONV, ENOTIMPL = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8, -9)
+
+
+class Config(Structure):
+    _fields_ = [("dim", c_int), ("n", c_int * 3), ("nt", c_int), ("nc", c_int), ("reg", c_int),
+                ("incompressible", c_int), ("beta", c_double), ("precision", c_int),
+                ("checkpoint_every", c_int), ("cfl_max", c_double)]
+
+
+class SolveOpts(Structure):
+    _fields_ = [("max_outer", c_int), ("gtol", c_double), ("tau_J", c_double), ("pcg_maxit", c_int),
+                ("cfl_guard", c_int), ("verbose", c_int)]
+
+
+class SolveReport(Structure):
+    _fields_ = [("iterations", c_int), ("cg_iterations", c_int), ("n_pde", c_int),
+                ("line_search_failed", c_int), ("converged", c_int), ("J0", c_double), ("J", c_double),
+                ("J_dist", c_double), ("J_reg", c_double), ("gnorm0_inf", c_double),
+                ("gnorm_inf", c_double), ("seconds", c_double)]
+
+
+# name -> (restype, argtypes); every symbol declared in include/nkreg.h
+SIGNATURES = {
+    "nkreg_version": (c_char_p, []),
+    "nkreg_status_string": (c_char_p, [c_int]),
+    "nkreg_last_error": (c_char_p, []),
+    "nkreg_create": (c_int, [POINTER(Config), c_void_p, POINTER(c_void_p)]),
+    "nkreg_destroy": (c_int, [c_void_p]),
+    "nkreg_set_beta": (c_int, [c_void_p, c_double]),
+    "nkreg_set_images": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "nkreg_forward": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "nkreg_objective_gradient": (c_int, [c_void_p, c_void_p, POINTER(c_double), POINTER(c_double),
+                                         POINTER(c_double), c_void_p]),
+    "nkreg_objective": (c_int, [c_void_p, c_void_p, POINTER(c_double), POINTER(c_double),
+                                POINTER(c_double)]),
+    "nkreg_hessian_matvec": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "nkreg_precond_apply": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "nkreg_project": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "nkreg_pcg": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int, POINTER(c_int),
+                          POINTER(c_double)]),
+    "nkreg_det_grad_y": (c_int, [c_void_p, c_void_p, c_void_p, POINTER(c_double)]),
+    "nkreg_newton_solve": (c_int, [c_void_p, c_void_p, POINTER(SolveOpts), POINTER(SolveReport)]),
+    "nkreg_gradient": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "nkreg_divergence": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "nkreg_apply_reg": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "nkreg_dot": (c_int, [c_void_p, c_void_p, c_void_p, c_longlong, POINTER(c_double)]),
+    "nkreg_batch_create": (c_int, [c_int, POINTER(c_void_p), POINTER(c_void_p)]),
+    "nkreg_batch_destroy": (c_int, [c_void_p]),
+    "nkreg_batch_hessian_matvec": (c_int, [c_void_p, POINTER(c_void_p), POINTER(c_void_p)]),
+}
+
+_lib = None
+
+
+class NkregError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: {detail} (status {status})")
+        self.status = status
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libnkreg.so (built by paper_1408_6299_amd.build); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python __graft_entry__.py` or `python paper_1408_6299_amd/build.py` "
+                          "(the HIP library is required; there is no fallback)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(status: int, where: str) -> int:
+    if status == OK:
+        return status
+    lib = load()
+    detail = lib.nkreg_last_error().decode() or lib.nkreg_status_string(status).decode()
+    raise NkregError(status, where, detail)

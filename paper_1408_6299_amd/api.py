@@ -1,0 +1,273 @@
+"""Python face of the gfx950 registration library.
+
+Thin wrapper over the C ABI (include/nkreg.h): it checks and marshals torch
+tensors (device memory) and passes torch's current HIP stream. Every step of
+the computation runs in the library's HIP kernels; nothing here computes.
+"""
+from __future__ import annotations
+
+import ctypes
+from ctypes import byref, c_double, c_int, c_void_p
+from dataclasses import dataclass
+from typing import Optional, Sequence, Tuple
+
+import torch
+
+from . import _lib
+from ._lib import Config, NkregError, SolveOpts, SolveReport, check
+
+__all__ = ["Problem", "Batch", "NkregError", "SolveResult"]
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+@dataclass
+class SolveResult:
+    iterations: int
+    cg_iterations: int
+    n_pde: int
+    line_search_failed: bool
+    converged: bool
+    J0: float
+    J: float
+    J_dist: float
+    J_reg: float
+    gnorm0_inf: float
+    gnorm_inf: float
+    seconds: float
+    status: int
+
+
+class Problem:
+    """One registration problem (images, grid, time steps, regulariser) on the current GPU.
+
+    Fields are torch tensors on the GPU, contiguous, of dtype float32
+    (``precision=32``) or float64 (``precision=64``). Velocities have shape
+    (nc, d, *shape); images have shape ``shape``.
+    """
+
+    def __init__(self, shape: Sequence[int], nt: int, nc: int = 1, reg: int = 1,
+                 incompressible: bool = False, beta: float = 1e-2, precision: int = 32,
+                 cfl_max: float = 0.0, stream: Optional[torch.cuda.Stream] = None):
+        self.lib = _lib.load()
+        self.shape = tuple(int(s) for s in shape)
+        self.d = len(self.shape)
+        self.nt, self.nc, self.reg = int(nt), int(nc), int(reg)
+        self.incompressible = bool(incompressible)
+        self.precision = int(precision)
+        self.dtype = torch.float32 if self.precision == 32 else torch.float64
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        cfg = Config()
+        cfg.dim = self.d
+        for i in range(3):
+            cfg.n[i] = self.shape[i] if i < self.d else 1
+        cfg.nt, cfg.nc, cfg.reg = self.nt, self.nc, self.reg
+        cfg.incompressible = int(self.incompressible)
+        cfg.beta = float(beta)
+        cfg.precision = self.precision
+        cfg.checkpoint_every = 0
+        cfg.cfl_max = float(cfl_max)
+        self._beta = float(beta)
+        h = c_void_p()
+        check(self.lib.nkreg_create(byref(cfg), c_void_p(self.stream.cuda_stream), byref(h)), "nkreg_create")
+        self._h = h
+
+    # -- lifetime --
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.nkreg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers --
+    @property
+    def vshape(self) -> Tuple[int, ...]:
+        return (self.nc, self.d) + self.shape
+
+    @property
+    def hd(self) -> float:
+        import math
+        out = 1.0
+        for n in self.shape:
+            out *= 2.0 * math.pi / n
+        return out
+
+    @property
+    def beta(self) -> float:
+        return self._beta
+
+    @beta.setter
+    def beta(self, value: float) -> None:
+        check(self.lib.nkreg_set_beta(self._h, c_double(value)), "nkreg_set_beta")
+        self._beta = float(value)
+
+    def _check(self, t: torch.Tensor, shape: Tuple[int, ...], name: str) -> torch.Tensor:
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if t.device.type != "cuda":
+            raise ValueError(f"{name} must live on the GPU")
+        if t.dtype != self.dtype:
+            raise TypeError(f"{name} has dtype {t.dtype}, expected {self.dtype}")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {shape}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return t
+
+    def empty_v(self) -> torch.Tensor:
+        return torch.empty(self.vshape, dtype=self.dtype, device=self.device)
+
+    def zeros_v(self) -> torch.Tensor:
+        return torch.zeros(self.vshape, dtype=self.dtype, device=self.device)
+
+    # -- the calls of the C ABI --
+    def set_images(self, mT: torch.Tensor, mR: torch.Tensor) -> None:
+        self._check(mT, self.shape, "mT")
+        self._check(mR, self.shape, "mR")
+        check(self.lib.nkreg_set_images(self._h, _ptr(mT), _ptr(mR)), "nkreg_set_images")
+
+    def forward(self, v: torch.Tensor) -> torch.Tensor:
+        self._check(v, self.vshape, "v")
+        m1 = torch.empty(self.shape, dtype=self.dtype, device=self.device)
+        check(self.lib.nkreg_forward(self._h, _ptr(v), _ptr(m1)), "nkreg_forward")
+        return m1
+
+    def objective(self, v: torch.Tensor) -> Tuple[float, float, float]:
+        self._check(v, self.vshape, "v")
+        J, Jd, Jr = c_double(), c_double(), c_double()
+        check(self.lib.nkreg_objective(self._h, _ptr(v), byref(J), byref(Jd), byref(Jr)), "nkreg_objective")
+        return J.value, Jd.value, Jr.value
+
+    def objective_gradient(self, v: torch.Tensor, g: Optional[torch.Tensor] = None):
+        self._check(v, self.vshape, "v")
+        if g is None:
+            g = self.empty_v()
+        self._check(g, self.vshape, "g")
+        J, Jd, Jr = c_double(), c_double(), c_double()
+        check(self.lib.nkreg_objective_gradient(self._h, _ptr(v), byref(J), byref(Jd), byref(Jr), _ptr(g)),
+              "nkreg_objective_gradient")
+        return J.value, Jd.value, Jr.value, g
+
+    def hessian_matvec(self, vt: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        self._check(vt, self.vshape, "vt")
+        if out is None:
+            out = self.empty_v()
+        self._check(out, self.vshape, "out")
+        check(self.lib.nkreg_hessian_matvec(self._h, _ptr(vt), _ptr(out)), "nkreg_hessian_matvec")
+        return out
+
+    def precond(self, r: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        self._check(r, self.vshape, "r")
+        out = self.empty_v() if out is None else out
+        check(self.lib.nkreg_precond_apply(self._h, _ptr(r), _ptr(out)), "nkreg_precond_apply")
+        return out
+
+    def project(self, f: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        self._check(f, self.vshape, "f")
+        out = self.empty_v() if out is None else out
+        check(self.lib.nkreg_project(self._h, _ptr(f), _ptr(out)), "nkreg_project")
+        return out
+
+    def apply_reg(self, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        self._check(x, self.vshape, "x")
+        out = self.empty_v() if out is None else out
+        check(self.lib.nkreg_apply_reg(self._h, _ptr(x), _ptr(out)), "nkreg_apply_reg")
+        return out
+
+    def pcg(self, rhs: torch.Tensor, rtol: float, maxit: int = 0, out: Optional[torch.Tensor] = None):
+        """Returns (s, iterations, relative residual, converged)."""
+        self._check(rhs, self.vshape, "rhs")
+        out = self.empty_v() if out is None else out
+        it, rr = c_int(), c_double()
+        st = self.lib.nkreg_pcg(self._h, _ptr(rhs), _ptr(out), c_double(rtol), c_int(maxit), byref(it), byref(rr))
+        if st not in (_lib.OK, _lib.ENOCONV):
+            check(st, "nkreg_pcg")
+        return out, it.value, rr.value, st == _lib.OK
+
+    def det_grad_y(self, v: torch.Tensor) -> Tuple[torch.Tensor, Tuple[float, float, float, float]]:
+        self._check(v, self.vshape, "v")
+        det = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        stats = (c_double * 4)()
+        check(self.lib.nkreg_det_grad_y(self._h, _ptr(v), _ptr(det), stats), "nkreg_det_grad_y")
+        return det, tuple(stats)
+
+    def newton_solve(self, v: Optional[torch.Tensor] = None, gtol: float = 1e-3, max_outer: int = 50,
+                     tau_J: float = 1e-3, pcg_maxit: int = 0, cfl_guard: bool = False,
+                     verbose: bool = False) -> Tuple[torch.Tensor, SolveResult]:
+        """Gauss-Newton-Krylov solve from v (zero if None); returns (v, report)."""
+        v = self.zeros_v() if v is None else v.clone()
+        self._check(v, self.vshape, "v")
+        o = SolveOpts()
+        o.max_outer, o.gtol, o.tau_J = int(max_outer), float(gtol), float(tau_J)
+        o.pcg_maxit, o.cfl_guard, o.verbose = int(pcg_maxit), int(cfl_guard), int(verbose)
+        rep = SolveReport()
+        st = self.lib.nkreg_newton_solve(self._h, _ptr(v), byref(o), byref(rep))
+        if st not in (_lib.OK, _lib.ENOCONV):
+            check(st, "nkreg_newton_solve")
+        res = SolveResult(rep.iterations, rep.cg_iterations, rep.n_pde, bool(rep.line_search_failed),
+                          bool(rep.converged), rep.J0, rep.J, rep.J_dist, rep.J_reg, rep.gnorm0_inf,
+                          rep.gnorm_inf, rep.seconds, st)
+        return v, res
+
+    def gradient(self, u: torch.Tensor) -> torch.Tensor:
+        self._check(u, self.shape, "u")
+        out = torch.empty((self.d,) + self.shape, dtype=self.dtype, device=self.device)
+        check(self.lib.nkreg_gradient(self._h, _ptr(u), _ptr(out)), "nkreg_gradient")
+        return out
+
+    def divergence(self, w: torch.Tensor) -> torch.Tensor:
+        self._check(w, (self.d,) + self.shape, "w")
+        out = torch.empty(self.shape, dtype=self.dtype, device=self.device)
+        check(self.lib.nkreg_divergence(self._h, _ptr(w), _ptr(out)), "nkreg_divergence")
+        return out
+
+    def dot(self, a: torch.Tensor, b: torch.Tensor) -> float:
+        if a.dtype != self.dtype or b.dtype != self.dtype or a.numel() != b.numel():
+            raise ValueError("dot: operands must match the problem dtype and size")
+        out = c_double()
+        check(self.lib.nkreg_dot(self._h, _ptr(a.contiguous()), _ptr(b.contiguous()), a.numel(), byref(out)),
+              "nkreg_dot")
+        return out.value
+
+
+class Batch:
+    """Several independent problems whose Hessian matvecs are applied in one call."""
+
+    def __init__(self, problems: Sequence[Problem]):
+        self.lib = _lib.load()
+        self.problems = list(problems)
+        arr = (c_void_p * len(self.problems))(*[p._h.value for p in self.problems])
+        h = c_void_p()
+        check(self.lib.nkreg_batch_create(len(self.problems), arr, byref(h)), "nkreg_batch_create")
+        self._h = h
+
+    def hessian_matvec(self, vts: Sequence[torch.Tensor], outs: Optional[Sequence[torch.Tensor]] = None):
+        if outs is None:
+            outs = [p.empty_v() for p in self.problems]
+        for p, a, b in zip(self.problems, vts, outs):
+            p._check(a, p.vshape, "vt")
+            p._check(b, p.vshape, "out")
+        n = len(self.problems)
+        ins = (c_void_p * n)(*[t.data_ptr() for t in vts])
+        os_ = (c_void_p * n)(*[t.data_ptr() for t in outs])
+        check(self.lib.nkreg_batch_hessian_matvec(self._h, ins, os_), "nkreg_batch_hessian_matvec")
+        return outs
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.nkreg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

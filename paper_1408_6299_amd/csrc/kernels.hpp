@@ -1,0 +1,630 @@
+// Kernels of the transport sweeps and spectral operators.
+//
+// Spectral layout ("row spectrum"): every row along the contiguous last axis
+// (length L) is stored as its packed half spectrum, L/2 complex values:
+// P[0] = (X_0, X_{L/2}) and P[q] = X_q for 0 < q < L/2. A real field and its
+// row spectrum have the same size. Transforms along the other axes act on the
+// row spectrum in place of a full spectrum; the packed column q = 0 carries two
+// real sequences as one complex sequence, which a first derivative along
+// another axis (a purely imaginary, odd multiplier) keeps intact.
+//
+// All transforms are unnormalised; the 1/N factors are folded into the
+// derivative multipliers (1/N_axis), the row C2R epilogues (1/L) or the
+// spectral multiplier (1/prod N).
+#pragma once
+
+#include "common.hpp"
+#include "fft_lds.hpp"
+
+namespace nk {
+
+// ---------------------------------------------------------------------------
+// Column pass: FFT along a strided axis of a row spectrum.
+// Field layout: element (o, x, c) at o * (N * inner) + x * inner + c.
+// ---------------------------------------------------------------------------
+enum ColMode { COL_FWD = 0, COL_INV = 1, COL_DERIV = 2 };
+
+struct ColArgs {
+  int inner;        // complex elements between consecutive x
+  int ctile;        // columns per workgroup (<= CMAX, divides inner)
+  long long field;  // complex elements between fields (blockIdx.z)
+};
+
+template <typename R, int N, int CMAX, int NT, int MODE>
+__global__ __launch_bounds__(NT) void k_col(const cplx<R>* in, const cplx<R>* add,
+                                            cplx<R>* out, ColArgs a, R scale,
+                                            const cplx<R>* __restrict__ tw, int twb) {
+  __shared__ cplx<R> tile[N * CMAX];
+  const int C = a.ctile;
+  const long long base = (long long)blockIdx.z * a.field + (long long)blockIdx.y * N * a.inner +
+                         (long long)blockIdx.x * C;
+  const int tot = N * C;
+  for (int i = threadIdx.x; i < tot; i += NT) {
+    const int x = i / C, c = i - (i / C) * C;
+    tile[i] = in[base + (long long)x * a.inner + c];
+  }
+  __syncthreads();
+  if (MODE == COL_INV) {
+    fft_lds<R, N, CMAX, NT, true, true>(tile, C, 1, C, tw, twb);
+  } else {
+    fft_lds<R, N, CMAX, NT, false, true>(tile, C, 1, C, tw, twb);
+  }
+  if (MODE == COL_DERIV) {
+    for (int i = threadIdx.x; i < tot; i += NT) {
+      const int x = i / C;
+      const R k = R(deriv_wavenumber(x, N)) * scale;
+      tile[i] = cmul_i(tile[i], k);
+    }
+    __syncthreads();
+    fft_lds<R, N, CMAX, NT, true, true>(tile, C, 1, C, tw, twb);
+  }
+  for (int i = threadIdx.x; i < tot; i += NT) {
+    const int x = i / C, c = i - (i / C) * C;
+    const long long g = base + (long long)x * a.inner + c;
+    cplx<R> v = tile[i];
+    if (MODE == COL_INV) v = cscale(v, scale);
+    if (MODE == COL_DERIV && add) v = cadd(v, add[g]);
+    out[g] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Row stage: per row of the last axis, (1) C2R of KIN input row spectra,
+// (2) a pointwise epilogue (Heun stage, forcing, body force, ...),
+// (3) R2C of KOUT new real rows. One kernel per RK2 stage of every sweep.
+// ---------------------------------------------------------------------------
+enum StageKind {
+  ST_FWD1 = 0,   // state, stage 1: store grad m^j, acc = m + h/2 r1, out m + h r1
+  ST_FWD2 = 1,   // state, stage 2: store grad m*_j, out m^{j+1} = acc + h/2 r2
+  ST_INC1 = 2,   // incremental state, stage 1 (forcing -v~(t_j) . grad m^j)
+  ST_INC2 = 3,   // incremental state, stage 2 (forcing -v~(t_{j+1}) . grad m*_j)
+  ST_ADJINIT = 4,// lam = a*src_a + b*src_b; out v(t_nt) lam
+  ST_ADJ1 = 5,   // adjoint stage 1: s1 = div(v(t_{j+1}) lam); body force; out v(t_j) lam*
+  ST_ADJ2 = 6,   // adjoint stage 2: lam^j = acc + h/2 s2; out v(t_j) lam^j
+  ST_R2C = 7,    // plain R2C of a batch of real fields
+  ST_C2R = 8,    // plain C2R of a batch of row spectra (times scale)
+  ST_GRAD = 9,   // write the gradient of a batch of scalar fields
+  ST_DIV = 10    // write the divergence (already summed spectrum) as a real field
+};
+
+template <typename R>
+struct StageArgs {
+  const cplx<R>* spec;       // T / T* (grad kinds) or D (adjoint kinds) or batch input
+  const cplx<R>* s1;         // column derivative along x1 of spec (grad kinds)
+  const cplx<R>* s2;         // column derivative along x2 (3D grad kinds)
+  cplx<R>* out0;             // output row spectra (first / only)
+  cplx<R>* out1;             // second output spectrum (adjoint: w_2 or w_2 times ik_3)
+  cplx<R>* out2;             // third output spectrum (3D adjoint: w_3 times ik_3)
+  const R* vl;               // velocity coefficients [nc][d][n]
+  const R* vtl;              // incremental velocity coefficients [nc][d][n]
+  const R* g0;               // grad m^j   [d][n]
+  const R* g1;               // grad m*_j  [d][n]
+  R* g0w;                    // where FWD1 stores grad m^j
+  R* g1w;                    // where FWD2 stores grad m*_j
+  R* acc;                    // Heun accumulator [n]
+  R* lam;                    // adjoint state [n]
+  R* F;                      // body force accumulators [nc][d][n]
+  R* out_real;               // real output (m_1, gradient, divergence, C2R result)
+  const R* src_a;
+  const R* src_b;
+  R ca, cb;                  // lam = ca * src_a + cb * src_b (src_b may be null)
+  R h;                       // time step
+  R scale;                   // C2R output scale (ST_C2R, ST_GRAD, ST_DIV multiply by scale/L)
+  int nc;
+  int zero_state;            // INC1 at j = 0: the incremental state is zero
+  int write_real;            // FWD2/INC2: also store the new state as a real field
+  int skip_out;              // ADJ2 at j = 0: no further spectra needed
+  long long n;               // points per scalar field
+  long long fstride_in;      // batch stride (elements) of inputs (ST_R2C: reals, else complex)
+  long long fstride_out;     // batch stride of outputs
+  R b0[kMaxNc];              // b_l(t_j): velocity / force weights at the earlier node
+  R b1[kMaxNc];              // b_l(t_{j+1})
+  R bv[kMaxNc];              // weights of the velocity used for the outputs (ADJINIT/ADJ1/ADJ2)
+};
+
+template <int KIND, int D>
+struct StageShape {
+  // KIN: input row spectra after C2R; KOUT: real rows transformed by R2C.
+  static constexpr int KIN = (KIND == ST_FWD1 || KIND == ST_FWD2 || KIND == ST_INC1 || KIND == ST_INC2)
+                                 ? 1 + D
+                                 : (KIND == ST_ADJ1 || KIND == ST_ADJ2 || KIND == ST_C2R || KIND == ST_DIV)
+                                       ? 1
+                                       : (KIND == ST_GRAD ? D : 0);
+  static constexpr int KOUT = (KIND == ST_FWD1 || KIND == ST_FWD2 || KIND == ST_INC1 || KIND == ST_INC2 ||
+                               KIND == ST_R2C)
+                                  ? 1
+                                  : (KIND == ST_ADJINIT || KIND == ST_ADJ1 || KIND == ST_ADJ2) ? D : 0;
+  static constexpr int KMAX = KIN > KOUT ? (KIN > 0 ? KIN : 1) : (KOUT > 0 ? KOUT : 1);
+};
+
+template <typename R>
+__device__ __forceinline__ R vel_comb(const R* __restrict__ v, const R* w, int nc, int comp, int d,
+                                      long long n, long long p) {
+  if (nc == 1) return w[0] * v[(long long)comp * n + p];
+  R s = R(0);
+  for (int l = 0; l < nc; ++l) s += w[l] * v[((long long)l * d + comp) * n + p];
+  return s;
+}
+
+template <typename R, int L, int B, int NT, int KIND, int D>
+__global__ __launch_bounds__(NT) void k_row_stage(StageArgs<R> a, const cplx<R>* __restrict__ tw, int lmax) {
+  constexpr int M = L / 2;
+  constexpr int SS = M + 1;  // one complex of padding per row buffer
+  using SH = StageShape<KIND, D>;
+  constexpr int KIN = SH::KIN, KOUT = SH::KOUT, KMAX = SH::KMAX;
+  __shared__ cplx<R> lds[KMAX * B * SS];
+  const int twb = lmax / M;   // stride of a length-M transform in the table
+  const int twl = lmax / L;   // stride of the length-L packing twiddles
+  const long long row0 = (long long)blockIdx.x * B;
+  const long long n = a.n;
+  const int zero_in = (KIND == ST_INC1) ? a.zero_state : 0;
+
+  // ---- (1) load input row spectra into LDS, buffer s = k * B + b ----
+  if constexpr (KIN > 0) {
+    if (!zero_in) {
+      const long long fin = (long long)blockIdx.y * a.fstride_in;
+      for (int i = threadIdx.x; i < KIN * B * M; i += NT) {
+        const int k = i / (B * M);
+        const int rem = i - k * (B * M);
+        const int b = rem / M, q = rem - (rem / M) * M;
+        const long long g = fin + (row0 + b) * M + q;
+        cplx<R> v;
+        if constexpr (KIND == ST_GRAD) {
+          // k < D-1: column derivatives along x1 (x2); k = D-1: ik_last * spec
+          if (k == D - 1) {
+            const R kk = R(q == 0 ? 0 : q);
+            v = cmul_i(a.spec[g], kk);
+          } else {
+            v = (k == 0) ? a.s1[g] : a.s2[g];
+          }
+        } else if constexpr (KIN == 1 + D) {
+          // k = 0: the field; 1..D-1: column derivatives; D: ik_last * field
+          if (k == 0) v = a.spec[g];
+          else if (k == D) v = cmul_i(a.spec[g], R(q == 0 ? 0 : q));
+          else v = (k == 1) ? a.s1[g] : a.s2[g];
+        } else {
+          v = a.spec[g];
+        }
+        lds[(k * B + b) * SS + q] = v;
+      }
+      __syncthreads();
+      c2r_pre<R, M, NT>(lds, KIN * B, SS, tw, twl);
+      fft_lds<R, M, KIN * B, NT, true, false>(lds, KIN * B, SS, 1, tw, twb);
+    }
+  }
+
+  // ---- (2) pointwise epilogue over the B*L points of this workgroup ----
+  const R invL = R(1) / R(L);
+  for (int i = threadIdx.x; i < B * L; i += NT) {
+    const int b = i / L, x = i - (i / L) * L;
+    const long long p = (row0 + b) * L + x;
+    auto rbuf = [&](int k) -> R& { return reinterpret_cast<R*>(lds + (k * B + b) * SS)[x]; };
+    if constexpr (KIND == ST_FWD1 || KIND == ST_FWD2) {
+      const R m = rbuf(0) * invL;
+      R r = R(0);
+      const R* w = (KIND == ST_FWD1) ? a.b0 : a.b1;
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const R gc = rbuf(1 + c) * invL;
+        if (KIND == ST_FWD1) { if (a.g0w) a.g0w[(long long)c * n + p] = gc; }
+        else { if (a.g1w) a.g1w[(long long)c * n + p] = gc; }
+        r -= vel_comb(a.vl, w, a.nc, c, D, n, p) * gc;
+      }
+      if (KIND == ST_FWD1) {
+        a.acc[p] = m + R(0.5) * a.h * r;
+        rbuf(0) = m + a.h * r;
+      } else {
+        const R mn = a.acc[p] + R(0.5) * a.h * r;
+        if (a.write_real) a.out_real[p] = mn;
+        rbuf(0) = mn;
+      }
+    } else if constexpr (KIND == ST_INC1 || KIND == ST_INC2) {
+      const R* w = (KIND == ST_INC1) ? a.b0 : a.b1;
+      const R* gm = (KIND == ST_INC1) ? a.g0 : a.g1;
+      R r = R(0);
+      R m = R(0);
+      if (!zero_in) {
+        m = rbuf(0) * invL;
+#pragma unroll
+        for (int c = 0; c < D; ++c) r -= vel_comb(a.vl, w, a.nc, c, D, n, p) * (rbuf(1 + c) * invL);
+      }
+#pragma unroll
+      for (int c = 0; c < D; ++c) r -= vel_comb(a.vtl, w, a.nc, c, D, n, p) * gm[(long long)c * n + p];
+      if (KIND == ST_INC1) {
+        a.acc[p] = m + R(0.5) * a.h * r;
+        rbuf(0) = m + a.h * r;
+      } else {
+        const R mn = a.acc[p] + R(0.5) * a.h * r;
+        if (a.write_real) a.out_real[p] = mn;
+        rbuf(0) = mn;
+      }
+    } else if constexpr (KIND == ST_ADJINIT) {
+      R lam = a.ca * a.src_a[p];
+      if (a.src_b) lam += a.cb * a.src_b[p];
+      a.lam[p] = lam;
+#pragma unroll
+      for (int c = 0; c < D; ++c) rbuf(c) = vel_comb(a.vl, a.bv, a.nc, c, D, n, p) * lam;
+    } else if constexpr (KIND == ST_ADJ1) {
+      const R s1 = rbuf(0) * invL;
+      const R lam = a.lam[p];
+      const R lams = lam + a.h * s1;
+      a.acc[p] = lam + R(0.5) * a.h * s1;
+      const R hh = R(0.5) * a.h;
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const R gm = a.g0[(long long)c * n + p];
+        const R gms = a.g1[(long long)c * n + p];
+        for (int l = 0; l < a.nc; ++l) {
+          R* f = a.F + ((long long)l * D + c) * n + p;
+          *f += hh * (a.b0[l] * lams * gm + a.b1[l] * lam * gms);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < D; ++c) rbuf(c) = vel_comb(a.vl, a.bv, a.nc, c, D, n, p) * lams;
+    } else if constexpr (KIND == ST_ADJ2) {
+      const R s2 = rbuf(0) * invL;
+      const R lamj = a.acc[p] + R(0.5) * a.h * s2;
+      a.lam[p] = lamj;
+      if (!a.skip_out) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) rbuf(c) = vel_comb(a.vl, a.bv, a.nc, c, D, n, p) * lamj;
+      }
+    } else if constexpr (KIND == ST_R2C) {
+      const long long fin = (long long)blockIdx.y * a.fstride_in;
+      rbuf(0) = a.src_a[fin + p];
+    } else if constexpr (KIND == ST_C2R || KIND == ST_DIV) {
+      const long long fo = (long long)blockIdx.y * a.fstride_out;
+      a.out_real[fo + p] = rbuf(0) * invL * a.scale;
+    } else if constexpr (KIND == ST_GRAD) {
+      const long long fo = (long long)blockIdx.y * a.fstride_out;
+#pragma unroll
+      for (int c = 0; c < D; ++c) a.out_real[fo + (long long)c * n + p] = rbuf(c) * invL * a.scale;
+    }
+  }
+
+  // ---- (3) R2C of the new real rows and store ----
+  if constexpr (KOUT > 0) {
+    if (KIND == ST_ADJ2 && a.skip_out) return;  // uniform across the workgroup
+    __syncthreads();
+    fft_lds<R, M, KOUT * B, NT, false, false>(lds, KOUT * B, SS, 1, tw, twb);
+    r2c_post<R, M, NT>(lds, KOUT * B, SS, tw, twl);
+    const long long fo = (long long)blockIdx.y * a.fstride_out;
+    for (int i = threadIdx.x; i < KOUT * B * M; i += NT) {
+      const int k = i / (B * M);
+      const int rem = i - k * (B * M);
+      const int b = rem / M, q = rem - (rem / M) * M;
+      cplx<R> v = lds[(k * B + b) * SS + q];
+      const long long g = fo + (row0 + b) * M + q;
+      if constexpr (KOUT == D && D > 1) {
+        // adjoint kinds: the last product is differentiated along the last axis here
+        if (k == D - 1) v = cmul_i(v, R(q == 0 ? 0 : q));
+        cplx<R>* dst = (k == 0) ? a.out0 : (k == 1 ? a.out1 : a.out2);
+        dst[g] = v;
+      } else {
+        a.out0[g] = v;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Spectral multiplier on vector fields in full-spectrum layout (after the
+// forward transforms along every axis). Per coefficient l and mode k:
+//   OP_HESS: out = scale * (beta a(k) X + [K] Y)
+//   OP_PINV: out = scale * X / (beta a(k))  (k = 0: X)
+//   OP_A   : out = scale * a(k) X
+//   OP_K   : out = scale * K X
+// The packed plane q = 0 holds Z = A + iB with A the k_last = 0 plane and B the
+// k_last = N_last/2 plane; they are separated with the partner mode -k'.
+// ---------------------------------------------------------------------------
+enum SpecOp { OP_HESS = 0, OP_PINV = 1, OP_A = 2, OP_K = 3 };
+
+template <typename R>
+struct SpecArgs {
+  const cplx<R>* X;   // [nc][d][nspec]
+  const cplx<R>* Y;   // [nc][d][nspec] (OP_HESS)
+  cplx<R>* out;       // [nc][d][nspec]
+  int n1, n2, n3;     // grid (n3 = 1 for 2D); the last axis holds M = N_last/2 packed columns
+  int d, nc, reg, proj;
+  R beta, scale;
+  long long nspec;    // complex per scalar field
+};
+
+template <typename R, int D>
+__device__ __forceinline__ void spec_apply(const SpecArgs<R>& a, int op, const R kv[3], const R kt[3],
+                                           const cplx<R>* x, const cplx<R>* y, cplx<R>* o) {
+  R k2 = R(0), kt2 = R(0);
+#pragma unroll
+  for (int i = 0; i < D; ++i) { k2 += kv[i] * kv[i]; kt2 += kt[i] * kt[i]; }
+  const R sym = (a.reg == 1) ? k2 : k2 * k2;
+  cplx<R> kx = {R(0), R(0)};
+  if ((op == OP_K || (op == OP_HESS && a.proj)) && kt2 > R(0)) {
+    const cplx<R>* src = (op == OP_K) ? x : y;
+#pragma unroll
+    for (int i = 0; i < D; ++i) kx = cadd(kx, cscale(src[i], kt[i]));
+    kx = cscale(kx, R(1) / kt2);
+  }
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    cplx<R> r;
+    if (op == OP_HESS) {
+      cplx<R> yy = y[i];
+      if (a.proj) yy = csub(yy, cscale(kx, kt[i]));
+      r = cadd(cscale(x[i], a.beta * sym), yy);
+    } else if (op == OP_PINV) {
+      r = (sym > R(0)) ? cscale(x[i], R(1) / (a.beta * sym)) : x[i];
+    } else if (op == OP_A) {
+      r = cscale(x[i], sym);
+    } else {
+      r = csub(x[i], cscale(kx, kt[i]));
+    }
+    o[i] = cscale(r, a.scale);
+  }
+}
+
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_spec_mul(SpecArgs<R> a, int op) {
+  const int nl = (D == 2) ? a.n2 : a.n3;   // last axis length
+  const int M = nl / 2;
+  const long long rows = (long long)a.n1 * (D == 3 ? a.n2 : 1);
+  const long long tot = rows * M * a.nc;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int l = (int)(t / (rows * M));
+    const long long mi = t - (long long)l * rows * M;
+    const long long row = mi / M;
+    const int q = (int)(mi - row * M);
+    int i1, i2 = 0;
+    if (D == 2) { i1 = (int)row; } else { i1 = (int)(row / a.n2); i2 = (int)(row - (long long)i1 * a.n2); }
+    R kv[3], kt[3];
+    kv[0] = R(wavenumber(i1, a.n1)); kt[0] = R(deriv_wavenumber(i1, a.n1));
+    if (D == 3) { kv[1] = R(wavenumber(i2, a.n2)); kt[1] = R(deriv_wavenumber(i2, a.n2)); }
+    const long long base = (long long)l * D * a.nspec;
+    cplx<R> x[3], y[3], o[3];
+    if (q > 0) {
+      kv[D - 1] = R(q); kt[D - 1] = R(q);
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        x[i] = a.X[base + i * a.nspec + mi];
+        y[i] = a.Y ? a.Y[base + i * a.nspec + mi] : cplx<R>{R(0), R(0)};
+      }
+      spec_apply<R, D>(a, op, kv, kt, x, y, o);
+#pragma unroll
+      for (int i = 0; i < D; ++i) a.out[base + i * a.nspec + mi] = o[i];
+      continue;
+    }
+    // packed plane: pair (k', -k'); the lexicographically smaller row index handles both
+    const int j1 = (a.n1 - i1) % a.n1;
+    const int j2 = (D == 3) ? (a.n2 - i2) % a.n2 : 0;
+    const long long prow = (D == 2) ? j1 : (long long)j1 * a.n2 + j2;
+    if (prow < row) continue;
+    const long long mp = prow * M;
+    cplx<R> zA[3], zB[3], yA[3], yB[3];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const cplx<R> z = a.X[base + i * a.nspec + mi];
+      const cplx<R> zp = a.X[base + i * a.nspec + mp];
+      zA[i] = {R(0.5) * (z.x + zp.x), R(0.5) * (z.y - zp.y)};    // (z + conj zp)/2
+      zB[i] = {R(0.5) * (z.y + zp.y), -R(0.5) * (z.x - zp.x)};   // (z - conj zp)/(2i)
+      if (a.Y) {
+        const cplx<R> w = a.Y[base + i * a.nspec + mi];
+        const cplx<R> wp = a.Y[base + i * a.nspec + mp];
+        yA[i] = {R(0.5) * (w.x + wp.x), R(0.5) * (w.y - wp.y)};
+        yB[i] = {R(0.5) * (w.y + wp.y), -R(0.5) * (w.x - wp.x)};
+      } else {
+        yA[i] = yB[i] = {R(0), R(0)};
+      }
+    }
+    // A plane: k_last = 0; B plane: k_last = -N_last/2 (Nyquist: kept in a(k), zeroed in kt)
+    cplx<R> oA[3], oB[3];
+    kv[D - 1] = R(0); kt[D - 1] = R(0);
+    spec_apply<R, D>(a, op, kv, kt, zA, yA, oA);
+    kv[D - 1] = R(-M);
+    spec_apply<R, D>(a, op, kv, kt, zB, yB, oB);
+    // partner values: A(-k') = conj A(k'), B(-k') = conj B(k') (Hermitian planes).
+    // The multipliers are even, so the outputs keep that symmetry.
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      a.out[base + i * a.nspec + mi] = {oA[i].x - oB[i].y, oA[i].y + oB[i].x};   // oA + i oB
+      if (prow != row) {
+        a.out[base + i * a.nspec + mp] = {oA[i].x + oB[i].y, oB[i].x - oA[i].y}; // conj(oA) + i conj(oB)
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 reductions (deterministic: fixed grid, fixed tree) and vector updates.
+// ---------------------------------------------------------------------------
+constexpr int kRedBlocks = 512;
+constexpr int kRedThreads = 256;
+
+__device__ __forceinline__ double warp_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double warp_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+  return v;
+}
+
+template <bool MAX>
+__device__ __forceinline__ void block_reduce_store(double v, double* out) {
+  __shared__ double part[kRedThreads / 64];
+  v = MAX ? warp_max(v) : warp_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) part[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = part[0];
+    for (int i = 1; i < kRedThreads / 64; ++i) s = MAX ? fmax(s, part[i]) : s + part[i];
+    *out = s;
+  }
+}
+
+enum RedOp { RED_DOT = 0, RED_SUMSQ = 1, RED_MAXABS = 2, RED_SUM = 3, RED_SUMSQDIFF = 4 };
+
+// partial[blockIdx.x] = reduction over a grid-stride slice. A NaN anywhere
+// propagates into the sum (and is caught on the host); RED_MAXABS also turns a
+// NaN into +inf so that it is detected.
+template <typename R, int OP>
+__global__ __launch_bounds__(kRedThreads) void k_reduce(const R* __restrict__ x, const R* __restrict__ y,
+                                                        long long cnt, double* partial) {
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < cnt;
+       i += (long long)gridDim.x * kRedThreads) {
+    const double a = (double)x[i];
+    if (OP == RED_DOT) acc += a * (double)y[i];
+    else if (OP == RED_SUMSQ) acc += a * a;
+    else if (OP == RED_SUM) acc += a;
+    else if (OP == RED_SUMSQDIFF) { const double d = a - (double)y[i]; acc += d * d; }
+    else { const double m = fabs(a); acc = (m != m) ? INFINITY : fmax(acc, m); }
+  }
+  block_reduce_store<OP == RED_MAXABS>(acc, partial + blockIdx.x);
+}
+
+template <bool MAX>
+__global__ __launch_bounds__(kRedThreads) void k_reduce_final(const double* __restrict__ partial, int np,
+                                                              double* out) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += kRedThreads) acc = MAX ? fmax(acc, partial[i]) : acc + partial[i];
+  block_reduce_store<MAX>(acc, out);
+}
+
+// min / max / sum / sum of squares about a shift, of an FP64 field (det F statistics)
+__global__ __launch_bounds__(kRedThreads) void k_stats(const double* __restrict__ x, long long cnt, double shift,
+                                                       double* partial /* [4][blocks] */) {
+  double mn = INFINITY, mx = -INFINITY, s = 0.0, s2 = 0.0;
+  for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < cnt;
+       i += (long long)gridDim.x * kRedThreads) {
+    const double v = x[i];
+    mn = fmin(mn, v); mx = fmax(mx, v);
+    s += v;
+    s2 += (v - shift) * (v - shift);
+  }
+  const int nb = gridDim.x;
+  // min via max of negatives
+  block_reduce_store<true>(-mn, partial + blockIdx.x);
+  __syncthreads();
+  block_reduce_store<true>(mx, partial + nb + blockIdx.x);
+  __syncthreads();
+  block_reduce_store<false>(s, partial + 2 * nb + blockIdx.x);
+  __syncthreads();
+  block_reduce_store<false>(s2, partial + 3 * nb + blockIdx.x);
+}
+
+// y = a*x + b*y   (a, b host scalars)
+template <typename R>
+__global__ void k_axpby(long long cnt, R a, const R* __restrict__ x, R b, R* __restrict__ y) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+       i += (long long)gridDim.x * blockDim.x)
+    y[i] = a * x[i] + b * y[i];
+}
+
+// z = a*x + b*y
+template <typename R>
+__global__ void k_lincomb(long long cnt, R a, const R* __restrict__ x, R b, const R* __restrict__ y,
+                          R* __restrict__ z) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+       i += (long long)gridDim.x * blockDim.x)
+    z[i] = a * x[i] + b * y[i];
+}
+
+template <typename R>
+__global__ void k_fill(long long cnt, R v, R* __restrict__ y) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+       i += (long long)gridDim.x * blockDim.x)
+    y[i] = v;
+}
+
+template <typename RS, typename RD>
+__global__ void k_convert(long long cnt, const RS* __restrict__ x, RD* __restrict__ y) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+       i += (long long)gridDim.x * blockDim.x)
+    y[i] = (RD)x[i];
+}
+
+// ---------------------------------------------------------------------------
+// Deformation gradient (FP64): Heun on dt F = -(v . grad) F + (grad v) F.
+// F, gradF: [d][d][n] and [d][d][d][n] (gradF[i][j][k] = D_k F_ij); gv: [d][d][n]
+// (gv[i][k] = D_k v^i); v: [d][n].
+// mode 0: Fs = F + h rhs(F), acc = F + h/2 rhs(F);  mode 1: F = acc + h/2 rhs(Fs)
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void k_defgrad_stage(long long n, double h, const double* __restrict__ v,
+                                const double* __restrict__ gv, const double* __restrict__ Fin,
+                                const double* __restrict__ gradF, double* __restrict__ acc,
+                                double* __restrict__ Fout, int mode) {
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+       p += (long long)gridDim.x * blockDim.x) {
+    double vv[D], G[D][D], Fm[D][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      vv[i] = v[i * n + p];
+#pragma unroll
+      for (int k = 0; k < D; ++k) { G[i][k] = gv[(i * D + k) * n + p]; Fm[i][k] = Fin[(i * D + k) * n + p]; }
+    }
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        double r = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) r += -vv[k] * gradF[((i * D + j) * D + k) * n + p] + G[i][k] * Fm[k][j];
+        const long long o = (i * D + j) * n + p;
+        if (mode == 0) {
+          acc[o] = Fm[i][j] + 0.5 * h * r;
+          Fout[o] = Fm[i][j] + h * r;
+        } else {
+          Fout[o] = acc[o] + 0.5 * h * r;
+        }
+      }
+    }
+  }
+}
+
+template <int D>
+__global__ void k_det(long long n, const double* __restrict__ F, double* __restrict__ out) {
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+       p += (long long)gridDim.x * blockDim.x) {
+    if (D == 2) {
+      out[p] = F[0 * n + p] * F[3 * n + p] - F[1 * n + p] * F[2 * n + p];
+    } else {
+      const double a = F[0 * n + p], b = F[1 * n + p], c = F[2 * n + p];
+      const double d = F[3 * n + p], e = F[4 * n + p], f = F[5 * n + p];
+      const double g = F[6 * n + p], hh = F[7 * n + p], i = F[8 * n + p];
+      out[p] = a * (e * i - f * hh) - b * (d * i - f * g) + c * (d * hh - e * g);
+    }
+  }
+}
+
+template <int D>
+__global__ void k_identity_tensor(long long n, double* __restrict__ F) {
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+       p += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = 0; j < D; ++j) F[(i * D + j) * n + p] = (i == j) ? 1.0 : 0.0;
+  }
+}
+
+// v(t) = sum_l b_l v_l converted to FP64 (det F works in FP64)
+struct Weights {
+  double w[kMaxNc];
+};
+
+template <typename R>
+__global__ void k_vel_at(long long cnt /* d*n */, int nc, const R* __restrict__ vl, Weights b,
+                         double* __restrict__ out) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+       i += (long long)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int l = 0; l < nc; ++l) s += b.w[l] * (double)vl[(long long)l * cnt + i];
+    out[i] = s;
+  }
+}
+
+}  // namespace nk

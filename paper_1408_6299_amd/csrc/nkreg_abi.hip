@@ -1,0 +1,218 @@
+// extern "C" entry points of the registration library (declared in include/nkreg.h).
+#include <cstring>
+#include <string>
+
+#include "problem.hpp"
+
+struct nkreg_problem {
+  nk::ProblemBase* impl;
+};
+
+struct nkreg_batch {
+  std::vector<nkreg_problem*> items;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+template <typename F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const nk::HipError& e) {
+    return fail(e.code, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(NKREG_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(NKREG_EHIP, e.what());
+  } catch (...) {
+    return fail(NKREG_EHIP, "unknown error");
+  }
+}
+
+bool pow2_in_range(int v) { return v >= nk::kMinN && v <= nk::kMaxN && (v & (v - 1)) == 0; }
+
+int validate(const nkreg_config* c) {
+  if (!c) return fail(NKREG_EINVAL, "null config");
+  if (c->dim != 2 && c->dim != 3) return fail(NKREG_EINVAL, "dim must be 2 or 3");
+  if (c->reg != 1 && c->reg != 2) return fail(NKREG_EINVAL, "reg must be 1 (H1) or 2 (H2)");
+  if (!(c->beta > 0.0)) return fail(NKREG_EINVAL, "beta must be positive");
+  if (c->nt < 1) return fail(NKREG_EINVAL, "nt must be >= 1");
+  if (c->nc < 1 || c->nc > nk::kMaxNc) return fail(NKREG_EINVAL, "nc must be in [1, 16]");
+  if (c->precision != 32 && c->precision != 64) return fail(NKREG_EINVAL, "precision must be 32 or 64");
+  if (c->incompressible != 0 && c->incompressible != 1) return fail(NKREG_EINVAL, "incompressible must be 0 or 1");
+  if (c->checkpoint_every != 0) return fail(NKREG_ENOTIMPL, "trajectory checkpointing is not available");
+  for (int i = 0; i < c->dim; ++i)
+    if (!pow2_in_range(c->n[i])) return fail(NKREG_ESHAPE, "grid sizes must be powers of two in [8, 512]");
+  return NKREG_OK;
+}
+
+#define NEED(ptr)                                                        \
+  do {                                                                   \
+    if (!(ptr)) return fail(NKREG_EINVAL, "null argument: " #ptr);       \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+const char* nkreg_version(void) { return "nkreg 1.0 gfx950"; }
+
+const char* nkreg_status_string(int s) {
+  switch (s) {
+    case NKREG_OK: return "ok";
+    case NKREG_EINVAL: return "invalid argument";
+    case NKREG_ESHAPE: return "unsupported shape";
+    case NKREG_ENOMEM: return "out of device memory";
+    case NKREG_EHIP: return "HIP runtime error";
+    case NKREG_ESTATE: return "call order: no cached state";
+    case NKREG_ENONFINITE: return "non-finite value";
+    case NKREG_ECFL: return "CFL bound violated";
+    case NKREG_ENOCONV: return "iteration limit reached";
+    case NKREG_ENOTIMPL: return "not implemented";
+    default: return "unknown status";
+  }
+}
+
+const char* nkreg_last_error(void) { return g_last_error.c_str(); }
+
+int nkreg_create(const nkreg_config* cfg, void* hip_stream, nkreg_problem** out) {
+  NEED(out);
+  *out = nullptr;
+  int st = validate(cfg);
+  if (st != NKREG_OK) return st;
+  return guarded([&]() {
+    hipStream_t s = (hipStream_t)hip_stream;
+    nk::ProblemBase* impl;
+    if (cfg->precision == 32) impl = new nk::ProblemT<float>(*cfg, s);
+    else impl = new nk::ProblemT<double>(*cfg, s);
+    *out = new nkreg_problem{impl};
+    return (int)NKREG_OK;
+  });
+}
+
+int nkreg_destroy(nkreg_problem* p) {
+  if (!p) return NKREG_OK;
+  return guarded([&]() {
+    (void)hipStreamSynchronize(p->impl->stream());
+    delete p->impl;
+    delete p;
+    return (int)NKREG_OK;
+  });
+}
+
+int nkreg_set_beta(nkreg_problem* p, double beta) {
+  NEED(p);
+  if (!(beta > 0.0)) return fail(NKREG_EINVAL, "beta must be positive");
+  p->impl->cfg.beta = beta;
+  return NKREG_OK;
+}
+
+int nkreg_set_images(nkreg_problem* p, const void* mT, const void* mR) {
+  NEED(p); NEED(mT); NEED(mR);
+  return guarded([&]() { p->impl->set_images(mT, mR); return (int)NKREG_OK; });
+}
+
+int nkreg_forward(nkreg_problem* p, const void* v, void* m1) {
+  NEED(p); NEED(v);
+  return guarded([&]() { p->impl->forward(v, m1); return (int)NKREG_OK; });
+}
+
+int nkreg_objective(nkreg_problem* p, const void* v, double* J, double* Jd, double* Jr) {
+  NEED(p); NEED(v);
+  return guarded([&]() { p->impl->objective(v, J, Jd, Jr); return (int)NKREG_OK; });
+}
+
+int nkreg_objective_gradient(nkreg_problem* p, const void* v, double* J, double* Jd, double* Jr, void* g) {
+  NEED(p); NEED(v);
+  return guarded([&]() { p->impl->objective_gradient(v, J, Jd, Jr, g); return (int)NKREG_OK; });
+}
+
+int nkreg_hessian_matvec(nkreg_problem* p, const void* vt, void* out) {
+  NEED(p); NEED(vt); NEED(out);
+  if (vt == out) return fail(NKREG_EINVAL, "input and output may not alias");
+  return guarded([&]() { p->impl->hessian_matvec(vt, out); return (int)NKREG_OK; });
+}
+
+int nkreg_precond_apply(nkreg_problem* p, const void* r, void* z) {
+  NEED(p); NEED(r); NEED(z);
+  return guarded([&]() { p->impl->precond(r, z); return (int)NKREG_OK; });
+}
+
+int nkreg_project(nkreg_problem* p, const void* f, void* out) {
+  NEED(p); NEED(f); NEED(out);
+  return guarded([&]() { p->impl->project(f, out); return (int)NKREG_OK; });
+}
+
+int nkreg_pcg(nkreg_problem* p, const void* rhs, void* s, double rtol, int maxit, int* iters, double* relres) {
+  NEED(p); NEED(rhs); NEED(s);
+  if (!(rtol >= 0.0)) return fail(NKREG_EINVAL, "rtol must be >= 0");
+  return guarded([&]() { return p->impl->pcg(rhs, s, rtol, maxit, iters, relres); });
+}
+
+int nkreg_det_grad_y(nkreg_problem* p, const void* v, void* detF, double* stats) {
+  NEED(p); NEED(v);
+  return guarded([&]() { p->impl->det_grad_y(v, detF, stats); return (int)NKREG_OK; });
+}
+
+int nkreg_newton_solve(nkreg_problem* p, void* v, const nkreg_solve_opts* opts, nkreg_solve_report* rep) {
+  NEED(p); NEED(v);
+  return guarded([&]() { return p->impl->newton(v, opts, rep); });
+}
+
+int nkreg_gradient(nkreg_problem* p, const void* u, void* g) {
+  NEED(p); NEED(u); NEED(g);
+  return guarded([&]() { p->impl->gradient(u, g); return (int)NKREG_OK; });
+}
+
+int nkreg_divergence(nkreg_problem* p, const void* w, void* s) {
+  NEED(p); NEED(w); NEED(s);
+  return guarded([&]() { p->impl->divergence(w, s); return (int)NKREG_OK; });
+}
+
+int nkreg_apply_reg(nkreg_problem* p, const void* x, void* out) {
+  NEED(p); NEED(x); NEED(out);
+  return guarded([&]() { p->impl->apply_reg(x, out); return (int)NKREG_OK; });
+}
+
+int nkreg_dot(nkreg_problem* p, const void* a, const void* b, long long cnt, double* out) {
+  NEED(p); NEED(a); NEED(b); NEED(out);
+  if (cnt < 0) return fail(NKREG_EINVAL, "negative count");
+  return guarded([&]() { *out = p->impl->dot(a, b, cnt); return (int)NKREG_OK; });
+}
+
+int nkreg_batch_create(int count, nkreg_problem* const* items, nkreg_batch** out) {
+  NEED(out);
+  *out = nullptr;
+  if (count < 0 || (count > 0 && !items)) return fail(NKREG_EINVAL, "bad batch");
+  for (int i = 0; i < count; ++i)
+    if (!items[i]) return fail(NKREG_EINVAL, "null batch item");
+  return guarded([&]() {
+    nkreg_batch* b = new nkreg_batch;
+    b->items.assign(items, items + count);
+    *out = b;
+    return (int)NKREG_OK;
+  });
+}
+
+int nkreg_batch_destroy(nkreg_batch* b) {
+  delete b;
+  return NKREG_OK;
+}
+
+int nkreg_batch_hessian_matvec(nkreg_batch* b, const void* const* vt, void* const* out) {
+  NEED(b);
+  if (!b->items.empty()) { NEED(vt); NEED(out); }
+  return guarded([&]() {
+    for (size_t i = 0; i < b->items.size(); ++i) b->items[i]->impl->hessian_matvec(vt[i], out[i]);
+    return (int)NKREG_OK;
+  });
+}
+
+}  // extern "C"

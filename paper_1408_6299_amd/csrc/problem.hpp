@@ -1,0 +1,589 @@
+// One registration problem on one GPU: buffers, RK2 sweeps, the reduced
+// gradient, the Gauss-Newton Hessian matvec, PCG, the outer iteration and the
+// deformation gradient.
+#pragma once
+
+#include <chrono>
+#include <cstdio>
+#include <memory>
+#include <vector>
+
+#include "../../include/nkreg.h"
+#include "spectral.hpp"
+
+namespace nk {
+
+// b_l(t) = T_{l-1}(2t - 1): shifted Chebyshev polynomials (e:expansion).
+inline void cheb_basis(int nc, double t, double* out) {
+  const double s = 2.0 * t - 1.0;
+  double t0 = 1.0, t1 = s;
+  for (int l = 0; l < nc; ++l) {
+    if (l == 0) out[l] = 1.0;
+    else if (l == 1) out[l] = s;
+    else {
+      const double t2 = 2.0 * s * t1 - t0;
+      t0 = t1;
+      t1 = t2;
+      out[l] = t2;
+    }
+  }
+}
+
+template <typename R>
+struct DevBuf {
+  R* p = nullptr;
+  size_t count = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t n) { alloc(n); }
+  void alloc(size_t n) {
+    release();
+    if (n == 0) return;
+    if (hipMalloc(&p, n * sizeof(R)) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      throw HipError(-3, "hipMalloc of " + std::to_string(n * sizeof(R)) + " bytes failed");
+    }
+    count = n;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    count = 0;
+  }
+  ~DevBuf() { release(); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+};
+
+// Host-visible FP64 reduction slots.
+class Reducer {
+ public:
+  hipStream_t s = nullptr;
+  DevBuf<double> partial;   // [4][kRedBlocks]
+  DevBuf<double> result;    // slots
+  double* host = nullptr;   // pinned
+  static constexpr int kSlots = 16;
+
+  void init(hipStream_t stream) {
+    s = stream;
+    partial.alloc(4 * kRedBlocks);
+    result.alloc(kSlots);
+    NK_HIP(hipHostMalloc(&host, kSlots * sizeof(double), hipHostMallocDefault));
+  }
+  ~Reducer() {
+    if (host) (void)hipHostFree(host);
+  }
+
+  template <typename R>
+  void enqueue(int op, const R* x, const R* y, long long cnt, int slot) {
+    const int nb = (int)std::max<long long>(1, std::min<long long>(kRedBlocks, (cnt + kRedThreads - 1) / kRedThreads));
+    switch (op) {
+      case RED_DOT: hipLaunchKernelGGL((k_reduce<R, RED_DOT>), dim3(nb), dim3(kRedThreads), 0, s, x, y, cnt, partial.p); break;
+      case RED_SUMSQ: hipLaunchKernelGGL((k_reduce<R, RED_SUMSQ>), dim3(nb), dim3(kRedThreads), 0, s, x, y, cnt, partial.p); break;
+      case RED_SUM: hipLaunchKernelGGL((k_reduce<R, RED_SUM>), dim3(nb), dim3(kRedThreads), 0, s, x, y, cnt, partial.p); break;
+      case RED_SUMSQDIFF: hipLaunchKernelGGL((k_reduce<R, RED_SUMSQDIFF>), dim3(nb), dim3(kRedThreads), 0, s, x, y, cnt, partial.p); break;
+      default: hipLaunchKernelGGL((k_reduce<R, RED_MAXABS>), dim3(nb), dim3(kRedThreads), 0, s, x, y, cnt, partial.p); break;
+    }
+    NK_LAUNCHED();
+    if (op == RED_MAXABS)
+      hipLaunchKernelGGL((k_reduce_final<true>), dim3(1), dim3(kRedThreads), 0, s, partial.p, nb, result.p + slot);
+    else
+      hipLaunchKernelGGL((k_reduce_final<false>), dim3(1), dim3(kRedThreads), 0, s, partial.p, nb, result.p + slot);
+    NK_LAUNCHED();
+  }
+  // copies slots [0, n) to the host and waits
+  void fetch(int n) {
+    NK_HIP(hipMemcpyAsync(host, result.p, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    NK_HIP(hipStreamSynchronize(s));
+  }
+  template <typename R>
+  double one(int op, const R* x, const R* y, long long cnt) {
+    enqueue<R>(op, x, y, cnt, 0);
+    fetch(1);
+    return host[0];
+  }
+};
+
+inline int launch_blocks(long long cnt) {
+  return (int)std::max<long long>(1, std::min<long long>((cnt + 255) / 256, 8192));
+}
+
+class ProblemBase {
+ public:
+  nkreg_config cfg{};
+  virtual ~ProblemBase() = default;
+  virtual void set_images(const void* mT, const void* mR) = 0;
+  virtual void forward(const void* v, void* m1) = 0;
+  virtual void objective(const void* v, double* J, double* Jd, double* Jr) = 0;
+  virtual void objective_gradient(const void* v, double* J, double* Jd, double* Jr, void* g) = 0;
+  virtual void hessian_matvec(const void* vt, void* out) = 0;
+  virtual void precond(const void* r, void* z) = 0;
+  virtual void project(const void* f, void* out) = 0;
+  virtual int pcg(const void* rhs, void* s, double rtol, int maxit, int* iters, double* relres) = 0;
+  virtual void det_grad_y(const void* v, void* detF, double* stats) = 0;
+  virtual int newton(void* v, const nkreg_solve_opts* o, nkreg_solve_report* rep) = 0;
+  virtual void gradient(const void* u, void* g) = 0;
+  virtual void divergence(const void* w, void* s) = 0;
+  virtual void apply_reg(const void* x, void* out) = 0;
+  virtual double dot(const void* a, const void* b, long long cnt) = 0;
+  virtual hipStream_t stream() const = 0;
+};
+
+template <typename R>
+class ProblemT final : public ProblemBase {
+ public:
+  Grid g;
+  hipStream_t s;
+  Spectral<R> sp;
+  Reducer red;
+  int nc, d, nt;
+  long long n, nv;     // points per scalar field; values per velocity (nc*d*n)
+  bool have_images = false;
+  bool state_valid = false;
+
+  DevBuf<R> mT, mR, v, traj, acc, lam, m1, mt1, F, tmpv;
+  DevBuf<cplx<R>> T, Ts, S1, S2, U, Dsp, Xs, Ys;
+  // Krylov / driver vectors
+  DevBuf<R> kx, kr, kz, kp, kq, gbuf, sbuf, vtrial, rhsbuf;
+
+  ProblemT(const nkreg_config& c, hipStream_t stream)
+      : g(make_grid(c.dim, c.n)), s(stream), sp(g, stream) {
+    cfg = c;
+    nc = c.nc;
+    d = c.dim;
+    nt = c.nt;
+    n = g.npts;
+    nv = (long long)nc * d * n;
+    red.init(s);
+    mT.alloc(n); mR.alloc(n); v.alloc(nv);
+    traj.alloc((size_t)2 * nt * d * n);
+    acc.alloc(n); lam.alloc(n); m1.alloc(n); mt1.alloc(n);
+    F.alloc(nv); tmpv.alloc(nv);
+    T.alloc(g.nspec); Ts.alloc(g.nspec); S1.alloc(g.nspec); S2.alloc(g.nspec);
+    U.alloc((size_t)3 * g.nspec); Dsp.alloc(g.nspec);
+    Xs.alloc((size_t)nc * d * g.nspec); Ys.alloc((size_t)nc * d * g.nspec);
+    kx.alloc(nv); kr.alloc(nv); kz.alloc(nv); kp.alloc(nv); kq.alloc(nv);
+    gbuf.alloc(nv); sbuf.alloc(nv); vtrial.alloc(nv); rhsbuf.alloc(nv);
+  }
+
+  hipStream_t stream() const override { return s; }
+
+  R* trajp(int j, int stage) { return traj.p + ((size_t)(2 * j + stage)) * d * n; }
+
+  void basis(double t, R* out) {
+    double b[kMaxNc];
+    cheb_basis(nc, t, b);
+    for (int l = 0; l < kMaxNc; ++l) out[l] = l < nc ? (R)b[l] : R(0);
+  }
+
+  void copy(void* dst, const void* src, size_t bytes) {
+    NK_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
+  }
+
+  void set_images(const void* a, const void* b) override {
+    copy(mT.p, a, n * sizeof(R));
+    copy(mR.p, b, n * sizeof(R));
+    have_images = true;
+    state_valid = false;
+  }
+
+  // ---- state equation (Heun), optionally recording the trajectory ----
+  void forward_sweep(const R* vl, bool record, R* m1out) {
+    const R h = R(1.0 / nt);
+    sp.r2c(mT.p, T.p, 1);
+    for (int j = 0; j < nt; ++j) {
+      sp.deriv_cols(T.p, S1.p, S2.p);
+      StageArgs<R> a{};
+      a.spec = T.p; a.s1 = S1.p; a.s2 = S2.p; a.out0 = Ts.p;
+      a.vl = vl; a.nc = nc; a.h = h; a.acc = acc.p;
+      a.g0w = record ? trajp(j, 0) : nullptr;
+      basis(j * (double)h, a.b0);
+      sp.template row<ST_FWD1>(a, 1);
+      sp.deriv_cols(Ts.p, S1.p, S2.p);
+      StageArgs<R> b{};
+      b.spec = Ts.p; b.s1 = S1.p; b.s2 = S2.p; b.out0 = T.p;
+      b.vl = vl; b.nc = nc; b.h = h; b.acc = acc.p;
+      b.g1w = record ? trajp(j, 1) : nullptr;
+      basis((j + 1) * (double)h, b.b1);
+      b.write_real = (j == nt - 1);
+      b.out_real = m1out;
+      sp.template row<ST_FWD2>(b, 1);
+    }
+  }
+
+  // ---- adjoint (conservative, backward Heun) with body-force accumulation ----
+  // lam(1) = ca*src_a + cb*src_b; F (nc*d fields) = time-integrated lam grad m.
+  void adjoint_sweep(const R* vl, R ca, const R* src_a, R cb, const R* src_b, R* Fout) {
+    const R h = R(1.0 / nt);
+    const long long ns = g.nspec;
+    cplx<R>* U0 = U.p;
+    cplx<R>* U1 = U.p + ns;
+    cplx<R>* U2 = U.p + 2 * ns;
+    hipLaunchKernelGGL((k_fill<R>), dim3(launch_blocks(nv)), dim3(256), 0, s, nv, R(0), Fout);
+    NK_LAUNCHED();
+    StageArgs<R> a{};
+    a.vl = vl; a.nc = nc; a.h = h;
+    a.src_a = src_a; a.src_b = src_b; a.ca = ca; a.cb = cb;
+    a.lam = lam.p; a.out0 = U0; a.out1 = U1; a.out2 = U2;
+    basis(1.0, a.bv);
+    sp.template row<ST_ADJINIT>(a, 1);
+    for (int j = nt - 1; j >= 0; --j) {
+      sp.div_cols(U0, U1, U2, S2.p, Dsp.p);
+      StageArgs<R> b{};
+      b.spec = Dsp.p; b.vl = vl; b.nc = nc; b.h = h;
+      b.lam = lam.p; b.acc = acc.p; b.F = Fout;
+      b.g0 = trajp(j, 0); b.g1 = trajp(j, 1);
+      basis(j * (double)h, b.b0);
+      basis((j + 1) * (double)h, b.b1);
+      basis(j * (double)h, b.bv);
+      b.out0 = U0; b.out1 = U1; b.out2 = U2;
+      sp.template row<ST_ADJ1>(b, 1);
+      sp.div_cols(U0, U1, U2, S2.p, Dsp.p);
+      StageArgs<R> c{};
+      c.spec = Dsp.p; c.vl = vl; c.nc = nc; c.h = h;
+      c.lam = lam.p; c.acc = acc.p;
+      basis(j * (double)h, c.bv);
+      c.skip_out = (j == 0);
+      c.out0 = U0; c.out1 = U1; c.out2 = U2;
+      sp.template row<ST_ADJ2>(c, 1);
+    }
+  }
+
+  // ---- incremental state (GN), m~(0) = 0; writes m~_1 to mt1 ----
+  void incremental_sweep(const R* vl, const R* vtl) {
+    const R h = R(1.0 / nt);
+    for (int j = 0; j < nt; ++j) {
+      if (j > 0) sp.deriv_cols(T.p, S1.p, S2.p);
+      StageArgs<R> a{};
+      a.spec = T.p; a.s1 = S1.p; a.s2 = S2.p; a.out0 = Ts.p;
+      a.vl = vl; a.vtl = vtl; a.nc = nc; a.h = h; a.acc = acc.p;
+      a.g0 = trajp(j, 0);
+      a.zero_state = (j == 0);
+      basis(j * (double)h, a.b0);
+      sp.template row<ST_INC1>(a, 1);
+      sp.deriv_cols(Ts.p, S1.p, S2.p);
+      StageArgs<R> b{};
+      b.spec = Ts.p; b.s1 = S1.p; b.s2 = S2.p; b.out0 = T.p;
+      b.vl = vl; b.vtl = vtl; b.nc = nc; b.h = h; b.acc = acc.p;
+      b.g1 = trajp(j, 1);
+      basis((j + 1) * (double)h, b.b1);
+      b.write_real = (j == nt - 1);
+      b.out_real = mt1.p;
+      sp.template row<ST_INC2>(b, 1);
+    }
+  }
+
+  void check_velocity_cfl(const R* vl) {
+    if (cfg.cfl_max <= 0) return;
+    // max_t |v^i(t)| <= sum_l max |v_l^i| since |T_l| <= 1 on [0, 1]
+    double worst = 0.0;
+    for (int i = 0; i < d; ++i) {
+      double bound = 0.0;
+      for (int l = 0; l < nc; ++l) bound += red.one<R>(RED_MAXABS, vl + ((long long)l * d + i) * n, nullptr, n);
+      worst = std::max(worst, bound / (2.0 * M_PI / g.n[i]));
+    }
+    const double cfl = worst / nt;
+    if (!(cfl <= cfg.cfl_max)) throw HipError(NKREG_ECFL, "CFL number " + std::to_string(cfl) + " above cfl_max");
+  }
+
+  double cfl_number(const R* vl) {
+    double worst = 0.0;
+    for (int i = 0; i < d; ++i) {
+      double bound = 0.0;
+      for (int l = 0; l < nc; ++l) bound += red.one<R>(RED_MAXABS, vl + ((long long)l * d + i) * n, nullptr, n);
+      worst = std::max(worst, bound / (2.0 * M_PI / g.n[i]));
+    }
+    return worst / nt;
+  }
+
+  void need_images() {
+    if (!have_images) throw HipError(NKREG_ESTATE, "set_images has not been called");
+  }
+
+  void forward(const void* vin, void* m1out) override {
+    need_images();
+    const R* vl = (const R*)vin;
+    copy(v.p, vl, nv * sizeof(R));
+    forward_sweep(v.p, true, m1.p);
+    if (m1out) copy(m1out, m1.p, n * sizeof(R));
+    state_valid = false;  // a gradient (adjoint) is still needed before matvecs
+    traj_valid = true;
+  }
+  bool traj_valid = false;
+
+  // J_dist, J_reg from m1 and v (FP64 reductions); uses tmpv and Xs/Ys.
+  void objective_terms(const R* vl, double* Jd, double* Jr) {
+    sp.vecop(OP_A, vl, nullptr, tmpv.p, nc, cfg.reg, 0, R(cfg.beta), Xs.p, Ys.p);
+    red.enqueue<R>(RED_SUMSQDIFF, mR.p, m1.p, n, 0);
+    red.enqueue<R>(RED_DOT, vl, tmpv.p, nv, 1);
+    red.fetch(2);
+    *Jd = 0.5 * g.hd * red.host[0];
+    *Jr = 0.5 * cfg.beta * g.hd * red.host[1];
+    if (!std::isfinite(*Jd) || !std::isfinite(*Jr)) throw HipError(NKREG_ENONFINITE, "objective is not finite");
+  }
+
+  void objective(const void* vin, double* J, double* Jd, double* Jr) override {
+    need_images();
+    const R* vl = (const R*)vin;
+    forward_sweep(vl, false, m1.p);
+    state_valid = false;
+    traj_valid = false;
+    double jd, jr;
+    objective_terms(vl, &jd, &jr);
+    if (J) *J = jd + jr;
+    if (Jd) *Jd = jd;
+    if (Jr) *Jr = jr;
+  }
+
+  void objective_gradient(const void* vin, double* J, double* Jd, double* Jr, void* gout) override {
+    need_images();
+    const R* vl = (const R*)vin;
+    check_velocity_cfl(vl);
+    copy(v.p, vl, nv * sizeof(R));
+    forward_sweep(v.p, true, m1.p);
+    traj_valid = true;
+    double jd, jr;
+    objective_terms(v.p, &jd, &jr);
+    adjoint_sweep(v.p, R(1), mR.p, R(-1), m1.p, F.p);
+    R* gdst = gout ? (R*)gout : gbuf.p;
+    sp.vecop(OP_HESS, v.p, F.p, gdst, nc, cfg.reg, cfg.incompressible, R(cfg.beta), Xs.p, Ys.p);
+    state_valid = true;
+    if (J) *J = jd + jr;
+    if (Jd) *Jd = jd;
+    if (Jr) *Jr = jr;
+  }
+
+  void hessian_matvec(const void* vtin, void* out) override {
+    if (!state_valid) throw HipError(NKREG_ESTATE, "no gradient computed at the current velocity");
+    const R* vt = (const R*)vtin;
+    incremental_sweep(v.p, vt);
+    adjoint_sweep(v.p, R(-1), mt1.p, R(0), nullptr, F.p);
+    sp.vecop(OP_HESS, vt, F.p, (R*)out, nc, cfg.reg, cfg.incompressible, R(cfg.beta), Xs.p, Ys.p);
+  }
+
+  void precond(const void* r, void* z) override {
+    sp.vecop(OP_PINV, (const R*)r, nullptr, (R*)z, nc, cfg.reg, 0, R(cfg.beta), Xs.p, Ys.p);
+  }
+  void project(const void* f, void* out) override {
+    sp.vecop(OP_K, (const R*)f, nullptr, (R*)out, nc, cfg.reg, 1, R(cfg.beta), Xs.p, Ys.p);
+  }
+  void apply_reg(const void* x, void* out) override {
+    sp.vecop(OP_A, (const R*)x, nullptr, (R*)out, nc, cfg.reg, 0, R(cfg.beta), Xs.p, Ys.p);
+  }
+  void gradient(const void* u, void* gout) override {
+    sp.gradient((const R*)u, (R*)gout, 1, T.p, S1.p, S2.p);
+  }
+  void divergence(const void* w, void* out) override {
+    sp.divergence((const R*)w, (R*)out, U.p, S2.p, Dsp.p);
+  }
+  double dot(const void* a, const void* b, long long cnt) override {
+    return red.one<R>(RED_DOT, (const R*)a, (const R*)b, cnt);
+  }
+
+  void axpby(long long cnt, double a, const R* x, double b, R* y) {
+    hipLaunchKernelGGL((k_axpby<R>), dim3(launch_blocks(cnt)), dim3(256), 0, s, cnt, (R)a, x, (R)b, y);
+    NK_LAUNCHED();
+  }
+  void lincomb(long long cnt, double a, const R* x, double b, const R* y, R* z) {
+    hipLaunchKernelGGL((k_lincomb<R>), dim3(launch_blocks(cnt)), dim3(256), 0, s, cnt, (R)a, x, (R)b, y, z);
+    NK_LAUNCHED();
+  }
+
+  // ---- PCG (textbook preconditioned CG, x0 = 0) ----
+  int pcg(const void* rhsin, void* sout, double rtol, int maxit, int* iters, double* relres) override {
+    if (!state_valid) throw HipError(NKREG_ESTATE, "no gradient computed at the current velocity");
+    const R* rhs = (const R*)rhsin;
+    R* x = (R*)sout;
+    if (maxit <= 0) maxit = (int)std::min<long long>(nv, 1 << 30);
+    hipLaunchKernelGGL((k_fill<R>), dim3(launch_blocks(nv)), dim3(256), 0, s, nv, R(0), x);
+    NK_LAUNCHED();
+    copy(kr.p, rhs, nv * sizeof(R));
+    const double nb = std::sqrt(red.one<R>(RED_SUMSQ, kr.p, nullptr, nv));
+    if (!std::isfinite(nb)) throw HipError(NKREG_ENONFINITE, "right-hand side is not finite");
+    if (nb == 0.0) {
+      if (iters) *iters = 0;
+      if (relres) *relres = 0.0;
+      return NKREG_OK;
+    }
+    const double tol = rtol * nb;
+    precond(kr.p, kz.p);
+    copy(kp.p, kz.p, nv * sizeof(R));
+    double rz = red.one<R>(RED_DOT, kr.p, kz.p, nv);
+    double rn = nb;
+    int it = 0;
+    bool ok = rn <= tol;
+    while (!ok && it < maxit) {
+      hessian_matvec(kp.p, kq.p);
+      const double pq = red.one<R>(RED_DOT, kp.p, kq.p, nv);
+      if (!std::isfinite(pq)) throw HipError(NKREG_ENONFINITE, "p.Hp is not finite");
+      if (pq <= 0.0) break;  // non-positive curvature
+      const double alpha = rz / pq;
+      axpby(nv, alpha, kp.p, 1.0, x);
+      axpby(nv, -alpha, kq.p, 1.0, kr.p);
+      ++it;
+      rn = std::sqrt(red.one<R>(RED_SUMSQ, kr.p, nullptr, nv));
+      if (rn <= tol) { ok = true; break; }
+      precond(kr.p, kz.p);
+      const double rz_new = red.one<R>(RED_DOT, kr.p, kz.p, nv);
+      lincomb(nv, 1.0, kz.p, rz_new / rz, kp.p, kp.p);
+      rz = rz_new;
+    }
+    if (iters) *iters = it;
+    if (relres) *relres = rn / nb;
+    return ok ? NKREG_OK : NKREG_ENOCONV;
+  }
+
+  // ---- outer iteration (GN-PCG, Armijo, relative-gradient or C1-C5 rule) ----
+  int newton(void* vio, const nkreg_solve_opts* o, nkreg_solve_report* rep) override {
+    need_images();
+    auto t0 = std::chrono::steady_clock::now();
+    nkreg_solve_opts opt{};
+    opt.max_outer = 50; opt.gtol = 1e-3; opt.tau_J = 1e-3; opt.pcg_maxit = 0; opt.cfl_guard = 0;
+    if (o) opt = *o;
+    nkreg_solve_report r{};
+    R* vk = (R*)vio;
+    double J, Jd, Jr;
+    objective_gradient(vk, &J, &Jd, &Jr, gbuf.p);
+    r.n_pde += 2;
+    r.J0 = J;
+    const double g0inf = red.one<R>(RED_MAXABS, gbuf.p, nullptr, nv);
+    const double g0two = std::sqrt(red.one<R>(RED_SUMSQ, gbuf.p, nullptr, nv));
+    r.gnorm0_inf = g0inf;
+    double ginf = g0inf, gtwo = g0two;
+    double Jprev = J;
+    int k = 0;
+    bool conv = false;
+    const double eps = 2.220446049250313e-16;
+    while (true) {
+      if (opt.gtol > 0) {
+        if (ginf <= opt.gtol * g0inf || g0inf == 0.0) { conv = true; break; }
+      } else {
+        const bool c4 = ginf < 1e3 * eps;
+        if (k > 0) {
+          const double dv = red.one<R>(RED_MAXABS, sbuf.p, nullptr, nv);  // |v_{k-1} - v_k| = alpha |s|
+          const double vinf = red.one<R>(RED_MAXABS, vk, nullptr, nv);
+          const bool c1 = (Jprev - J) < opt.tau_J * (1.0 + r.J0);
+          const bool c2 = dv < std::sqrt(opt.tau_J) * (1.0 + vinf);
+          const bool c3 = ginf < std::cbrt(opt.tau_J) * (1.0 + r.J0);
+          if ((c1 && c2 && c3) || c4) { conv = true; break; }
+        } else if (c4) { conv = true; break; }
+      }
+      if (k >= opt.max_outer) break;
+      const double eta = std::min(0.5, std::sqrt(gtwo / g0two));
+      lincomb(nv, -1.0, gbuf.p, 0.0, gbuf.p, rhsbuf.p);
+      int its = 0;
+      double rr = 0;
+      (void)pcg(rhsbuf.p, sbuf.p, eta, opt.pcg_maxit, &its, &rr);
+      r.cg_iterations += its;
+      r.n_pde += 2 * its;
+      if (cfg.incompressible) project(sbuf.p, sbuf.p);
+      if (opt.cfl_guard && cfg.cfl_max > 0) {
+        for (int h = 0; h < 30; ++h) {
+          lincomb(nv, 1.0, vk, 1.0, sbuf.p, vtrial.p);
+          if (cfl_number(vtrial.p) <= cfg.cfl_max) break;
+          axpby(nv, 0.0, sbuf.p, 0.5, sbuf.p);
+        }
+      }
+      // Armijo backtracking from alpha = 1, c1 = 1e-4, at most 20 halvings
+      const double slope = g.hd * red.one<R>(RED_DOT, gbuf.p, sbuf.p, nv);
+      double alpha = 1.0;
+      bool accepted = false;
+      for (int trial = 0; trial <= 20; ++trial) {
+        lincomb(nv, 1.0, vk, alpha, sbuf.p, vtrial.p);
+        double Jt;
+        objective(vtrial.p, &Jt, nullptr, nullptr);
+        r.n_pde += 1;
+        if (Jt <= J + 1e-4 * alpha * slope) { accepted = true; break; }
+        alpha *= 0.5;
+      }
+      if (!accepted) { r.line_search_failed = 1; break; }
+      axpby(nv, alpha, sbuf.p, 1.0, vk);
+      axpby(nv, 0.0, sbuf.p, alpha, sbuf.p);  // keep alpha*s for C2
+      Jprev = J;
+      objective_gradient(vk, &J, &Jd, &Jr, gbuf.p);
+      r.n_pde += 2;
+      ginf = red.one<R>(RED_MAXABS, gbuf.p, nullptr, nv);
+      gtwo = std::sqrt(red.one<R>(RED_SUMSQ, gbuf.p, nullptr, nv));
+      ++k;
+      if (opt.verbose)
+        fprintf(stderr, "[nkreg] k=%d J=%.6e Jd=%.6e |g|inf=%.3e rel=%.3e cg=%d alpha=%g\n", k, J, Jd, ginf,
+                ginf / g0inf, its, alpha);
+    }
+    NK_HIP(hipStreamSynchronize(s));
+    r.iterations = k;
+    r.converged = conv ? 1 : 0;
+    r.J = J; r.J_dist = Jd; r.J_reg = Jr;
+    r.gnorm_inf = ginf;
+    r.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (rep) *rep = r;
+    if (r.line_search_failed) return NKREG_ENOCONV;
+    return conv ? NKREG_OK : NKREG_ENOCONV;
+  }
+
+  // ---- deformation gradient in FP64 ----
+  std::unique_ptr<Spectral<double>> sp64;
+  void det_grad_y(const void* vin, void* detF, double* stats) override {
+    if (!sp64) sp64.reset(new Spectral<double>(g, s));
+    Spectral<double>& q = *sp64;
+    const long long dd = (long long)d * d;
+    DevBuf<double> vel((size_t)d * n), gv((size_t)dd * n), Fm((size_t)dd * n), Fs((size_t)dd * n),
+        Ac((size_t)dd * n), gF((size_t)dd * d * n), det(n);
+    DevBuf<cplx<double>> Tq((size_t)dd * g.nspec), S1q((size_t)dd * g.nspec), S2q((size_t)dd * g.nspec);
+    const R* vl = (const R*)vin;
+    const double h = 1.0 / nt;
+    auto vel_at = [&](double t) {
+      Weights w{};
+      cheb_basis(nc, t, w.w);
+      hipLaunchKernelGGL((k_vel_at<R>), dim3(launch_blocks((long long)d * n)), dim3(256), 0, s,
+                         (long long)d * n, nc, vl, w, vel.p);
+      NK_LAUNCHED();
+      q.gradient(vel.p, gv.p, d, Tq.p, S1q.p, S2q.p);
+    };
+    if (d == 2) hipLaunchKernelGGL((k_identity_tensor<2>), dim3(launch_blocks(n)), dim3(256), 0, s, n, Fm.p);
+    else hipLaunchKernelGGL((k_identity_tensor<3>), dim3(launch_blocks(n)), dim3(256), 0, s, n, Fm.p);
+    NK_LAUNCHED();
+    vel_at(0.0);
+    for (int j = 0; j < nt; ++j) {
+      if (nc > 1 && j > 0) vel_at(j * h);
+      q.gradient(Fm.p, gF.p, (int)dd, Tq.p, S1q.p, S2q.p);
+      if (d == 2) hipLaunchKernelGGL((k_defgrad_stage<2>), dim3(launch_blocks(n)), dim3(256), 0, s, n, h, vel.p, gv.p, Fm.p, gF.p, Ac.p, Fs.p, 0);
+      else hipLaunchKernelGGL((k_defgrad_stage<3>), dim3(launch_blocks(n)), dim3(256), 0, s, n, h, vel.p, gv.p, Fm.p, gF.p, Ac.p, Fs.p, 0);
+      NK_LAUNCHED();
+      if (nc > 1) vel_at((j + 1) * h);
+      q.gradient(Fs.p, gF.p, (int)dd, Tq.p, S1q.p, S2q.p);
+      if (d == 2) hipLaunchKernelGGL((k_defgrad_stage<2>), dim3(launch_blocks(n)), dim3(256), 0, s, n, h, vel.p, gv.p, Fs.p, gF.p, Ac.p, Fm.p, 1);
+      else hipLaunchKernelGGL((k_defgrad_stage<3>), dim3(launch_blocks(n)), dim3(256), 0, s, n, h, vel.p, gv.p, Fs.p, gF.p, Ac.p, Fm.p, 1);
+      NK_LAUNCHED();
+    }
+    if (d == 2) hipLaunchKernelGGL((k_det<2>), dim3(launch_blocks(n)), dim3(256), 0, s, n, Fm.p, det.p);
+    else hipLaunchKernelGGL((k_det<3>), dim3(launch_blocks(n)), dim3(256), 0, s, n, Fm.p, det.p);
+    NK_LAUNCHED();
+    // statistics: min, max, mean, population std (two passes for the std)
+    const int nb = (int)std::max<long long>(1, std::min<long long>(kRedBlocks, (n + kRedThreads - 1) / kRedThreads));
+    hipLaunchKernelGGL(k_stats, dim3(nb), dim3(kRedThreads), 0, s, det.p, n, 0.0, red.partial.p);
+    NK_LAUNCHED();
+    std::vector<double> part(4 * nb);
+    NK_HIP(hipMemcpyAsync(part.data(), red.partial.p, 4 * nb * sizeof(double), hipMemcpyDeviceToHost, s));
+    NK_HIP(hipStreamSynchronize(s));
+    double mn = INFINITY, mx = -INFINITY, sum = 0.0;
+    for (int b = 0; b < nb; ++b) {
+      mn = std::min(mn, -part[b]);
+      mx = std::max(mx, part[nb + b]);
+      sum += part[2 * nb + b];
+    }
+    const double mean = sum / (double)n;
+    hipLaunchKernelGGL(k_stats, dim3(nb), dim3(kRedThreads), 0, s, det.p, n, mean, red.partial.p);
+    NK_LAUNCHED();
+    NK_HIP(hipMemcpyAsync(part.data(), red.partial.p, 4 * nb * sizeof(double), hipMemcpyDeviceToHost, s));
+    NK_HIP(hipStreamSynchronize(s));
+    double ss = 0.0;
+    for (int b = 0; b < nb; ++b) ss += part[3 * nb + b];
+    if (stats) {
+      stats[0] = mn; stats[1] = mx; stats[2] = mean; stats[3] = std::sqrt(ss / (double)n);
+    }
+    if (detF) NK_HIP(hipMemcpyAsync(detF, det.p, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    NK_HIP(hipStreamSynchronize(s));
+  }
+};
+
+}  // namespace nk

@@ -1,0 +1,284 @@
+// Host-side launchers of the spectral pipelines on one grid and one stream.
+#pragma once
+
+#include <cmath>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace nk {
+
+struct HipError : std::runtime_error {
+  int code;
+  HipError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define NK_HIP(call)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      throw ::nk::HipError(-4, std::string(#call) + ": " + hipGetErrorString(e_));           \
+  } while (0)
+
+#define NK_LAUNCHED()                                                                         \
+  do {                                                                                        \
+    hipError_t e_ = hipGetLastError();                                                        \
+    if (e_ != hipSuccess) throw ::nk::HipError(-4, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+struct Grid {
+  int d = 2;
+  int n[3] = {1, 1, 1};
+  long long npts = 0;    // real values per scalar field
+  long long nspec = 0;   // complex values per scalar field (npts / 2)
+  int L = 0;             // last axis length
+  long long rows = 0;    // rows along the last axis
+  int lmax = 0;          // longest axis (twiddle table length)
+  double hd = 0.0;       // cell volume prod(2 pi / N_i)
+};
+
+inline Grid make_grid(int d, const int* n) {
+  Grid g;
+  g.d = d;
+  g.npts = 1;
+  g.lmax = 0;
+  g.hd = 1.0;
+  for (int i = 0; i < d; ++i) {
+    g.n[i] = n[i];
+    g.npts *= n[i];
+    g.lmax = std::max(g.lmax, n[i]);
+    g.hd *= 2.0 * M_PI / n[i];
+  }
+  g.L = n[d - 1];
+  g.rows = g.npts / g.L;
+  g.nspec = g.npts / 2;
+  return g;
+}
+
+// Rows per workgroup of the row kernels, by row length.
+constexpr int row_block(int L) { return L >= 512 ? 2 : (L >= 256 ? 4 : 8); }
+constexpr int kRowThreads = 256;
+constexpr int kColThreads = 256;
+constexpr int col_cmax(int N) { return 1024 / N > 1 ? 1024 / N : 1; }
+
+template <typename R>
+class Spectral {
+ public:
+  Grid g;
+  hipStream_t s = nullptr;
+  cplx<R>* tw = nullptr;  // exp(-2 pi i m / lmax), m < lmax
+
+  Spectral() = default;
+  Spectral(const Grid& grid, hipStream_t stream) : g(grid), s(stream) {
+    std::vector<cplx<R>> h(g.lmax);
+    for (int m = 0; m < g.lmax; ++m) {
+      const double a = -2.0 * M_PI * (double)m / (double)g.lmax;
+      h[m] = {(R)std::cos(a), (R)std::sin(a)};
+    }
+    NK_HIP(hipMalloc(&tw, sizeof(cplx<R>) * g.lmax));
+    NK_HIP(hipMemcpy(tw, h.data(), sizeof(cplx<R>) * g.lmax, hipMemcpyHostToDevice));
+  }
+  Spectral(const Spectral&) = delete;
+  Spectral& operator=(const Spectral&) = delete;
+  ~Spectral() {
+    if (tw) (void)hipFree(tw);
+  }
+
+  // ---- column passes ----
+  // axis 0 = x1 for any d; axis 1 = x2 for d = 3.
+  void col(int mode, int axis, const cplx<R>* in, const cplx<R>* add, cplx<R>* out, int nf, R scale) {
+    int N, outer;
+    long long inner;
+    const int M = g.L / 2;
+    if (g.d == 2) { N = g.n[0]; outer = 1; inner = M; }
+    else if (axis == 0) { N = g.n[0]; outer = 1; inner = (long long)g.n[1] * M; }
+    else { N = g.n[1]; outer = g.n[0]; inner = M; }
+    switch (N) {
+      case 8: col_n<8>(mode, in, add, out, nf, scale, outer, inner); break;
+      case 16: col_n<16>(mode, in, add, out, nf, scale, outer, inner); break;
+      case 32: col_n<32>(mode, in, add, out, nf, scale, outer, inner); break;
+      case 64: col_n<64>(mode, in, add, out, nf, scale, outer, inner); break;
+      case 128: col_n<128>(mode, in, add, out, nf, scale, outer, inner); break;
+      case 256: col_n<256>(mode, in, add, out, nf, scale, outer, inner); break;
+      case 512: col_n<512>(mode, in, add, out, nf, scale, outer, inner); break;
+      default: throw HipError(-2, "unsupported axis length");
+    }
+  }
+
+  // ---- row stages ----
+  template <int KIND>
+  void row(StageArgs<R>& a, int nf) {
+    a.n = g.npts;
+    if (g.d == 2) row_d<KIND, 2>(a, nf);
+    else row_d<KIND, 3>(a, nf);
+  }
+
+  // ---- composite pipelines ----
+  // S1 (and S2 in 3D) = column derivatives of the row spectrum T.
+  void deriv_cols(const cplx<R>* T, cplx<R>* S1, cplx<R>* S2, int nf = 1) {
+    if (g.d == 3) col(COL_DERIV, 1, T, nullptr, S2, nf, R(1) / R(g.n[1]));
+    col(COL_DERIV, 0, T, nullptr, S1, nf, R(1) / R(g.n[0]));
+  }
+  // D = row spectrum of div(w) from U0, U1 (2D: U1 already times ik_2) [, U2 times ik_3].
+  void div_cols(const cplx<R>* U0, const cplx<R>* U1, const cplx<R>* U2, cplx<R>* tmp, cplx<R>* D) {
+    if (g.d == 2) {
+      col(COL_DERIV, 0, U0, U1, D, 1, R(1) / R(g.n[0]));
+    } else {
+      col(COL_DERIV, 1, U1, U2, tmp, 1, R(1) / R(g.n[1]));
+      col(COL_DERIV, 0, U0, tmp, D, 1, R(1) / R(g.n[0]));
+    }
+  }
+
+  void r2c(const R* in, cplx<R>* out, int nf) {
+    StageArgs<R> a{};
+    a.src_a = in;
+    a.out0 = out;
+    a.fstride_in = g.npts;
+    a.fstride_out = g.nspec;
+    row<ST_R2C>(a, nf);
+  }
+  void c2r(const cplx<R>* in, R* out, int nf, R scale) {
+    StageArgs<R> a{};
+    a.spec = in;
+    a.out_real = out;
+    a.scale = scale;
+    a.fstride_in = g.nspec;
+    a.fstride_out = g.npts;
+    row<ST_C2R>(a, nf);
+  }
+
+  // g (nf x d fields) = gradient of nf scalar fields u; T, S1, S2 hold nf spectra each.
+  void gradient(const R* u, R* out, int nf, cplx<R>* T, cplx<R>* S1, cplx<R>* S2) {
+    r2c(u, T, nf);
+    deriv_cols(T, S1, S2, nf);
+    StageArgs<R> a{};
+    a.spec = T; a.s1 = S1; a.s2 = S2;
+    a.out_real = out;
+    a.scale = R(1);
+    a.fstride_in = g.nspec;
+    a.fstride_out = (long long)g.d * g.npts;
+    row<ST_GRAD>(a, nf);
+  }
+
+  // s = div w for one vector field w (d fields); U holds d spectra, tmp/D one each.
+  void divergence(const R* w, R* out, cplx<R>* U, cplx<R>* tmp, cplx<R>* D) {
+    r2c(w, U, g.d);
+    ik_last(U + (g.d - 1) * g.nspec);  // the last component is differentiated in the row domain
+    div_cols(U, U + g.nspec, g.d == 3 ? U + 2 * g.nspec : nullptr, tmp, D);
+    StageArgs<R> b{};
+    b.spec = D;
+    b.out_real = out;
+    b.scale = R(1);
+    b.fstride_in = g.nspec;
+    b.fstride_out = g.npts;
+    row<ST_DIV>(b, 1);
+  }
+
+  // in-place multiplication of one row spectrum by i k_last (Nyquist and k = 0 -> 0)
+  void ik_last(cplx<R>* T);
+
+  // out (nc x d fields) = op(X, Y); Xs, Ys workspace of nc*d spectra each.
+  void vecop(int op, const R* X, const R* Y, R* out, int nc, int reg, int proj, R beta, cplx<R>* Xs,
+             cplx<R>* Ys) {
+    const int nf = nc * g.d;
+    r2c(X, Xs, nf);
+    if (Y) r2c(Y, Ys, nf);
+    if (g.d == 3) {
+      col(COL_FWD, 1, Xs, nullptr, Xs, nf, R(1));
+      if (Y) col(COL_FWD, 1, Ys, nullptr, Ys, nf, R(1));
+    }
+    col(COL_FWD, 0, Xs, nullptr, Xs, nf, R(1));
+    if (Y) col(COL_FWD, 0, Ys, nullptr, Ys, nf, R(1));
+    SpecArgs<R> a{};
+    a.X = Xs; a.Y = Y ? Ys : nullptr; a.out = Xs;
+    a.n1 = g.n[0]; a.n2 = g.n[1]; a.n3 = g.d == 3 ? g.n[2] : 1;
+    a.d = g.d; a.nc = nc; a.reg = reg; a.proj = proj;
+    a.beta = beta;
+    double sc = 1.0;
+    for (int i = 0; i < g.d - 1; ++i) sc /= g.n[i];
+    a.scale = (R)sc;
+    a.nspec = g.nspec;
+    const long long work = (long long)nc * g.nspec;
+    const int blocks = (int)std::min<long long>((work + 255) / 256, 4096);
+    if (g.d == 2) hipLaunchKernelGGL((k_spec_mul<R, 2>), dim3(blocks), dim3(256), 0, s, a, op);
+    else hipLaunchKernelGGL((k_spec_mul<R, 3>), dim3(blocks), dim3(256), 0, s, a, op);
+    NK_LAUNCHED();
+    col(COL_INV, 0, Xs, nullptr, Xs, nf, R(1));
+    if (g.d == 3) col(COL_INV, 1, Xs, nullptr, Xs, nf, R(1));
+    c2r(Xs, out, nf, R(1));
+  }
+
+ private:
+  template <int N>
+  void col_n(int mode, const cplx<R>* in, const cplx<R>* add, cplx<R>* out, int nf, R scale, int outer,
+             long long inner) {
+    constexpr int CMAX = col_cmax(N);
+    ColArgs a;
+    a.inner = (int)inner;
+    a.ctile = (int)std::min<long long>(CMAX, inner);
+    a.field = g.nspec;
+    dim3 grid((unsigned)(inner / a.ctile), (unsigned)outer, (unsigned)nf);
+    const int twb = g.lmax / N;
+    switch (mode) {
+      case COL_FWD:
+        hipLaunchKernelGGL((k_col<R, N, CMAX, kColThreads, COL_FWD>), grid, dim3(kColThreads), 0, s, in, add,
+                           out, a, scale, tw, twb);
+        break;
+      case COL_INV:
+        hipLaunchKernelGGL((k_col<R, N, CMAX, kColThreads, COL_INV>), grid, dim3(kColThreads), 0, s, in, add,
+                           out, a, scale, tw, twb);
+        break;
+      default:
+        hipLaunchKernelGGL((k_col<R, N, CMAX, kColThreads, COL_DERIV>), grid, dim3(kColThreads), 0, s, in, add,
+                           out, a, scale, tw, twb);
+        break;
+    }
+    NK_LAUNCHED();
+  }
+
+  template <int KIND, int D>
+  void row_d(StageArgs<R>& a, int nf) {
+    switch (g.L) {
+      case 8: row_l<KIND, D, 8>(a, nf); break;
+      case 16: row_l<KIND, D, 16>(a, nf); break;
+      case 32: row_l<KIND, D, 32>(a, nf); break;
+      case 64: row_l<KIND, D, 64>(a, nf); break;
+      case 128: row_l<KIND, D, 128>(a, nf); break;
+      case 256: row_l<KIND, D, 256>(a, nf); break;
+      case 512: row_l<KIND, D, 512>(a, nf); break;
+      default: throw HipError(-2, "unsupported row length");
+    }
+  }
+
+  template <int KIND, int D, int L>
+  void row_l(StageArgs<R>& a, int nf) {
+    constexpr int B = row_block(L);
+    dim3 grid((unsigned)(g.rows / B), (unsigned)nf);
+    hipLaunchKernelGGL((k_row_stage<R, L, B, kRowThreads, KIND, D>), grid, dim3(kRowThreads), 0, s, a, tw,
+                       g.lmax);
+    NK_LAUNCHED();
+  }
+};
+
+template <typename R>
+__global__ void k_ik_last(cplx<R>* T, long long rows, int M) {
+  const long long tot = rows * M;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < tot;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int q = (int)(i % M);
+    T[i] = q == 0 ? cplx<R>{R(0), R(0)} : cmul_i(T[i], R(q));
+  }
+}
+
+template <typename R>
+void Spectral<R>::ik_last(cplx<R>* T) {
+  const long long tot = g.nspec;
+  const int blocks = (int)std::min<long long>((tot + 255) / 256, 4096);
+  hipLaunchKernelGGL((k_ik_last<R>), dim3(blocks), dim3(256), 0, s, T, g.rows, g.L / 2);
+  NK_LAUNCHED();
+}
+
+}  // namespace nk

@@ -1,0 +1,230 @@
+"""GPU (HIP, gfx950) vs FP64 oracle parity, element by element, through the C ABI.
+
+Tolerances: FP64 GPU vs oracle to rounding (<= 1e-10 relative, max norm); FP32
+GPU vs oracle to <= 1e-5 relative (the stated precision target), looser only
+where noted with the reason.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import defgrad as odg
+from oracle import krylov as okr
+from oracle import reduced as ord_
+from oracle import spectral as osp
+from oracle import transport as otr
+from tests.helpers import rel_inf, rel_l2, smooth_inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {64: 1e-10, 32: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def nk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1408_6299_amd as nk
+    return nk
+
+
+def dev_t(a, prec):
+    dt = torch.float32 if prec == 32 else torch.float64
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda").to(dt).contiguous()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().double().cpu().numpy()
+
+
+SHAPES = [(8, 8), (16, 32), (64, 64), (8, 16, 8), (16, 8, 32)]
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_gradient_and_divergence(nk, shape, prec):
+    rng = np.random.default_rng(1)
+    u = rng.standard_normal(shape)
+    w = rng.standard_normal((len(shape),) + shape)
+    p = nk.Problem(shape, 4, precision=prec)
+    g = host(p.gradient(dev_t(u, prec)))
+    assert rel_inf(g, osp.grad(u)) < (1e-12 if prec == 64 else 2e-6)
+    s = host(p.divergence(dev_t(w, prec)))
+    assert rel_inf(s, osp.div(w)) < (1e-12 if prec == 64 else 2e-6)
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("shape,nc,reg", [((8, 8), 1, 1), ((32, 16), 2, 2), ((8, 16, 8), 1, 2), ((16, 16, 8), 2, 1)])
+def test_spectral_operators(nk, shape, nc, reg, prec):
+    rng = np.random.default_rng(2)
+    d = len(shape)
+    x = rng.standard_normal((nc, d) + shape)
+    beta = 3e-3
+    p = nk.Problem(shape, 4, nc=nc, reg=reg, beta=beta, precision=prec)
+    tol = 1e-12 if prec == 64 else 3e-6
+    assert rel_inf(host(p.apply_reg(dev_t(x, prec))), osp.apply_A(x, reg, d)) < tol
+    assert rel_inf(host(p.precond(dev_t(x, prec))), osp.apply_Pinv(x, reg, beta, d)) < tol
+    ref_k = np.stack([osp.apply_K(x[l]) for l in range(nc)])
+    assert rel_inf(host(p.project(dev_t(x, prec))), ref_k) < tol
+
+
+def make_pair(nk, shape, nt, nc, reg, gamma, beta, prec, vscale=0.5):
+    mT, mR, vstar, w = smooth_inputs(shape, nt, nc=nc, divfree=bool(gamma))
+    P = ord_.Problem(mT, mR, nt, nc, reg, gamma, beta)
+    G = nk.Problem(shape, nt, nc=nc, reg=reg, incompressible=bool(gamma), beta=beta, precision=prec)
+    G.set_images(dev_t(mT, prec), dev_t(mR, prec))
+    return P, G, vscale * vstar, w
+
+
+CASES = [
+    # shape, nt, nc, reg, gamma, beta
+    ((16, 16), 6, 1, 1, 0, 1e-2),
+    ((64, 64), 16, 1, 1, 0, 1e-2),
+    ((32, 64), 8, 3, 2, 1, 1e-3),
+    ((8, 16, 8), 4, 1, 2, 1, 1e-3),
+    ((16, 8, 16), 6, 2, 1, 0, 1e-2),
+]
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("case", CASES)
+def test_forward_objective_gradient_matvec(nk, case, prec):
+    shape, nt, nc, reg, gamma, beta = case
+    P, G, v, w = make_pair(nk, shape, nt, nc, reg, gamma, beta, prec)
+    tol = TOL[prec]
+    # state equation
+    m1 = host(G.forward(dev_t(v, prec)))
+    ref_m1 = otr.forward_only(P.mT, v, nt)
+    assert rel_inf(m1, ref_m1) < tol
+    # objective and reduced gradient
+    S = ord_.objective_gradient(P, v)
+    J, Jd, Jr, g = G.objective_gradient(dev_t(v, prec))
+    assert abs(J - S.J) <= (1e-10 if prec == 64 else 1e-4) * abs(S.J)
+    assert abs(Jr - S.J_reg) <= (1e-10 if prec == 64 else 1e-5) * abs(S.J_reg)
+    assert rel_inf(host(g), S.g) < (tol if prec == 64 else 1e-4)
+    assert rel_l2(host(g), S.g) < (tol if prec == 64 else 1e-5)
+    # Gauss-Newton Hessian matvec
+    hw = host(G.hessian_matvec(dev_t(w, prec)))
+    ref = ord_.hessian_matvec(P, S, w)
+    assert rel_inf(hw, ref) < (tol if prec == 64 else 2e-5)
+    assert rel_l2(hw, ref) < tol
+    G.close()
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_pcg_fixed_iterations_matches_oracle(nk, prec):
+    shape, nt, nc, reg, gamma, beta = (32, 32), 8, 1, 2, 0, 1e-2
+    P, G, v, w = make_pair(nk, shape, nt, nc, reg, gamma, beta, prec)
+    S = ord_.objective_gradient(P, v)
+    _, _, _, g = G.objective_gradient(dev_t(v, prec))
+    rhs = -S.g
+    for maxit in (1, 4):
+        x_ref, it_ref, rr_ref, _ = okr.pcg(lambda q: ord_.hessian_matvec(P, S, q),
+                                           lambda r: ord_.precond(P, r), rhs, 0.0, maxit)
+        s, it, rr, conv = G.pcg(dev_t(rhs, prec), 0.0, maxit)
+        assert it == it_ref == maxit and not conv
+        assert rel_inf(host(s), x_ref) < (1e-9 if prec == 64 else 1e-4)
+        assert abs(rr - rr_ref) <= (1e-8 if prec == 64 else 1e-4) * rr_ref
+    s, it, rr, conv = G.pcg(dev_t(rhs, prec), 1e-2, 0)
+    assert conv and rr <= 1e-2
+
+
+@pytest.mark.parametrize("shape,nc,divfree", [((32, 32), 1, False), ((32, 32), 3, True), ((8, 16, 8), 1, True)])
+def test_det_grad_y(nk, shape, nc, divfree):
+    nt = 8
+    v = synth.bandlimited_velocity(shape, 12, 3, 0.8, divfree=divfree, nc=nc)
+    ref_det, ref_stats = odg.det_stats(v, nt)
+    for prec in (64, 32):
+        G = nk.Problem(shape, nt, nc=nc, precision=prec)
+        vv = dev_t(v, prec)
+        det, stats = G.det_grad_y(vv)
+        # FP64 on both sides; an FP32 problem rounds v to FP32 first
+        vin = host(vv)
+        if prec == 32:
+            ref_det32, ref_stats32 = odg.det_stats(vin, nt)
+            assert np.abs(host(det) - ref_det32).max() < 1e-10
+            assert np.allclose(stats, ref_stats32, rtol=0, atol=1e-10)
+        else:
+            assert np.abs(host(det) - ref_det).max() < 1e-10
+            assert np.allclose(stats, ref_stats, rtol=0, atol=1e-10)
+
+
+def test_call_order_and_cfl_errors(nk):
+    shape, nt = (16, 16), 4
+    G = nk.Problem(shape, nt, precision=64, cfl_max=0.2)
+    mT, mR, vstar, w = smooth_inputs(shape, nt)
+    with pytest.raises(nk.NkregError) as ei:
+        G.forward(dev_t(vstar, 64))
+    assert ei.value.status == -5  # no images yet
+    G.set_images(dev_t(mT, 64), dev_t(mR, 64))
+    with pytest.raises(nk.NkregError) as ei:
+        G.hessian_matvec(dev_t(w, 64))
+    assert ei.value.status == -5
+    big = np.zeros((1, 2) + shape)
+    big[0, 0] = 10.0  # CFL number 10 * 16 / (2 pi) / 4 >> 0.2
+    with pytest.raises(nk.NkregError) as ei:
+        G.objective_gradient(dev_t(big, 64))
+    assert ei.value.status == -7
+    nanimg = mT.copy()
+    nanimg[3, 3] = np.nan
+    G.set_images(dev_t(nanimg, 64), dev_t(mR, 64))
+    with pytest.raises(nk.NkregError) as ei:
+        G.objective_gradient(dev_t(0 * vstar, 64))
+    assert ei.value.status == -6
+
+
+def test_batch_matches_single_items(nk):
+    specs = [((16, 16), 6), ((32, 32), 6), ((64, 64), 8)]
+    probs, ws, refs = [], [], []
+    for shape, nt in specs:
+        mT, mR, vstar, w = smooth_inputs(shape, nt)
+        G = nk.Problem(shape, nt, precision=32)
+        G.set_images(dev_t(mT, 32), dev_t(mR, 32))
+        G.objective_gradient(dev_t(0.5 * vstar, 32))
+        probs.append(G)
+        ws.append(dev_t(w, 32))
+        refs.append(host(G.hessian_matvec(ws[-1])))
+    B = nk.Batch(probs)
+    outs = B.hessian_matvec(ws)
+    for o, r in zip(outs, refs):
+        assert np.array_equal(host(o), r)
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_newton_solve_matches_oracle(nk, prec):
+    shape, nt, reg, beta = (32, 32), 8, 2, 1e-2
+    P, G, _, _ = make_pair(nk, shape, nt, 1, reg, 0, beta, prec)
+    v_ref, rep_ref, S_ref = okr.gauss_newton(P, gtol=1e-3, max_outer=20)
+    v, rep = G.newton_solve(gtol=1e-3, max_outer=20)
+    assert rep.converged and rep_ref.converged
+    mis0 = np.sum((P.mR - P.mT) ** 2)
+    rel_ref = 2 * S_ref.J_dist / (P.hd * mis0)
+    rel_gpu = 2 * rep.J_dist / (P.hd * mis0)
+    assert abs(rel_gpu - rel_ref) <= 1e-4
+    if prec == 64:
+        assert rep.iterations == rep_ref.iterations
+        assert rel_inf(host(v), v_ref) < 1e-8
+    else:
+        assert abs(rep.iterations - rep_ref.iterations) <= 1
+        assert rel_l2(host(v), v_ref) < 1e-3
+
+
+def test_autograd_gradient_matches_finite_differences(nk):
+    from paper_1408_6299_amd import objective
+    shape, nt = (32, 32), 8
+    P, G, v, _ = make_pair(nk, shape, nt, 1, 2, 0, 1e-3, 64)
+    vt = dev_t(v, 64).requires_grad_(True)
+    J = objective(vt, G)
+    J.backward()
+    grad = vt.grad.detach()
+    for seed in range(20, 25):
+        w = synth.bandlimited_velocity(shape, seed, 4, 0.05)
+        wt = dev_t(w, 64)
+        eps = 1e-4
+        jp = G.objective(dev_t(v + eps * w, 64))[0]
+        jm = G.objective(dev_t(v - eps * w, 64))[0]
+        fd = (jp - jm) / (2 * eps)
+        an = float((grad * wt).sum())
+        assert abs(fd - an) <= 1e-7 * abs(an) + 1e-14
