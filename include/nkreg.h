@@ -19,10 +19,16 @@
  *   tensors) owned by the caller. The library reads them during the call (or,
  *   for asynchronous calls, before the stream reaches the call's end) and never
  *   frees or keeps them. Pointers named h_* are host pointers.
- * - Element type of every field is float if config.precision == 32 and double
- *   if 64. Fields are contiguous, row-major, last axis fastest, axis 0 = x1.
+ * - Arrays are contiguous, row-major, last axis fastest, axis 0 = x1.
  *   A scalar field has n = N1*N2(*N3) values; x_j = 2 pi j / N_i.
- *   A velocity (coefficients) has layout [nc][d][N1][N2](N3).
+ *   A velocity-shaped array has layout [nc][d][N1][N2](N3).
+ * - Element types: scalar fields (images, m_1, the gradient / divergence
+ *   building blocks) use the transport precision, float if
+ *   config.precision == 32 and double if 64. Velocity-shaped arrays (velocity
+ *   coefficients, gradients, Hessian products, Krylov vectors) are double in
+ *   both modes: the transport solves run in the transport precision, the
+ *   control space (including the spectral operators beta A, K and the
+ *   preconditioner applied to it) runs in FP64.
  * - Gradients and Hessian products are the nodal values of the L2-Riesz
  *   representative: dJ[w] = h_d * sum(g * w), h_d = prod(2 pi / N_i). This is
  *   the scaling of the paper's Table t:eigenvalues.
@@ -61,7 +67,7 @@ typedef struct {
   int reg;              /* 1: H1 seminorm, A = -Lap;  2: H2 seminorm, A = Lap^2 */
   int incompressible;   /* gamma: 1 applies the Leray projection K to body forces */
   double beta;          /* regularisation weight, > 0 */
-  int precision;        /* 32 or 64: element type of fields and FFTs */
+  int precision;        /* 32 or 64: precision of the transport solves, their FFTs and scalar fields */
   int checkpoint_every; /* 0: keep the full state trajectory (the only mode in this version) */
   double cfl_max;       /* CFL bound checked by nkreg_objective_gradient; <= 0 disables */
 } nkreg_config;
@@ -76,6 +82,8 @@ typedef struct {
   int pcg_maxit;        /* cap on PCG iterations per Newton step; <= 0: n (system size) */
   int cfl_guard;        /* 1: halve the step until h_t max|v^i|/h_x^i <= cfl_max before the line search */
   int verbose;          /* 1: print one line per outer iteration to stderr */
+  double gref_inf;      /* > 0: ||g_0||_inf of the relative gradient rule (continuation passes the
+                           first level's value); <= 0: the gradient at the solve's starting point */
 } nkreg_solve_opts;
 
 /* What the outer iteration did (quantities of interest, Table t:quantities-of-interest). */
@@ -168,8 +176,20 @@ int nkreg_divergence(nkreg_problem* p, const void* d_w, void* d_s);
 /* d_out = A d_x (nc*d*n values, A = -Lap or Lap^2 per component). */
 int nkreg_apply_reg(nkreg_problem* p, const void* d_x, void* d_out);
 
-/* Host reductions in FP64 over cnt elements of the problem's precision. */
+/* FP64 inner product sum(a*b) of two double arrays of cnt elements. Synchronises. */
 int nkreg_dot(nkreg_problem* p, const void* d_a, const void* d_b, long long cnt, double* h_out);
+
+/* Launch timing of one kernel of the library. nkreg_timer_arm selects a kernel
+ * (row stages: 0 state stage 1, 1 state stage 2, 2 incremental stage 1,
+ * 3 incremental stage 2, 4 adjoint start, 5 adjoint stage 1, 6 adjoint stage 2,
+ * 7 R2C, 8 C2R, 9 gradient, 10 divergence; column passes: 20 forward, 21 inverse,
+ * 22 derivative) and records HIP events on the handle's stream around each of
+ * its next `capacity` launches. nkreg_timer_read synchronises, returns the
+ * number of recorded launches, their average duration in milliseconds and the
+ * average algorithmic bytes per launch (fields read plus fields written), and
+ * disarms the timer. */
+int nkreg_timer_arm(nkreg_problem* p, int kernel_id, int capacity);
+int nkreg_timer_read(nkreg_problem* p, int* launches, double* avg_ms, double* bytes_per_launch);
 
 /* Batched Gauss-Newton matvecs over independent problems of uneven sizes
  * (each a handle created with nkreg_create on the same stream and with a

@@ -20,7 +20,7 @@ class Config(Structure):
 
 class SolveOpts(Structure):
     _fields_ = [("max_outer", c_int), ("gtol", c_double), ("tau_J", c_double), ("pcg_maxit", c_int),
-                ("cfl_guard", c_int), ("verbose", c_int)]
+                ("cfl_guard", c_int), ("verbose", c_int), ("gref_inf", c_double)]
 
 
 class SolveReport(Structure):
@@ -55,6 +55,8 @@ SIGNATURES = {
     "nkreg_divergence": (c_int, [c_void_p, c_void_p, c_void_p]),
     "nkreg_apply_reg": (c_int, [c_void_p, c_void_p, c_void_p]),
     "nkreg_dot": (c_int, [c_void_p, c_void_p, c_void_p, c_longlong, POINTER(c_double)]),
+    "nkreg_timer_arm": (c_int, [c_void_p, c_int, c_int]),
+    "nkreg_timer_read": (c_int, [c_void_p, POINTER(c_int), POINTER(c_double), POINTER(c_double)]),
     "nkreg_batch_create": (c_int, [c_int, POINTER(c_void_p), POINTER(c_void_p)]),
     "nkreg_batch_destroy": (c_int, [c_void_p]),
     "nkreg_batch_hessian_matvec": (c_int, [c_void_p, POINTER(c_void_p), POINTER(c_void_p)]),

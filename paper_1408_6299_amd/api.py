@@ -43,9 +43,11 @@ class SolveResult:
 class Problem:
     """One registration problem (images, grid, time steps, regulariser) on the current GPU.
 
-    Fields are torch tensors on the GPU, contiguous, of dtype float32
-    (``precision=32``) or float64 (``precision=64``). Velocities have shape
-    (nc, d, *shape); images have shape ``shape``.
+    Tensors live on the GPU and are contiguous. Images and other scalar fields
+    have shape ``shape`` and the transport dtype: float32 (``precision=32``) or
+    float64 (``precision=64``). Velocity-shaped arrays (velocity coefficients,
+    gradients, Hessian products, Krylov vectors) have shape (nc, d, *shape) and
+    are float64 in both modes.
     """
 
     def __init__(self, shape: Sequence[int], nt: int, nc: int = 1, reg: int = 1,
@@ -58,6 +60,7 @@ class Problem:
         self.incompressible = bool(incompressible)
         self.precision = int(precision)
         self.dtype = torch.float32 if self.precision == 32 else torch.float64
+        self.vdtype = torch.float64
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         cfg = Config()
@@ -114,8 +117,9 @@ class Problem:
             raise TypeError(f"{name} must be a torch tensor")
         if t.device.type != "cuda":
             raise ValueError(f"{name} must live on the GPU")
-        if t.dtype != self.dtype:
-            raise TypeError(f"{name} has dtype {t.dtype}, expected {self.dtype}")
+        want = self.vdtype if tuple(shape) == self.vshape else self.dtype
+        if t.dtype != want:
+            raise TypeError(f"{name} has dtype {t.dtype}, expected {want}")
         if tuple(t.shape) != tuple(shape):
             raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {shape}")
         if not t.is_contiguous():
@@ -123,10 +127,10 @@ class Problem:
         return t
 
     def empty_v(self) -> torch.Tensor:
-        return torch.empty(self.vshape, dtype=self.dtype, device=self.device)
+        return torch.empty(self.vshape, dtype=self.vdtype, device=self.device)
 
     def zeros_v(self) -> torch.Tensor:
-        return torch.zeros(self.vshape, dtype=self.dtype, device=self.device)
+        return torch.zeros(self.vshape, dtype=self.vdtype, device=self.device)
 
     # -- the calls of the C ABI --
     def set_images(self, mT: torch.Tensor, mR: torch.Tensor) -> None:
@@ -201,13 +205,18 @@ class Problem:
 
     def newton_solve(self, v: Optional[torch.Tensor] = None, gtol: float = 1e-3, max_outer: int = 50,
                      tau_J: float = 1e-3, pcg_maxit: int = 0, cfl_guard: bool = False,
-                     verbose: bool = False) -> Tuple[torch.Tensor, SolveResult]:
-        """Gauss-Newton-Krylov solve from v (zero if None); returns (v, report)."""
+                     verbose: bool = False, gref_inf: float = 0.0) -> Tuple[torch.Tensor, SolveResult]:
+        """Gauss-Newton-Krylov solve from v (zero if None); returns (v, report).
+
+        ``gref_inf`` > 0 replaces ||g_0||_inf in the relative gradient rule (used by
+        beta continuation to measure every level against the first level's gradient).
+        """
         v = self.zeros_v() if v is None else v.clone()
         self._check(v, self.vshape, "v")
         o = SolveOpts()
         o.max_outer, o.gtol, o.tau_J = int(max_outer), float(gtol), float(tau_J)
         o.pcg_maxit, o.cfl_guard, o.verbose = int(pcg_maxit), int(cfl_guard), int(verbose)
+        o.gref_inf = float(gref_inf)
         rep = SolveReport()
         st = self.lib.nkreg_newton_solve(self._h, _ptr(v), byref(o), byref(rep))
         if st not in (_lib.OK, _lib.ENOCONV):
@@ -216,6 +225,20 @@ class Problem:
                           bool(rep.converged), rep.J0, rep.J, rep.J_dist, rep.J_reg, rep.gnorm0_inf,
                           rep.gnorm_inf, rep.seconds, st)
         return v, res
+
+    def continuation(self, betas: Sequence[float], v: Optional[torch.Tensor] = None, gtol: float = 1e-3,
+                     max_outer: int = 50, **kw) -> Tuple[torch.Tensor, list]:
+        """Solve for each beta in turn, warm-starting from the previous level; the relative
+        gradient rule of every level is measured against the first level's ||g_0||_inf."""
+        reports = []
+        gref = 0.0
+        for b in betas:
+            self.beta = b
+            v, rep = self.newton_solve(v, gtol=gtol, max_outer=max_outer, gref_inf=gref, **kw)
+            if gref == 0.0:
+                gref = rep.gnorm0_inf
+            reports.append(rep)
+        return v, reports
 
     def gradient(self, u: torch.Tensor) -> torch.Tensor:
         self._check(u, self.shape, "u")
@@ -229,9 +252,24 @@ class Problem:
         check(self.lib.nkreg_divergence(self._h, _ptr(w), _ptr(out)), "nkreg_divergence")
         return out
 
+    # kernel identifiers for timer_arm
+    KERNELS = {"state1": 0, "state2": 1, "inc1": 2, "inc2": 3, "adjinit": 4, "adj1": 5, "adj2": 6,
+               "r2c": 7, "c2r": 8, "grad": 9, "div": 10, "col_fwd": 20, "col_inv": 21, "col_deriv": 22}
+
+    def timer_arm(self, kernel: str, capacity: int = 4096) -> None:
+        """Record HIP events around each of the next ``capacity`` launches of ``kernel``."""
+        check(self.lib.nkreg_timer_arm(self._h, c_int(self.KERNELS[kernel]), c_int(capacity)), "nkreg_timer_arm")
+
+    def timer_read(self) -> Tuple[int, float, float]:
+        """(launches, average ms per launch, algorithmic bytes per launch); disarms."""
+        n, ms, b = c_int(), c_double(), c_double()
+        check(self.lib.nkreg_timer_read(self._h, byref(n), byref(ms), byref(b)), "nkreg_timer_read")
+        return n.value, ms.value, b.value
+
     def dot(self, a: torch.Tensor, b: torch.Tensor) -> float:
-        if a.dtype != self.dtype or b.dtype != self.dtype or a.numel() != b.numel():
-            raise ValueError("dot: operands must match the problem dtype and size")
+        """FP64 inner product sum(a*b) of two float64 GPU tensors of equal size."""
+        if a.dtype != torch.float64 or b.dtype != torch.float64 or a.numel() != b.numel():
+            raise ValueError("dot: operands must be float64 tensors of equal size")
         out = c_double()
         check(self.lib.nkreg_dot(self._h, _ptr(a.contiguous()), _ptr(b.contiguous()), a.numel(), byref(out)),
               "nkreg_dot")

@@ -187,6 +187,17 @@ int nkreg_dot(nkreg_problem* p, const void* a, const void* b, long long cnt, dou
   return guarded([&]() { *out = p->impl->dot(a, b, cnt); return (int)NKREG_OK; });
 }
 
+int nkreg_timer_arm(nkreg_problem* p, int kernel_id, int capacity) {
+  NEED(p);
+  if (capacity < 1 || capacity > (1 << 16)) return fail(NKREG_EINVAL, "capacity must be in [1, 65536]");
+  return guarded([&]() { p->impl->timer_arm(kernel_id, capacity); return (int)NKREG_OK; });
+}
+
+int nkreg_timer_read(nkreg_problem* p, int* launches, double* avg_ms, double* bytes_per_launch) {
+  NEED(p);
+  return guarded([&]() { p->impl->timer_read(launches, avg_ms, bytes_per_launch); return (int)NKREG_OK; });
+}
+
 int nkreg_batch_create(int count, nkreg_problem* const* items, nkreg_batch** out) {
   NEED(out);
   *out = nullptr;

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cstdio>
 #include <memory>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/nkreg.h"
@@ -127,27 +128,40 @@ class ProblemBase {
   virtual void apply_reg(const void* x, void* out) = 0;
   virtual double dot(const void* a, const void* b, long long cnt) = 0;
   virtual hipStream_t stream() const = 0;
+  virtual void timer_arm(int id, int capacity) = 0;
+  virtual void timer_read(int* launches, double* avg_ms, double* bytes) = 0;
 };
 
+// R is the transport precision (state, adjoint and incremental sweeps, their
+// FFTs and the trajectory). The control space -- velocity coefficients,
+// gradients, Krylov vectors and the spectral finalize (beta A, K, the
+// preconditioner) -- is FP64 in both modes: the H2 symbol |k|^4 would amplify
+// FP32 rounding of a velocity at the grid's corner wavenumbers far above the
+// gradient itself, while control-space work is O(1) per matvec against the
+// O(nt) transport work.
 template <typename R>
 class ProblemT final : public ProblemBase {
  public:
+  static constexpr bool kF64 = std::is_same<R, double>::value;
   Grid g;
   hipStream_t s;
-  Spectral<R> sp;
+  Spectral<R> sp;          // transport precision
+  Spectral<double> sp64;   // control space
   Reducer red;
   int nc, d, nt;
   long long n, nv;     // points per scalar field; values per velocity (nc*d*n)
   bool have_images = false;
   bool state_valid = false;
 
-  DevBuf<R> mT, mR, v, traj, acc, lam, m1, mt1, F, tmpv;
-  DevBuf<cplx<R>> T, Ts, S1, S2, U, Dsp, Xs, Ys;
-  // Krylov / driver vectors
-  DevBuf<R> kx, kr, kz, kp, kq, gbuf, sbuf, vtrial, rhsbuf;
+  // transport precision
+  DevBuf<R> mT, mR, traj, acc, lam, m1, mt1, vR, vtR, F;
+  DevBuf<cplx<R>> T, Ts, S1, S2, U, Dsp;
+  // control space (FP64)
+  DevBuf<double> v, F64, tmpv, kx, kr, kz, kp, kq, gbuf, sbuf, vtrial, rhsbuf;
+  DevBuf<cplx<double>> Xs, Ys;
 
   ProblemT(const nkreg_config& c, hipStream_t stream)
-      : g(make_grid(c.dim, c.n)), s(stream), sp(g, stream) {
+      : g(make_grid(c.dim, c.n)), s(stream), sp(g, stream), sp64(g, stream) {
     cfg = c;
     nc = c.nc;
     d = c.dim;
@@ -155,18 +169,34 @@ class ProblemT final : public ProblemBase {
     n = g.npts;
     nv = (long long)nc * d * n;
     red.init(s);
-    mT.alloc(n); mR.alloc(n); v.alloc(nv);
+    mT.alloc(n); mR.alloc(n);
     traj.alloc((size_t)2 * nt * d * n);
     acc.alloc(n); lam.alloc(n); m1.alloc(n); mt1.alloc(n);
-    F.alloc(nv); tmpv.alloc(nv);
+    F.alloc(nv);
+    if (!kF64) { vR.alloc(nv); vtR.alloc(nv); F64.alloc(nv); }
     T.alloc(g.nspec); Ts.alloc(g.nspec); S1.alloc(g.nspec); S2.alloc(g.nspec);
     U.alloc((size_t)3 * g.nspec); Dsp.alloc(g.nspec);
+    v.alloc(nv); tmpv.alloc(nv);
     Xs.alloc((size_t)nc * d * g.nspec); Ys.alloc((size_t)nc * d * g.nspec);
     kx.alloc(nv); kr.alloc(nv); kz.alloc(nv); kp.alloc(nv); kq.alloc(nv);
     gbuf.alloc(nv); sbuf.alloc(nv); vtrial.alloc(nv); rhsbuf.alloc(nv);
   }
 
   hipStream_t stream() const override { return s; }
+
+  KernelTimer timer;
+  void timer_arm(int id, int capacity) override {
+    timer.arm(id, capacity);
+    sp.timer = &timer;
+  }
+  void timer_read(int* launches, double* avg_ms, double* bytes) override {
+    const double ms = timer.average_ms();
+    if (launches) *launches = timer.used;
+    if (avg_ms) *avg_ms = ms;
+    if (bytes) *bytes = timer.used ? timer.bytes / timer.used : 0.0;
+    timer.armed = -1;
+    sp.timer = nullptr;
+  }
 
   R* trajp(int j, int stage) { return traj.p + ((size_t)(2 * j + stage)) * d * n; }
 
@@ -178,6 +208,27 @@ class ProblemT final : public ProblemBase {
 
   void copy(void* dst, const void* src, size_t bytes) {
     NK_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
+  }
+
+  // FP64 control vector -> transport precision (aliases in FP64 mode)
+  const R* to_transport(const double* x, DevBuf<R>& dst) {
+    if constexpr (kF64) {
+      return x;
+    } else {
+      hipLaunchKernelGGL((k_convert<double, R>), dim3(launch_blocks(nv)), dim3(256), 0, s, nv, x, dst.p);
+      NK_LAUNCHED();
+      return dst.p;
+    }
+  }
+  // body force in transport precision -> FP64
+  const double* force64() {
+    if constexpr (kF64) {
+      return F.p;
+    } else {
+      hipLaunchKernelGGL((k_convert<R, double>), dim3(launch_blocks(nv)), dim3(256), 0, s, nv, F.p, F64.p);
+      NK_LAUNCHED();
+      return F64.p;
+    }
   }
 
   void set_images(const void* a, const void* b) override {
@@ -273,27 +324,23 @@ class ProblemT final : public ProblemBase {
     }
   }
 
-  void check_velocity_cfl(const R* vl) {
-    if (cfg.cfl_max <= 0) return;
-    // max_t |v^i(t)| <= sum_l max |v_l^i| since |T_l| <= 1 on [0, 1]
+  // h_t max over i of (sum_l max|v_l^i|) / h_x^i; bounds the CFL number since
+  // |T_l| <= 1 on [0, 1] (equal to it for nc = 1).
+  double cfl_number(const double* vl) {
     double worst = 0.0;
     for (int i = 0; i < d; ++i) {
       double bound = 0.0;
-      for (int l = 0; l < nc; ++l) bound += red.one<R>(RED_MAXABS, vl + ((long long)l * d + i) * n, nullptr, n);
-      worst = std::max(worst, bound / (2.0 * M_PI / g.n[i]));
-    }
-    const double cfl = worst / nt;
-    if (!(cfl <= cfg.cfl_max)) throw HipError(NKREG_ECFL, "CFL number " + std::to_string(cfl) + " above cfl_max");
-  }
-
-  double cfl_number(const R* vl) {
-    double worst = 0.0;
-    for (int i = 0; i < d; ++i) {
-      double bound = 0.0;
-      for (int l = 0; l < nc; ++l) bound += red.one<R>(RED_MAXABS, vl + ((long long)l * d + i) * n, nullptr, n);
+      for (int l = 0; l < nc; ++l)
+        bound += red.one<double>(RED_MAXABS, vl + ((long long)l * d + i) * n, nullptr, n);
       worst = std::max(worst, bound / (2.0 * M_PI / g.n[i]));
     }
     return worst / nt;
+  }
+
+  void check_velocity_cfl(const double* vl) {
+    if (cfg.cfl_max <= 0) return;
+    const double cfl = cfl_number(vl);
+    if (!(cfl <= cfg.cfl_max)) throw HipError(NKREG_ECFL, "CFL number " + std::to_string(cfl) + " above cfl_max");
   }
 
   void need_images() {
@@ -302,20 +349,18 @@ class ProblemT final : public ProblemBase {
 
   void forward(const void* vin, void* m1out) override {
     need_images();
-    const R* vl = (const R*)vin;
-    copy(v.p, vl, nv * sizeof(R));
-    forward_sweep(v.p, true, m1.p);
+    copy(v.p, vin, nv * sizeof(double));
+    const R* vl = to_transport(v.p, vR);
+    forward_sweep(vl, true, m1.p);
     if (m1out) copy(m1out, m1.p, n * sizeof(R));
-    state_valid = false;  // a gradient (adjoint) is still needed before matvecs
-    traj_valid = true;
+    state_valid = false;  // the adjoint solve of a gradient is still needed before matvecs
   }
-  bool traj_valid = false;
 
-  // J_dist, J_reg from m1 and v (FP64 reductions); uses tmpv and Xs/Ys.
-  void objective_terms(const R* vl, double* Jd, double* Jr) {
-    sp.vecop(OP_A, vl, nullptr, tmpv.p, nc, cfg.reg, 0, R(cfg.beta), Xs.p, Ys.p);
+  // J_dist (FP64 reduction of the transport-precision mismatch) and J_reg (FP64).
+  void objective_terms(const double* vl, double* Jd, double* Jr) {
+    sp64.vecop(OP_A, vl, nullptr, tmpv.p, nc, cfg.reg, 0, cfg.beta, Xs.p, Ys.p);
     red.enqueue<R>(RED_SUMSQDIFF, mR.p, m1.p, n, 0);
-    red.enqueue<R>(RED_DOT, vl, tmpv.p, nv, 1);
+    red.enqueue<double>(RED_DOT, vl, tmpv.p, nv, 1);
     red.fetch(2);
     *Jd = 0.5 * g.hd * red.host[0];
     *Jr = 0.5 * cfg.beta * g.hd * red.host[1];
@@ -324,10 +369,9 @@ class ProblemT final : public ProblemBase {
 
   void objective(const void* vin, double* J, double* Jd, double* Jr) override {
     need_images();
-    const R* vl = (const R*)vin;
-    forward_sweep(vl, false, m1.p);
+    const double* vl = (const double*)vin;
+    forward_sweep(to_transport(vl, vtR), false, m1.p);
     state_valid = false;
-    traj_valid = false;
     double jd, jr;
     objective_terms(vl, &jd, &jr);
     if (J) *J = jd + jr;
@@ -337,16 +381,15 @@ class ProblemT final : public ProblemBase {
 
   void objective_gradient(const void* vin, double* J, double* Jd, double* Jr, void* gout) override {
     need_images();
-    const R* vl = (const R*)vin;
-    check_velocity_cfl(vl);
-    copy(v.p, vl, nv * sizeof(R));
-    forward_sweep(v.p, true, m1.p);
-    traj_valid = true;
+    check_velocity_cfl((const double*)vin);
+    copy(v.p, vin, nv * sizeof(double));
+    const R* vl = to_transport(v.p, vR);
+    forward_sweep(vl, true, m1.p);
     double jd, jr;
     objective_terms(v.p, &jd, &jr);
-    adjoint_sweep(v.p, R(1), mR.p, R(-1), m1.p, F.p);
-    R* gdst = gout ? (R*)gout : gbuf.p;
-    sp.vecop(OP_HESS, v.p, F.p, gdst, nc, cfg.reg, cfg.incompressible, R(cfg.beta), Xs.p, Ys.p);
+    adjoint_sweep(vl, R(1), mR.p, R(-1), m1.p, F.p);
+    double* gdst = gout ? (double*)gout : gbuf.p;
+    sp64.vecop(OP_HESS, v.p, force64(), gdst, nc, cfg.reg, cfg.incompressible, cfg.beta, Xs.p, Ys.p);
     state_valid = true;
     if (J) *J = jd + jr;
     if (Jd) *Jd = jd;
@@ -355,20 +398,21 @@ class ProblemT final : public ProblemBase {
 
   void hessian_matvec(const void* vtin, void* out) override {
     if (!state_valid) throw HipError(NKREG_ESTATE, "no gradient computed at the current velocity");
-    const R* vt = (const R*)vtin;
-    incremental_sweep(v.p, vt);
-    adjoint_sweep(v.p, R(-1), mt1.p, R(0), nullptr, F.p);
-    sp.vecop(OP_HESS, vt, F.p, (R*)out, nc, cfg.reg, cfg.incompressible, R(cfg.beta), Xs.p, Ys.p);
+    const double* vt = (const double*)vtin;
+    const R* vl = kF64 ? (const R*)v.p : vR.p;
+    incremental_sweep(vl, to_transport(vt, vtR));
+    adjoint_sweep(vl, R(-1), mt1.p, R(0), nullptr, F.p);
+    sp64.vecop(OP_HESS, vt, force64(), (double*)out, nc, cfg.reg, cfg.incompressible, cfg.beta, Xs.p, Ys.p);
   }
 
   void precond(const void* r, void* z) override {
-    sp.vecop(OP_PINV, (const R*)r, nullptr, (R*)z, nc, cfg.reg, 0, R(cfg.beta), Xs.p, Ys.p);
+    sp64.vecop(OP_PINV, (const double*)r, nullptr, (double*)z, nc, cfg.reg, 0, cfg.beta, Xs.p, Ys.p);
   }
   void project(const void* f, void* out) override {
-    sp.vecop(OP_K, (const R*)f, nullptr, (R*)out, nc, cfg.reg, 1, R(cfg.beta), Xs.p, Ys.p);
+    sp64.vecop(OP_K, (const double*)f, nullptr, (double*)out, nc, cfg.reg, 1, cfg.beta, Xs.p, Ys.p);
   }
   void apply_reg(const void* x, void* out) override {
-    sp.vecop(OP_A, (const R*)x, nullptr, (R*)out, nc, cfg.reg, 0, R(cfg.beta), Xs.p, Ys.p);
+    sp64.vecop(OP_A, (const double*)x, nullptr, (double*)out, nc, cfg.reg, 0, cfg.beta, Xs.p, Ys.p);
   }
   void gradient(const void* u, void* gout) override {
     sp.gradient((const R*)u, (R*)gout, 1, T.p, S1.p, S2.p);
@@ -377,28 +421,28 @@ class ProblemT final : public ProblemBase {
     sp.divergence((const R*)w, (R*)out, U.p, S2.p, Dsp.p);
   }
   double dot(const void* a, const void* b, long long cnt) override {
-    return red.one<R>(RED_DOT, (const R*)a, (const R*)b, cnt);
+    return red.one<double>(RED_DOT, (const double*)a, (const double*)b, cnt);
   }
 
-  void axpby(long long cnt, double a, const R* x, double b, R* y) {
-    hipLaunchKernelGGL((k_axpby<R>), dim3(launch_blocks(cnt)), dim3(256), 0, s, cnt, (R)a, x, (R)b, y);
+  void axpby(long long cnt, double a, const double* x, double b, double* y) {
+    hipLaunchKernelGGL((k_axpby<double>), dim3(launch_blocks(cnt)), dim3(256), 0, s, cnt, a, x, b, y);
     NK_LAUNCHED();
   }
-  void lincomb(long long cnt, double a, const R* x, double b, const R* y, R* z) {
-    hipLaunchKernelGGL((k_lincomb<R>), dim3(launch_blocks(cnt)), dim3(256), 0, s, cnt, (R)a, x, (R)b, y, z);
+  void lincomb(long long cnt, double a, const double* x, double b, const double* y, double* z) {
+    hipLaunchKernelGGL((k_lincomb<double>), dim3(launch_blocks(cnt)), dim3(256), 0, s, cnt, a, x, b, y, z);
     NK_LAUNCHED();
   }
 
   // ---- PCG (textbook preconditioned CG, x0 = 0) ----
   int pcg(const void* rhsin, void* sout, double rtol, int maxit, int* iters, double* relres) override {
     if (!state_valid) throw HipError(NKREG_ESTATE, "no gradient computed at the current velocity");
-    const R* rhs = (const R*)rhsin;
-    R* x = (R*)sout;
+    const double* rhs = (const double*)rhsin;
+    double* x = (double*)sout;
     if (maxit <= 0) maxit = (int)std::min<long long>(nv, 1 << 30);
-    hipLaunchKernelGGL((k_fill<R>), dim3(launch_blocks(nv)), dim3(256), 0, s, nv, R(0), x);
+    hipLaunchKernelGGL((k_fill<double>), dim3(launch_blocks(nv)), dim3(256), 0, s, nv, 0.0, x);
     NK_LAUNCHED();
-    copy(kr.p, rhs, nv * sizeof(R));
-    const double nb = std::sqrt(red.one<R>(RED_SUMSQ, kr.p, nullptr, nv));
+    copy(kr.p, rhs, nv * sizeof(double));
+    const double nb = std::sqrt(red.one<double>(RED_SUMSQ, kr.p, nullptr, nv));
     if (!std::isfinite(nb)) throw HipError(NKREG_ENONFINITE, "right-hand side is not finite");
     if (nb == 0.0) {
       if (iters) *iters = 0;
@@ -407,24 +451,27 @@ class ProblemT final : public ProblemBase {
     }
     const double tol = rtol * nb;
     precond(kr.p, kz.p);
-    copy(kp.p, kz.p, nv * sizeof(R));
-    double rz = red.one<R>(RED_DOT, kr.p, kz.p, nv);
+    copy(kp.p, kz.p, nv * sizeof(double));
+    double rz = red.one<double>(RED_DOT, kr.p, kz.p, nv);
     double rn = nb;
     int it = 0;
     bool ok = rn <= tol;
     while (!ok && it < maxit) {
       hessian_matvec(kp.p, kq.p);
-      const double pq = red.one<R>(RED_DOT, kp.p, kq.p, nv);
+      const double pq = red.one<double>(RED_DOT, kp.p, kq.p, nv);
       if (!std::isfinite(pq)) throw HipError(NKREG_ENONFINITE, "p.Hp is not finite");
       if (pq <= 0.0) break;  // non-positive curvature
       const double alpha = rz / pq;
       axpby(nv, alpha, kp.p, 1.0, x);
       axpby(nv, -alpha, kq.p, 1.0, kr.p);
       ++it;
-      rn = std::sqrt(red.one<R>(RED_SUMSQ, kr.p, nullptr, nv));
-      if (rn <= tol) { ok = true; break; }
       precond(kr.p, kz.p);
-      const double rz_new = red.one<R>(RED_DOT, kr.p, kz.p, nv);
+      red.enqueue<double>(RED_SUMSQ, kr.p, nullptr, nv, 0);
+      red.enqueue<double>(RED_DOT, kr.p, kz.p, nv, 1);
+      red.fetch(2);
+      rn = std::sqrt(red.host[0]);
+      const double rz_new = red.host[1];
+      if (rn <= tol) { ok = true; break; }
       lincomb(nv, 1.0, kz.p, rz_new / rz, kp.p, kp.p);
       rz = rz_new;
     }
@@ -432,7 +479,6 @@ class ProblemT final : public ProblemBase {
     if (relres) *relres = rn / nb;
     return ok ? NKREG_OK : NKREG_ENOCONV;
   }
-
   // ---- outer iteration (GN-PCG, Armijo, relative-gradient or C1-C5 rule) ----
   int newton(void* vio, const nkreg_solve_opts* o, nkreg_solve_report* rep) override {
     need_images();
@@ -441,14 +487,15 @@ class ProblemT final : public ProblemBase {
     opt.max_outer = 50; opt.gtol = 1e-3; opt.tau_J = 1e-3; opt.pcg_maxit = 0; opt.cfl_guard = 0;
     if (o) opt = *o;
     nkreg_solve_report r{};
-    R* vk = (R*)vio;
+    double* vk = (double*)vio;
     double J, Jd, Jr;
     objective_gradient(vk, &J, &Jd, &Jr, gbuf.p);
     r.n_pde += 2;
     r.J0 = J;
-    const double g0inf = red.one<R>(RED_MAXABS, gbuf.p, nullptr, nv);
-    const double g0two = std::sqrt(red.one<R>(RED_SUMSQ, gbuf.p, nullptr, nv));
-    r.gnorm0_inf = g0inf;
+    const double gstart = red.one<double>(RED_MAXABS, gbuf.p, nullptr, nv);
+    const double g0inf = opt.gref_inf > 0 ? opt.gref_inf : gstart;
+    const double g0two = std::sqrt(red.one<double>(RED_SUMSQ, gbuf.p, nullptr, nv));
+    r.gnorm0_inf = gstart;
     double ginf = g0inf, gtwo = g0two;
     double Jprev = J;
     int k = 0;
@@ -460,8 +507,8 @@ class ProblemT final : public ProblemBase {
       } else {
         const bool c4 = ginf < 1e3 * eps;
         if (k > 0) {
-          const double dv = red.one<R>(RED_MAXABS, sbuf.p, nullptr, nv);  // |v_{k-1} - v_k| = alpha |s|
-          const double vinf = red.one<R>(RED_MAXABS, vk, nullptr, nv);
+          const double dv = red.one<double>(RED_MAXABS, sbuf.p, nullptr, nv);  // |v_{k-1} - v_k| = alpha |s|
+          const double vinf = red.one<double>(RED_MAXABS, vk, nullptr, nv);
           const bool c1 = (Jprev - J) < opt.tau_J * (1.0 + r.J0);
           const bool c2 = dv < std::sqrt(opt.tau_J) * (1.0 + vinf);
           const bool c3 = ginf < std::cbrt(opt.tau_J) * (1.0 + r.J0);
@@ -485,7 +532,7 @@ class ProblemT final : public ProblemBase {
         }
       }
       // Armijo backtracking from alpha = 1, c1 = 1e-4, at most 20 halvings
-      const double slope = g.hd * red.one<R>(RED_DOT, gbuf.p, sbuf.p, nv);
+      const double slope = g.hd * red.one<double>(RED_DOT, gbuf.p, sbuf.p, nv);
       double alpha = 1.0;
       bool accepted = false;
       for (int trial = 0; trial <= 20; ++trial) {
@@ -502,8 +549,8 @@ class ProblemT final : public ProblemBase {
       Jprev = J;
       objective_gradient(vk, &J, &Jd, &Jr, gbuf.p);
       r.n_pde += 2;
-      ginf = red.one<R>(RED_MAXABS, gbuf.p, nullptr, nv);
-      gtwo = std::sqrt(red.one<R>(RED_SUMSQ, gbuf.p, nullptr, nv));
+      ginf = red.one<double>(RED_MAXABS, gbuf.p, nullptr, nv);
+      gtwo = std::sqrt(red.one<double>(RED_SUMSQ, gbuf.p, nullptr, nv));
       ++k;
       if (opt.verbose)
         fprintf(stderr, "[nkreg] k=%d J=%.6e Jd=%.6e |g|inf=%.3e rel=%.3e cg=%d alpha=%g\n", k, J, Jd, ginf,
@@ -521,20 +568,18 @@ class ProblemT final : public ProblemBase {
   }
 
   // ---- deformation gradient in FP64 ----
-  std::unique_ptr<Spectral<double>> sp64;
   void det_grad_y(const void* vin, void* detF, double* stats) override {
-    if (!sp64) sp64.reset(new Spectral<double>(g, s));
-    Spectral<double>& q = *sp64;
+    Spectral<double>& q = sp64;
     const long long dd = (long long)d * d;
     DevBuf<double> vel((size_t)d * n), gv((size_t)dd * n), Fm((size_t)dd * n), Fs((size_t)dd * n),
         Ac((size_t)dd * n), gF((size_t)dd * d * n), det(n);
     DevBuf<cplx<double>> Tq((size_t)dd * g.nspec), S1q((size_t)dd * g.nspec), S2q((size_t)dd * g.nspec);
-    const R* vl = (const R*)vin;
+    const double* vl = (const double*)vin;
     const double h = 1.0 / nt;
     auto vel_at = [&](double t) {
       Weights w{};
       cheb_basis(nc, t, w.w);
-      hipLaunchKernelGGL((k_vel_at<R>), dim3(launch_blocks((long long)d * n)), dim3(256), 0, s,
+      hipLaunchKernelGGL((k_vel_at<double>), dim3(launch_blocks((long long)d * n)), dim3(256), 0, s,
                          (long long)d * n, nc, vl, w, vel.p);
       NK_LAUNCHED();
       q.gradient(vel.p, gv.p, d, Tq.p, S1q.p, S2q.p);

@@ -64,12 +64,58 @@ constexpr int kRowThreads = 256;
 constexpr int kColThreads = 256;
 constexpr int col_cmax(int N) { return 1024 / N > 1 ? 1024 / N : 1; }
 
+// Kernel identifiers for launch timing: row-stage kinds are 0..10 (StageKind),
+// column passes are 20 + ColMode.
+constexpr int kColIdBase = 20;
+
+// Records a pair of HIP events around every launch of one armed kernel and
+// accumulates that launch's algorithmic bytes (field reads + writes).
+struct KernelTimer {
+  int armed = -1;
+  int used = 0;
+  double bytes = 0.0;
+  std::vector<hipEvent_t> ev;
+  ~KernelTimer() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+  void arm(int id, int capacity) {
+    if ((int)ev.size() < 2 * capacity) {
+      const size_t old = ev.size();
+      ev.resize(2 * capacity);
+      for (size_t i = old; i < ev.size(); ++i) NK_HIP(hipEventCreate(&ev[i]));
+    }
+    armed = id;
+    used = 0;
+    bytes = 0.0;
+  }
+  bool want(int id) const { return id == armed && 2 * (used + 1) <= (int)ev.size(); }
+  void before(hipStream_t s) { NK_HIP(hipEventRecord(ev[2 * used], s)); }
+  void after(hipStream_t s, double b) {
+    NK_HIP(hipEventRecord(ev[2 * used + 1], s));
+    ++used;
+    bytes += b;
+  }
+  // average launch duration (ms) over the recorded launches; synchronises
+  double average_ms() {
+    if (used == 0) return 0.0;
+    NK_HIP(hipEventSynchronize(ev[2 * used - 1]));
+    double tot = 0.0;
+    for (int i = 0; i < used; ++i) {
+      float ms = 0.f;
+      NK_HIP(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+      tot += ms;
+    }
+    return tot / used;
+  }
+};
+
 template <typename R>
 class Spectral {
  public:
   Grid g;
   hipStream_t s = nullptr;
   cplx<R>* tw = nullptr;  // exp(-2 pi i m / lmax), m < lmax
+  KernelTimer* timer = nullptr;
 
   Spectral() = default;
   Spectral(const Grid& grid, hipStream_t stream) : g(grid), s(stream) {
@@ -222,6 +268,8 @@ class Spectral {
     a.field = g.nspec;
     dim3 grid((unsigned)(inner / a.ctile), (unsigned)outer, (unsigned)nf);
     const int twb = g.lmax / N;
+    const bool timed = timer && timer->want(kColIdBase + mode);
+    if (timed) timer->before(s);
     switch (mode) {
       case COL_FWD:
         hipLaunchKernelGGL((k_col<R, N, CMAX, kColThreads, COL_FWD>), grid, dim3(kColThreads), 0, s, in, add,
@@ -237,6 +285,7 @@ class Spectral {
         break;
     }
     NK_LAUNCHED();
+    if (timed) timer->after(s, (double)nf * g.nspec * sizeof(cplx<R>) * (add ? 3 : 2));
   }
 
   template <int KIND, int D>
@@ -257,9 +306,31 @@ class Spectral {
   void row_l(StageArgs<R>& a, int nf) {
     constexpr int B = row_block(L);
     dim3 grid((unsigned)(g.rows / B), (unsigned)nf);
+    const bool timed = timer && timer->want(KIND);
+    if (timed) timer->before(s);
     hipLaunchKernelGGL((k_row_stage<R, L, B, kRowThreads, KIND, D>), grid, dim3(kRowThreads), 0, s, a, tw,
                        g.lmax);
     NK_LAUNCHED();
+    if (timed) timer->after(s, (double)nf * stage_fields<KIND>(a, D) * g.npts * sizeof(R));
+  }
+
+  // Scalar fields (real field or row spectrum, same size) one launch of a row
+  // stage reads plus writes, per batch item.
+  template <int KIND>
+  static double stage_fields(const StageArgs<R>& a, int D) {
+    const double v = (double)a.nc * D;  // velocity coefficient fields
+    switch (KIND) {
+      case ST_FWD1: return D + v + (a.g0w ? D : 0) + 2;
+      case ST_FWD2: return D + v + 1 + (a.g1w ? D : 0) + 1 + (a.write_real ? 1 : 0);
+      case ST_INC1: return (a.zero_state ? 0 : D) + 2 * v + D + 2;
+      case ST_INC2: return D + 2 * v + D + 1 + 1 + (a.write_real ? 1 : 0);
+      case ST_ADJINIT: return (a.src_b ? 2 : 1) + v + 1 + D;
+      case ST_ADJ1: return 1 + 1 + 2 * D + 2 * v + 1 + D + v;
+      case ST_ADJ2: return a.skip_out ? 3 : 2 + v + 1 + D;
+      case ST_R2C: case ST_C2R: case ST_DIV: return 2;
+      case ST_GRAD: return D + D;
+      default: return 0;
+    }
   }
 };
 
