@@ -114,6 +114,12 @@ int nkreg_destroy(nkreg_problem* p);
 /* Change beta (continuation; Section "Parameter Selection"). Keeps the cached state. */
 int nkreg_set_beta(nkreg_problem* p, double beta);
 
+/* Hessian matvecs are captured into a HIP graph per (input, output) pointer
+ * pair and replayed (the default); enable = 0 launches every kernel eagerly.
+ * The library runs on an internal stream joined to the caller's stream at every
+ * call, so capture works also when the caller uses the null stream. */
+int nkreg_use_graphs(nkreg_problem* p, int enable);
+
 /* Copy the template m_T and reference m_R (each n values) into the handle. */
 int nkreg_set_images(nkreg_problem* p, const void* d_mT, const void* d_mR);
 
@@ -187,7 +193,8 @@ int nkreg_dot(nkreg_problem* p, const void* d_a, const void* d_b, long long cnt,
  * its next `capacity` launches. nkreg_timer_read synchronises, returns the
  * number of recorded launches, their average duration in milliseconds and the
  * average algorithmic bytes per launch (fields read plus fields written), and
- * disarms the timer. */
+ * disarms the timer. While the timer is armed, Hessian matvecs launch eagerly
+ * instead of replaying their HIP graph (graph-recorded events cannot be timed). */
 int nkreg_timer_arm(nkreg_problem* p, int kernel_id, int capacity);
 int nkreg_timer_read(nkreg_problem* p, int* launches, double* avg_ms, double* bytes_per_launch);
 

@@ -38,6 +38,7 @@ SIGNATURES = {
     "nkreg_create": (c_int, [POINTER(Config), c_void_p, POINTER(c_void_p)]),
     "nkreg_destroy": (c_int, [c_void_p]),
     "nkreg_set_beta": (c_int, [c_void_p, c_double]),
+    "nkreg_use_graphs": (c_int, [c_void_p, c_int]),
     "nkreg_set_images": (c_int, [c_void_p, c_void_p, c_void_p]),
     "nkreg_forward": (c_int, [c_void_p, c_void_p, c_void_p]),
     "nkreg_objective_gradient": (c_int, [c_void_p, c_void_p, POINTER(c_double), POINTER(c_double),
@@ -76,6 +77,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     global _lib
     if _lib is not None:
         return _lib
+    # torch's HIP runtime must be loaded first: libnkreg.so then binds to that
+    # runtime instead of bringing a second HIP/HSA runtime into the process,
+    # which leaves the device invisible to one of them.
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python __graft_entry__.py` or `python paper_1408_6299_amd/build.py` "
                           "(the HIP library is required; there is no fallback)")

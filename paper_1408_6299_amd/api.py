@@ -112,6 +112,10 @@ class Problem:
         check(self.lib.nkreg_set_beta(self._h, c_double(value)), "nkreg_set_beta")
         self._beta = float(value)
 
+    def use_graphs(self, enable: bool) -> None:
+        """Replay Hessian matvecs from a captured HIP graph (default) or launch eagerly."""
+        check(self.lib.nkreg_use_graphs(self._h, c_int(int(enable))), "nkreg_use_graphs")
+
     def _check(self, t: torch.Tensor, shape: Tuple[int, ...], name: str) -> torch.Tensor:
         if not isinstance(t, torch.Tensor):
             raise TypeError(f"{name} must be a torch tensor")

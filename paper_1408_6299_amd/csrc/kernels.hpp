@@ -14,68 +14,30 @@
 #pragma once
 
 #include "common.hpp"
-#include "fft_lds.hpp"
 
 namespace nk {
 
 // ---------------------------------------------------------------------------
-// Column pass: FFT along a strided axis of a row spectrum.
-// Field layout: element (o, x, c) at o * (N * inner) + x * inner + c.
+// Column pass: FFT along a strided axis of a row spectrum (kernel k_col_w in
+// kernels_wave.hpp). Field layout: element (o, x, c) at o * (N * inner) + x * inner + c.
 // ---------------------------------------------------------------------------
 enum ColMode { COL_FWD = 0, COL_INV = 1, COL_DERIV = 2 };
 
 struct ColArgs {
   int inner;        // complex elements between consecutive x
-  int ctile;        // columns per workgroup (<= CMAX, divides inner)
+  int ctile;        // columns per workgroup
   long long field;  // complex elements between fields (blockIdx.z)
 };
-
-template <typename R, int N, int CMAX, int NT, int MODE>
-__global__ __launch_bounds__(NT) void k_col(const cplx<R>* in, const cplx<R>* add,
-                                            cplx<R>* out, ColArgs a, R scale,
-                                            const cplx<R>* __restrict__ tw, int twb) {
-  __shared__ cplx<R> tile[N * CMAX];
-  const int C = a.ctile;
-  const long long base = (long long)blockIdx.z * a.field + (long long)blockIdx.y * N * a.inner +
-                         (long long)blockIdx.x * C;
-  const int tot = N * C;
-  for (int i = threadIdx.x; i < tot; i += NT) {
-    const int x = i / C, c = i - (i / C) * C;
-    tile[i] = in[base + (long long)x * a.inner + c];
-  }
-  __syncthreads();
-  if (MODE == COL_INV) {
-    fft_lds<R, N, CMAX, NT, true, true>(tile, C, 1, C, tw, twb);
-  } else {
-    fft_lds<R, N, CMAX, NT, false, true>(tile, C, 1, C, tw, twb);
-  }
-  if (MODE == COL_DERIV) {
-    for (int i = threadIdx.x; i < tot; i += NT) {
-      const int x = i / C;
-      const R k = R(deriv_wavenumber(x, N)) * scale;
-      tile[i] = cmul_i(tile[i], k);
-    }
-    __syncthreads();
-    fft_lds<R, N, CMAX, NT, true, true>(tile, C, 1, C, tw, twb);
-  }
-  for (int i = threadIdx.x; i < tot; i += NT) {
-    const int x = i / C, c = i - (i / C) * C;
-    const long long g = base + (long long)x * a.inner + c;
-    cplx<R> v = tile[i];
-    if (MODE == COL_INV) v = cscale(v, scale);
-    if (MODE == COL_DERIV && add) v = cadd(v, add[g]);
-    out[g] = v;
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Row stage: per row of the last axis, (1) C2R of KIN input row spectra,
 // (2) a pointwise epilogue (Heun stage, forcing, body force, ...),
-// (3) R2C of KOUT new real rows. One kernel per RK2 stage of every sweep.
+// (3) R2C of KOUT new real rows. One kernel per RK2 stage of every sweep;
+// the kernel itself is k_row_w (kernels_wave.hpp).
 // ---------------------------------------------------------------------------
 enum StageKind {
   ST_FWD1 = 0,   // state, stage 1: store grad m^j, acc = m + h/2 r1, out m + h r1
-  ST_FWD2 = 1,   // state, stage 2: store grad m*_j, out m^{j+1} = acc + h/2 r2
+  ST_FWD2 = 1,   // state, stage 2: store grad m*_j, m^{j+1} = acc + h/2 r2 (real and spectrum)
   ST_INC1 = 2,   // incremental state, stage 1 (forcing -v~(t_j) . grad m^j)
   ST_INC2 = 3,   // incremental state, stage 2 (forcing -v~(t_{j+1}) . grad m*_j)
   ST_ADJINIT = 4,// lam = a*src_a + b*src_b; out v(t_nt) lam
@@ -104,7 +66,8 @@ struct StageArgs {
   R* acc;                    // Heun accumulator [n]
   R* lam;                    // adjoint state [n]
   R* F;                      // body force accumulators [nc][d][n]
-  R* out_real;               // real output (m_1, gradient, divergence, C2R result)
+  R* out_real;               // real output (new state of stage 2, gradient, divergence, C2R result)
+  const R* mreal;            // stage 1: the transported field at t_j as a real array
   const R* src_a;
   const R* src_b;
   R ca, cb;                  // lam = ca * src_a + cb * src_b (src_b may be null)
@@ -112,7 +75,7 @@ struct StageArgs {
   R scale;                   // C2R output scale (ST_C2R, ST_GRAD, ST_DIV multiply by scale/L)
   int nc;
   int zero_state;            // INC1 at j = 0: the incremental state is zero
-  int write_real;            // FWD2/INC2: also store the new state as a real field
+  int write_real;            // unused (stage 2 always stores the new state as a real field)
   int skip_out;              // ADJ2 at j = 0: no further spectra needed
   long long n;               // points per scalar field
   long long fstride_in;      // batch stride (elements) of inputs (ST_R2C: reals, else complex)
@@ -125,11 +88,12 @@ struct StageArgs {
 template <int KIND, int D>
 struct StageShape {
   // KIN: input row spectra after C2R; KOUT: real rows transformed by R2C.
-  static constexpr int KIN = (KIND == ST_FWD1 || KIND == ST_FWD2 || KIND == ST_INC1 || KIND == ST_INC2)
-                                 ? 1 + D
-                                 : (KIND == ST_ADJ1 || KIND == ST_ADJ2 || KIND == ST_C2R || KIND == ST_DIV)
-                                       ? 1
-                                       : (KIND == ST_GRAD ? D : 0);
+  // The transport stages need only the gradient of the transported field: the
+  // field itself travels as a real array (stage 2 stores it, stage 1 reads it).
+  static constexpr int KIN = (KIND == ST_FWD1 || KIND == ST_FWD2 || KIND == ST_INC1 || KIND == ST_INC2 ||
+                              KIND == ST_GRAD)
+                                 ? D
+                                 : (KIND == ST_ADJ1 || KIND == ST_ADJ2 || KIND == ST_C2R || KIND == ST_DIV) ? 1 : 0;
   static constexpr int KOUT = (KIND == ST_FWD1 || KIND == ST_FWD2 || KIND == ST_INC1 || KIND == ST_INC2 ||
                                KIND == ST_R2C)
                                   ? 1
@@ -144,167 +108,6 @@ __device__ __forceinline__ R vel_comb(const R* __restrict__ v, const R* w, int n
   R s = R(0);
   for (int l = 0; l < nc; ++l) s += w[l] * v[((long long)l * d + comp) * n + p];
   return s;
-}
-
-template <typename R, int L, int B, int NT, int KIND, int D>
-__global__ __launch_bounds__(NT) void k_row_stage(StageArgs<R> a, const cplx<R>* __restrict__ tw, int lmax) {
-  constexpr int M = L / 2;
-  constexpr int SS = M + 1;  // one complex of padding per row buffer
-  using SH = StageShape<KIND, D>;
-  constexpr int KIN = SH::KIN, KOUT = SH::KOUT, KMAX = SH::KMAX;
-  __shared__ cplx<R> lds[KMAX * B * SS];
-  const int twb = lmax / M;   // stride of a length-M transform in the table
-  const int twl = lmax / L;   // stride of the length-L packing twiddles
-  const long long row0 = (long long)blockIdx.x * B;
-  const long long n = a.n;
-  const int zero_in = (KIND == ST_INC1) ? a.zero_state : 0;
-
-  // ---- (1) load input row spectra into LDS, buffer s = k * B + b ----
-  if constexpr (KIN > 0) {
-    if (!zero_in) {
-      const long long fin = (long long)blockIdx.y * a.fstride_in;
-      for (int i = threadIdx.x; i < KIN * B * M; i += NT) {
-        const int k = i / (B * M);
-        const int rem = i - k * (B * M);
-        const int b = rem / M, q = rem - (rem / M) * M;
-        const long long g = fin + (row0 + b) * M + q;
-        cplx<R> v;
-        if constexpr (KIND == ST_GRAD) {
-          // k < D-1: column derivatives along x1 (x2); k = D-1: ik_last * spec
-          if (k == D - 1) {
-            const R kk = R(q == 0 ? 0 : q);
-            v = cmul_i(a.spec[g], kk);
-          } else {
-            v = (k == 0) ? a.s1[g] : a.s2[g];
-          }
-        } else if constexpr (KIN == 1 + D) {
-          // k = 0: the field; 1..D-1: column derivatives; D: ik_last * field
-          if (k == 0) v = a.spec[g];
-          else if (k == D) v = cmul_i(a.spec[g], R(q == 0 ? 0 : q));
-          else v = (k == 1) ? a.s1[g] : a.s2[g];
-        } else {
-          v = a.spec[g];
-        }
-        lds[(k * B + b) * SS + q] = v;
-      }
-      __syncthreads();
-      c2r_pre<R, M, NT>(lds, KIN * B, SS, tw, twl);
-      fft_lds<R, M, KIN * B, NT, true, false>(lds, KIN * B, SS, 1, tw, twb);
-    }
-  }
-
-  // ---- (2) pointwise epilogue over the B*L points of this workgroup ----
-  const R invL = R(1) / R(L);
-  for (int i = threadIdx.x; i < B * L; i += NT) {
-    const int b = i / L, x = i - (i / L) * L;
-    const long long p = (row0 + b) * L + x;
-    auto rbuf = [&](int k) -> R& { return reinterpret_cast<R*>(lds + (k * B + b) * SS)[x]; };
-    if constexpr (KIND == ST_FWD1 || KIND == ST_FWD2) {
-      const R m = rbuf(0) * invL;
-      R r = R(0);
-      const R* w = (KIND == ST_FWD1) ? a.b0 : a.b1;
-#pragma unroll
-      for (int c = 0; c < D; ++c) {
-        const R gc = rbuf(1 + c) * invL;
-        if (KIND == ST_FWD1) { if (a.g0w) a.g0w[(long long)c * n + p] = gc; }
-        else { if (a.g1w) a.g1w[(long long)c * n + p] = gc; }
-        r -= vel_comb(a.vl, w, a.nc, c, D, n, p) * gc;
-      }
-      if (KIND == ST_FWD1) {
-        a.acc[p] = m + R(0.5) * a.h * r;
-        rbuf(0) = m + a.h * r;
-      } else {
-        const R mn = a.acc[p] + R(0.5) * a.h * r;
-        if (a.write_real) a.out_real[p] = mn;
-        rbuf(0) = mn;
-      }
-    } else if constexpr (KIND == ST_INC1 || KIND == ST_INC2) {
-      const R* w = (KIND == ST_INC1) ? a.b0 : a.b1;
-      const R* gm = (KIND == ST_INC1) ? a.g0 : a.g1;
-      R r = R(0);
-      R m = R(0);
-      if (!zero_in) {
-        m = rbuf(0) * invL;
-#pragma unroll
-        for (int c = 0; c < D; ++c) r -= vel_comb(a.vl, w, a.nc, c, D, n, p) * (rbuf(1 + c) * invL);
-      }
-#pragma unroll
-      for (int c = 0; c < D; ++c) r -= vel_comb(a.vtl, w, a.nc, c, D, n, p) * gm[(long long)c * n + p];
-      if (KIND == ST_INC1) {
-        a.acc[p] = m + R(0.5) * a.h * r;
-        rbuf(0) = m + a.h * r;
-      } else {
-        const R mn = a.acc[p] + R(0.5) * a.h * r;
-        if (a.write_real) a.out_real[p] = mn;
-        rbuf(0) = mn;
-      }
-    } else if constexpr (KIND == ST_ADJINIT) {
-      R lam = a.ca * a.src_a[p];
-      if (a.src_b) lam += a.cb * a.src_b[p];
-      a.lam[p] = lam;
-#pragma unroll
-      for (int c = 0; c < D; ++c) rbuf(c) = vel_comb(a.vl, a.bv, a.nc, c, D, n, p) * lam;
-    } else if constexpr (KIND == ST_ADJ1) {
-      const R s1 = rbuf(0) * invL;
-      const R lam = a.lam[p];
-      const R lams = lam + a.h * s1;
-      a.acc[p] = lam + R(0.5) * a.h * s1;
-      const R hh = R(0.5) * a.h;
-#pragma unroll
-      for (int c = 0; c < D; ++c) {
-        const R gm = a.g0[(long long)c * n + p];
-        const R gms = a.g1[(long long)c * n + p];
-        for (int l = 0; l < a.nc; ++l) {
-          R* f = a.F + ((long long)l * D + c) * n + p;
-          *f += hh * (a.b0[l] * lams * gm + a.b1[l] * lam * gms);
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < D; ++c) rbuf(c) = vel_comb(a.vl, a.bv, a.nc, c, D, n, p) * lams;
-    } else if constexpr (KIND == ST_ADJ2) {
-      const R s2 = rbuf(0) * invL;
-      const R lamj = a.acc[p] + R(0.5) * a.h * s2;
-      a.lam[p] = lamj;
-      if (!a.skip_out) {
-#pragma unroll
-        for (int c = 0; c < D; ++c) rbuf(c) = vel_comb(a.vl, a.bv, a.nc, c, D, n, p) * lamj;
-      }
-    } else if constexpr (KIND == ST_R2C) {
-      const long long fin = (long long)blockIdx.y * a.fstride_in;
-      rbuf(0) = a.src_a[fin + p];
-    } else if constexpr (KIND == ST_C2R || KIND == ST_DIV) {
-      const long long fo = (long long)blockIdx.y * a.fstride_out;
-      a.out_real[fo + p] = rbuf(0) * invL * a.scale;
-    } else if constexpr (KIND == ST_GRAD) {
-      const long long fo = (long long)blockIdx.y * a.fstride_out;
-#pragma unroll
-      for (int c = 0; c < D; ++c) a.out_real[fo + (long long)c * n + p] = rbuf(c) * invL * a.scale;
-    }
-  }
-
-  // ---- (3) R2C of the new real rows and store ----
-  if constexpr (KOUT > 0) {
-    if (KIND == ST_ADJ2 && a.skip_out) return;  // uniform across the workgroup
-    __syncthreads();
-    fft_lds<R, M, KOUT * B, NT, false, false>(lds, KOUT * B, SS, 1, tw, twb);
-    r2c_post<R, M, NT>(lds, KOUT * B, SS, tw, twl);
-    const long long fo = (long long)blockIdx.y * a.fstride_out;
-    for (int i = threadIdx.x; i < KOUT * B * M; i += NT) {
-      const int k = i / (B * M);
-      const int rem = i - k * (B * M);
-      const int b = rem / M, q = rem - (rem / M) * M;
-      cplx<R> v = lds[(k * B + b) * SS + q];
-      const long long g = fo + (row0 + b) * M + q;
-      if constexpr (KOUT == D && D > 1) {
-        // adjoint kinds: the last product is differentiated along the last axis here
-        if (k == D - 1) v = cmul_i(v, R(q == 0 ? 0 : q));
-        cplx<R>* dst = (k == 0) ? a.out0 : (k == 1 ? a.out1 : a.out2);
-        dst[g] = v;
-      } else {
-        a.out0[g] = v;
-      }
-    }
-  }
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,376 @@
+// Row-stage and column-pass kernels built on register-resident wave FFTs.
+//
+// Row stage: one wavefront per workgroup; each row of the contiguous last
+// axis (length L, M = L/2 complex) is held by LS = M/E lanes. Global loads of
+// every operand the pointwise epilogue needs are issued at kernel start, so
+// their latency overlaps the inverse transforms. The real <-> half-complex
+// packing is done in registers on (q, M - q) pairs; transforms exchange data
+// only inside the wavefront.
+//
+// Column pass: one wavefront per workgroup handling 64 / LS columns (lanes of
+// neighbouring columns are adjacent, so loads of small transforms coalesce);
+// workgroups are ordered so that neighbouring columns share an XCD and its L2.
+#pragma once
+
+#include "kernels.hpp"
+#include "wave_fft.hpp"
+
+namespace nk {
+
+// pointwise product of two real pairs stored as cplx
+template <typename R>
+__device__ __forceinline__ cplx<R> pmul(cplx<R> a, cplx<R> b) { return {a.x * b.x, a.y * b.y}; }
+template <typename R>
+__device__ __forceinline__ cplx<R> pfma(cplx<R> a, cplx<R> b, cplx<R> c) { return {a.x * b.x + c.x, a.y * b.y + c.y}; }
+
+// C2R packing step on a pair (q, M - q): packed half spectrum -> Z of the
+// half-length complex transform (scaled so the unnormalised inverse gives L x).
+template <typename R>
+__device__ __forceinline__ void c2r_pair(cplx<R> xq, cplx<R> xm, cplx<R> w, cplx<R>& zq, cplx<R>& zm) {
+  const cplx<R> e = {xq.x + xm.x, xq.y - xm.y};
+  const cplx<R> dq = {xq.x - xm.x, xq.y + xm.y};
+  const cplx<R> o = cmulc(dq, w);
+  zq = {e.x - o.y, e.y + o.x};
+  zm = {e.x + o.y, o.x - e.y};
+}
+
+// R2C unpacking step on a pair: Z of the half-length transform -> packed half spectrum.
+template <typename R>
+__device__ __forceinline__ void r2c_pair(cplx<R> zq, cplx<R> zm, cplx<R> w, cplx<R>& xq, cplx<R>& xm) {
+  const cplx<R> e = {R(0.5) * (zq.x + zm.x), R(0.5) * (zq.y - zm.y)};
+  const cplx<R> o = {R(0.5) * (zq.y + zm.y), -R(0.5) * (zq.x - zm.x)};
+  const cplx<R> wo = cmul(o, w);
+  xq = cadd(e, wo);
+  xm = cconj(csub(e, wo));
+}
+
+// velocity-like combination sum_l w_l f[(l*D + c) n + p] as a real pair
+template <typename R, int D, bool NC1>
+__device__ __forceinline__ cplx<R> comb2(const R* __restrict__ f, const R* w, int nc, int c, long long n,
+                                         long long pc) {
+  const cplx<R>* F = reinterpret_cast<const cplx<R>*>(f);
+  const long long n2 = n / 2;
+  if (NC1) return cscale(F[(long long)c * n2 + pc], w[0]);
+  cplx<R> s = {R(0), R(0)};
+  for (int l = 0; l < nc; ++l) s = cadd(s, cscale(F[((long long)l * D + c) * n2 + pc], w[l]));
+  return s;
+}
+
+template <typename R, int L, int E, int KIND, int D, bool NC1>
+__global__ __launch_bounds__(64) void k_row_w(StageArgs<R> a, const cplx<R>* __restrict__ tw, int lmax) {
+  constexpr int M = L / 2;
+  using P = WavePlan<M, E>;
+  constexpr int LS = P::LS;
+  constexpr int SPW = 64 / LS;
+  constexpr int PADM = padded<M>(M);
+  constexpr int H = E / 2;
+  using SH = StageShape<KIND, D>;
+  constexpr int KIN = SH::KIN, KOUT = SH::KOUT, KMAX = SH::KMAX;
+  constexpr bool FWDK = (KIND == ST_FWD1 || KIND == ST_FWD2);
+  constexpr bool INCK = (KIND == ST_INC1 || KIND == ST_INC2);
+  constexpr bool ADJOUT = (KIND == ST_ADJINIT || KIND == ST_ADJ1 || KIND == ST_ADJ2);
+  __shared__ cplx<R> lds[SPW * KMAX * PADM];
+
+  const int lane = threadIdx.x;
+  const int sr = lane / LS, j = lane - sr * LS;
+  const long long rows = a.n / L;
+  const long long rowr = (long long)blockIdx.x * SPW + sr;
+  const bool live = rowr < rows;
+  const long long row = live ? rowr : rows - 1;
+  const long long n = a.n;
+  const long long c0 = row * M;  // first complex slot (point pair) of the row
+  cplx<R>* S = lds + sr * KMAX * PADM;
+  const int twl = lmax / L;
+  const R invL = R(1) / R(L);
+  const R h = a.h;
+  const R hh = R(0.5) * a.h;
+
+  WaveTwiddles<R, M, E> T;
+  T.load(j, tw, lmax / M);
+  cplx<R> wq[H];
+  int qa[H], qb[H];
+#pragma unroll
+  for (int t = 0; t < H; ++t) {
+    const bool sp = (j == 0 && t == 0);
+    qa[t] = sp ? 0 : j + LS * t;
+    qb[t] = sp ? M / 2 : M - (j + LS * t);
+    wq[t] = tw[(sp ? M / 2 : qa[t]) * twl];
+  }
+  auto pidx = [&](int e) -> long long { return c0 + j + LS * e; };
+  auto ld2 = [&](const R* f, int e) -> cplx<R> { return reinterpret_cast<const cplx<R>*>(f)[pidx(e)]; };
+  auto st2 = [&](R* f, int e, cplx<R> v) {
+    if (live) reinterpret_cast<cplx<R>*>(f)[pidx(e)] = v;
+  };
+
+  // ---- prefetch the epilogue's operands (natural layout, point pairs) ----
+  constexpr int DV = (FWDK || INCK || ADJOUT) ? D : 1;
+  constexpr int DW = INCK ? D : 1;
+  constexpr int DG = (INCK || KIND == ST_ADJ1) ? D : 1;
+  constexpr int DF = (KIND == ST_ADJ1 && NC1) ? D : 1;
+  cplx<R> V[DV][E], W[DW][E], G0[DG][E], G1[DG][E], FV[DF][E], X1[E], X2[E];
+  const R* wv = (KIND == ST_FWD1 || KIND == ST_INC1) ? a.b0 : ((KIND == ST_FWD2 || KIND == ST_INC2) ? a.b1 : a.bv);
+  const bool need_v = !(KIND == ST_ADJ2 && a.skip_out);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    if constexpr (FWDK || INCK || ADJOUT) {
+      if (need_v) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) V[c][e] = comb2<R, D, NC1>(a.vl, wv, a.nc, c, n, pidx(e));
+      }
+    }
+    if constexpr (INCK) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        W[c][e] = comb2<R, D, NC1>(a.vtl, wv, a.nc, c, n, pidx(e));
+        G0[c][e] = ld2((KIND == ST_INC1 ? a.g0 : a.g1) + (long long)c * n, e);
+      }
+    }
+    if constexpr (KIND == ST_ADJ1) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        G0[c][e] = ld2(a.g0 + (long long)c * n, e);
+        G1[c][e] = ld2(a.g1 + (long long)c * n, e);
+        if constexpr (NC1) FV[c][e] = ld2(a.F + (long long)c * n, e);
+      }
+      X1[e] = ld2(a.lam, e);
+    }
+    if constexpr (KIND == ST_FWD2 || KIND == ST_INC2 || KIND == ST_ADJ2) X1[e] = ld2(a.acc, e);
+    if constexpr (KIND == ST_FWD1) X2[e] = ld2(a.mreal, e);
+    if constexpr (KIND == ST_INC1) X2[e] = a.zero_state ? cplx<R>{R(0), R(0)} : ld2(a.mreal, e);
+    if constexpr (KIND == ST_ADJINIT) {
+      X1[e] = ld2(a.src_a, e);
+      X2[e] = a.src_b ? ld2(a.src_b, e) : cplx<R>{R(0), R(0)};
+    }
+    if constexpr (KIND == ST_R2C) X1[e] = ld2(a.src_a + (long long)blockIdx.y * a.fstride_in, e);
+  }
+
+  // ---- input row spectra: pair layout -> C2R packing -> natural layout -> inverse FFT ----
+  constexpr int KA = KIN > 0 ? KIN : 1;
+  cplx<R> A[KA][E];
+  const int zero_in = (KIND == ST_INC1) ? a.zero_state : 0;
+  if constexpr (KIN > 0) {
+    if (!zero_in) {
+      const long long fin = (long long)blockIdx.y * a.fstride_in;
+#pragma unroll
+      for (int k = 0; k < KIN; ++k) {
+        const cplx<R>* src;
+        bool ik = false;
+        if constexpr (KIND == ST_GRAD || FWDK || INCK) {
+          // gradient components: column derivatives, then i k_last times the row spectrum
+          if (k == D - 1) { src = a.spec; ik = true; }
+          else src = (k == 0) ? a.s1 : a.s2;
+        } else {
+          src = a.spec;
+        }
+        src += fin + c0;
+        cplx<R> xa[H], xb[H];
+#pragma unroll
+        for (int t = 0; t < H; ++t) { xa[t] = src[qa[t]]; xb[t] = src[qb[t]]; }
+#pragma unroll
+        for (int t = 0; t < H; ++t) {
+          if (ik) {
+            xa[t] = (qa[t] == 0) ? cplx<R>{R(0), R(0)} : cmul_i(xa[t], R(qa[t]));
+            xb[t] = cmul_i(xb[t], R(qb[t]));
+          }
+          cplx<R> za, zb;
+          if (j == 0 && t == 0) {
+            za = {xa[t].x + xa[t].y, xa[t].x - xa[t].y};
+            cplx<R> unused;
+            c2r_pair(xb[t], xb[t], wq[t], zb, unused);
+          } else {
+            c2r_pair(xa[t], xb[t], wq[t], za, zb);
+          }
+          S[k * PADM + pad32(qa[t])] = za;
+          S[k * PADM + pad32(qb[t])] = zb;
+        }
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int k = 0; k < KIN; ++k)
+#pragma unroll
+        for (int e = 0; e < E; ++e) A[k][e] = S[k * PADM + pad32(j + LS * e)];
+      wave_lds_sync();
+#pragma unroll
+      for (int k = 0; k < KIN; ++k) wave_fft<R, M, E, true>(A[k], j, S + k * PADM, T);
+    }
+  }
+
+  // ---- pointwise epilogue (natural layout) ----
+  constexpr int KO = KOUT > 0 ? KOUT : 1;
+  cplx<R> O[KO][E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    if constexpr (FWDK) {
+      cplx<R> r = {R(0), R(0)};
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const cplx<R> gc = cscale(A[c][e], invL);
+        if (KIND == ST_FWD1) { if (a.g0w) st2(a.g0w + (long long)c * n, e, gc); }
+        else { if (a.g1w) st2(a.g1w + (long long)c * n, e, gc); }
+        r = csub(r, pmul(V[c][e], gc));
+      }
+      if (KIND == ST_FWD1) {
+        const cplx<R> m = X2[e];
+        st2(a.acc, e, cadd(m, cscale(r, hh)));
+        O[0][e] = cadd(m, cscale(r, h));
+      } else {
+        const cplx<R> mn = cadd(X1[e], cscale(r, hh));
+        st2(a.out_real, e, mn);
+        O[0][e] = mn;
+      }
+    } else if constexpr (INCK) {
+      cplx<R> r = {R(0), R(0)};
+      if (!zero_in) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) r = csub(r, pmul(V[c][e], cscale(A[c][e], invL)));
+      }
+#pragma unroll
+      for (int c = 0; c < D; ++c) r = csub(r, pmul(W[c][e], G0[c][e]));
+      if (KIND == ST_INC1) {
+        const cplx<R> m = X2[e];
+        st2(a.acc, e, cadd(m, cscale(r, hh)));
+        O[0][e] = cadd(m, cscale(r, h));
+      } else {
+        const cplx<R> mn = cadd(X1[e], cscale(r, hh));
+        st2(a.out_real, e, mn);
+        O[0][e] = mn;
+      }
+    } else if constexpr (KIND == ST_ADJINIT) {
+      const cplx<R> lam = cadd(cscale(X1[e], a.ca), cscale(X2[e], a.cb));
+      st2(a.lam, e, lam);
+#pragma unroll
+      for (int c = 0; c < D; ++c) O[c][e] = pmul(V[c][e], lam);
+    } else if constexpr (KIND == ST_ADJ1) {
+      const cplx<R> s1 = cscale(A[0][e], invL);
+      const cplx<R> lam = X1[e];
+      const cplx<R> lams = cadd(lam, cscale(s1, h));
+      st2(a.acc, e, cadd(lam, cscale(s1, hh)));
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const cplx<R> t0 = pmul(lams, G0[c][e]);
+        const cplx<R> t1 = pmul(lam, G1[c][e]);
+        if constexpr (NC1) {
+          const cplx<R> f = cadd(FV[c][e], cscale(cadd(cscale(t0, a.b0[0]), cscale(t1, a.b1[0])), hh));
+          st2(a.F + (long long)c * n, e, f);
+        } else {
+          for (int l = 0; l < a.nc; ++l) {
+            R* fp = a.F + ((long long)l * D + c) * n;
+            const cplx<R> f0 = ld2(fp, e);
+            st2(fp, e, cadd(f0, cscale(cadd(cscale(t0, a.b0[l]), cscale(t1, a.b1[l])), hh)));
+          }
+        }
+        O[c][e] = pmul(V[c][e], lams);
+      }
+    } else if constexpr (KIND == ST_ADJ2) {
+      const cplx<R> s2 = cscale(A[0][e], invL);
+      const cplx<R> lam = cadd(X1[e], cscale(s2, hh));
+      st2(a.lam, e, lam);
+      if (!a.skip_out) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) O[c][e] = pmul(V[c][e], lam);
+      }
+    } else if constexpr (KIND == ST_R2C) {
+      O[0][e] = X1[e];
+    } else if constexpr (KIND == ST_C2R || KIND == ST_DIV) {
+      st2(a.out_real + (long long)blockIdx.y * a.fstride_out, e, cscale(A[0][e], invL * a.scale));
+    } else if constexpr (KIND == ST_GRAD) {
+#pragma unroll
+      for (int c = 0; c < D; ++c)
+        st2(a.out_real + (long long)blockIdx.y * a.fstride_out + (long long)c * n, e,
+            cscale(A[c][e], invL * a.scale));
+    }
+  }
+
+  // ---- forward FFT of the new rows -> R2C unpacking -> store in pair layout ----
+  if constexpr (KOUT > 0) {
+    if (KIND == ST_ADJ2 && a.skip_out) return;  // uniform across the workgroup
+#pragma unroll
+    for (int k = 0; k < KOUT; ++k) wave_fft<R, M, E, false>(O[k], j, S + k * PADM, T);
+#pragma unroll
+    for (int k = 0; k < KOUT; ++k)
+#pragma unroll
+      for (int e = 0; e < E; ++e) S[k * PADM + pad32(j + LS * e)] = O[k][e];
+    wave_lds_sync();
+    const long long fo = (long long)blockIdx.y * a.fstride_out;
+#pragma unroll
+    for (int k = 0; k < KOUT; ++k) {
+      cplx<R>* dst;
+      if constexpr (ADJOUT) dst = (k == 0) ? a.out0 : (k == 1 ? a.out1 : a.out2);
+      else dst = a.out0;
+      dst += fo + c0;
+      const bool ik = ADJOUT && D > 1 && k == D - 1;
+#pragma unroll
+      for (int t = 0; t < H; ++t) {
+        const cplx<R> za = S[k * PADM + pad32(qa[t])];
+        const cplx<R> zb = S[k * PADM + pad32(qb[t])];
+        cplx<R> xa, xb;
+        if (j == 0 && t == 0) {
+          xa = {za.x + za.y, za.x - za.y};
+          cplx<R> unused;
+          r2c_pair(zb, zb, wq[t], xb, unused);
+        } else {
+          r2c_pair(za, zb, wq[t], xa, xb);
+        }
+        if (ik) {
+          xa = (qa[t] == 0) ? cplx<R>{R(0), R(0)} : cmul_i(xa, R(qa[t]));
+          xb = cmul_i(xb, R(qb[t]));
+        }
+        if (live) {
+          dst[qa[t]] = xa;
+          dst[qb[t]] = xb;
+        }
+      }
+    }
+  }
+}
+
+template <typename R, int N, int E, int MODE>
+__global__ __launch_bounds__(64) void k_col_w(const cplx<R>* in, const cplx<R>* add, cplx<R>* out, ColArgs a,
+                                              R scale, const cplx<R>* __restrict__ tw, int twb) {
+  using P = WavePlan<N, E>;
+  constexpr int LS = P::LS;
+  constexpr int SPW = 64 / LS;
+  constexpr int PADN = padded<N>(N);
+  __shared__ cplx<R> lds[SPW * PADN];
+  const int lane = threadIdx.x;
+  const int c = lane % SPW, j = lane / SPW;
+  const int nbx = gridDim.x;
+  const int bx = (nbx % 8 == 0) ? (int)(blockIdx.x % 8) * (nbx / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
+  const long long colr = (long long)bx * SPW + c;
+  const bool live = colr < a.inner;
+  const long long col = live ? colr : a.inner - 1;
+  const long long base = (long long)blockIdx.z * a.field + (long long)blockIdx.y * N * a.inner + col;
+  cplx<R> v[E], ad[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = in[base + (long long)(j + LS * e) * a.inner];
+  const bool has_add = (MODE == COL_DERIV) && add != nullptr;
+  if (has_add) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) ad[e] = add[base + (long long)(j + LS * e) * a.inner];
+  }
+  WaveTwiddles<R, N, E> T;
+  T.load(j, tw, twb);
+  cplx<R>* S = lds + c * PADN;
+  if (MODE == COL_INV) {
+    wave_fft<R, N, E, true>(v, j, S, T);
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = cscale(v[e], scale);
+  } else {
+    wave_fft<R, N, E, false>(v, j, S, T);
+  }
+  if (MODE == COL_DERIV) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = cmul_i(v[e], R(deriv_wavenumber(j + LS * e, N)) * scale);
+    wave_fft<R, N, E, true>(v, j, S, T);
+    if (has_add) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = cadd(v[e], ad[e]);
+    }
+  }
+  if (live) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) out[base + (long long)(j + LS * e) * a.inner] = v[e];
+  }
+}
+
+}  // namespace nk

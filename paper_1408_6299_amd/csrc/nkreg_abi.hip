@@ -53,6 +53,18 @@ int validate(const nkreg_config* c) {
   return NKREG_OK;
 }
 
+// Joins the library's internal stream to the caller's stream around a call.
+struct Join {
+  nk::ProblemBase* p;
+  explicit Join(nk::ProblemBase* q) : p(q) { p->enter(); }
+  ~Join() {
+    try {
+      p->leave();
+    } catch (...) {
+    }
+  }
+};
+
 #define NEED(ptr)                                                        \
   do {                                                                   \
     if (!(ptr)) return fail(NKREG_EINVAL, "null argument: " #ptr);       \
@@ -110,92 +122,96 @@ int nkreg_destroy(nkreg_problem* p) {
 int nkreg_set_beta(nkreg_problem* p, double beta) {
   NEED(p);
   if (!(beta > 0.0)) return fail(NKREG_EINVAL, "beta must be positive");
-  p->impl->cfg.beta = beta;
-  return NKREG_OK;
+  return guarded([&]() { Join j_(p->impl); p->impl->set_beta(beta); return (int)NKREG_OK; });
+}
+
+int nkreg_use_graphs(nkreg_problem* p, int enable) {
+  NEED(p);
+  return guarded([&]() { Join j_(p->impl); p->impl->use_graph_capture(enable != 0); return (int)NKREG_OK; });
 }
 
 int nkreg_set_images(nkreg_problem* p, const void* mT, const void* mR) {
   NEED(p); NEED(mT); NEED(mR);
-  return guarded([&]() { p->impl->set_images(mT, mR); return (int)NKREG_OK; });
+  return guarded([&]() { Join j_(p->impl); p->impl->set_images(mT, mR); return (int)NKREG_OK; });
 }
 
 int nkreg_forward(nkreg_problem* p, const void* v, void* m1) {
   NEED(p); NEED(v);
-  return guarded([&]() { p->impl->forward(v, m1); return (int)NKREG_OK; });
+  return guarded([&]() { Join j_(p->impl); p->impl->forward(v, m1); return (int)NKREG_OK; });
 }
 
 int nkreg_objective(nkreg_problem* p, const void* v, double* J, double* Jd, double* Jr) {
   NEED(p); NEED(v);
-  return guarded([&]() { p->impl->objective(v, J, Jd, Jr); return (int)NKREG_OK; });
+  return guarded([&]() { Join j_(p->impl); p->impl->objective(v, J, Jd, Jr); return (int)NKREG_OK; });
 }
 
 int nkreg_objective_gradient(nkreg_problem* p, const void* v, double* J, double* Jd, double* Jr, void* g) {
   NEED(p); NEED(v);
-  return guarded([&]() { p->impl->objective_gradient(v, J, Jd, Jr, g); return (int)NKREG_OK; });
+  return guarded([&]() { Join j_(p->impl); p->impl->objective_gradient(v, J, Jd, Jr, g); return (int)NKREG_OK; });
 }
 
 int nkreg_hessian_matvec(nkreg_problem* p, const void* vt, void* out) {
   NEED(p); NEED(vt); NEED(out);
   if (vt == out) return fail(NKREG_EINVAL, "input and output may not alias");
-  return guarded([&]() { p->impl->hessian_matvec(vt, out); return (int)NKREG_OK; });
+  return guarded([&]() { Join j_(p->impl); p->impl->hessian_matvec(vt, out); return (int)NKREG_OK; });
 }
 
 int nkreg_precond_apply(nkreg_problem* p, const void* r, void* z) {
   NEED(p); NEED(r); NEED(z);
-  return guarded([&]() { p->impl->precond(r, z); return (int)NKREG_OK; });
+  return guarded([&]() { Join j_(p->impl); p->impl->precond(r, z); return (int)NKREG_OK; });
 }
 
 int nkreg_project(nkreg_problem* p, const void* f, void* out) {
   NEED(p); NEED(f); NEED(out);
-  return guarded([&]() { p->impl->project(f, out); return (int)NKREG_OK; });
+  return guarded([&]() { Join j_(p->impl); p->impl->project(f, out); return (int)NKREG_OK; });
 }
 
 int nkreg_pcg(nkreg_problem* p, const void* rhs, void* s, double rtol, int maxit, int* iters, double* relres) {
   NEED(p); NEED(rhs); NEED(s);
   if (!(rtol >= 0.0)) return fail(NKREG_EINVAL, "rtol must be >= 0");
-  return guarded([&]() { return p->impl->pcg(rhs, s, rtol, maxit, iters, relres); });
+  return guarded([&]() { Join j_(p->impl); return p->impl->pcg(rhs, s, rtol, maxit, iters, relres); });
 }
 
 int nkreg_det_grad_y(nkreg_problem* p, const void* v, void* detF, double* stats) {
   NEED(p); NEED(v);
-  return guarded([&]() { p->impl->det_grad_y(v, detF, stats); return (int)NKREG_OK; });
+  return guarded([&]() { Join j_(p->impl); p->impl->det_grad_y(v, detF, stats); return (int)NKREG_OK; });
 }
 
 int nkreg_newton_solve(nkreg_problem* p, void* v, const nkreg_solve_opts* opts, nkreg_solve_report* rep) {
   NEED(p); NEED(v);
-  return guarded([&]() { return p->impl->newton(v, opts, rep); });
+  return guarded([&]() { Join j_(p->impl); return p->impl->newton(v, opts, rep); });
 }
 
 int nkreg_gradient(nkreg_problem* p, const void* u, void* g) {
   NEED(p); NEED(u); NEED(g);
-  return guarded([&]() { p->impl->gradient(u, g); return (int)NKREG_OK; });
+  return guarded([&]() { Join j_(p->impl); p->impl->gradient(u, g); return (int)NKREG_OK; });
 }
 
 int nkreg_divergence(nkreg_problem* p, const void* w, void* s) {
   NEED(p); NEED(w); NEED(s);
-  return guarded([&]() { p->impl->divergence(w, s); return (int)NKREG_OK; });
+  return guarded([&]() { Join j_(p->impl); p->impl->divergence(w, s); return (int)NKREG_OK; });
 }
 
 int nkreg_apply_reg(nkreg_problem* p, const void* x, void* out) {
   NEED(p); NEED(x); NEED(out);
-  return guarded([&]() { p->impl->apply_reg(x, out); return (int)NKREG_OK; });
+  return guarded([&]() { Join j_(p->impl); p->impl->apply_reg(x, out); return (int)NKREG_OK; });
 }
 
 int nkreg_dot(nkreg_problem* p, const void* a, const void* b, long long cnt, double* out) {
   NEED(p); NEED(a); NEED(b); NEED(out);
   if (cnt < 0) return fail(NKREG_EINVAL, "negative count");
-  return guarded([&]() { *out = p->impl->dot(a, b, cnt); return (int)NKREG_OK; });
+  return guarded([&]() { Join j_(p->impl); *out = p->impl->dot(a, b, cnt); return (int)NKREG_OK; });
 }
 
 int nkreg_timer_arm(nkreg_problem* p, int kernel_id, int capacity) {
   NEED(p);
   if (capacity < 1 || capacity > (1 << 16)) return fail(NKREG_EINVAL, "capacity must be in [1, 65536]");
-  return guarded([&]() { p->impl->timer_arm(kernel_id, capacity); return (int)NKREG_OK; });
+  return guarded([&]() { Join j_(p->impl); p->impl->timer_arm(kernel_id, capacity); return (int)NKREG_OK; });
 }
 
 int nkreg_timer_read(nkreg_problem* p, int* launches, double* avg_ms, double* bytes_per_launch) {
   NEED(p);
-  return guarded([&]() { p->impl->timer_read(launches, avg_ms, bytes_per_launch); return (int)NKREG_OK; });
+  return guarded([&]() { Join j_(p->impl); p->impl->timer_read(launches, avg_ms, bytes_per_launch); return (int)NKREG_OK; });
 }
 
 int nkreg_batch_create(int count, nkreg_problem* const* items, nkreg_batch** out) {
@@ -221,7 +237,10 @@ int nkreg_batch_hessian_matvec(nkreg_batch* b, const void* const* vt, void* cons
   NEED(b);
   if (!b->items.empty()) { NEED(vt); NEED(out); }
   return guarded([&]() {
+    // every item runs on its own internal stream, so independent matvecs overlap
+    for (auto* it : b->items) it->impl->enter();
     for (size_t i = 0; i < b->items.size(); ++i) b->items[i]->impl->hessian_matvec(vt[i], out[i]);
+    for (auto* it : b->items) it->impl->leave();
     return (int)NKREG_OK;
   });
 }

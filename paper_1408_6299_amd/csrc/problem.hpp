@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cstdio>
 #include <memory>
+#include <cstdlib>
 #include <type_traits>
 #include <vector>
 
@@ -128,6 +129,12 @@ class ProblemBase {
   virtual void apply_reg(const void* x, void* out) = 0;
   virtual double dot(const void* a, const void* b, long long cnt) = 0;
   virtual hipStream_t stream() const = 0;
+  virtual void set_beta(double beta) = 0;
+  virtual void use_graph_capture(bool on) = 0;
+  // Every call runs on the library's internal stream: enter() makes it wait for
+  // the caller's stream, leave() makes the caller's stream wait for it.
+  virtual void enter() = 0;
+  virtual void leave() = 0;
   virtual void timer_arm(int id, int capacity) = 0;
   virtual void timer_read(int* launches, double* avg_ms, double* bytes) = 0;
 };
@@ -144,7 +151,8 @@ class ProblemT final : public ProblemBase {
  public:
   static constexpr bool kF64 = std::is_same<R, double>::value;
   Grid g;
-  hipStream_t s;
+  hipStream_t user_s;      // the caller's stream (may be the null stream)
+  hipStream_t s;           // internal stream: all work, capturable into graphs
   Spectral<R> sp;          // transport precision
   Spectral<double> sp64;   // control space
   Reducer red;
@@ -160,8 +168,18 @@ class ProblemT final : public ProblemBase {
   DevBuf<double> v, F64, tmpv, kx, kr, kz, kp, kq, gbuf, sbuf, vtrial, rhsbuf;
   DevBuf<cplx<double>> Xs, Ys;
 
+  static hipStream_t make_stream() {
+    hipStream_t st;
+    NK_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));  // default priority
+    return st;
+  }
+
   ProblemT(const nkreg_config& c, hipStream_t stream)
-      : g(make_grid(c.dim, c.n)), s(stream), sp(g, stream), sp64(g, stream) {
+      : g(make_grid(c.dim, c.n)), user_s(stream), s(make_stream()), sp(g, s), sp64(g, s) {
+    NK_HIP(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
+    NK_HIP(hipEventCreateWithFlags(&ev_out, hipEventDisableTiming));
+    const char* ng = std::getenv("NKREG_NO_GRAPHS");
+    use_graphs = !(ng && ng[0] == '1');
     cfg = c;
     nc = c.nc;
     d = c.dim;
@@ -184,8 +202,47 @@ class ProblemT final : public ProblemBase {
 
   hipStream_t stream() const override { return s; }
 
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  void enter() override {
+    NK_HIP(hipEventRecord(ev_in, user_s));
+    NK_HIP(hipStreamWaitEvent(s, ev_in, 0));
+  }
+  void leave() override {
+    NK_HIP(hipEventRecord(ev_out, s));
+    NK_HIP(hipStreamWaitEvent(user_s, ev_out, 0));
+  }
+
+  // ---- HIP graph of the Hessian matvec, keyed by its (input, output) pointers ----
+  bool use_graphs = true;
+  struct GraphEntry {
+    const void* in = nullptr;
+    void* out = nullptr;
+    hipGraphExec_t exec = nullptr;
+  } mv_graph;
+  void drop_graphs() {
+    if (mv_graph.exec) (void)hipGraphExecDestroy(mv_graph.exec);
+    mv_graph = GraphEntry{};
+  }
+  ~ProblemT() override {
+    (void)hipStreamSynchronize(s);
+    drop_graphs();
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    (void)hipStreamDestroy(s);
+  }
+  void use_graph_capture(bool on) override {
+    NK_HIP(hipStreamSynchronize(s));
+    drop_graphs();
+    use_graphs = on;
+  }
+  void set_beta(double beta) override {
+    cfg.beta = beta;
+    drop_graphs();  // beta is a kernel argument of the captured finalize
+  }
+
   KernelTimer timer;
   void timer_arm(int id, int capacity) override {
+    NK_HIP(hipStreamSynchronize(s));
     timer.arm(id, capacity);
     sp.timer = &timer;
   }
@@ -196,6 +253,7 @@ class ProblemT final : public ProblemBase {
     if (bytes) *bytes = timer.used ? timer.bytes / timer.used : 0.0;
     timer.armed = -1;
     sp.timer = nullptr;
+    drop_graphs();
   }
 
   R* trajp(int j, int stage) { return traj.p + ((size_t)(2 * j + stage)) * d * n; }
@@ -248,6 +306,7 @@ class ProblemT final : public ProblemBase {
       a.spec = T.p; a.s1 = S1.p; a.s2 = S2.p; a.out0 = Ts.p;
       a.vl = vl; a.nc = nc; a.h = h; a.acc = acc.p;
       a.g0w = record ? trajp(j, 0) : nullptr;
+      a.mreal = (j == 0) ? mT.p : m1out;
       basis(j * (double)h, a.b0);
       sp.template row<ST_FWD1>(a, 1);
       sp.deriv_cols(Ts.p, S1.p, S2.p);
@@ -256,8 +315,7 @@ class ProblemT final : public ProblemBase {
       b.vl = vl; b.nc = nc; b.h = h; b.acc = acc.p;
       b.g1w = record ? trajp(j, 1) : nullptr;
       basis((j + 1) * (double)h, b.b1);
-      b.write_real = (j == nt - 1);
-      b.out_real = m1out;
+      b.out_real = m1out;  // m^{j+1}; m_1 after the last step
       sp.template row<ST_FWD2>(b, 1);
     }
   }
@@ -310,6 +368,7 @@ class ProblemT final : public ProblemBase {
       a.vl = vl; a.vtl = vtl; a.nc = nc; a.h = h; a.acc = acc.p;
       a.g0 = trajp(j, 0);
       a.zero_state = (j == 0);
+      a.mreal = mt1.p;
       basis(j * (double)h, a.b0);
       sp.template row<ST_INC1>(a, 1);
       sp.deriv_cols(Ts.p, S1.p, S2.p);
@@ -318,8 +377,7 @@ class ProblemT final : public ProblemBase {
       b.vl = vl; b.vtl = vtl; b.nc = nc; b.h = h; b.acc = acc.p;
       b.g1 = trajp(j, 1);
       basis((j + 1) * (double)h, b.b1);
-      b.write_real = (j == nt - 1);
-      b.out_real = mt1.p;
+      b.out_real = mt1.p;  // m~^{j+1}; m~_1 after the last step
       sp.template row<ST_INC2>(b, 1);
     }
   }
@@ -398,6 +456,38 @@ class ProblemT final : public ProblemBase {
 
   void hessian_matvec(const void* vtin, void* out) override {
     if (!state_valid) throw HipError(NKREG_ESTATE, "no gradient computed at the current velocity");
+    // HIP events recorded by graph nodes cannot be timed, so an armed kernel
+    // timer makes the matvec launch eagerly.
+    if (!use_graphs || timer.armed >= 0) {
+      matvec_body(vtin, out);
+      return;
+    }
+    if (!(mv_graph.exec && mv_graph.in == vtin && mv_graph.out == out)) {
+      drop_graphs();
+      hipGraph_t graph = nullptr;
+      NK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      try {
+        matvec_body(vtin, out);
+      } catch (...) {
+        (void)hipStreamEndCapture(s, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        throw;
+      }
+      NK_HIP(hipStreamEndCapture(s, &graph));
+      const hipError_t e = hipGraphInstantiate(&mv_graph.exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) {
+        mv_graph = GraphEntry{};
+        throw HipError(NKREG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+      }
+      mv_graph.in = vtin;
+      mv_graph.out = out;
+    }
+    NK_HIP(hipGraphLaunch(mv_graph.exec, s));
+  }
+
+  // One Gauss-Newton matvec as a sequence of launches on the internal stream.
+  void matvec_body(const void* vtin, void* out) {
     const double* vt = (const double*)vtin;
     const R* vl = kF64 ? (const R*)v.p : vR.p;
     incremental_sweep(vl, to_transport(vt, vtR));

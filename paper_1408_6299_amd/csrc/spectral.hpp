@@ -8,6 +8,7 @@
 
 #include "common.hpp"
 #include "kernels.hpp"
+#include "kernels_wave.hpp"
 
 namespace nk {
 
@@ -58,11 +59,9 @@ inline Grid make_grid(int d, const int* n) {
   return g;
 }
 
-// Rows per workgroup of the row kernels, by row length.
-constexpr int row_block(int L) { return L >= 512 ? 2 : (L >= 256 ? 4 : 8); }
-constexpr int kRowThreads = 256;
-constexpr int kColThreads = 256;
-constexpr int col_cmax(int N) { return 1024 / N > 1 ? 1024 / N : 1; }
+// Complex elements per lane of the row-stage and column transforms.
+constexpr int kRowE = 4;
+constexpr int kColE = 8;
 
 // Kernel identifiers for launch timing: row-stage kinds are 0..10 (StageKind),
 // column passes are 20 + ColMode.
@@ -258,30 +257,29 @@ class Spectral {
   }
 
  private:
+  // Column transforms: one wavefront per workgroup, kColE elements per lane.
   template <int N>
   void col_n(int mode, const cplx<R>* in, const cplx<R>* add, cplx<R>* out, int nf, R scale, int outer,
              long long inner) {
-    constexpr int CMAX = col_cmax(N);
+    constexpr int E = kColE;
+    constexpr int SPW = 64 / WavePlan<N, E>::LS;
     ColArgs a;
     a.inner = (int)inner;
-    a.ctile = (int)std::min<long long>(CMAX, inner);
+    a.ctile = SPW;
     a.field = g.nspec;
-    dim3 grid((unsigned)(inner / a.ctile), (unsigned)outer, (unsigned)nf);
+    dim3 grid((unsigned)((inner + SPW - 1) / SPW), (unsigned)outer, (unsigned)nf);
     const int twb = g.lmax / N;
     const bool timed = timer && timer->want(kColIdBase + mode);
     if (timed) timer->before(s);
     switch (mode) {
       case COL_FWD:
-        hipLaunchKernelGGL((k_col<R, N, CMAX, kColThreads, COL_FWD>), grid, dim3(kColThreads), 0, s, in, add,
-                           out, a, scale, tw, twb);
+        hipLaunchKernelGGL((k_col_w<R, N, E, COL_FWD>), grid, dim3(64), 0, s, in, add, out, a, scale, tw, twb);
         break;
       case COL_INV:
-        hipLaunchKernelGGL((k_col<R, N, CMAX, kColThreads, COL_INV>), grid, dim3(kColThreads), 0, s, in, add,
-                           out, a, scale, tw, twb);
+        hipLaunchKernelGGL((k_col_w<R, N, E, COL_INV>), grid, dim3(64), 0, s, in, add, out, a, scale, tw, twb);
         break;
       default:
-        hipLaunchKernelGGL((k_col<R, N, CMAX, kColThreads, COL_DERIV>), grid, dim3(kColThreads), 0, s, in, add,
-                           out, a, scale, tw, twb);
+        hipLaunchKernelGGL((k_col_w<R, N, E, COL_DERIV>), grid, dim3(64), 0, s, in, add, out, a, scale, tw, twb);
         break;
     }
     NK_LAUNCHED();
@@ -304,12 +302,17 @@ class Spectral {
 
   template <int KIND, int D, int L>
   void row_l(StageArgs<R>& a, int nf) {
-    constexpr int B = row_block(L);
-    dim3 grid((unsigned)(g.rows / B), (unsigned)nf);
+    constexpr int E = kRowE;
+    constexpr int SPW = 64 / WavePlan<L / 2, E>::LS;
+    dim3 grid((unsigned)((g.rows + SPW - 1) / SPW), (unsigned)nf);
     const bool timed = timer && timer->want(KIND);
     if (timed) timer->before(s);
-    hipLaunchKernelGGL((k_row_stage<R, L, B, kRowThreads, KIND, D>), grid, dim3(kRowThreads), 0, s, a, tw,
-                       g.lmax);
+    constexpr bool uses_nc = (KIND == ST_FWD1 || KIND == ST_FWD2 || KIND == ST_INC1 || KIND == ST_INC2 ||
+                              KIND == ST_ADJINIT || KIND == ST_ADJ1 || KIND == ST_ADJ2);
+    if (!uses_nc || a.nc <= 1)
+      hipLaunchKernelGGL((k_row_w<R, L, E, KIND, D, true>), grid, dim3(64), 0, s, a, tw, g.lmax);
+    else if constexpr (uses_nc)
+      hipLaunchKernelGGL((k_row_w<R, L, E, KIND, D, false>), grid, dim3(64), 0, s, a, tw, g.lmax);
     NK_LAUNCHED();
     if (timed) timer->after(s, (double)nf * stage_fields<KIND>(a, D) * g.npts * sizeof(R));
   }
@@ -320,10 +323,10 @@ class Spectral {
   static double stage_fields(const StageArgs<R>& a, int D) {
     const double v = (double)a.nc * D;  // velocity coefficient fields
     switch (KIND) {
-      case ST_FWD1: return D + v + (a.g0w ? D : 0) + 2;
-      case ST_FWD2: return D + v + 1 + (a.g1w ? D : 0) + 1 + (a.write_real ? 1 : 0);
-      case ST_INC1: return (a.zero_state ? 0 : D) + 2 * v + D + 2;
-      case ST_INC2: return D + 2 * v + D + 1 + 1 + (a.write_real ? 1 : 0);
+      case ST_FWD1: return D + 1 + v + (a.g0w ? D : 0) + 2;
+      case ST_FWD2: return D + v + 1 + (a.g1w ? D : 0) + 2;
+      case ST_INC1: return (a.zero_state ? 0 : D + 1) + 2 * v + D + 2;
+      case ST_INC2: return D + 2 * v + D + 1 + 2;
       case ST_ADJINIT: return (a.src_b ? 2 : 1) + v + 1 + D;
       case ST_ADJ1: return 1 + 1 + 2 * D + 2 * v + 1 + D + v;
       case ST_ADJ2: return a.skip_out ? 3 : 2 + v + 1 + D;

@@ -45,6 +45,18 @@ def host(t):
     return t.detach().double().cpu().numpy()
 
 
+def test_single_hip_runtime_in_process(nk):
+    """The library binds to torch's HIP runtime: one libamdhip64 mapped, and it works."""
+    maps = open("/proc/self/maps").read().splitlines()
+    hip = {l.split()[-1] for l in maps if "libamdhip64" in l}
+    nkreg = {l.split()[-1] for l in maps if "libnkreg" in l}
+    assert len(hip) == 1, hip
+    assert len(nkreg) == 1 and next(iter(nkreg)).startswith(
+        __import__("os").path.dirname(__import__("os").path.dirname(__import__("os").path.abspath(__file__))))
+    p = nk.Problem((8, 8), 2, precision=64)
+    p.close()
+
+
 SHAPES = [(8, 8), (16, 32), (64, 64), (8, 16, 8), (16, 8, 32)]
 
 
@@ -238,3 +250,23 @@ def test_autograd_gradient_matches_finite_differences(nk):
         fd = (jp - jm) / (2 * eps)
         an = float((grad * wt).sum())
         assert abs(fd - an) <= 1e-7 * abs(an) + 1e-14
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+def test_graph_replays_match_eager_matvec(nk, prec):
+    """Captured matvec graphs replayed several times, with other library work in between,
+    give bit-identical results to eager launches."""
+    shape, nt = (32, 64), 8
+    P, G, v, w = make_pair(nk, shape, nt, 2, 2, 1, 1e-3, prec)
+    G.objective_gradient(dev_v(v))
+    wt = dev_v(w)
+    G.use_graphs(False)
+    ref = host(G.hessian_matvec(wt))
+    G.use_graphs(True)
+    out = G.empty_v()
+    for rep in range(4):
+        G.hessian_matvec(wt, out)
+        assert np.array_equal(host(out), ref), rep
+        G.precond(dev_v(v))                       # eager work between replays
+        G.hessian_matvec(dev_v(0.5 * w))          # a different pointer pair: new capture
+        torch.cuda.synchronize()
