@@ -96,7 +96,8 @@ def main() -> int:
         steps = args.steps if prec == 32 else max(10, args.steps // 4)
         timed_pcg_steps(G, rhs, args.warmup, torch)
         secs = timed_pcg_steps(G, rhs, steps, torch)   # matvecs replay their captured HIP graph
-        r = {"steps": steps, "seconds": secs, "matvecs_per_s": steps / secs, "ms_per_step": 1e3 * secs / steps}
+        r = {"steps": steps, "seconds": secs, "matvecs_per_s": steps / secs, "ms_per_step": 1e3 * secs / steps,
+             "launch": G.describe()}
         if prec == 32:
             # second timed region, same workload: HIP events around every launch of the
             # dominant kernel (the library launches eagerly while its timer is armed)
@@ -144,6 +145,7 @@ def main() -> int:
         "data": "synthetic (seeded smooth image; reference = template transported by a seeded band-limited velocity)",
         "config": {"workload": spec.name, "grid": list(shape), "nt": nt, "nc": 1, "reg": "H2",
                    "beta": spec.beta, "incompressible": False, "step": "one GN-PCG iteration (matvec-dominated)"},
+        "launch": results[32]["launch"],
         "fp64": {"matvecs_per_s": results[64]["matvecs_per_s"], "ms_per_step": results[64]["ms_per_step"],
                  "fp32_speedup": results[32]["matvecs_per_s"] / results[64]["matvecs_per_s"]},
     }

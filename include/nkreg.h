@@ -68,7 +68,9 @@ typedef struct {
   int incompressible;   /* gamma: 1 applies the Leray projection K to body forces */
   double beta;          /* regularisation weight, > 0 */
   int precision;        /* 32 or 64: precision of the transport solves, their FFTs and scalar fields */
-  int checkpoint_every; /* 0: keep the full state trajectory (the only mode in this version) */
+  int checkpoint_every; /* 0: keep grad m^j, grad m*_j for all j (2 nt d fields); K > 0: keep m at
+                           every K-th step and recompute a K-step segment inside each adjoint
+                           and incremental sweep (2 K d fields; one extra state solve per sweep) */
   double cfl_max;       /* CFL bound checked by nkreg_objective_gradient; <= 0 disables */
 } nkreg_config;
 
@@ -119,6 +121,12 @@ int nkreg_set_beta(nkreg_problem* p, double beta);
  * The library runs on an internal stream joined to the caller's stream at every
  * call, so capture works also when the caller uses the null stream. */
 int nkreg_use_graphs(nkreg_problem* p, int enable);
+
+/* Writes a JSON object describing the handle's launch configuration (transport
+ * precision, graph use, elements per lane of the row and column transforms and
+ * the autotuner's timings, which it records at the first graph capture) into
+ * buf (len bytes, NUL-terminated, truncated if needed). */
+int nkreg_describe(nkreg_problem* p, char* buf, int len);
 
 /* Copy the template m_T and reference m_R (each n values) into the handle. */
 int nkreg_set_images(nkreg_problem* p, const void* d_mT, const void* d_mR);
@@ -199,8 +207,11 @@ int nkreg_timer_arm(nkreg_problem* p, int kernel_id, int capacity);
 int nkreg_timer_read(nkreg_problem* p, int* launches, double* avg_ms, double* bytes_per_launch);
 
 /* Batched Gauss-Newton matvecs over independent problems of uneven sizes
- * (each a handle created with nkreg_create on the same stream and with a
- * cached state). One call applies H_i to vt_i for every item i. */
+ * (each a handle with a cached state). One call applies H_i to vt_i for every
+ * item i as a single HIP-graph launch whose independent branches are the items'
+ * matvecs on their own streams, so small items run concurrently. The graph is
+ * captured on the first call and replayed while the pointer sets and the
+ * items' configurations are unchanged. The batch does not own its items. */
 typedef struct nkreg_batch nkreg_batch;
 int nkreg_batch_create(int count, nkreg_problem* const* items, nkreg_batch** out);
 int nkreg_batch_destroy(nkreg_batch* b);

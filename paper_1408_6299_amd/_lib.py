@@ -39,6 +39,7 @@ SIGNATURES = {
     "nkreg_destroy": (c_int, [c_void_p]),
     "nkreg_set_beta": (c_int, [c_void_p, c_double]),
     "nkreg_use_graphs": (c_int, [c_void_p, c_int]),
+    "nkreg_describe": (c_int, [c_void_p, ctypes.c_char_p, c_int]),
     "nkreg_set_images": (c_int, [c_void_p, c_void_p, c_void_p]),
     "nkreg_forward": (c_int, [c_void_p, c_void_p, c_void_p]),
     "nkreg_objective_gradient": (c_int, [c_void_p, c_void_p, POINTER(c_double), POINTER(c_double),

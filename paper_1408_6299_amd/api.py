@@ -52,7 +52,8 @@ class Problem:
 
     def __init__(self, shape: Sequence[int], nt: int, nc: int = 1, reg: int = 1,
                  incompressible: bool = False, beta: float = 1e-2, precision: int = 32,
-                 cfl_max: float = 0.0, stream: Optional[torch.cuda.Stream] = None):
+                 cfl_max: float = 0.0, stream: Optional[torch.cuda.Stream] = None,
+                 checkpoint_every: int = 0):
         self.lib = _lib.load()
         self.shape = tuple(int(s) for s in shape)
         self.d = len(self.shape)
@@ -71,7 +72,7 @@ class Problem:
         cfg.incompressible = int(self.incompressible)
         cfg.beta = float(beta)
         cfg.precision = self.precision
-        cfg.checkpoint_every = 0
+        cfg.checkpoint_every = int(checkpoint_every)
         cfg.cfl_max = float(cfl_max)
         self._beta = float(beta)
         h = c_void_p()
@@ -111,6 +112,13 @@ class Problem:
     def beta(self, value: float) -> None:
         check(self.lib.nkreg_set_beta(self._h, c_double(value)), "nkreg_set_beta")
         self._beta = float(value)
+
+    def describe(self) -> dict:
+        """Launch configuration of the handle (tile choices, autotuner timings)."""
+        import json
+        buf = ctypes.create_string_buffer(1024)
+        check(self.lib.nkreg_describe(self._h, buf, 1024), "nkreg_describe")
+        return json.loads(buf.value.decode())
 
     def use_graphs(self, enable: bool) -> None:
         """Replay Hessian matvecs from a captured HIP graph (default) or launch eagerly."""

@@ -324,12 +324,22 @@ __global__ __launch_bounds__(64) void k_row_w(StageArgs<R> a, const cplx<R>* __r
   }
 }
 
+template <int N, int E>
+struct ColShape {
+  static constexpr int LS = WavePlan<N, E>::LS;       // lanes per column
+  static constexpr int SPW = LS >= 64 ? 1 : 64 / LS;  // columns per workgroup
+  static constexpr int NT = LS >= 64 ? LS : 64;       // threads per workgroup
+  static constexpr bool BLOCK = LS > 64;              // a column spans several waves
+};
+
 template <typename R, int N, int E, int MODE>
-__global__ __launch_bounds__(64) void k_col_w(const cplx<R>* in, const cplx<R>* add, cplx<R>* out, ColArgs a,
-                                              R scale, const cplx<R>* __restrict__ tw, int twb) {
-  using P = WavePlan<N, E>;
-  constexpr int LS = P::LS;
-  constexpr int SPW = 64 / LS;
+__global__ __launch_bounds__((ColShape<N, E>::NT)) void k_col_w(const cplx<R>* in, const cplx<R>* add, cplx<R>* out,
+                                                              ColArgs a, R scale, const cplx<R>* __restrict__ tw,
+                                                              int twb) {
+  using CS = ColShape<N, E>;
+  constexpr int LS = CS::LS;
+  constexpr int SPW = CS::SPW;
+  constexpr bool BLK = CS::BLOCK;
   constexpr int PADN = padded<N>(N);
   __shared__ cplx<R> lds[SPW * PADN];
   const int lane = threadIdx.x;
@@ -352,16 +362,16 @@ __global__ __launch_bounds__(64) void k_col_w(const cplx<R>* in, const cplx<R>* 
   T.load(j, tw, twb);
   cplx<R>* S = lds + c * PADN;
   if (MODE == COL_INV) {
-    wave_fft<R, N, E, true>(v, j, S, T);
+    wave_fft<R, N, E, true, BLK>(v, j, S, T);
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = cscale(v[e], scale);
   } else {
-    wave_fft<R, N, E, false>(v, j, S, T);
+    wave_fft<R, N, E, false, BLK>(v, j, S, T);
   }
   if (MODE == COL_DERIV) {
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = cmul_i(v[e], R(deriv_wavenumber(j + LS * e, N)) * scale);
-    wave_fft<R, N, E, true>(v, j, S, T);
+    wave_fft<R, N, E, true, BLK>(v, j, S, T);
     if (has_add) {
 #pragma unroll
       for (int e = 0; e < E; ++e) v[e] = cadd(v[e], ad[e]);

@@ -1,5 +1,7 @@
 // extern "C" entry points of the registration library (declared in include/nkreg.h).
+#include <cstdio>
 #include <cstring>
+#include <memory>
 #include <string>
 
 #include "problem.hpp"
@@ -8,8 +10,26 @@ struct nkreg_problem {
   nk::ProblemBase* impl;
 };
 
+// A batch replays one HIP graph whose independent branches are the items'
+// matvecs, each on its item's internal stream (so they run concurrently).
 struct nkreg_batch {
   std::vector<nkreg_problem*> items;
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, done = nullptr;
+  std::vector<hipEvent_t> joins, waits;
+  hipGraphExec_t exec = nullptr;
+  std::vector<const void*> key_in;
+  std::vector<void*> key_out;
+  std::vector<unsigned> key_gen;
+  ~nkreg_batch() {
+    if (s) (void)hipStreamSynchronize(s);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    for (hipEvent_t e : joins) (void)hipEventDestroy(e);
+    for (hipEvent_t e : waits) (void)hipEventDestroy(e);
+    if (fork) (void)hipEventDestroy(fork);
+    if (done) (void)hipEventDestroy(done);
+    if (s) (void)hipStreamDestroy(s);
+  }
 };
 
 namespace {
@@ -47,7 +67,7 @@ int validate(const nkreg_config* c) {
   if (c->nc < 1 || c->nc > nk::kMaxNc) return fail(NKREG_EINVAL, "nc must be in [1, 16]");
   if (c->precision != 32 && c->precision != 64) return fail(NKREG_EINVAL, "precision must be 32 or 64");
   if (c->incompressible != 0 && c->incompressible != 1) return fail(NKREG_EINVAL, "incompressible must be 0 or 1");
-  if (c->checkpoint_every != 0) return fail(NKREG_ENOTIMPL, "trajectory checkpointing is not available");
+  if (c->checkpoint_every < 0) return fail(NKREG_EINVAL, "checkpoint_every must be >= 0");
   for (int i = 0; i < c->dim; ++i)
     if (!pow2_in_range(c->n[i])) return fail(NKREG_ESHAPE, "grid sizes must be powers of two in [8, 512]");
   return NKREG_OK;
@@ -128,6 +148,16 @@ int nkreg_set_beta(nkreg_problem* p, double beta) {
 int nkreg_use_graphs(nkreg_problem* p, int enable) {
   NEED(p);
   return guarded([&]() { Join j_(p->impl); p->impl->use_graph_capture(enable != 0); return (int)NKREG_OK; });
+}
+
+int nkreg_describe(nkreg_problem* p, char* buf, int len) {
+  NEED(p); NEED(buf);
+  if (len < 1) return fail(NKREG_EINVAL, "buffer length must be positive");
+  return guarded([&]() {
+    const std::string d = p->impl->describe();
+    std::snprintf(buf, (size_t)len, "%s", d.c_str());
+    return (int)NKREG_OK;
+  });
 }
 
 int nkreg_set_images(nkreg_problem* p, const void* mT, const void* mR) {
@@ -221,9 +251,18 @@ int nkreg_batch_create(int count, nkreg_problem* const* items, nkreg_batch** out
   for (int i = 0; i < count; ++i)
     if (!items[i]) return fail(NKREG_EINVAL, "null batch item");
   return guarded([&]() {
-    nkreg_batch* b = new nkreg_batch;
+    std::unique_ptr<nkreg_batch> b(new nkreg_batch);
     b->items.assign(items, items + count);
-    *out = b;
+    NK_HIP(hipStreamCreateWithFlags(&b->s, hipStreamNonBlocking));
+    NK_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+    NK_HIP(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
+    b->joins.resize(count);
+    b->waits.resize(count);
+    for (int i = 0; i < count; ++i) {
+      NK_HIP(hipEventCreateWithFlags(&b->joins[i], hipEventDisableTiming));
+      NK_HIP(hipEventCreateWithFlags(&b->waits[i], hipEventDisableTiming));
+    }
+    *out = b.release();
     return (int)NKREG_OK;
   });
 }
@@ -237,10 +276,50 @@ int nkreg_batch_hessian_matvec(nkreg_batch* b, const void* const* vt, void* cons
   NEED(b);
   if (!b->items.empty()) { NEED(vt); NEED(out); }
   return guarded([&]() {
-    // every item runs on its own internal stream, so independent matvecs overlap
-    for (auto* it : b->items) it->impl->enter();
-    for (size_t i = 0; i < b->items.size(); ++i) b->items[i]->impl->hessian_matvec(vt[i], out[i]);
-    for (auto* it : b->items) it->impl->leave();
+    const size_t cnt = b->items.size();
+    if (cnt == 0) return (int)NKREG_OK;
+    bool stale = !b->exec || b->key_in.size() != cnt;
+    for (size_t i = 0; i < cnt && !stale; ++i)
+      stale = b->key_in[i] != vt[i] || b->key_out[i] != out[i] || b->key_gen[i] != b->items[i]->impl->generation;
+    if (stale) {
+      if (b->exec) (void)hipGraphExecDestroy(b->exec);
+      b->exec = nullptr;
+      hipGraph_t graph = nullptr;
+      NK_HIP(hipStreamBeginCapture(b->s, hipStreamCaptureModeThreadLocal));
+      try {
+        NK_HIP(hipEventRecord(b->fork, b->s));
+        for (size_t i = 0; i < cnt; ++i) {
+          nk::ProblemBase* p = b->items[i]->impl;
+          NK_HIP(hipStreamWaitEvent(p->stream(), b->fork, 0));
+          p->matvec_launches(vt[i], out[i]);
+          NK_HIP(hipEventRecord(b->joins[i], p->stream()));
+          NK_HIP(hipStreamWaitEvent(b->s, b->joins[i], 0));
+        }
+      } catch (...) {
+        (void)hipStreamEndCapture(b->s, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        throw;
+      }
+      NK_HIP(hipStreamEndCapture(b->s, &graph));
+      const hipError_t e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) {
+        b->exec = nullptr;
+        throw nk::HipError(NKREG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+      }
+      b->key_in.assign(vt, vt + cnt);
+      b->key_out.assign(out, out + cnt);
+      b->key_gen.resize(cnt);
+      for (size_t i = 0; i < cnt; ++i) b->key_gen[i] = b->items[i]->impl->generation;
+    }
+    // the batch stream waits for every caller stream; every caller stream waits for the batch
+    for (size_t i = 0; i < cnt; ++i) {
+      NK_HIP(hipEventRecord(b->waits[i], b->items[i]->impl->caller_stream()));
+      NK_HIP(hipStreamWaitEvent(b->s, b->waits[i], 0));
+    }
+    NK_HIP(hipGraphLaunch(b->exec, b->s));
+    NK_HIP(hipEventRecord(b->done, b->s));
+    for (size_t i = 0; i < cnt; ++i) NK_HIP(hipStreamWaitEvent(b->items[i]->impl->caller_stream(), b->done, 0));
     return (int)NKREG_OK;
   });
 }

@@ -5,7 +5,11 @@
 
 #include <chrono>
 #include <cstdio>
+#include <array>
+#include <map>
 #include <memory>
+#include <mutex>
+#include <string>
 #include <cstdlib>
 #include <type_traits>
 #include <vector>
@@ -131,6 +135,13 @@ class ProblemBase {
   virtual hipStream_t stream() const = 0;
   virtual void set_beta(double beta) = 0;
   virtual void use_graph_capture(bool on) = 0;
+  virtual std::string describe() = 0;
+  // One matvec as eager launches on the internal stream (used when a batch
+  // captures several problems into one graph); checks the cached state.
+  virtual void matvec_launches(const void* vt, void* out) = 0;
+  virtual hipStream_t caller_stream() const = 0;
+  // bumped whenever captured graphs become stale (beta change, graph switch, timer)
+  unsigned generation = 0;
   // Every call runs on the library's internal stream: enter() makes it wait for
   // the caller's stream, leave() makes the caller's stream wait for it.
   virtual void enter() = 0;
@@ -146,6 +157,19 @@ class ProblemBase {
 // FP32 rounding of a velocity at the grid's corner wavenumbers far above the
 // gradient itself, while control-space work is O(1) per matvec against the
 // O(nt) transport work.
+// Column-tile choices made by the autotuner, shared by every handle of the
+// process: one entry per (grid, transport precision). The candidates round
+// differently, so sharing the choice keeps all handles of one shape
+// bit-identical to each other.
+struct TuneTable {
+  std::mutex m;
+  std::map<std::array<int, 4>, int> col_e;
+};
+inline TuneTable& tune_table() {
+  static TuneTable t;
+  return t;
+}
+
 template <typename R>
 class ProblemT final : public ProblemBase {
  public:
@@ -164,6 +188,11 @@ class ProblemT final : public ProblemBase {
   // transport precision
   DevBuf<R> mT, mR, traj, acc, lam, m1, mt1, vR, vtR, F;
   DevBuf<cplx<R>> T, Ts, S1, S2, U, Dsp;
+  // trajectory checkpointing: m at the start of every K-step segment, and the
+  // scratch of the segment recomputation (disjoint from the sweeps' buffers)
+  int K = 0, nseg = 1, seglen = 0, traj_base = 0;
+  DevBuf<R> ckpt, accr, mr;
+  DevBuf<cplx<R>> Tr, Tsr, S1r, S2r;
   // control space (FP64)
   DevBuf<double> v, F64, tmpv, kx, kr, kz, kp, kq, gbuf, sbuf, vtrial, rhsbuf;
   DevBuf<cplx<double>> Xs, Ys;
@@ -188,7 +217,15 @@ class ProblemT final : public ProblemBase {
     nv = (long long)nc * d * n;
     red.init(s);
     mT.alloc(n); mR.alloc(n);
-    traj.alloc((size_t)2 * nt * d * n);
+    K = (c.checkpoint_every > 0 && c.checkpoint_every < nt) ? c.checkpoint_every : 0;
+    nseg = K ? (nt + K - 1) / K : 1;
+    seglen = K ? K : nt;
+    traj.alloc((size_t)2 * seglen * d * n);
+    if (K) {
+      ckpt.alloc((size_t)nseg * n);
+      accr.alloc(n); mr.alloc(n);
+      Tr.alloc(g.nspec); Tsr.alloc(g.nspec); S1r.alloc(g.nspec); S2r.alloc(g.nspec);
+    }
     acc.alloc(n); lam.alloc(n); m1.alloc(n); mt1.alloc(n);
     F.alloc(nv);
     if (!kF64) { vR.alloc(nv); vtR.alloc(nv); F64.alloc(nv); }
@@ -198,6 +235,7 @@ class ProblemT final : public ProblemBase {
     Xs.alloc((size_t)nc * d * g.nspec); Ys.alloc((size_t)nc * d * g.nspec);
     kx.alloc(nv); kr.alloc(nv); kz.alloc(nv); kp.alloc(nv); kq.alloc(nv);
     gbuf.alloc(nv); sbuf.alloc(nv); vtrial.alloc(nv); rhsbuf.alloc(nv);
+    tune_columns();
   }
 
   hipStream_t stream() const override { return s; }
@@ -222,7 +260,13 @@ class ProblemT final : public ProblemBase {
   void drop_graphs() {
     if (mv_graph.exec) (void)hipGraphExecDestroy(mv_graph.exec);
     mv_graph = GraphEntry{};
+    ++generation;
   }
+  void matvec_launches(const void* vt, void* out) override {
+    if (!state_valid) throw HipError(NKREG_ESTATE, "no gradient computed at the current velocity");
+    matvec_body(vt, out);
+  }
+  hipStream_t caller_stream() const override { return user_s; }
   ~ProblemT() override {
     (void)hipStreamSynchronize(s);
     drop_graphs();
@@ -256,7 +300,8 @@ class ProblemT final : public ProblemBase {
     drop_graphs();
   }
 
-  R* trajp(int j, int stage) { return traj.p + ((size_t)(2 * j + stage)) * d * n; }
+  // grad m^j (stage 0) and grad m*_j (stage 1) of the steps held in the trajectory buffer
+  R* trajp(int j, int stage) { return traj.p + ((size_t)(2 * (j - traj_base) + stage)) * d * n; }
 
   void basis(double t, R* out) {
     double b[kMaxNc];
@@ -296,28 +341,63 @@ class ProblemT final : public ProblemBase {
     state_valid = false;
   }
 
-  // ---- state equation (Heun), optionally recording the trajectory ----
-  void forward_sweep(const R* vl, bool record, R* m1out) {
+  // ---- state equation (Heun) ----
+  struct SweepBufs {
+    cplx<R>* T;
+    cplx<R>* Ts;
+    cplx<R>* S1;
+    cplx<R>* S2;
+    R* acc;
+  };
+  SweepBufs main_bufs() { return {T.p, Ts.p, S1.p, S2.p, acc.p}; }
+  SweepBufs recompute_bufs() { return {Tr.p, Tsr.p, S1r.p, S2r.p, accr.p}; }
+
+  // Steps j0..j1-1 from m^{j0} = m_start; m_state receives m^{j+1} after each
+  // step. record: store grad m^j, grad m*_j in the trajectory buffer.
+  // store_ckpt: copy m at every segment boundary into the checkpoints.
+  void state_steps(const R* vl, int j0, int j1, const R* m_start, R* m_state, const SweepBufs& B, bool record,
+                   bool store_ckpt) {
     const R h = R(1.0 / nt);
-    sp.r2c(mT.p, T.p, 1);
-    for (int j = 0; j < nt; ++j) {
-      sp.deriv_cols(T.p, S1.p, S2.p);
+    sp.r2c(m_start, B.T, 1);
+    for (int j = j0; j < j1; ++j) {
+      sp.deriv_cols(B.T, B.S1, B.S2);
       StageArgs<R> a{};
-      a.spec = T.p; a.s1 = S1.p; a.s2 = S2.p; a.out0 = Ts.p;
-      a.vl = vl; a.nc = nc; a.h = h; a.acc = acc.p;
+      a.spec = B.T; a.s1 = B.S1; a.s2 = B.S2; a.out0 = B.Ts;
+      a.vl = vl; a.nc = nc; a.h = h; a.acc = B.acc;
       a.g0w = record ? trajp(j, 0) : nullptr;
-      a.mreal = (j == 0) ? mT.p : m1out;
+      a.mreal = (j == j0) ? m_start : m_state;
       basis(j * (double)h, a.b0);
       sp.template row<ST_FWD1>(a, 1);
-      sp.deriv_cols(Ts.p, S1.p, S2.p);
+      sp.deriv_cols(B.Ts, B.S1, B.S2);
       StageArgs<R> b{};
-      b.spec = Ts.p; b.s1 = S1.p; b.s2 = S2.p; b.out0 = T.p;
-      b.vl = vl; b.nc = nc; b.h = h; b.acc = acc.p;
+      b.spec = B.Ts; b.s1 = B.S1; b.s2 = B.S2; b.out0 = B.T;
+      b.vl = vl; b.nc = nc; b.h = h; b.acc = B.acc;
       b.g1w = record ? trajp(j, 1) : nullptr;
       basis((j + 1) * (double)h, b.b1);
-      b.out_real = m1out;  // m^{j+1}; m_1 after the last step
+      b.out_real = m_state;  // m^{j+1}
       sp.template row<ST_FWD2>(b, 1);
+      if (store_ckpt && (j + 1) % K == 0 && j + 1 < nt) copy(ckpt.p + (size_t)((j + 1) / K) * n, m_state, n * sizeof(R));
     }
+  }
+
+  // Forward solve from m_T; m1out receives m_1. With record, the trajectory is
+  // kept in full or, when checkpointing, only m at the segment starts.
+  void forward_sweep(const R* vl, bool record, R* m1out) {
+    if (!K) {
+      traj_base = 0;
+      state_steps(vl, 0, nt, mT.p, m1out, main_bufs(), record, false);
+    } else {
+      if (record) copy(ckpt.p, mT.p, n * sizeof(R));
+      state_steps(vl, 0, nt, mT.p, m1out, main_bufs(), false, record);
+    }
+  }
+
+  // Makes the trajectory of segment sgi available (recomputed from its checkpoint).
+  void load_segment(const R* vl, int sgi) {
+    if (!K) return;
+    const int j0 = sgi * K, j1 = std::min(nt, j0 + K);
+    traj_base = j0;
+    state_steps(vl, j0, j1, ckpt.p + (size_t)sgi * n, mr.p, recompute_bufs(), true, false);
   }
 
   // ---- adjoint (conservative, backward Heun) with body-force accumulation ----
@@ -337,6 +417,7 @@ class ProblemT final : public ProblemBase {
     basis(1.0, a.bv);
     sp.template row<ST_ADJINIT>(a, 1);
     for (int j = nt - 1; j >= 0; --j) {
+      if (K && (j == nt - 1 || (j + 1) % K == 0)) load_segment(vl, j / K);
       sp.div_cols(U0, U1, U2, S2.p, Dsp.p);
       StageArgs<R> b{};
       b.spec = Dsp.p; b.vl = vl; b.nc = nc; b.h = h;
@@ -362,6 +443,7 @@ class ProblemT final : public ProblemBase {
   void incremental_sweep(const R* vl, const R* vtl) {
     const R h = R(1.0 / nt);
     for (int j = 0; j < nt; ++j) {
+      if (K && j % K == 0) load_segment(vl, j / K);
       if (j > 0) sp.deriv_cols(T.p, S1.p, S2.p);
       StageArgs<R> a{};
       a.spec = T.p; a.s1 = S1.p; a.s2 = S2.p; a.out0 = Ts.p;
@@ -464,26 +546,99 @@ class ProblemT final : public ProblemBase {
     }
     if (!(mv_graph.exec && mv_graph.in == vtin && mv_graph.out == out)) {
       drop_graphs();
-      hipGraph_t graph = nullptr;
-      NK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      try {
-        matvec_body(vtin, out);
-      } catch (...) {
-        (void)hipStreamEndCapture(s, &graph);
-        if (graph) (void)hipGraphDestroy(graph);
-        throw;
-      }
-      NK_HIP(hipStreamEndCapture(s, &graph));
-      const hipError_t e = hipGraphInstantiate(&mv_graph.exec, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
-      if (e != hipSuccess) {
-        mv_graph = GraphEntry{};
-        throw HipError(NKREG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-      }
+      mv_graph.exec = capture_matvec(vtin, out);
       mv_graph.in = vtin;
       mv_graph.out = out;
     }
     NK_HIP(hipGraphLaunch(mv_graph.exec, s));
+  }
+
+  hipGraphExec_t capture_matvec(const void* vtin, void* out) {
+    hipGraph_t graph = nullptr;
+    NK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    try {
+      matvec_body(vtin, out);
+    } catch (...) {
+      (void)hipStreamEndCapture(s, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      throw;
+    }
+    NK_HIP(hipStreamEndCapture(s, &graph));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) throw HipError(NKREG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    return exec;
+  }
+
+  // Tile autotuner, run once per handle at creation, before any result is
+  // computed: the column transforms run with 8 complex elements per lane (one
+  // wavefront per 512-point column) or 4 (two wavefronts per column). For each
+  // candidate a HIP graph of kTuneReps derivative and divergence column passes
+  // over zeroed spectra is captured on the internal stream and replayed under
+  // HIP events; the fastest candidate is kept. The choice is shared by every
+  // handle of the same grid and precision in the process, so they all compute
+  // bit-identical results. NKREG_COL_E in the environment fixes the choice.
+  static constexpr int kTuneReps = 16;
+  std::string tuning;
+  std::array<int, 4> tune_key() const { return {g.n[0], g.n[1], g.n[2], kF64 ? 64 : 32}; }
+  void tune_columns() {
+    if (std::getenv("NKREG_COL_E")) {
+      tuning = "col_E=" + std::to_string(sp.colE) + " (fixed)";
+      return;
+    }
+    TuneTable& tt = tune_table();
+    std::lock_guard<std::mutex> lk(tt.m);
+    if (auto it = tt.col_e.find(tune_key()); it != tt.col_e.end()) {
+      sp.colE = it->second;
+      tuning = "col_E=" + std::to_string(sp.colE) + " (chosen earlier in this process for this grid)";
+      return;
+    }
+    const long long ns = g.nspec;
+    hipLaunchKernelGGL((k_fill<R>), dim3(launch_blocks(2 * ns)), dim3(256), 0, s, 2 * ns, R(0), (R*)T.p);
+    hipLaunchKernelGGL((k_fill<R>), dim3(launch_blocks(6 * ns)), dim3(256), 0, s, 6 * ns, R(0), (R*)U.p);
+    NK_LAUNCHED();
+    hipEvent_t e0, e1;
+    NK_HIP(hipEventCreate(&e0));
+    NK_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    int bestE = sp.colE;
+    for (int ce : {8, 4}) {
+      sp.colE = ce;
+      hipGraph_t graph = nullptr;
+      NK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      for (int r = 0; r < kTuneReps; ++r) {
+        sp.deriv_cols(T.p, S1.p, S2.p);
+        sp.div_cols(U.p, U.p + ns, U.p + 2 * ns, S2.p, Dsp.p);
+      }
+      NK_HIP(hipStreamEndCapture(s, &graph));
+      hipGraphExec_t ex = nullptr;
+      const hipError_t ie = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ie != hipSuccess) throw HipError(NKREG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+      NK_HIP(hipGraphLaunch(ex, s));  // warm-up
+      NK_HIP(hipEventRecord(e0, s));
+      for (int r = 0; r < 3; ++r) NK_HIP(hipGraphLaunch(ex, s));
+      NK_HIP(hipEventRecord(e1, s));
+      NK_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      NK_HIP(hipEventElapsedTime(&ms, e0, e1));
+      (void)hipGraphExecDestroy(ex);
+      const float us_per_pass = 1e3f * ms / (3.0f * kTuneReps * (g.d == 2 ? 2 : 4));
+      tuning += (tuning.empty() ? "" : ", ") + std::string("col_E=") + std::to_string(ce) + ": " +
+                std::to_string(us_per_pass) + " us/pass";
+      if (ms < best) { best = ms; bestE = ce; }
+    }
+    sp.colE = bestE;
+    tt.col_e[tune_key()] = bestE;
+    tuning += "; chose col_E=" + std::to_string(bestE);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  std::string describe() override {
+    return std::string("{\"transport_precision\": ") + (kF64 ? "64" : "32") + ", \"graphs\": " +
+           (use_graphs ? "true" : "false") + ", \"row_E\": " + std::to_string(kRowE) + ", \"col_E\": " +
+           std::to_string(sp.colE) + ", \"autotune\": \"" + tuning + "\"}";
   }
 
   // One Gauss-Newton matvec as a sequence of launches on the internal stream.

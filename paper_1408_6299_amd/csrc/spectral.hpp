@@ -2,6 +2,7 @@
 #pragma once
 
 #include <cmath>
+#include <cstdlib>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -61,7 +62,6 @@ inline Grid make_grid(int d, const int* n) {
 
 // Complex elements per lane of the row-stage and column transforms.
 constexpr int kRowE = 4;
-constexpr int kColE = 8;
 
 // Kernel identifiers for launch timing: row-stage kinds are 0..10 (StageKind),
 // column passes are 20 + ColMode.
@@ -115,9 +115,13 @@ class Spectral {
   hipStream_t s = nullptr;
   cplx<R>* tw = nullptr;  // exp(-2 pi i m / lmax), m < lmax
   KernelTimer* timer = nullptr;
+  // elements per lane of the column transforms: 8 (one wave per 512-point column)
+  // or 4 (two waves per 512-point column); chosen by the matvec autotuner
+  int colE = 8;
 
   Spectral() = default;
   Spectral(const Grid& grid, hipStream_t stream) : g(grid), s(stream) {
+    if (const char* ce = std::getenv("NKREG_COL_E")) colE = std::atoi(ce) == 4 ? 4 : 8;
     std::vector<cplx<R>> h(g.lmax);
     for (int m = 0; m < g.lmax; ++m) {
       const double a = -2.0 * M_PI * (double)m / (double)g.lmax;
@@ -257,12 +261,18 @@ class Spectral {
   }
 
  private:
-  // Column transforms: one wavefront per workgroup, kColE elements per lane.
+  // Column transforms: one or two wavefronts per column workgroup.
   template <int N>
   void col_n(int mode, const cplx<R>* in, const cplx<R>* add, cplx<R>* out, int nf, R scale, int outer,
              long long inner) {
-    constexpr int E = kColE;
-    constexpr int SPW = 64 / WavePlan<N, E>::LS;
+    if (colE == 4 && N >= 8) col_ne<N, 4>(mode, in, add, out, nf, scale, outer, inner);
+    else col_ne<N, 8>(mode, in, add, out, nf, scale, outer, inner);
+  }
+  template <int N, int E>
+  void col_ne(int mode, const cplx<R>* in, const cplx<R>* add, cplx<R>* out, int nf, R scale, int outer,
+              long long inner) {
+    using CS = ColShape<N, E>;
+    constexpr int SPW = CS::SPW;
     ColArgs a;
     a.inner = (int)inner;
     a.ctile = SPW;
@@ -273,13 +283,13 @@ class Spectral {
     if (timed) timer->before(s);
     switch (mode) {
       case COL_FWD:
-        hipLaunchKernelGGL((k_col_w<R, N, E, COL_FWD>), grid, dim3(64), 0, s, in, add, out, a, scale, tw, twb);
+        hipLaunchKernelGGL((k_col_w<R, N, E, COL_FWD>), grid, dim3(CS::NT), 0, s, in, add, out, a, scale, tw, twb);
         break;
       case COL_INV:
-        hipLaunchKernelGGL((k_col_w<R, N, E, COL_INV>), grid, dim3(64), 0, s, in, add, out, a, scale, tw, twb);
+        hipLaunchKernelGGL((k_col_w<R, N, E, COL_INV>), grid, dim3(CS::NT), 0, s, in, add, out, a, scale, tw, twb);
         break;
       default:
-        hipLaunchKernelGGL((k_col_w<R, N, E, COL_DERIV>), grid, dim3(64), 0, s, in, add, out, a, scale, tw, twb);
+        hipLaunchKernelGGL((k_col_w<R, N, E, COL_DERIV>), grid, dim3(CS::NT), 0, s, in, add, out, a, scale, tw, twb);
         break;
     }
     NK_LAUNCHED();

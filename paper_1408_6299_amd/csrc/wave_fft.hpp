@@ -81,6 +81,7 @@ __device__ __forceinline__ void dft_small(cplx<R> (&v)[RR]) {
 template <int M, int E>
 struct WavePlan {
   static_assert((M & (M - 1)) == 0 && (E == 2 || E == 4 || E == 8) && M >= E, "plan");
+  static_assert(M / E <= 256, "a sequence spans at most four wavefronts");
   static constexpr int LOG = ilog2(M);
   static constexpr int LE = ilog2(E);
   static constexpr int NFULL = LOG / LE;           // radix-E passes
@@ -134,7 +135,9 @@ __device__ __forceinline__ int pad32(int i) { return i + (i >> 5); }
 template <int M>
 constexpr int padded(int m) { return m + m / 32 + 1; }
 
-template <typename R, int M, int E, bool INV>
+// BLOCK = true when a sequence spans several wavefronts of the workgroup
+// (M / E > 64 lanes): exchanges then synchronise the whole workgroup.
+template <typename R, int M, int E, bool INV, bool BLOCK = false>
 __device__ __forceinline__ void wave_fft(cplx<R> (&a)[E], int j, cplx<R>* s, const WaveTwiddles<R, M, E>& T) {
   using P = WavePlan<M, E>;
   constexpr int LS = P::LS;
@@ -192,10 +195,10 @@ __device__ __forceinline__ void wave_fft(cplx<R> (&a)[E], int j, cplx<R>* s, con
 #pragma unroll
         for (int r = 0; r < RR; ++r) s[pad32(base + r * Ns)] = a[b + r * BPL];
       }
-      wave_lds_sync();
+      if (BLOCK) __syncthreads(); else wave_lds_sync();
 #pragma unroll
       for (int e = 0; e < E; ++e) a[e] = s[pad32(j + LS * e)];
-      wave_lds_sync();
+      if (BLOCK) __syncthreads(); else wave_lds_sync();
     }
   }
 }

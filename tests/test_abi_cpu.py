@@ -66,7 +66,7 @@ def make_cfg(**kw):
     (dict(n=(4, 64, 1)), _lib.ESHAPE),
     (dict(n=(1024, 64, 1)), _lib.ESHAPE),
     (dict(dim=3, n=(64, 64, 12)), _lib.ESHAPE),
-    (dict(checkpoint_every=8), _lib.ENOTIMPL),
+    (dict(checkpoint_every=-1), _lib.EINVAL),
 ])
 def test_invalid_configs_are_rejected_before_any_device_work(kw, code):
     lib = _lib.load()

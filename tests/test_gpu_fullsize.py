@@ -1,0 +1,242 @@
+"""Parity at the configurations' full sizes, in the launch configuration bench.py
+times (captured matvec graphs), against the FP64 oracle where it finishes in
+seconds and through properties that hold at any size where it does not (256^3).
+
+FP32 tolerances: 1e-5 relative (L2) for m_1, the gradient at v = 0 and the
+Hessian matvec; FP64: 1e-10 (rounding).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import defgrad as odg
+from oracle import krylov as okr
+from oracle import reduced as ord_
+from oracle import transport as otr
+from tests.helpers import rel_inf, rel_l2
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1408_6299_amd as nk
+    return nk
+
+
+def dev_t(a, prec):
+    dt = torch.float32 if prec == 32 else torch.float64
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda").to(dt).contiguous()
+
+
+def dev_v(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda").contiguous()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().double().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def c2lit():
+    spec = synth.CONFIGS["c2lit"]
+    mT, vstar = synth.make_inputs(spec)
+    mR = otr.forward_only(mT, vstar, spec.nt)
+    P = ord_.Problem(mT, mR, spec.nt, 1, spec.reg, 0, spec.beta)
+    S0 = ord_.objective_gradient(P, np.zeros(P.vshape()))
+    w = synth.bandlimited_velocity(spec.shape, 20, 16, 0.02)
+    Hw = ord_.hessian_matvec(P, S0, w)
+    return spec, P, vstar, S0, w, Hw
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+def test_c2lit_512_gradient_and_matvec(nk, c2lit, prec):
+    """512^2, nt = 32, H2, beta = 1e-4: the bench workload."""
+    spec, P, vstar, S0, w, Hw = c2lit
+    G = nk.Problem(spec.shape, spec.nt, 1, spec.reg, False, spec.beta, precision=prec)
+    G.set_images(dev_t(P.mT, prec), dev_t(P.mR, prec))
+    tol = 1e-5 if prec == 32 else 1e-10
+    m1 = host(G.forward(dev_v(vstar)))
+    assert rel_l2(m1, P.mR) < tol
+    J, Jd, Jr, g = G.objective_gradient(G.zeros_v())
+    assert abs(J - S0.J) <= tol * abs(S0.J)
+    assert rel_l2(host(g), S0.g) < tol
+    out = G.empty_v()
+    wt = dev_v(w)
+    for _ in range(2):  # capture, then replay
+        G.hessian_matvec(wt, out)
+        assert rel_l2(host(out), Hw) < tol
+    if prec == 64:
+        assert rel_inf(host(g), S0.g) < tol and rel_inf(host(out), Hw) < tol
+    G.close()
+
+
+def test_c2lit_512_autograd_fd_five_directions(nk, c2lit):
+    """torch.autograd gradient (hand-written adjoint) vs central differences at 5 directions."""
+    from paper_1408_6299_amd import objective
+    spec, P, vstar, S0, w, Hw = c2lit
+    G = nk.Problem(spec.shape, spec.nt, 1, spec.reg, False, spec.beta, precision=64)
+    G.set_images(dev_t(P.mT, 64), dev_t(P.mR, 64))
+    v0 = 0.5 * vstar
+    vt = dev_v(v0).requires_grad_(True)
+    objective(vt, G).backward()
+    grad = vt.grad.detach()
+    for seed in range(20, 25):
+        d = synth.bandlimited_velocity(spec.shape, seed, 16, 0.01)
+        eps = 1e-3
+        fd = (G.objective(dev_v(v0 + eps * d))[0] - G.objective(dev_v(v0 - eps * d))[0]) / (2 * eps)
+        an = float((grad * dev_v(d)).sum())
+        assert abs(fd - an) <= 1e-6 * abs(an), (seed, fd, an)
+    G.close()
+
+
+def test_c0_64_gauss_newton_solve_matches_oracle(nk):
+    """64^2 FP64, H1, beta = 1e-2, nt = 16: the whole GN-PCG solve to relative gradient 1e-3."""
+    spec = synth.CONFIGS["c0"]
+    mT, vstar = synth.make_inputs(spec)
+    mR = otr.forward_only(mT, vstar, spec.nt)
+    P = ord_.Problem(mT, mR, spec.nt, 1, spec.reg, 0, spec.beta)
+    v_ref, rep_ref, S_ref = okr.gauss_newton(P, gtol=1e-3, max_outer=50)
+    G = nk.Problem(spec.shape, spec.nt, 1, spec.reg, False, spec.beta, precision=64)
+    G.set_images(dev_t(mT, 64), dev_t(mR, 64))
+    v, rep = G.newton_solve(gtol=1e-3, max_outer=50)
+    assert rep.converged and rep_ref.converged
+    assert rep.iterations == rep_ref.iterations
+    assert rep.cg_iterations == rep_ref.matvecs
+    assert rel_inf(host(v), v_ref) < 1e-8
+    mis0 = np.sum((mR - mT) ** 2)
+    assert abs(2 * rep.J_dist / (P.hd * mis0) - 2 * S_ref.J_dist / (P.hd * mis0)) < 1e-4
+    G.close()
+
+
+def test_c1_256_three_coefficients_stokes(nk):
+    """256^2, n_c = 3 Chebyshev coefficients, H2 + Stokes, beta = 1e-3, nt = 408, FP32 and FP64."""
+    spec = synth.CONFIGS["c1"]
+    mT, vstar = synth.make_inputs(spec)
+    mR = otr.forward_only(mT, vstar, spec.nt)
+    P = ord_.Problem(mT, mR, spec.nt, spec.nc, spec.reg, 1, spec.beta)
+    S0 = ord_.objective_gradient(P, np.zeros(P.vshape()))
+    w = synth.bandlimited_velocity(spec.shape, 30, 8, 0.1, divfree=True, nc=3)
+    Hw = ord_.hessian_matvec(P, S0, w)
+    for prec in (32, 64):
+        tol = 1e-5 if prec == 32 else 1e-10
+        G = nk.Problem(spec.shape, spec.nt, spec.nc, spec.reg, True, spec.beta, precision=prec)
+        G.set_images(dev_t(mT, prec), dev_t(mR, prec))
+        J, _, _, g = G.objective_gradient(G.zeros_v())
+        assert rel_l2(host(g), S0.g) < tol
+        assert rel_l2(host(G.hessian_matvec(dev_v(w))), Hw) < tol
+        G.close()
+
+
+def test_c1_256_det_grad_y_of_divergence_free_velocity(nk):
+    """det F_1 statistics in FP64 for the three-coefficient divergence-free velocity."""
+    spec = synth.CONFIGS["c1"]
+    _, vstar = synth.make_inputs(spec)
+    nt = 64  # the oracle's cost grows with nt; the statistic is a parity check, not a convergence study
+    ref_det, ref_stats = odg.det_stats(vstar, nt)
+    G = nk.Problem(spec.shape, nt, spec.nc, spec.reg, True, spec.beta, precision=32)
+    det, stats = G.det_grad_y(dev_v(vstar))
+    assert np.abs(host(det) - ref_det).max() < 1e-10
+    assert np.allclose(stats, ref_stats, rtol=0, atol=1e-10)
+    assert abs(stats[0] - 1) < 1e-2 and abs(stats[1] - 1) < 1e-2
+    G.close()
+
+
+def test_c3_batch_subset(nk):
+    """Batched workload: every grid size of the 64-item batch, one graph launch, equal to
+    single-item matvecs bit for bit; the smallest item against the oracle."""
+    specs = synth.batch_specs()
+    picks, seen = [], set()
+    for i, sp in enumerate(specs):
+        if sp.shape[0] not in seen:
+            seen.add(sp.shape[0])
+            picks.append(i)
+    picks += [i for i in range(len(specs)) if i not in picks][:4]
+    probs, ws, refs, host_items = [], [], [], []
+    for i in picks:
+        sp = specs[i]
+        mT, vstar = synth.make_inputs(sp)
+        G = nk.Problem(sp.shape, sp.nt, 1, sp.reg, False, sp.beta, precision=32)
+        gen = nk.Problem(sp.shape, sp.nt, 1, sp.reg, False, sp.beta, precision=64)
+        gen.set_images(dev_t(mT, 64), torch.zeros(sp.shape, dtype=torch.float64, device="cuda"))
+        mR = host(gen.forward(dev_v(vstar)))
+        gen.close()
+        G.set_images(dev_t(mT, 32), dev_t(mR, 32))
+        G.objective_gradient(G.zeros_v())
+        w = synth.bandlimited_velocity(sp.shape, 500 + i, 6, 0.05)
+        probs.append(G)
+        ws.append(dev_v(w))
+        refs.append(host(G.hessian_matvec(ws[-1])))
+        host_items.append((mT, mR, w, sp))
+    B = nk.Batch(probs)
+    for _ in range(2):
+        outs = B.hessian_matvec(ws)
+        for o, r in zip(outs, refs):
+            assert np.array_equal(host(o), r)
+    k = int(np.argmin([sp.shape[0] for (_, _, _, sp) in host_items]))
+    mT, mR, w, sp = host_items[k]
+    P = ord_.Problem(mT, mR, sp.nt, 1, sp.reg, 0, sp.beta)
+    S0 = ord_.objective_gradient(P, np.zeros(P.vshape()))
+    assert rel_l2(refs[k], ord_.hessian_matvec(P, S0, w)) < 1e-5
+
+
+def test_c4_64cube_oracle_parity(nk):
+    """The 3D generator (smooth image, divergence-free band-limited velocity, H2 + Stokes)
+    at 64^3, nt = 32, checkpointing every 8 steps, against the oracle."""
+    spec = synth.CONFIGS["c4"]
+    shape = (64, 64, 64)
+    mT = synth.smooth_image(shape, spec.image_seed, spec.image_width / 16.0)
+    vstar = synth.bandlimited_velocity(shape, spec.vel_seed, 4, synth.cfl_literal_linf(64, 32), divfree=True,
+                                       norm="linf")
+    mR = otr.forward_only(mT, vstar, spec.nt)
+    P = ord_.Problem(mT, mR, spec.nt, 1, spec.reg, 1, spec.beta)
+    S0 = ord_.objective_gradient(P, np.zeros(P.vshape()))
+    w = synth.bandlimited_velocity(shape, 41, 4, 0.05, divfree=True)
+    Hw = ord_.hessian_matvec(P, S0, w)
+    for prec in (32, 64):
+        tol = 1e-5 if prec == 32 else 1e-10
+        G = nk.Problem(shape, spec.nt, 1, spec.reg, True, spec.beta, precision=prec, checkpoint_every=8)
+        G.set_images(dev_t(mT, prec), dev_t(mR, prec))
+        _, _, _, g = G.objective_gradient(G.zeros_v())
+        assert rel_l2(host(g), S0.g) < tol
+        assert rel_l2(host(G.hessian_matvec(dev_v(w))), Hw) < tol
+        G.close()
+
+
+def test_c4_256cube_properties(nk):
+    """256^3 FP32, H2 + Stokes, beta = 1e-3, nt = 32, checkpoint every 8: the oracle cannot run
+    here, so check what holds at any size: a constant image stays constant, checkpointing is
+    exact, the GN Hessian is symmetric, FP32 agrees with FP64, and det F_1 = 1 for the
+    divergence-free velocity to O(h_t^2)."""
+    spec = synth.CONFIGS["c4"]
+    shape, nt = spec.shape, spec.nt
+    mT, vstar = synth.make_inputs(spec)
+    G32 = nk.Problem(shape, nt, 1, spec.reg, True, spec.beta, precision=32, checkpoint_every=8)
+    const = torch.full(shape, 0.37, dtype=torch.float32, device="cuda")
+    G32.set_images(const, const)
+    m1 = G32.forward(dev_v(vstar))
+    assert float((m1 - 0.37).abs().max()) < 1e-6
+    # reference image from the library's FP64 forward solve (input synthesis, not a check)
+    G64 = nk.Problem(shape, nt, 1, spec.reg, True, spec.beta, precision=64, checkpoint_every=8)
+    G64.set_images(dev_t(mT, 64), torch.zeros(shape, dtype=torch.float64, device="cuda"))
+    mR = G64.forward(dev_v(vstar))
+    G64.set_images(dev_t(mT, 64), mR)
+    G32.set_images(dev_t(mT, 32), mR.float())
+    _, _, _, g64 = G64.objective_gradient(G64.zeros_v())
+    _, _, _, g32 = G32.objective_gradient(G32.zeros_v())
+    assert rel_l2(host(g32), host(g64)) < 1e-5
+    u = dev_v(synth.bandlimited_velocity(shape, 51, 6, 0.05, divfree=True))
+    w = dev_v(synth.bandlimited_velocity(shape, 52, 6, 0.05, divfree=True))
+    Hu64, Hw64 = G64.hessian_matvec(u), G64.hessian_matvec(w)
+    a, b = float((u * Hw64).sum()), float((Hu64 * w).sum())
+    assert abs(a - b) <= 1e-12 * abs(a)
+    Hw32 = G32.hessian_matvec(w)
+    assert rel_l2(host(Hw32), host(Hw64)) < 1e-5
+    det, stats = G32.det_grad_y(dev_v(vstar))
+    assert abs(stats[0] - 1) < 1e-3 and abs(stats[1] - 1) < 1e-3 and abs(stats[2] - 1) < 1e-4
+    G32.close()
+    G64.close()

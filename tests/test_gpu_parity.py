@@ -270,3 +270,45 @@ def test_graph_replays_match_eager_matvec(nk, prec):
         G.precond(dev_v(v))                       # eager work between replays
         G.hessian_matvec(dev_v(0.5 * w))          # a different pointer pair: new capture
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+@pytest.mark.parametrize("shape,nt,nc,gamma", [((32, 32), 8, 1, 0), ((8, 16, 8), 6, 2, 1)])
+def test_checkpointed_trajectory_is_bit_identical(nk, shape, nt, nc, gamma, prec):
+    """Keeping m every K steps and recomputing segments reproduces the full-trajectory
+    gradient and matvec exactly (same kernels, same order), also when K does not divide nt."""
+    mT, mR, vstar, w = smooth_inputs(shape, nt, nc=nc, divfree=bool(gamma))
+    outs = []
+    for K in (0, 3, 2):
+        G = nk.Problem(shape, nt, nc=nc, reg=2, incompressible=bool(gamma), beta=1e-3, precision=prec,
+                       checkpoint_every=K)
+        G.set_images(dev_t(mT, prec), dev_t(mR, prec))
+        J, _, _, g = G.objective_gradient(dev_v(0.5 * vstar))
+        hw = G.hessian_matvec(dev_v(w))
+        outs.append((J, host(g), host(hw)))
+        G.close()
+    for J, g, hw in outs[1:]:
+        assert J == outs[0][0]
+        assert np.array_equal(g, outs[0][1])
+        assert np.array_equal(hw, outs[0][2])
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+def test_handles_of_one_grid_share_the_tile_choice(nk, prec):
+    """The column-tile autotuner runs at handle creation and its choice is shared per grid
+    and precision, so a second handle reproduces the first one's results bit for bit."""
+    shape, nt = (64, 32), 6
+    mT, mR, vstar, w = smooth_inputs(shape, nt)
+    res = []
+    for _ in range(2):
+        G = nk.Problem(shape, nt, reg=2, beta=1e-3, precision=prec)
+        desc = G.describe()
+        assert desc["col_E"] in (4, 8) and "col_E" in desc["autotune"], desc
+        G.set_images(dev_t(mT, prec), dev_t(mR, prec))
+        J, _, _, g = G.objective_gradient(dev_v(0.5 * vstar))
+        res.append((desc["col_E"], J, host(g), host(G.hessian_matvec(dev_v(w)))))
+        G.close()
+    assert res[0][0] == res[1][0]
+    assert res[0][1] == res[1][1]
+    assert np.array_equal(res[0][2], res[1][2])
+    assert np.array_equal(res[0][3], res[1][3])
