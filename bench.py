@@ -26,6 +26,75 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+KERNEL_SYMBOLS = {"col_deriv": "k_col_w<{t}, {n}, {e}, 2>", "col_fwd": "k_col_w<{t}, {n}, {e}, 0>",
+                  "col_inv": "k_col_w<{t}, {n}, {e}, 1>"}
+COUNTERS = os.path.join(ROOT, "profiles", "col_deriv_512sq_fp32_hbm_counters.md")
+
+
+def source_digest() -> str:
+    """SHA-256 over the HIP sources; counter readings are only valid for the code they measured."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1408_6299_amd", "csrc")
+    for fn in sorted(os.listdir(d)):
+        if fn.endswith((".hpp", ".hip", ".h")):
+            h.update(fn.encode())
+            h.update(open(os.path.join(d, fn), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(symbol: str):
+    """HBM bytes per launch of `symbol` from the committed counter summary, or None when the
+    summary is missing, covers another kernel, or was taken on different sources."""
+    try:
+        text = open(COUNTERS).read()
+        block = text.split("```json", 1)[1].split("```", 1)[0]
+        rec = json.loads(block)
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec.get("source_sha256") != source_digest():
+        return None
+    k = rec.get("kernels", {}).get(symbol)
+    return None if k is None else k["traffic_bytes_per_launch"]
+
+
+def sleep_cycles_for(ms: float, torch) -> int:
+    """Cycles of torch's device spin kernel that take about `ms` milliseconds."""
+    cyc = 1_000_000
+    torch.cuda._sleep(cyc)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    torch.cuda._sleep(cyc)
+    e1.record()
+    torch.cuda.synchronize()
+    return max(1, int(cyc * ms / max(e0.elapsed_time(e1), 1e-3)))
+
+
+def kernel_pass(G, kernel, vt, out, reps, torch, cap=4096):
+    """Times every launch of `kernel` in `reps` eager matvecs. Each matvec's launches are
+    queued behind a device spin of a few milliseconds, so they run back to back as in a
+    graph replay instead of trickling in at the host's launch rate."""
+    cyc = sleep_cycles_for(8.0, torch)
+    G.timer_arm(kernel, capacity=cap)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        torch.cuda._sleep(cyc)
+        G.hessian_matvec(vt, out)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    launches, avg_ms, bytes_per = G.timer_read()
+    return {"name": kernel, "launches": launches, "avg_us": 1e3 * avg_ms, "bytes_per_launch": bytes_per,
+            "matvecs": reps, "seconds": secs}
+
+
+def roofline(kernel: str, symbol: str, rec: dict, traffic=None) -> dict:
+    ach = rec["bytes_per_launch"] / (rec["avg_us"] * 1e-6) / 1e9
+    return {"bound": "hbm", "kernel": kernel, "symbol": symbol, "launches": rec["launches"], "matvecs": rec["matvecs"],
+            "avg_us": rec["avg_us"], "bytes_per_launch": rec["bytes_per_launch"],
+            "timing": "HIP events stamped by each dispatch (hipExtLaunchKernelGGL) over eager matvecs of the "
+                      "same workload, each queued behind a device spin so its launches run back to back",
+            "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "traffic": traffic}
 
 
 def log(*a):
@@ -46,6 +115,106 @@ def timed_pcg_steps(prob, rhs, steps, torch):
     return time.perf_counter() - t0
 
 
+def batch_section(nk, synth, torch, reps):
+    """64 independent 2D pairs of uneven grid sizes (64^2..512^2), H1, beta 1e-2, nt = 16:
+    one graph-captured batched matvec versus the same items one after another (each a
+    graph replay of its own), and the FP64 batch."""
+    dev = torch.device("cuda:0")
+    specs = synth.batch_specs()
+    inputs = []
+    for i, sp in enumerate(specs):
+        mT, vstar = synth.make_inputs(sp)
+        gen = nk.Problem(sp.shape, sp.nt, 1, sp.reg, False, sp.beta, precision=64)
+        gen.set_images(torch.from_numpy(mT).to(dev), torch.zeros(sp.shape, dtype=torch.float64, device=dev))
+        mR = gen.forward(torch.from_numpy(vstar).to(dev)).cpu().numpy()
+        gen.close()
+        w = synth.bandlimited_velocity(sp.shape, 500 + i, 6, 0.05)
+        inputs.append((sp, mT, mR, w))
+    out = {"items": len(specs), "grids": {str(n): sum(1 for s in specs if s.shape[0] == n) for n in (64, 128, 256, 512)},
+           "nt": specs[0].nt}
+    pts = sum(int(np.prod(sp.shape)) for sp in specs)
+    for prec in (32, 64):
+        dt = torch.float32 if prec == 32 else torch.float64
+        probs, ws, outs = [], [], []
+        for sp, mT, mR, w in inputs:
+            G = nk.Problem(sp.shape, sp.nt, 1, sp.reg, False, sp.beta, precision=prec)
+            G.set_images(torch.from_numpy(mT).to(dev).to(dt), torch.from_numpy(mR).to(dev).to(dt))
+            G.objective_gradient(G.zeros_v())
+            probs.append(G)
+            ws.append(torch.from_numpy(w).to(dev))
+            outs.append(G.empty_v())
+        B = nk.Batch(probs)
+        for _ in range(2):
+            B.hessian_matvec(ws, outs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            B.hessian_matvec(ws, outs)
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - t0) / reps
+        r = {"batched_ms": 1e3 * tb, "item_matvecs_per_s": len(specs) / tb, "mpoints_per_s": pts * 1e-6 / tb}
+        if prec == 32:
+            for G, w, o in zip(probs, ws, outs):
+                G.hessian_matvec(w, o)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                for G, w, o in zip(probs, ws, outs):
+                    G.hessian_matvec(w, o)
+            torch.cuda.synchronize()
+            ts = (time.perf_counter() - t0) / reps
+            r["sequential_ms"] = 1e3 * ts
+            r["batched_speedup_vs_sequential"] = ts / tb
+        out[f"fp{prec}"] = r
+        log(f"batch FP{prec}: {r['batched_ms']:.3f} ms per batched matvec ({r['item_matvecs_per_s']:.0f} item-matvecs/s)"
+            + (f", sequential {r['sequential_ms']:.3f} ms" if prec == 32 else ""))
+        B.close()
+        for G in probs:
+            G.close()
+    out["fp32_batched_speedup_vs_fp64_batched"] = out["fp64"]["batched_ms"] / out["fp32"]["batched_ms"]
+    return out
+
+
+def cube_section(nk, synth, torch, reps, kernel):
+    """256^3, nt = 32, H2 + Stokes, beta 1e-3, stationary divergence-free velocity at CFL 0.1,
+    trajectory checkpointed every 8 steps: Hessian matvec time, FP32 and FP64."""
+    dev = torch.device("cuda:0")
+    spec = synth.CONFIGS["c4"]
+    shape, nt = spec.shape, spec.nt
+    mT, vstar = synth.make_inputs(spec)
+    w = synth.bandlimited_velocity(shape, 52, 6, 0.05, divfree=True)
+    gen = nk.Problem(shape, nt, 1, spec.reg, True, spec.beta, precision=64, checkpoint_every=spec.checkpoint_every)
+    gen.set_images(torch.from_numpy(mT).to(dev), torch.zeros(shape, dtype=torch.float64, device=dev))
+    mR = gen.forward(torch.from_numpy(vstar).to(dev))
+    gen.close()
+    out = {"grid": list(shape), "nt": nt, "checkpoint_every": spec.checkpoint_every}
+    for prec in (32, 64):
+        dt = torch.float32 if prec == 32 else torch.float64
+        G = nk.Problem(shape, nt, 1, spec.reg, True, spec.beta, precision=prec, checkpoint_every=spec.checkpoint_every)
+        G.set_images(torch.from_numpy(mT).to(dev).to(dt), mR.to(dt))
+        G.objective_gradient(G.zeros_v())
+        wt = torch.from_numpy(w).to(dev)
+        o = G.empty_v()
+        G.hessian_matvec(wt, o)
+        torch.cuda.synchronize()
+        n = reps if prec == 32 else max(1, reps // 2)
+        t0 = time.perf_counter()
+        for _ in range(n):
+            G.hessian_matvec(wt, o)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / n
+        out[f"fp{prec}"] = {"matvec_ms": 1e3 * t, "matvecs_per_s": 1.0 / t}
+        log(f"256^3 FP{prec}: {1e3 * t:.1f} ms per matvec")
+        if prec == 32:
+            k = kernel_pass(G, kernel, wt, o, 1, torch)
+            if k["launches"]:
+                sym = KERNEL_SYMBOLS.get(kernel, kernel).format(t="float", n=shape[-1], e=G.describe()["col_E"])
+                out["roofline"] = roofline(kernel, sym, k)
+        G.close()
+    out["fp32_speedup"] = out["fp64"]["matvec_ms"] / out["fp32"]["matvec_ms"]
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -56,6 +225,11 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-solve", action="store_true", help="skip the Newton time-to-solution runs")
     ap.add_argument("--cpu-matvecs", type=int, default=16, help="oracle matvecs in the CPU sample")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 run of the headline workload")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-pair batched workload")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration) and exit")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 256^3 workload")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -69,6 +243,16 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        # a copy of known size: its FETCH_SIZE / WRITE_SIZE readings scale the counters to bytes
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": 4 * n, "launches": 3}), flush=True)
+        return 0
     spec = synth.CONFIGS["c2lit"]
     shape, nt = spec.shape, spec.nt
     mT_h, vstar_h = synth.make_inputs(spec)
@@ -87,7 +271,7 @@ def main() -> int:
     gen.close()
 
     results = {}
-    for prec in (32, 64):
+    for prec in ((32,) if args.no_fp64 else (32, 64)):
         dt = torch.float32 if prec == 32 else torch.float64
         G = nk.Problem(shape, nt, 1, spec.reg, False, spec.beta, precision=prec)
         G.set_images(to(mT_h, dt), to(mR_h, dt))
@@ -101,12 +285,7 @@ def main() -> int:
         if prec == 32:
             # second timed region, same workload: HIP events around every launch of the
             # dominant kernel (the library launches eagerly while its timer is armed)
-            ksteps = max(5, steps // 4)
-            G.timer_arm(args.kernel, capacity=512 * ksteps)
-            ksecs = timed_pcg_steps(G, rhs, ksteps, torch)
-            launches, avg_ms, bytes_per = G.timer_read()
-            r["kernel"] = {"name": args.kernel, "launches": launches, "avg_us": 1e3 * avg_ms,
-                           "bytes_per_launch": bytes_per, "eager_ms_per_step": 1e3 * ksecs / ksteps}
+            r["kernel"] = kernel_pass(G, args.kernel, rhs, G.empty_v(), 20, torch)
         log(f"FP{prec}: {r['matvecs_per_s']:.1f} matvecs/s ({r['ms_per_step']:.3f} ms per PCG iteration)")
         if not args.no_solve:
             # time-to-solution: beta continuation 1e-1 -> 1e-4, warm-started, relative gradient 1e-3
@@ -146,21 +325,21 @@ def main() -> int:
         "config": {"workload": spec.name, "grid": list(shape), "nt": nt, "nc": 1, "reg": "H2",
                    "beta": spec.beta, "incompressible": False, "step": "one GN-PCG iteration (matvec-dominated)"},
         "launch": results[32]["launch"],
-        "fp64": {"matvecs_per_s": results[64]["matvecs_per_s"], "ms_per_step": results[64]["ms_per_step"],
-                 "fp32_speedup": results[32]["matvecs_per_s"] / results[64]["matvecs_per_s"]},
     }
+    if 64 in results:
+        out["fp64"] = {"matvecs_per_s": results[64]["matvecs_per_s"], "ms_per_step": results[64]["ms_per_step"],
+                       "fp32_speedup": results[32]["matvecs_per_s"] / results[64]["matvecs_per_s"]}
     if not args.no_solve:
-        out["newton_fp32"] = results[32]["newton"]
-        out["newton_fp64"] = results[64]["newton"]
+        for prec in results:
+            out[f"newton_fp{prec}"] = results[prec]["newton"]
     k = results[32]["kernel"]
     if k["launches"] > 0 and k["avg_us"] > 0:
-        ach = k["bytes_per_launch"] / (k["avg_us"] * 1e-6) / 1e9
-        out["roofline"] = {"bound": "hbm", "kernel": k["name"], "launches": k["launches"],
-                           "avg_us": k["avg_us"], "bytes_per_launch": k["bytes_per_launch"],
-                           "timing": "HIP events around each launch, eager pass of the same workload "
-                                     f"({k['eager_ms_per_step']:.3f} ms per step without graph replay)",
-                           "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                           "traffic": None}
+        sym = KERNEL_SYMBOLS.get(k["name"], k["name"]).format(t="float", n=shape[-1], e=results[32]["launch"]["col_E"])
+        out["roofline"] = roofline(k["name"], sym, k, measured_traffic(sym))
+    if not args.no_batch:
+        out["batch"] = batch_section(nk, synth, torch, reps=10)
+    if not args.no_3d:
+        out["cube_256"] = cube_section(nk, synth, torch, reps=4, kernel=args.kernel)
     if not args.no_cpu:
         from oracle import reduced as ord_
         from oracle import spectral as osp

@@ -9,6 +9,8 @@
 
 #include "common.hpp"
 #include "kernels.hpp"
+#include <hip/hip_ext.h>
+
 #include "kernels_wave.hpp"
 
 namespace nk {
@@ -88,9 +90,12 @@ struct KernelTimer {
     bytes = 0.0;
   }
   bool want(int id) const { return id == armed && 2 * (used + 1) <= (int)ev.size(); }
-  void before(hipStream_t s) { NK_HIP(hipEventRecord(ev[2 * used], s)); }
-  void after(hipStream_t s, double b) {
-    NK_HIP(hipEventRecord(ev[2 * used + 1], s));
+  // Events of the next timed launch. They are handed to hipExtLaunchKernelGGL,
+  // which stamps them with the dispatch's own start and end, so the elapsed
+  // time is the kernel's execution time without the queue's dispatch latency.
+  hipEvent_t start_event() const { return ev[2 * used]; }
+  hipEvent_t stop_event() const { return ev[2 * used + 1]; }
+  void done(double b) {
     ++used;
     bytes += b;
   }
@@ -118,6 +123,16 @@ class Spectral {
   // elements per lane of the column transforms: 8 (one wave per 512-point column)
   // or 4 (two waves per 512-point column); chosen by the matvec autotuner
   int colE = 8;
+
+  // Launches a kernel on the handle's stream; a timed launch carries the timer's events.
+  template <typename... KArgs, typename... Args>
+  void launch(void (*k)(KArgs...), dim3 grid, dim3 block, bool timed, Args... args) {
+    if (timed)
+      hipExtLaunchKernelGGL(k, grid, block, 0, s, timer->start_event(), timer->stop_event(), 0, args...);
+    else
+      hipLaunchKernelGGL(k, grid, block, 0, s, args...);
+    NK_LAUNCHED();
+  }
 
   Spectral() = default;
   Spectral(const Grid& grid, hipStream_t stream) : g(grid), s(stream) {
@@ -280,20 +295,19 @@ class Spectral {
     dim3 grid((unsigned)((inner + SPW - 1) / SPW), (unsigned)outer, (unsigned)nf);
     const int twb = g.lmax / N;
     const bool timed = timer && timer->want(kColIdBase + mode);
-    if (timed) timer->before(s);
     switch (mode) {
       case COL_FWD:
-        hipLaunchKernelGGL((k_col_w<R, N, E, COL_FWD>), grid, dim3(CS::NT), 0, s, in, add, out, a, scale, tw, twb);
+        launch(k_col_w<R, N, E, COL_FWD>, grid, dim3(CS::NT), timed, in, add, out, a, scale, (const cplx<R>*)tw, twb);
         break;
       case COL_INV:
-        hipLaunchKernelGGL((k_col_w<R, N, E, COL_INV>), grid, dim3(CS::NT), 0, s, in, add, out, a, scale, tw, twb);
+        launch(k_col_w<R, N, E, COL_INV>, grid, dim3(CS::NT), timed, in, add, out, a, scale, (const cplx<R>*)tw, twb);
         break;
       default:
-        hipLaunchKernelGGL((k_col_w<R, N, E, COL_DERIV>), grid, dim3(CS::NT), 0, s, in, add, out, a, scale, tw, twb);
+        launch(k_col_w<R, N, E, COL_DERIV>, grid, dim3(CS::NT), timed, in, add, out, a, scale, (const cplx<R>*)tw,
+               twb);
         break;
     }
-    NK_LAUNCHED();
-    if (timed) timer->after(s, (double)nf * g.nspec * sizeof(cplx<R>) * (add ? 3 : 2));
+    if (timed) timer->done((double)nf * g.nspec * sizeof(cplx<R>) * (add ? 3 : 2));
   }
 
   template <int KIND, int D>
@@ -316,15 +330,13 @@ class Spectral {
     constexpr int SPW = 64 / WavePlan<L / 2, E>::LS;
     dim3 grid((unsigned)((g.rows + SPW - 1) / SPW), (unsigned)nf);
     const bool timed = timer && timer->want(KIND);
-    if (timed) timer->before(s);
     constexpr bool uses_nc = (KIND == ST_FWD1 || KIND == ST_FWD2 || KIND == ST_INC1 || KIND == ST_INC2 ||
                               KIND == ST_ADJINIT || KIND == ST_ADJ1 || KIND == ST_ADJ2);
     if (!uses_nc || a.nc <= 1)
-      hipLaunchKernelGGL((k_row_w<R, L, E, KIND, D, true>), grid, dim3(64), 0, s, a, tw, g.lmax);
+      launch(k_row_w<R, L, E, KIND, D, true>, grid, dim3(64), timed, a, (const cplx<R>*)tw, g.lmax);
     else if constexpr (uses_nc)
-      hipLaunchKernelGGL((k_row_w<R, L, E, KIND, D, false>), grid, dim3(64), 0, s, a, tw, g.lmax);
-    NK_LAUNCHED();
-    if (timed) timer->after(s, (double)nf * stage_fields<KIND>(a, D) * g.npts * sizeof(R));
+      launch(k_row_w<R, L, E, KIND, D, false>, grid, dim3(64), timed, a, (const cplx<R>*)tw, g.lmax);
+    if (timed) timer->done((double)nf * stage_fields<KIND>(a, D) * g.npts * sizeof(R));
   }
 
   // Scalar fields (real field or row spectrum, same size) one launch of a row
