@@ -197,8 +197,9 @@ int nkreg_dot(nkreg_problem* p, const void* d_a, const void* d_b, long long cnt,
  * (row stages: 0 state stage 1, 1 state stage 2, 2 incremental stage 1,
  * 3 incremental stage 2, 4 adjoint start, 5 adjoint stage 1, 6 adjoint stage 2,
  * 7 R2C, 8 C2R, 9 gradient, 10 divergence; column passes: 20 forward, 21 inverse,
- * 22 derivative) and records HIP events on the handle's stream around each of
- * its next `capacity` launches. nkreg_timer_read synchronises, returns the
+ * 22 derivative) and times each of its next `capacity` launches with a pair of
+ * HIP events that the dispatch itself stamps (hipExtLaunchKernelGGL on the
+ * handle's internal stream). nkreg_timer_read synchronises, returns the
  * number of recorded launches, their average duration in milliseconds and the
  * average algorithmic bytes per launch (fields read plus fields written), and
  * disarms the timer. While the timer is armed, Hessian matvecs launch eagerly

@@ -269,7 +269,7 @@ class Problem:
                "r2c": 7, "c2r": 8, "grad": 9, "div": 10, "col_fwd": 20, "col_inv": 21, "col_deriv": 22}
 
     def timer_arm(self, kernel: str, capacity: int = 4096) -> None:
-        """Record HIP events around each of the next ``capacity`` launches of ``kernel``."""
+        """Time each of the next ``capacity`` launches of ``kernel`` with dispatch-stamped HIP events."""
         check(self.lib.nkreg_timer_arm(self._h, c_int(self.KERNELS[kernel]), c_int(capacity)), "nkreg_timer_arm")
 
     def timer_read(self) -> Tuple[int, float, float]:
