@@ -26,8 +26,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
-KERNEL_SYMBOLS = {"col_deriv": "k_col_w<{t}, {n}, {e}, 2>", "col_fwd": "k_col_w<{t}, {n}, {e}, 0>",
-                  "col_inv": "k_col_w<{t}, {n}, {e}, 1>"}
 COUNTERS = os.path.join(ROOT, "profiles", "col_deriv_512sq_fp32_hbm_counters.md")
 
 
@@ -85,6 +83,14 @@ def kernel_pass(G, kernel, vt, out, reps, torch, cap=4096):
     launches, avg_ms, bytes_per = G.timer_read()
     return {"name": kernel, "launches": launches, "avg_us": 1e3 * avg_ms, "bytes_per_launch": bytes_per,
             "matvecs": reps, "seconds": secs}
+
+
+def symbol_of(kernel: str, launch: dict) -> str:
+    """Kernel symbol of a timed kernel, as rocprof names it (column passes: the variant the
+    handle's autotuner chose, from its description; the first axis's symbol in 3D)."""
+    if kernel == "col_deriv":
+        return launch["col_deriv_symbols"][0]
+    return kernel
 
 
 def roofline(kernel: str, symbol: str, rec: dict, traffic=None) -> dict:
@@ -208,7 +214,7 @@ def cube_section(nk, synth, torch, reps, kernel):
         if prec == 32:
             k = kernel_pass(G, kernel, wt, o, 1, torch)
             if k["launches"]:
-                sym = KERNEL_SYMBOLS.get(kernel, kernel).format(t="float", n=shape[-1], e=G.describe()["col_E"])
+                sym = symbol_of(kernel, G.describe())
                 out["roofline"] = roofline(kernel, sym, k)
         G.close()
     out["fp32_speedup"] = out["fp64"]["matvec_ms"] / out["fp32"]["matvec_ms"]
@@ -334,7 +340,7 @@ def main() -> int:
             out[f"newton_fp{prec}"] = results[prec]["newton"]
     k = results[32]["kernel"]
     if k["launches"] > 0 and k["avg_us"] > 0:
-        sym = KERNEL_SYMBOLS.get(k["name"], k["name"]).format(t="float", n=shape[-1], e=results[32]["launch"]["col_E"])
+        sym = symbol_of(k["name"], results[32]["launch"])
         out["roofline"] = roofline(k["name"], sym, k, measured_traffic(sym))
     if not args.no_batch:
         out["batch"] = batch_section(nk, synth, torch, reps=10)

@@ -25,8 +25,10 @@ enum ColMode { COL_FWD = 0, COL_INV = 1, COL_DERIV = 2 };
 
 struct ColArgs {
   int inner;        // complex elements between consecutive x
-  int ctile;        // columns per workgroup
+  int ctile;        // columns per workgroup (per tile for the tiled pass)
   long long field;  // complex elements between fields (blockIdx.z)
+  int ntx;          // tiled pass: tiles across the inner extent
+  int ntiles;       // tiled pass: tiles per field (ntx * outer)
 };
 
 // ---------------------------------------------------------------------------

@@ -62,7 +62,7 @@ __global__ __launch_bounds__(64) void k_row_w(StageArgs<R> a, const cplx<R>* __r
   using P = WavePlan<M, E>;
   constexpr int LS = P::LS;
   constexpr int SPW = 64 / LS;
-  constexpr int PADM = padded<M>(M);
+  constexpr int PADM = padded_e<E>(M);
   constexpr int H = E / 2;
   using SH = StageShape<KIND, D>;
   constexpr int KIN = SH::KIN, KOUT = SH::KOUT, KMAX = SH::KMAX;
@@ -180,15 +180,15 @@ __global__ __launch_bounds__(64) void k_row_w(StageArgs<R> a, const cplx<R>* __r
           } else {
             c2r_pair(xa[t], xb[t], wq[t], za, zb);
           }
-          S[k * PADM + pad32(qa[t])] = za;
-          S[k * PADM + pad32(qb[t])] = zb;
+          S[k * PADM + pad_e<E>(qa[t])] = za;
+          S[k * PADM + pad_e<E>(qb[t])] = zb;
         }
       }
       wave_lds_sync();
 #pragma unroll
       for (int k = 0; k < KIN; ++k)
 #pragma unroll
-        for (int e = 0; e < E; ++e) A[k][e] = S[k * PADM + pad32(j + LS * e)];
+        for (int e = 0; e < E; ++e) A[k][e] = S[k * PADM + pad_e<E>(j + LS * e)];
       wave_lds_sync();
 #pragma unroll
       for (int k = 0; k < KIN; ++k) wave_fft<R, M, E, true>(A[k], j, S + k * PADM, T);
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(64) void k_row_w(StageArgs<R> a, const cplx<R>* __r
 #pragma unroll
     for (int k = 0; k < KOUT; ++k)
 #pragma unroll
-      for (int e = 0; e < E; ++e) S[k * PADM + pad32(j + LS * e)] = O[k][e];
+      for (int e = 0; e < E; ++e) S[k * PADM + pad_e<E>(j + LS * e)] = O[k][e];
     wave_lds_sync();
     const long long fo = (long long)blockIdx.y * a.fstride_out;
 #pragma unroll
@@ -301,8 +301,8 @@ __global__ __launch_bounds__(64) void k_row_w(StageArgs<R> a, const cplx<R>* __r
       const bool ik = ADJOUT && D > 1 && k == D - 1;
 #pragma unroll
       for (int t = 0; t < H; ++t) {
-        const cplx<R> za = S[k * PADM + pad32(qa[t])];
-        const cplx<R> zb = S[k * PADM + pad32(qb[t])];
+        const cplx<R> za = S[k * PADM + pad_e<E>(qa[t])];
+        const cplx<R> zb = S[k * PADM + pad_e<E>(qb[t])];
         cplx<R> xa, xb;
         if (j == 0 && t == 0) {
           xa = {za.x + za.y, za.x - za.y};
@@ -340,7 +340,7 @@ __global__ __launch_bounds__((ColShape<N, E>::NT)) void k_col_w(const cplx<R>* i
   constexpr int LS = CS::LS;
   constexpr int SPW = CS::SPW;
   constexpr bool BLK = CS::BLOCK;
-  constexpr int PADN = padded<N>(N);
+  constexpr int PADN = padded_e<E>(N);
   __shared__ cplx<R> lds[SPW * PADN];
   const int lane = threadIdx.x;
   const int c = lane % SPW, j = lane / SPW;
@@ -380,6 +380,94 @@ __global__ __launch_bounds__((ColShape<N, E>::NT)) void k_col_w(const cplx<R>* i
   if (live) {
 #pragma unroll
     for (int e = 0; e < E; ++e) out[base + (long long)(j + LS * e) * a.inner] = v[e];
+  }
+}
+
+// Tiled column pass for long strided axes. A workgroup owns CT adjacent
+// columns (CT * sizeof(cplx) = 64 or 128 bytes, a whole cache line per row):
+// it stages the N x CT tile through LDS with row-coalesced loads, transforms
+// the columns with the register wave FFT (E = 8), using each column's own tile
+// slots as its exchange scratch, and writes the tile back row-coalesced.
+// Column passes of the plain kernel touch one 8- or 16-byte element per row
+// and rely on neighbouring workgroups to use the rest of each line; here every
+// byte a row load fetches is used by the same workgroup. The tile is stored
+// column by column (element r of column c at c * CPITCH + r + r / 8) with
+// CPITCH = 2 mod 32, which keeps both the row-wise staging and the column
+// transforms free of LDS bank conflicts. One tile per workgroup: the small
+// register footprint lets four workgroups share a compute unit, which hides
+// the staging latency better than prefetching the next tile would.
+template <typename R, int N, int CT>
+struct TileShape {
+  static constexpr int E = 8;
+  static constexpr int LS = WavePlan<N, E>::LS;   // lanes per column
+  static_assert(LS <= 64, "a column fits one wavefront");
+  static constexpr int SPW = 64 / LS;             // columns per wavefront per round
+  static_assert(SPW <= CT, "a wavefront's columns fit in the tile");
+  static constexpr int W = (CT / SPW) < 4 ? (CT / SPW) : 4;   // wavefronts per workgroup
+  static constexpr int NT = 64 * W;
+  static constexpr int PER_ROUND = W * SPW;       // divides CT: every lane owns a column
+  static constexpr int ROUNDS = CT / PER_ROUND;
+  static constexpr int CPITCH = ((padded_e<E>(N) + 29) / 32) * 32 + 2;   // >= padded length, = 2 mod 32
+  static constexpr int ROWS_PER_STEP = NT / CT;   // tile rows per coalesced load step
+  static_assert(CT % PER_ROUND == 0 && NT % CT == 0 && N % (NT / CT) == 0, "tile shape");
+  static_assert(CPITCH >= padded_e<E>(N) && CPITCH % 32 == 2, "tile pitch");
+};
+
+template <typename R, int N, int CT, int MODE>
+__global__ __launch_bounds__((TileShape<R, N, CT>::NT)) void k_col_t(const cplx<R>* in, const cplx<R>* add,
+                                                                     cplx<R>* out, ColArgs a, R scale,
+                                                                     const cplx<R>* __restrict__ tw, int twb) {
+  using TS = TileShape<R, N, CT>;
+  constexpr int E = TS::E, LS = TS::LS, SPW = TS::SPW, CP = TS::CPITCH;
+  constexpr int RPS = TS::ROWS_PER_STEP;
+  constexpr int K = N / RPS;                      // tile elements each thread moves
+  __shared__ cplx<R> tile[CT * CP];
+  const int t = threadIdx.x;
+  const int tc0 = t % CT, r0 = t / CT;
+  const int w = t >> 6, lane = t & 63;
+  const int cl = lane / LS, j = lane % LS;        // a half-wavefront's exchanges stay in one column
+  // tile (x, y) covers columns x * CT .. x * CT + CT - 1 of outer slice y
+  const int x = (int)blockIdx.x % a.ntx, y = (int)blockIdx.x / a.ntx;
+  const long long base = (long long)blockIdx.z * a.field + (long long)y * N * a.inner + (long long)x * CT;
+  // row-coalesced load of the N x CT tile
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    tile[tc0 * CP + pad_e<E>(r0 + k * RPS)] = in[base + (long long)(r0 + k * RPS) * a.inner + tc0];
+  WaveTwiddles<R, N, E> T;
+  T.load(j, tw, twb);
+  __syncthreads();
+#pragma unroll 1
+  for (int rd = 0; rd < TS::ROUNDS; ++rd) {
+    cplx<R>* col = tile + (rd * TS::PER_ROUND + w * SPW + cl) * CP;
+    cplx<R> v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = col[pad_e<E>(j + LS * e)];
+    // the wavefront's reads of its columns complete before exchanges overwrite them
+    wave_lds_sync();
+    if (MODE == COL_INV) {
+      wave_fft<R, N, E, true>(v, j, col, T);
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = cscale(v[e], scale);
+    } else {
+      wave_fft<R, N, E, false>(v, j, col, T);
+    }
+    if (MODE == COL_DERIV) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = cmul_i(v[e], R(deriv_wavenumber(j + LS * e, N)) * scale);
+      wave_fft<R, N, E, true>(v, j, col, T);
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) col[pad_e<E>(j + LS * e)] = v[e];
+  }
+  __syncthreads();
+  const bool has_add = (MODE == COL_DERIV) && add != nullptr;
+#pragma unroll 4
+  for (int k = 0; k < K; ++k) {
+    const int r = r0 + k * RPS;
+    const long long gi = base + (long long)r * a.inner + tc0;
+    cplx<R> v = tile[tc0 * CP + pad_e<E>(r)];
+    if (has_add) v = cadd(v, add[gi]);
+    out[gi] = v;
   }
 }
 

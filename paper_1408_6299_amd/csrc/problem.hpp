@@ -580,18 +580,19 @@ class ProblemT final : public ProblemBase {
   // handle of the same grid and precision in the process, so they all compute
   // bit-identical results. NKREG_COL_E in the environment fixes the choice.
   static constexpr int kTuneReps = 16;
+  static std::string col_variant_name(int ce) { return ce == 0 ? "col=tiled" : "col_E=" + std::to_string(ce); }
   std::string tuning;
   std::array<int, 4> tune_key() const { return {g.n[0], g.n[1], g.n[2], kF64 ? 64 : 32}; }
   void tune_columns() {
     if (std::getenv("NKREG_COL_E")) {
-      tuning = "col_E=" + std::to_string(sp.colE) + " (fixed)";
+      tuning = col_variant_name(sp.colE) + " (fixed)";
       return;
     }
     TuneTable& tt = tune_table();
     std::lock_guard<std::mutex> lk(tt.m);
     if (auto it = tt.col_e.find(tune_key()); it != tt.col_e.end()) {
       sp.colE = it->second;
-      tuning = "col_E=" + std::to_string(sp.colE) + " (chosen earlier in this process for this grid)";
+      tuning = col_variant_name(sp.colE) + " (chosen earlier in this process for this grid)";
       return;
     }
     const long long ns = g.nspec;
@@ -603,7 +604,9 @@ class ProblemT final : public ProblemBase {
     NK_HIP(hipEventCreate(&e1));
     float best = 1e30f;
     int bestE = sp.colE;
-    for (int ce : {8, 4}) {
+    std::vector<int> cands = {8, 4};
+    if (sp.any_tiled_pass()) cands.push_back(0);
+    for (int ce : cands) {
       sp.colE = ce;
       hipGraph_t graph = nullptr;
       NK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -625,20 +628,26 @@ class ProblemT final : public ProblemBase {
       NK_HIP(hipEventElapsedTime(&ms, e0, e1));
       (void)hipGraphExecDestroy(ex);
       const float us_per_pass = 1e3f * ms / (3.0f * kTuneReps * (g.d == 2 ? 2 : 4));
-      tuning += (tuning.empty() ? "" : ", ") + std::string("col_E=") + std::to_string(ce) + ": " +
-                std::to_string(us_per_pass) + " us/pass";
+      tuning += (tuning.empty() ? "" : ", ") + col_variant_name(ce) + ": " + std::to_string(us_per_pass) + " us/pass";
       if (ms < best) { best = ms; bestE = ce; }
     }
     sp.colE = bestE;
     tt.col_e[tune_key()] = bestE;
-    tuning += "; chose col_E=" + std::to_string(bestE);
+    tuning += "; chose " + col_variant_name(bestE);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+  }
+  std::string col_symbols() const {
+    std::string out;
+    for (int axis = g.d - 2; axis >= 0; --axis)
+      out += (out.empty() ? "\"" : ", \"") + sp.col_deriv_symbol(axis) + "\"";
+    return out;
   }
   std::string describe() override {
     return std::string("{\"transport_precision\": ") + (kF64 ? "64" : "32") + ", \"graphs\": " +
            (use_graphs ? "true" : "false") + ", \"row_E\": " + std::to_string(kRowE) + ", \"col_E\": " +
-           std::to_string(sp.colE) + ", \"autotune\": \"" + tuning + "\"}";
+           std::to_string(sp.colE) + ", \"col_deriv_symbols\": [" + col_symbols() + "], \"autotune\": \"" + tuning +
+           "\"}";
   }
 
   // One Gauss-Newton matvec as a sequence of launches on the internal stream.

@@ -120,8 +120,10 @@ class Spectral {
   hipStream_t s = nullptr;
   cplx<R>* tw = nullptr;  // exp(-2 pi i m / lmax), m < lmax
   KernelTimer* timer = nullptr;
-  // elements per lane of the column transforms: 8 (one wave per 512-point column)
-  // or 4 (two waves per 512-point column); chosen by the matvec autotuner
+  // Column-pass variant, chosen by the autotuner: 8 or 4 = one workgroup per
+  // column group with that many complex elements per lane (8: one wavefront per
+  // 512-point column, 4: two); 0 = tiled through LDS (k_col_t) wherever the
+  // axis is long enough and the columns split into whole tiles, else 8.
   int colE = 8;
 
   // Launches a kernel on the handle's stream; a timed launch carries the timer's events.
@@ -136,7 +138,10 @@ class Spectral {
 
   Spectral() = default;
   Spectral(const Grid& grid, hipStream_t stream) : g(grid), s(stream) {
-    if (const char* ce = std::getenv("NKREG_COL_E")) colE = std::atoi(ce) == 4 ? 4 : 8;
+    if (const char* ce = std::getenv("NKREG_COL_E")) {
+      const int v = std::atoi(ce);
+      colE = (std::string(ce) == "tiled" || v == 0) ? 0 : (v == 4 ? 4 : 8);
+    }
     std::vector<cplx<R>> h(g.lmax);
     for (int m = 0; m < g.lmax; ++m) {
       const double a = -2.0 * M_PI * (double)m / (double)g.lmax;
@@ -153,13 +158,48 @@ class Spectral {
 
   // ---- column passes ----
   // axis 0 = x1 for any d; axis 1 = x2 for d = 3.
-  void col(int mode, int axis, const cplx<R>* in, const cplx<R>* add, cplx<R>* out, int nf, R scale) {
-    int N, outer;
-    long long inner;
+  // Length, outer count and stride (complex elements) of the columns along an axis.
+  void col_geometry(int axis, int& N, int& outer, long long& inner) const {
     const int M = g.L / 2;
     if (g.d == 2) { N = g.n[0]; outer = 1; inner = M; }
     else if (axis == 0) { N = g.n[0]; outer = 1; inner = (long long)g.n[1] * M; }
     else { N = g.n[1]; outer = g.n[0]; inner = M; }
+  }
+  // Columns per tile of the tiled pass: one cache line (128 bytes) of each row,
+  // halved until the tile data stays within 40 KiB of LDS, at least 4.
+  static constexpr int tile_ct_n(int N) {
+    int ct = 128 / (int)sizeof(cplx<R>);
+    while (ct > 4 && (long long)N * ct * (long long)sizeof(cplx<R>) > 40960) ct /= 2;
+    return ct;
+  }
+  template <int N>
+  static constexpr int tile_ct() { return tile_ct_n(N); }
+  static bool tile_ok(int N, long long inner) { return N >= 64 && inner % tile_ct_n(N) == 0; }
+  // True if the tiled variant applies to at least one column pass of this grid.
+  bool any_tiled_pass() const {
+    for (int axis = 0; axis < g.d - 1; ++axis) {
+      int N, outer;
+      long long inner;
+      col_geometry(axis, N, outer, inner);
+      if (tile_ok(N, inner)) return true;
+    }
+    return false;
+  }
+  // Kernel symbol of the derivative pass along an axis with the current variant.
+  std::string col_deriv_symbol(int axis) const {
+    int N, outer;
+    long long inner;
+    col_geometry(axis, N, outer, inner);
+    const std::string t = sizeof(R) == 4 ? "float" : "double";
+    if (colE == 0 && tile_ok(N, inner))
+      return "k_col_t<" + t + ", " + std::to_string(N) + ", " + std::to_string(tile_ct_n(N)) + ", 2>";
+    return "k_col_w<" + t + ", " + std::to_string(N) + ", " + std::to_string(colE == 4 ? 4 : 8) + ", 2>";
+  }
+
+  void col(int mode, int axis, const cplx<R>* in, const cplx<R>* add, cplx<R>* out, int nf, R scale) {
+    int N, outer;
+    long long inner;
+    col_geometry(axis, N, outer, inner);
     switch (N) {
       case 8: col_n<8>(mode, in, add, out, nf, scale, outer, inner); break;
       case 16: col_n<16>(mode, in, add, out, nf, scale, outer, inner); break;
@@ -280,15 +320,43 @@ class Spectral {
   template <int N>
   void col_n(int mode, const cplx<R>* in, const cplx<R>* add, cplx<R>* out, int nf, R scale, int outer,
              long long inner) {
+    if constexpr (N >= 64) {
+      if (colE == 0 && tile_ok(N, inner)) {
+        col_tiled<N>(mode, in, add, out, nf, scale, outer, inner);
+        return;
+      }
+    }
     if (colE == 4 && N >= 8) col_ne<N, 4>(mode, in, add, out, nf, scale, outer, inner);
     else col_ne<N, 8>(mode, in, add, out, nf, scale, outer, inner);
+  }
+  template <int N>
+  void col_tiled(int mode, const cplx<R>* in, const cplx<R>* add, cplx<R>* out, int nf, R scale, int outer,
+                 long long inner) {
+    constexpr int CT = tile_ct<N>();
+    using TS = TileShape<R, N, CT>;
+    ColArgs a{};
+    a.inner = (int)inner;
+    a.ctile = CT;
+    a.field = g.nspec;
+    a.ntx = (int)(inner / CT);
+    a.ntiles = a.ntx * outer;
+    dim3 grid((unsigned)a.ntiles, 1u, (unsigned)nf);
+    const int twb = g.lmax / N;
+    const bool timed = timer && timer->want(kColIdBase + mode);
+    const cplx<R>* twc = tw;
+    switch (mode) {
+      case COL_FWD: launch(k_col_t<R, N, CT, COL_FWD>, grid, dim3(TileShape<R, N, CT>::NT), timed, in, add, out, a, scale, twc, twb); break;
+      case COL_INV: launch(k_col_t<R, N, CT, COL_INV>, grid, dim3(TileShape<R, N, CT>::NT), timed, in, add, out, a, scale, twc, twb); break;
+      default: launch(k_col_t<R, N, CT, COL_DERIV>, grid, dim3(TileShape<R, N, CT>::NT), timed, in, add, out, a, scale, twc, twb); break;
+    }
+    if (timed) timer->done((double)nf * g.nspec * sizeof(cplx<R>) * (add ? 3 : 2));
   }
   template <int N, int E>
   void col_ne(int mode, const cplx<R>* in, const cplx<R>* add, cplx<R>* out, int nf, R scale, int outer,
               long long inner) {
     using CS = ColShape<N, E>;
     constexpr int SPW = CS::SPW;
-    ColArgs a;
+    ColArgs a{};
     a.inner = (int)inner;
     a.ctile = SPW;
     a.field = g.nspec;

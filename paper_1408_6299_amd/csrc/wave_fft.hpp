@@ -130,10 +130,14 @@ struct WaveTwiddles {
   }
 };
 
-// Scratch layout of a sequence: element i at s[i + i / 32] (one pad slot per 32).
-__device__ __forceinline__ int pad32(int i) { return i + (i >> 5); }
-template <int M>
-constexpr int padded(int m) { return m + m / 32 + 1; }
+// Scratch layout of a sequence: element i at s[i + i / E] (one pad slot per E
+// elements). The first Stockham pass writes each lane's E outputs at unit
+// stride, i.e. lanes E elements apart; the pad spreads those lanes over all
+// LDS banks (and keeps unit-stride accesses conflict-free).
+template <int E>
+__device__ __forceinline__ int pad_e(int i) { return i + i / E; }
+template <int E>
+constexpr int padded_e(int m) { return m + m / E + 1; }
 
 // BLOCK = true when a sequence spans several wavefronts of the workgroup
 // (M / E > 64 lanes): exchanges then synchronise the whole workgroup.
@@ -193,11 +197,11 @@ __device__ __forceinline__ void wave_fft(cplx<R> (&a)[E], int j, cplx<R>* s, con
         const int kk = k % Ns;
         const int base = (k - kk) * RR + kk;
 #pragma unroll
-        for (int r = 0; r < RR; ++r) s[pad32(base + r * Ns)] = a[b + r * BPL];
+        for (int r = 0; r < RR; ++r) s[pad_e<E>(base + r * Ns)] = a[b + r * BPL];
       }
       if (BLOCK) __syncthreads(); else wave_lds_sync();
 #pragma unroll
-      for (int e = 0; e < E; ++e) a[e] = s[pad32(j + LS * e)];
+      for (int e = 0; e < E; ++e) a[e] = s[pad_e<E>(j + LS * e)];
       if (BLOCK) __syncthreads(); else wave_lds_sync();
     }
   }

@@ -312,3 +312,40 @@ def test_handles_of_one_grid_share_the_tile_choice(nk, prec):
     assert res[0][1] == res[1][1]
     assert np.array_equal(res[0][2], res[1][2])
     assert np.array_equal(res[0][3], res[1][3])
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("variant", ["8", "4", "tiled"])
+@pytest.mark.parametrize("shape,nt,gamma", [((64, 128), 6, 0), ((64, 32, 64), 4, 1), ((128, 64, 32), 3, 0)])
+def test_column_variants_match_oracle(nk, monkeypatch, shape, nt, gamma, variant, prec):
+    """Each column-pass variant the autotuner can pick (8 or 4 complex per lane, or the
+    LDS-tiled pass) gives the oracle's gradient and GN matvec, in 2D and 3D, with the tiled
+    pass used on every axis long enough for it."""
+    monkeypatch.setenv("NKREG_COL_E", variant)
+    mT, mR, vstar, w = smooth_inputs(shape, nt, divfree=bool(gamma))
+    P = ord_.Problem(mT, mR, nt, 1, 2, gamma, 1e-3)
+    S = ord_.objective_gradient(P, 0.5 * vstar)
+    Hw = ord_.hessian_matvec(P, S, w)
+    G = nk.Problem(shape, nt, reg=2, incompressible=bool(gamma), beta=1e-3, precision=prec)
+    syms = G.describe()["col_deriv_symbols"]
+    if variant == "tiled":
+        # axes of at least 64 points take the tiled pass, shorter ones the 8-per-lane pass
+        lengths = [shape[0]] if len(shape) == 2 else [shape[1], shape[0]]
+        for n_ax, sym in zip(lengths, syms):
+            assert sym.startswith("k_col_t<" if n_ax >= 64 else "k_col_w<"), syms
+    else:
+        assert all(s.startswith("k_col_w<") and s.endswith(f", {variant}, 2>") for s in syms), syms
+    G.set_images(dev_t(mT, prec), dev_t(mR, prec))
+    _, _, _, g = G.objective_gradient(dev_v(0.5 * vstar))
+    hw = host(G.hessian_matvec(dev_v(w)))
+    tol = TOL[prec]
+    assert rel_l2(host(g), S.g) < (tol if prec == 64 else 1e-4)
+    assert rel_l2(hw, Hw) < tol
+    # spectral gradient and divergence of a smooth field go through the same passes
+    u = synth.smooth_image(shape, 9, 0.6 * min(shape) ** 2 / 16.0)
+    if prec == 32:
+        u = u.astype(np.float32).astype(np.float64)   # the oracle sees the field the kernel sees
+    gu = host(G.gradient(dev_t(u, prec)))
+    assert rel_inf(gu, osp.grad(u)) < (1e-12 if prec == 64 else 2e-5)
+    assert rel_l2(gu, osp.grad(u)) < (1e-12 if prec == 64 else 1e-5)
+    G.close()
