@@ -123,8 +123,9 @@ def timed_pcg_steps(prob, rhs, steps, torch):
 
 def batch_section(nk, synth, torch, reps):
     """64 independent 2D pairs of uneven grid sizes (64^2..512^2), H1, beta 1e-2, nt = 16:
-    one graph-captured batched matvec versus the same items one after another (each a
-    graph replay of its own), and the FP64 batch."""
+    one graph-captured batched matvec (items of one grid size share every kernel launch)
+    versus the same items one after another (each a graph replay of its own), and the
+    FP64 batch."""
     dev = torch.device("cuda:0")
     specs = synth.batch_specs()
     inputs = []
@@ -153,6 +154,7 @@ def batch_section(nk, synth, torch, reps):
         for _ in range(2):
             B.hessian_matvec(ws, outs)
         torch.cuda.synchronize()
+        out["groups"] = B.groups()
         t0 = time.perf_counter()
         for _ in range(reps):
             B.hessian_matvec(ws, outs)

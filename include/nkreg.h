@@ -209,12 +209,18 @@ int nkreg_timer_read(nkreg_problem* p, int* launches, double* avg_ms, double* by
 
 /* Batched Gauss-Newton matvecs over independent problems of uneven sizes
  * (each a handle with a cached state). One call applies H_i to vt_i for every
- * item i as a single HIP-graph launch whose independent branches are the items'
- * matvecs on their own streams, so small items run concurrently. The graph is
- * captured on the first call and replayed while the pointer sets and the
- * items' configurations are unchanged. The batch does not own its items. */
+ * item i as a single HIP-graph launch. Items with the same grid, time steps,
+ * scheme and precision form a group: each kernel of the matvec runs once for
+ * the whole group, reading every item's pointers and scalars (beta included)
+ * from a device table, and groups run as independent graph branches. Results
+ * are bit-identical to the items' own nkreg_hessian_matvec. The graph and its
+ * tables are built on the first call and replayed while the pointer sets and
+ * the items' configurations are unchanged. The batch does not own its items.
+ * nkreg_batch_groups reports the grouping of the last built graph: the number
+ * of groups and (up to cap entries) their sizes. */
 typedef struct nkreg_batch nkreg_batch;
 int nkreg_batch_create(int count, nkreg_problem* const* items, nkreg_batch** out);
+int nkreg_batch_groups(nkreg_batch* b, int* groups, int* sizes, int cap);
 int nkreg_batch_destroy(nkreg_batch* b);
 int nkreg_batch_hessian_matvec(nkreg_batch* b, const void* const* d_vt, void* const* d_Hvt);
 

@@ -9,7 +9,7 @@ from __future__ import annotations
 import ctypes
 from ctypes import byref, c_double, c_int, c_void_p
 from dataclasses import dataclass
-from typing import Optional, Sequence, Tuple
+from typing import List, Optional, Sequence, Tuple
 
 import torch
 
@@ -310,6 +310,13 @@ class Batch:
         os_ = (c_void_p * n)(*[t.data_ptr() for t in outs])
         check(self.lib.nkreg_batch_hessian_matvec(self._h, ins, os_), "nkreg_batch_hessian_matvec")
         return outs
+
+    def groups(self) -> List[int]:
+        """Sizes of the item groups that share launches in the last built batch graph."""
+        n = c_int()
+        sizes = (c_int * max(1, len(self.problems)))()
+        check(self.lib.nkreg_batch_groups(self._h, byref(n), sizes, len(self.problems)), "nkreg_batch_groups")
+        return [sizes[i] for i in range(n.value)]
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -168,7 +168,7 @@ __device__ __forceinline__ void spec_apply(const SpecArgs<R>& a, int op, const R
 }
 
 template <typename R, int D>
-__global__ __launch_bounds__(256) void k_spec_mul(SpecArgs<R> a, int op) {
+__device__ __forceinline__ void spec_mul_body(const SpecArgs<R>& a, int op) {
   const int nl = (D == 2) ? a.n2 : a.n3;   // last axis length
   const int M = nl / 2;
   const long long rows = (long long)a.n1 * (D == 3 ? a.n2 : 1);
@@ -236,6 +236,16 @@ __global__ __launch_bounds__(256) void k_spec_mul(SpecArgs<R> a, int op) {
       }
     }
   }
+}
+
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_spec_mul(SpecArgs<R> a, int op) {
+  spec_mul_body<R, D>(a, op);
+}
+// One launch over the items of a batch group: item blockIdx.z uses tab[blockIdx.z].
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_spec_mul_t(const SpecArgs<R>* __restrict__ tab, int op) {
+  spec_mul_body<R, D>(tab[blockIdx.z], op);
 }
 
 // ---------------------------------------------------------------------------
@@ -346,6 +356,28 @@ __global__ void k_fill(long long cnt, R v, R* __restrict__ y) {
 
 template <typename RS, typename RD>
 __global__ void k_convert(long long cnt, const RS* __restrict__ x, RD* __restrict__ y) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+       i += (long long)gridDim.x * blockDim.x)
+    y[i] = (RD)x[i];
+}
+
+// Batch-group forms: item blockIdx.z takes its pointers from the table.
+template <typename R>
+__global__ void k_fill_t(long long cnt, R v, R* const* __restrict__ tab) {
+  R* __restrict__ y = tab[blockIdx.z];
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+       i += (long long)gridDim.x * blockDim.x)
+    y[i] = v;
+}
+template <typename RS, typename RD>
+struct ConvPtrs {
+  const RS* x;
+  RD* y;
+};
+template <typename RS, typename RD>
+__global__ void k_convert_t(long long cnt, const ConvPtrs<RS, RD>* __restrict__ tab) {
+  const RS* __restrict__ x = tab[blockIdx.z].x;
+  RD* __restrict__ y = tab[blockIdx.z].y;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
        i += (long long)gridDim.x * blockDim.x)
     y[i] = (RD)x[i];

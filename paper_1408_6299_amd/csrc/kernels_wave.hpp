@@ -57,7 +57,7 @@ __device__ __forceinline__ cplx<R> comb2(const R* __restrict__ f, const R* w, in
 }
 
 template <typename R, int L, int E, int KIND, int D, bool NC1>
-__global__ __launch_bounds__(64) void k_row_w(StageArgs<R> a, const cplx<R>* __restrict__ tw, int lmax) {
+__device__ __forceinline__ void row_body(const StageArgs<R>& a, const cplx<R>* __restrict__ tw, int lmax) {
   constexpr int M = L / 2;
   using P = WavePlan<M, E>;
   constexpr int LS = P::LS;
@@ -324,6 +324,25 @@ __global__ __launch_bounds__(64) void k_row_w(StageArgs<R> a, const cplx<R>* __r
   }
 }
 
+template <typename R, int L, int E, int KIND, int D, bool NC1>
+__global__ __launch_bounds__(64) void k_row_w(StageArgs<R> a, const cplx<R>* __restrict__ tw, int lmax) {
+  row_body<R, L, E, KIND, D, NC1>(a, tw, lmax);
+}
+// One launch over the items of a batch group: item blockIdx.z uses tab[blockIdx.z].
+template <typename R, int L, int E, int KIND, int D, bool NC1>
+__global__ __launch_bounds__(64) void k_row_wt(const StageArgs<R>* __restrict__ tab, const cplx<R>* __restrict__ tw,
+                                               int lmax) {
+  row_body<R, L, E, KIND, D, NC1>(tab[blockIdx.z], tw, lmax);
+}
+
+// Pointers of one column pass (per batch item in the group forms).
+template <typename R>
+struct ColPtrs {
+  const cplx<R>* in;
+  const cplx<R>* add;
+  cplx<R>* out;
+};
+
 template <int N, int E>
 struct ColShape {
   static constexpr int LS = WavePlan<N, E>::LS;       // lanes per column
@@ -333,9 +352,8 @@ struct ColShape {
 };
 
 template <typename R, int N, int E, int MODE>
-__global__ __launch_bounds__((ColShape<N, E>::NT)) void k_col_w(const cplx<R>* in, const cplx<R>* add, cplx<R>* out,
-                                                              ColArgs a, R scale, const cplx<R>* __restrict__ tw,
-                                                              int twb) {
+__device__ __forceinline__ void col_w_body(const cplx<R>* in, const cplx<R>* add, cplx<R>* out, const ColArgs& a,
+                                           R scale, const cplx<R>* __restrict__ tw, int twb, int fz) {
   using CS = ColShape<N, E>;
   constexpr int LS = CS::LS;
   constexpr int SPW = CS::SPW;
@@ -349,7 +367,7 @@ __global__ __launch_bounds__((ColShape<N, E>::NT)) void k_col_w(const cplx<R>* i
   const long long colr = (long long)bx * SPW + c;
   const bool live = colr < a.inner;
   const long long col = live ? colr : a.inner - 1;
-  const long long base = (long long)blockIdx.z * a.field + (long long)blockIdx.y * N * a.inner + col;
+  const long long base = (long long)fz * a.field + (long long)blockIdx.y * N * a.inner + col;
   cplx<R> v[E], ad[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = in[base + (long long)(j + LS * e) * a.inner];
@@ -383,6 +401,20 @@ __global__ __launch_bounds__((ColShape<N, E>::NT)) void k_col_w(const cplx<R>* i
   }
 }
 
+template <typename R, int N, int E, int MODE>
+__global__ __launch_bounds__((ColShape<N, E>::NT)) void k_col_w(const cplx<R>* in, const cplx<R>* add, cplx<R>* out,
+                                                              ColArgs a, R scale, const cplx<R>* __restrict__ tw,
+                                                              int twb) {
+  col_w_body<R, N, E, MODE>(in, add, out, a, scale, tw, twb, (int)blockIdx.z);
+}
+// Batch-group form: blockIdx.z = item * nfz + field.
+template <typename R, int N, int E, int MODE>
+__global__ __launch_bounds__((ColShape<N, E>::NT)) void k_col_wt(const ColPtrs<R>* __restrict__ tab, ColArgs a, R scale,
+                                                               const cplx<R>* __restrict__ tw, int twb, int nfz) {
+  const ColPtrs<R> p = tab[blockIdx.z / nfz];
+  col_w_body<R, N, E, MODE>(p.in, p.add, p.out, a, scale, tw, twb, (int)(blockIdx.z % nfz));
+}
+
 // Tiled column pass for long strided axes. A workgroup owns CT adjacent
 // columns (CT * sizeof(cplx) = 64 or 128 bytes, a whole cache line per row):
 // it stages the N x CT tile through LDS with row-coalesced loads, transforms
@@ -414,9 +446,8 @@ struct TileShape {
 };
 
 template <typename R, int N, int CT, int MODE>
-__global__ __launch_bounds__((TileShape<R, N, CT>::NT)) void k_col_t(const cplx<R>* in, const cplx<R>* add,
-                                                                     cplx<R>* out, ColArgs a, R scale,
-                                                                     const cplx<R>* __restrict__ tw, int twb) {
+__device__ __forceinline__ void col_t_body(const cplx<R>* in, const cplx<R>* add, cplx<R>* out, const ColArgs& a,
+                                           R scale, const cplx<R>* __restrict__ tw, int twb, int fz) {
   using TS = TileShape<R, N, CT>;
   constexpr int E = TS::E, LS = TS::LS, SPW = TS::SPW, CP = TS::CPITCH;
   constexpr int RPS = TS::ROWS_PER_STEP;
@@ -428,7 +459,7 @@ __global__ __launch_bounds__((TileShape<R, N, CT>::NT)) void k_col_t(const cplx<
   const int cl = lane / LS, j = lane % LS;        // a half-wavefront's exchanges stay in one column
   // tile (x, y) covers columns x * CT .. x * CT + CT - 1 of outer slice y
   const int x = (int)blockIdx.x % a.ntx, y = (int)blockIdx.x / a.ntx;
-  const long long base = (long long)blockIdx.z * a.field + (long long)y * N * a.inner + (long long)x * CT;
+  const long long base = (long long)fz * a.field + (long long)y * N * a.inner + (long long)x * CT;
   // row-coalesced load of the N x CT tile
 #pragma unroll
   for (int k = 0; k < K; ++k)
@@ -469,6 +500,21 @@ __global__ __launch_bounds__((TileShape<R, N, CT>::NT)) void k_col_t(const cplx<
     if (has_add) v = cadd(v, add[gi]);
     out[gi] = v;
   }
+}
+
+template <typename R, int N, int CT, int MODE>
+__global__ __launch_bounds__((TileShape<R, N, CT>::NT)) void k_col_t(const cplx<R>* in, const cplx<R>* add,
+                                                                     cplx<R>* out, ColArgs a, R scale,
+                                                                     const cplx<R>* __restrict__ tw, int twb) {
+  col_t_body<R, N, CT, MODE>(in, add, out, a, scale, tw, twb, (int)blockIdx.z);
+}
+// Batch-group form: blockIdx.z = item * nfz + field.
+template <typename R, int N, int CT, int MODE>
+__global__ __launch_bounds__((TileShape<R, N, CT>::NT)) void k_col_tt(const ColPtrs<R>* __restrict__ tab, ColArgs a,
+                                                                      R scale, const cplx<R>* __restrict__ tw, int twb,
+                                                                      int nfz) {
+  const ColPtrs<R> p = tab[blockIdx.z / nfz];
+  col_t_body<R, N, CT, MODE>(p.in, p.add, p.out, a, scale, tw, twb, (int)(blockIdx.z % nfz));
 }
 
 }  // namespace nk

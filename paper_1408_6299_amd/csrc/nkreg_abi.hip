@@ -10,20 +10,26 @@ struct nkreg_problem {
   nk::ProblemBase* impl;
 };
 
-// A batch replays one HIP graph whose independent branches are the items'
-// matvecs, each on its item's internal stream (so they run concurrently).
+// A batch replays one HIP graph. Items whose recorded matvec launch sequences
+// have the same shape (same grid, steps, scheme and precision) form a group;
+// every launch of a group's sequence becomes one launch over all its items,
+// whose per-item arguments come from a device table. Groups are independent
+// branches of the graph, each on the internal stream of its first item.
 struct nkreg_batch {
   std::vector<nkreg_problem*> items;
   hipStream_t s = nullptr;
   hipEvent_t fork = nullptr, done = nullptr;
   std::vector<hipEvent_t> joins, waits;
   hipGraphExec_t exec = nullptr;
+  void* tables = nullptr;  // device argument tables of the captured graph
+  std::vector<int> group_sizes;
   std::vector<const void*> key_in;
   std::vector<void*> key_out;
   std::vector<unsigned> key_gen;
   ~nkreg_batch() {
     if (s) (void)hipStreamSynchronize(s);
     if (exec) (void)hipGraphExecDestroy(exec);
+    if (tables) (void)hipFree(tables);
     for (hipEvent_t e : joins) (void)hipEventDestroy(e);
     for (hipEvent_t e : waits) (void)hipEventDestroy(e);
     if (fork) (void)hipEventDestroy(fork);
@@ -272,6 +278,47 @@ int nkreg_batch_destroy(nkreg_batch* b) {
   return NKREG_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Issues one recorded launch position for a whole group (tab = its table).
+void launch_group(const nk::LaunchRec& r, int G, void* tab, hipStream_t st) {
+  dim3 grid = r.grid;
+  const unsigned z = grid.z;
+  grid.z = z * (unsigned)G;
+  const void* tw = r.tw;
+  int iarg = r.iarg, nfz = r.nfz;
+  long long cnt = r.cnt;
+  nk::ColArgs ca = r.ca;
+  float sf = (float)r.scale, vf = (float)r.fval;
+  double sd = r.scale, vd = r.fval;
+  void* args[6];
+  switch (r.kind) {
+    case nk::LaunchRec::ROW: args[0] = &tab; args[1] = &tw; args[2] = &iarg; break;
+    case nk::LaunchRec::COL:
+      args[0] = &tab; args[1] = &ca; args[2] = r.f64 ? (void*)&sd : (void*)&sf; args[3] = &tw; args[4] = &iarg;
+      args[5] = &nfz;
+      break;
+    case nk::LaunchRec::FILL: args[0] = &cnt; args[1] = r.f64 ? (void*)&vd : (void*)&vf; args[2] = &tab; break;
+    case nk::LaunchRec::CONV: args[0] = &cnt; args[1] = &tab; break;
+    case nk::LaunchRec::SPEC: args[0] = &tab; args[1] = &iarg; break;
+    default: throw nk::HipError(NKREG_EHIP, "unexpected recorded launch");
+  }
+  NK_HIP(hipLaunchKernel(r.kernel, grid, r.block, args, 0, st));
+}
+
+bool same_sequence(const std::vector<nk::LaunchRec>& a, const std::vector<nk::LaunchRec>& b) {
+  if (a.size() != b.size()) return false;
+  for (size_t i = 0; i < a.size(); ++i)
+    if (!a[i].same_shape(b[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
 int nkreg_batch_hessian_matvec(nkreg_batch* b, const void* const* vt, void* const* out) {
   NEED(b);
   if (!b->items.empty()) { NEED(vt); NEED(out); }
@@ -282,18 +329,63 @@ int nkreg_batch_hessian_matvec(nkreg_batch* b, const void* const* vt, void* cons
     for (size_t i = 0; i < cnt && !stale; ++i)
       stale = b->key_in[i] != vt[i] || b->key_out[i] != out[i] || b->key_gen[i] != b->items[i]->impl->generation;
     if (stale) {
+      NK_HIP(hipStreamSynchronize(b->s));
       if (b->exec) (void)hipGraphExecDestroy(b->exec);
       b->exec = nullptr;
+      if (b->tables) (void)hipFree(b->tables);
+      b->tables = nullptr;
+      // record every item's matvec and group equal-shaped sequences
+      std::vector<nk::Recorder> recs(cnt);
+      for (size_t i = 0; i < cnt; ++i) b->items[i]->impl->record_matvec(vt[i], out[i], recs[i]);
+      std::vector<std::vector<size_t>> groups;
+      for (size_t i = 0; i < cnt; ++i) {
+        bool placed = false;
+        for (auto& g : groups) {
+          if (same_sequence(recs[g[0]].recs, recs[i].recs)) { g.push_back(i); placed = true; break; }
+        }
+        if (!placed) groups.push_back({i});
+      }
+      // argument tables: for each group and launch position, the items' entries side by side
+      std::vector<unsigned char> host;
+      std::vector<std::vector<size_t>> offs(groups.size());
+      for (size_t gi = 0; gi < groups.size(); ++gi) {
+        const auto& g = groups[gi];
+        const auto& seq = recs[g[0]].recs;
+        offs[gi].resize(seq.size());
+        for (size_t p = 0; p < seq.size(); ++p) {
+          if (seq[p].kind == nk::LaunchRec::COPY) continue;
+          host.resize((host.size() + 255) / 256 * 256);
+          offs[gi][p] = host.size();
+          for (size_t i : g) host.insert(host.end(), recs[i].recs[p].entry.begin(), recs[i].recs[p].entry.end());
+        }
+      }
+      if (!host.empty()) {
+        NK_HIP(hipMalloc(&b->tables, host.size()));
+        NK_HIP(hipMemcpy(b->tables, host.data(), host.size(), hipMemcpyHostToDevice));
+      }
+      b->group_sizes.clear();
+      for (auto& g : groups) b->group_sizes.push_back((int)g.size());
       hipGraph_t graph = nullptr;
       NK_HIP(hipStreamBeginCapture(b->s, hipStreamCaptureModeThreadLocal));
       try {
         NK_HIP(hipEventRecord(b->fork, b->s));
-        for (size_t i = 0; i < cnt; ++i) {
-          nk::ProblemBase* p = b->items[i]->impl;
-          NK_HIP(hipStreamWaitEvent(p->stream(), b->fork, 0));
-          p->matvec_launches(vt[i], out[i]);
-          NK_HIP(hipEventRecord(b->joins[i], p->stream()));
-          NK_HIP(hipStreamWaitEvent(b->s, b->joins[i], 0));
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+          const auto& g = groups[gi];
+          hipStream_t st = b->items[g[0]]->impl->stream();
+          NK_HIP(hipStreamWaitEvent(st, b->fork, 0));
+          const auto& seq = recs[g[0]].recs;
+          for (size_t p = 0; p < seq.size(); ++p) {
+            if (seq[p].kind == nk::LaunchRec::COPY) {
+              for (size_t i : g) {
+                const auto& r = recs[i].recs[p];
+                NK_HIP(hipMemcpyAsync(r.dst, r.src, r.bytes, hipMemcpyDeviceToDevice, st));
+              }
+            } else {
+              launch_group(seq[p], (int)g.size(), (unsigned char*)b->tables + offs[gi][p], st);
+            }
+          }
+          NK_HIP(hipEventRecord(b->joins[gi], st));
+          NK_HIP(hipStreamWaitEvent(b->s, b->joins[gi], 0));
         }
       } catch (...) {
         (void)hipStreamEndCapture(b->s, &graph);
@@ -322,6 +414,14 @@ int nkreg_batch_hessian_matvec(nkreg_batch* b, const void* const* vt, void* cons
     for (size_t i = 0; i < cnt; ++i) NK_HIP(hipStreamWaitEvent(b->items[i]->impl->caller_stream(), b->done, 0));
     return (int)NKREG_OK;
   });
+}
+
+int nkreg_batch_groups(nkreg_batch* b, int* groups, int* sizes, int cap) {
+  NEED(b); NEED(groups);
+  *groups = (int)b->group_sizes.size();
+  if (sizes)
+    for (int i = 0; i < cap && i < (int)b->group_sizes.size(); ++i) sizes[i] = b->group_sizes[i];
+  return NKREG_OK;
 }
 
 }  // extern "C"

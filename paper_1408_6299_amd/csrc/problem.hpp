@@ -139,6 +139,8 @@ class ProblemBase {
   // One matvec as eager launches on the internal stream (used when a batch
   // captures several problems into one graph); checks the cached state.
   virtual void matvec_launches(const void* vt, void* out) = 0;
+  // Records one matvec's launches (nothing is issued); checks the cached state.
+  virtual void record_matvec(const void* vt, void* out, Recorder& r) = 0;
   virtual hipStream_t caller_stream() const = 0;
   // bumped whenever captured graphs become stale (beta change, graph switch, timer)
   unsigned generation = 0;
@@ -309,8 +311,65 @@ class ProblemT final : public ProblemBase {
     for (int l = 0; l < kMaxNc; ++l) out[l] = l < nc ? (R)b[l] : R(0);
   }
 
+  // Recording for batch groups: while rec is set, the matvec's launches are
+  // recorded (here and in both spectral engines) instead of issued.
+  Recorder* rec = nullptr;
+  void record_matvec(const void* vt, void* out, Recorder& r) override {
+    if (!state_valid) throw HipError(NKREG_ESTATE, "no gradient computed at the current velocity");
+    rec = sp.rec = sp64.rec = &r;
+    try {
+      matvec_body(vt, out);
+    } catch (...) {
+      rec = sp.rec = sp64.rec = nullptr;
+      throw;
+    }
+    rec = sp.rec = sp64.rec = nullptr;
+  }
+
   void copy(void* dst, const void* src, size_t bytes) {
+    if (rec) {
+      LaunchRec r;
+      r.kind = LaunchRec::COPY;
+      r.dst = dst;
+      r.src = src;
+      r.bytes = bytes;
+      rec->recs.push_back(r);
+      return;
+    }
     NK_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
+  }
+  template <typename RS, typename RD>
+  void convert(long long cnt, const RS* x, RD* y) {
+    if (rec) {
+      LaunchRec r;
+      r.kind = LaunchRec::CONV;
+      r.kernel = (const void*)k_convert_t<RS, RD>;
+      r.grid = dim3(launch_blocks(cnt));
+      r.block = dim3(256);
+      r.cnt = cnt;
+      r.set_entry(ConvPtrs<RS, RD>{x, y});
+      rec->recs.push_back(r);
+      return;
+    }
+    hipLaunchKernelGGL((k_convert<RS, RD>), dim3(launch_blocks(cnt)), dim3(256), 0, s, cnt, x, y);
+    NK_LAUNCHED();
+  }
+  void fill(long long cnt, R v, R* y) {
+    if (rec) {
+      LaunchRec r;
+      r.kind = LaunchRec::FILL;
+      r.kernel = (const void*)k_fill_t<R>;
+      r.grid = dim3(launch_blocks(cnt));
+      r.block = dim3(256);
+      r.cnt = cnt;
+      r.fval = (double)v;
+      r.f64 = kF64;
+      r.set_entry(y);
+      rec->recs.push_back(r);
+      return;
+    }
+    hipLaunchKernelGGL((k_fill<R>), dim3(launch_blocks(cnt)), dim3(256), 0, s, cnt, v, y);
+    NK_LAUNCHED();
   }
 
   // FP64 control vector -> transport precision (aliases in FP64 mode)
@@ -318,8 +377,7 @@ class ProblemT final : public ProblemBase {
     if constexpr (kF64) {
       return x;
     } else {
-      hipLaunchKernelGGL((k_convert<double, R>), dim3(launch_blocks(nv)), dim3(256), 0, s, nv, x, dst.p);
-      NK_LAUNCHED();
+      convert<double, R>(nv, x, dst.p);
       return dst.p;
     }
   }
@@ -328,8 +386,7 @@ class ProblemT final : public ProblemBase {
     if constexpr (kF64) {
       return F.p;
     } else {
-      hipLaunchKernelGGL((k_convert<R, double>), dim3(launch_blocks(nv)), dim3(256), 0, s, nv, F.p, F64.p);
-      NK_LAUNCHED();
+      convert<R, double>(nv, F.p, F64.p);
       return F64.p;
     }
   }
@@ -408,8 +465,7 @@ class ProblemT final : public ProblemBase {
     cplx<R>* U0 = U.p;
     cplx<R>* U1 = U.p + ns;
     cplx<R>* U2 = U.p + 2 * ns;
-    hipLaunchKernelGGL((k_fill<R>), dim3(launch_blocks(nv)), dim3(256), 0, s, nv, R(0), Fout);
-    NK_LAUNCHED();
+    fill(nv, R(0), Fout);
     StageArgs<R> a{};
     a.vl = vl; a.nc = nc; a.h = h;
     a.src_a = src_a; a.src_b = src_b; a.ca = ca; a.cb = cb;

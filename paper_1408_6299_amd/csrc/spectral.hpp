@@ -3,6 +3,7 @@
 
 #include <cmath>
 #include <cstdlib>
+#include <cstring>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -113,6 +114,42 @@ struct KernelTimer {
   }
 };
 
+// A kernel launch recorded for a batch group instead of being issued: the
+// group (table) form of the kernel, its grid, this item's table entry and the
+// arguments every item of a group shares. A batch replays each position of
+// equal-shaped recordings as one launch over all items of the group.
+struct LaunchRec {
+  enum Kind { ROW, COL, FILL, CONV, SPEC, COPY };
+  int kind = ROW;
+  const void* kernel = nullptr;      // group form of the kernel
+  dim3 grid, block;
+  std::vector<unsigned char> entry;  // this item's table entry
+  const void* tw = nullptr;          // ROW, COL: twiddle table (equal across a group)
+  int iarg = 0;                      // ROW: lmax; COL: twb; SPEC: op
+  int nfz = 1;                       // COL: fields per item
+  ColArgs ca{};
+  double scale = 0.0, fval = 0.0;    // COL scale, FILL value
+  bool f64 = false;                  // precision of scale and fval
+  long long cnt = 0;                 // FILL, CONV element counts
+  void* dst = nullptr;               // COPY (issued per item)
+  const void* src = nullptr;
+  size_t bytes = 0;
+  template <typename T>
+  void set_entry(const T& v) {
+    entry.resize(sizeof(T));
+    std::memcpy(entry.data(), &v, sizeof(T));
+  }
+  bool same_shape(const LaunchRec& o) const {
+    return kind == o.kind && kernel == o.kernel && grid.x == o.grid.x && grid.y == o.grid.y &&
+           grid.z == o.grid.z && block.x == o.block.x && iarg == o.iarg && nfz == o.nfz &&
+           std::memcmp(&ca, &o.ca, sizeof(ColArgs)) == 0 && scale == o.scale && fval == o.fval && f64 == o.f64 &&
+           cnt == o.cnt && entry.size() == o.entry.size() && bytes == o.bytes;
+  }
+};
+struct Recorder {
+  std::vector<LaunchRec> recs;
+};
+
 template <typename R>
 class Spectral {
  public:
@@ -120,6 +157,7 @@ class Spectral {
   hipStream_t s = nullptr;
   cplx<R>* tw = nullptr;  // exp(-2 pi i m / lmax), m < lmax
   KernelTimer* timer = nullptr;
+  Recorder* rec = nullptr;  // when set, launches are recorded instead of issued
   // Column-pass variant, chosen by the autotuner: 8 or 4 = one workgroup per
   // column group with that many complex elements per lane (8: one wavefront per
   // 512-point column, 4: two); 0 = tiled through LDS (k_col_t) wherever the
@@ -307,9 +345,20 @@ class Spectral {
     a.nspec = g.nspec;
     const long long work = (long long)nc * g.nspec;
     const int blocks = (int)std::min<long long>((work + 255) / 256, 4096);
-    if (g.d == 2) hipLaunchKernelGGL((k_spec_mul<R, 2>), dim3(blocks), dim3(256), 0, s, a, op);
-    else hipLaunchKernelGGL((k_spec_mul<R, 3>), dim3(blocks), dim3(256), 0, s, a, op);
-    NK_LAUNCHED();
+    if (rec) {
+      LaunchRec r;
+      r.kind = LaunchRec::SPEC;
+      r.kernel = g.d == 2 ? (const void*)k_spec_mul_t<R, 2> : (const void*)k_spec_mul_t<R, 3>;
+      r.grid = dim3(blocks);
+      r.block = dim3(256);
+      r.iarg = op;
+      r.set_entry(a);
+      rec->recs.push_back(r);
+    } else {
+      if (g.d == 2) hipLaunchKernelGGL((k_spec_mul<R, 2>), dim3(blocks), dim3(256), 0, s, a, op);
+      else hipLaunchKernelGGL((k_spec_mul<R, 3>), dim3(blocks), dim3(256), 0, s, a, op);
+      NK_LAUNCHED();
+    }
     col(COL_INV, 0, Xs, nullptr, Xs, nf, R(1));
     if (g.d == 3) col(COL_INV, 1, Xs, nullptr, Xs, nf, R(1));
     c2r(Xs, out, nf, R(1));
@@ -317,6 +366,22 @@ class Spectral {
 
  private:
   // Column transforms: one or two wavefronts per column workgroup.
+  void record_col(const void* k, dim3 grid, dim3 block, int nf, const ColArgs& a, R scale, int twb,
+                  const cplx<R>* in, const cplx<R>* add, cplx<R>* out) {
+    LaunchRec r;
+    r.kind = LaunchRec::COL;
+    r.kernel = k;
+    r.grid = grid;
+    r.block = block;
+    r.nfz = nf;
+    r.ca = a;
+    r.scale = (double)scale;
+    r.f64 = sizeof(R) == 8;
+    r.tw = tw;
+    r.iarg = twb;
+    r.set_entry(ColPtrs<R>{in, add, out});
+    rec->recs.push_back(r);
+  }
   template <int N>
   void col_n(int mode, const cplx<R>* in, const cplx<R>* add, cplx<R>* out, int nf, R scale, int outer,
              long long inner) {
@@ -342,6 +407,13 @@ class Spectral {
     a.ntiles = a.ntx * outer;
     dim3 grid((unsigned)a.ntiles, 1u, (unsigned)nf);
     const int twb = g.lmax / N;
+    if (rec) {
+      const void* k = mode == COL_FWD   ? (const void*)k_col_tt<R, N, CT, COL_FWD>
+                      : mode == COL_INV ? (const void*)k_col_tt<R, N, CT, COL_INV>
+                                        : (const void*)k_col_tt<R, N, CT, COL_DERIV>;
+      record_col(k, grid, dim3(TileShape<R, N, CT>::NT), nf, a, scale, twb, in, add, out);
+      return;
+    }
     const bool timed = timer && timer->want(kColIdBase + mode);
     const cplx<R>* twc = tw;
     switch (mode) {
@@ -362,6 +434,13 @@ class Spectral {
     a.field = g.nspec;
     dim3 grid((unsigned)((inner + SPW - 1) / SPW), (unsigned)outer, (unsigned)nf);
     const int twb = g.lmax / N;
+    if (rec) {
+      const void* k = mode == COL_FWD   ? (const void*)k_col_wt<R, N, E, COL_FWD>
+                      : mode == COL_INV ? (const void*)k_col_wt<R, N, E, COL_INV>
+                                        : (const void*)k_col_wt<R, N, E, COL_DERIV>;
+      record_col(k, grid, dim3(CS::NT), nf, a, scale, twb, in, add, out);
+      return;
+    }
     const bool timed = timer && timer->want(kColIdBase + mode);
     switch (mode) {
       case COL_FWD:
@@ -394,12 +473,25 @@ class Spectral {
 
   template <int KIND, int D, int L>
   void row_l(StageArgs<R>& a, int nf) {
-    constexpr int E = kRowE;
+    constexpr int E = (L / 2 >= kRowE) ? kRowE : (L / 2 >= 4 ? 4 : 2);
     constexpr int SPW = 64 / WavePlan<L / 2, E>::LS;
     dim3 grid((unsigned)((g.rows + SPW - 1) / SPW), (unsigned)nf);
-    const bool timed = timer && timer->want(KIND);
     constexpr bool uses_nc = (KIND == ST_FWD1 || KIND == ST_FWD2 || KIND == ST_INC1 || KIND == ST_INC2 ||
                               KIND == ST_ADJINIT || KIND == ST_ADJ1 || KIND == ST_ADJ2);
+    if (rec) {
+      LaunchRec r;
+      r.kind = LaunchRec::ROW;
+      if (!uses_nc || a.nc <= 1) r.kernel = (const void*)k_row_wt<R, L, E, KIND, D, true>;
+      else if constexpr (uses_nc) r.kernel = (const void*)k_row_wt<R, L, E, KIND, D, false>;
+      r.grid = grid;
+      r.block = dim3(64);
+      r.tw = tw;
+      r.iarg = g.lmax;
+      r.set_entry(a);
+      rec->recs.push_back(r);
+      return;
+    }
+    const bool timed = timer && timer->want(KIND);
     if (!uses_nc || a.nc <= 1)
       launch(k_row_w<R, L, E, KIND, D, true>, grid, dim3(64), timed, a, (const cplx<R>*)tw, g.lmax);
     else if constexpr (uses_nc)
@@ -441,6 +533,7 @@ template <typename R>
 void Spectral<R>::ik_last(cplx<R>* T) {
   const long long tot = g.nspec;
   const int blocks = (int)std::min<long long>((tot + 255) / 256, 4096);
+  if (rec) throw HipError(-1, "ik_last cannot be recorded for a batch group");
   hipLaunchKernelGGL((k_ik_last<R>), dim3(blocks), dim3(256), 0, s, T, g.rows, g.L / 2);
   NK_LAUNCHED();
 }

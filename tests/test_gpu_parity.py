@@ -197,21 +197,47 @@ def test_call_order_and_cfl_errors(nk):
     assert ei.value.status == -6
 
 
+# (shape, nt, precision, beta, seed, checkpoint): items 0-2 share a group (beta and data
+# differ per item), 3-4 another, 5 differs only in nt, 6-7 are 3D Stokes with
+# checkpointing, 8 is FP64.
+BATCH_ITEMS = [((32, 32), 6, 32, 1e-2, 1, 0), ((32, 32), 6, 32, 1e-3, 2, 0), ((32, 32), 6, 32, 3e-2, 3, 0),
+               ((64, 32), 8, 32, 1e-2, 4, 0), ((64, 32), 8, 32, 1e-2, 5, 0), ((32, 32), 4, 32, 1e-2, 6, 0),
+               ((16, 8, 16), 6, 32, 1e-3, 7, 4), ((16, 8, 16), 6, 32, 1e-3, 8, 4), ((32, 32), 6, 64, 1e-2, 9, 0)]
+
+
 def test_batch_matches_single_items(nk):
-    specs = [((16, 16), 6), ((32, 32), 6), ((64, 64), 8)]
+    """Items of one configuration share each kernel launch (per-item pointers and beta from
+    a device table); the batched result equals every item's own matvec bit for bit, on
+    the first build and on replays, also after one item's beta changes."""
     probs, ws, refs = [], [], []
-    for shape, nt in specs:
-        mT, mR, vstar, w = smooth_inputs(shape, nt)
-        G = nk.Problem(shape, nt, precision=32)
-        G.set_images(dev_t(mT, 32), dev_t(mR, 32))
+    for shape, nt, prec, beta, seed, ck in BATCH_ITEMS:
+        gamma = len(shape) == 3
+        mT, mR, vstar, w = smooth_inputs(shape, nt, divfree=gamma, seed=seed)
+        G = nk.Problem(shape, nt, reg=2 if gamma else 1, incompressible=gamma, beta=beta, precision=prec,
+                       checkpoint_every=ck)
+        G.set_images(dev_t(mT, prec), dev_t(mR, prec))
         G.objective_gradient(dev_v(0.5 * vstar))
         probs.append(G)
         ws.append(dev_v(w))
         refs.append(host(G.hessian_matvec(ws[-1])))
     B = nk.Batch(probs)
-    outs = B.hessian_matvec(ws)
-    for o, r in zip(outs, refs):
-        assert np.array_equal(host(o), r)
+    outs = [p.empty_v() for p in probs]
+    for _ in range(3):
+        B.hessian_matvec(ws, outs)
+        for o, r in zip(outs, refs):
+            assert np.array_equal(host(o), r)
+    assert sorted(B.groups()) == [1, 1, 2, 2, 3]
+    # a beta change invalidates the graph; the rebuilt batch uses the new beta for that item
+    probs[1].beta = 5e-3
+    ref1 = host(probs[1].hessian_matvec(ws[1]))
+    assert not np.array_equal(ref1, refs[1])
+    B.hessian_matvec(ws, outs)
+    assert np.array_equal(host(outs[1]), ref1)
+    for i in (0, 2, 3, 8):
+        assert np.array_equal(host(outs[i]), refs[i])
+    B.close()
+    for p in probs:
+        p.close()
 
 
 @pytest.mark.parametrize("prec", [64, 32])
