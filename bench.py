@@ -154,7 +154,7 @@ def batch_section(nk, synth, torch, reps):
         for _ in range(2):
             B.hessian_matvec(ws, outs)
         torch.cuda.synchronize()
-        out["groups"] = B.groups()
+        out["groups"] = [{"items": n, "tiled_columns": t} for n, t in B.group_plan()]
         t0 = time.perf_counter()
         for _ in range(reps):
             B.hessian_matvec(ws, outs)

@@ -216,11 +216,14 @@ int nkreg_timer_read(nkreg_problem* p, int* launches, double* avg_ms, double* by
  * are bit-identical to the items' own nkreg_hessian_matvec. The graph and its
  * tables are built on the first call and replayed while the pointer sets and
  * the items' configurations are unchanged. The batch does not own its items.
- * nkreg_batch_groups reports the grouping of the last built graph: the number
- * of groups and (up to cap entries) their sizes. */
+ * Where the LDS-tiled column pass applies, each group times it against the
+ * per-column pass at the group's scale and keeps the faster (both give the
+ * same values). nkreg_batch_groups reports the last built graph: the number of
+ * groups and, for up to cap groups, their sizes and whether they use the tiled
+ * pass (sizes, tiled may be NULL). */
 typedef struct nkreg_batch nkreg_batch;
 int nkreg_batch_create(int count, nkreg_problem* const* items, nkreg_batch** out);
-int nkreg_batch_groups(nkreg_batch* b, int* groups, int* sizes, int cap);
+int nkreg_batch_groups(nkreg_batch* b, int* groups, int* sizes, int* tiled, int cap);
 int nkreg_batch_destroy(nkreg_batch* b);
 int nkreg_batch_hessian_matvec(nkreg_batch* b, const void* const* d_vt, void* const* d_Hvt);
 

@@ -313,10 +313,15 @@ class Batch:
 
     def groups(self) -> List[int]:
         """Sizes of the item groups that share launches in the last built batch graph."""
+        return [n for n, _ in self.group_plan()]
+
+    def group_plan(self) -> List[Tuple[int, bool]]:
+        """(items, uses the tiled column pass) per group of the last built batch graph."""
         n = c_int()
-        sizes = (c_int * max(1, len(self.problems)))()
-        check(self.lib.nkreg_batch_groups(self._h, byref(n), sizes, len(self.problems)), "nkreg_batch_groups")
-        return [sizes[i] for i in range(n.value)]
+        cap = max(1, len(self.problems))
+        sizes, tiled = (c_int * cap)(), (c_int * cap)()
+        check(self.lib.nkreg_batch_groups(self._h, byref(n), sizes, tiled, cap), "nkreg_batch_groups")
+        return [(sizes[i], bool(tiled[i])) for i in range(n.value)]
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

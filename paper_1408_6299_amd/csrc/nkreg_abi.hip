@@ -22,7 +22,7 @@ struct nkreg_batch {
   std::vector<hipEvent_t> joins, waits;
   hipGraphExec_t exec = nullptr;
   void* tables = nullptr;  // device argument tables of the captured graph
-  std::vector<int> group_sizes;
+  std::vector<int> group_sizes, variants;  // per group: items, column pass (8 or 0 = tiled)
   std::vector<const void*> key_in;
   std::vector<void*> key_out;
   std::vector<unsigned> key_gen;
@@ -315,6 +315,98 @@ bool same_sequence(const std::vector<nk::LaunchRec>& a, const std::vector<nk::La
   return true;
 }
 
+// The recorded launches of one group of items and where their tables live.
+struct GroupPlan {
+  std::vector<size_t> items;
+  std::vector<nk::Recorder> recs;  // one per item, equal-shaped
+  std::vector<size_t> offs;        // per launch position: table offset
+};
+
+// Appends the group's argument tables (items' entries side by side per position).
+void add_tables(GroupPlan& gp, std::vector<unsigned char>& host) {
+  const auto& seq = gp.recs[0].recs;
+  gp.offs.assign(seq.size(), 0);
+  for (size_t p = 0; p < seq.size(); ++p) {
+    if (seq[p].kind == nk::LaunchRec::COPY) continue;
+    host.resize((host.size() + 255) / 256 * 256);
+    gp.offs[p] = host.size();
+    for (const auto& r : gp.recs) host.insert(host.end(), r.recs[p].entry.begin(), r.recs[p].entry.end());
+  }
+}
+
+// Issues the group's launches on st (tables at base).
+void issue_group(const GroupPlan& gp, void* base, hipStream_t st) {
+  const auto& seq = gp.recs[0].recs;
+  for (size_t p = 0; p < seq.size(); ++p) {
+    if (seq[p].kind == nk::LaunchRec::COPY) {
+      for (const auto& r : gp.recs) {
+        const auto& c = r.recs[p];
+        NK_HIP(hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyDeviceToDevice, st));
+      }
+    } else {
+      launch_group(seq[p], (int)gp.recs.size(), (unsigned char*)base + gp.offs[p], st);
+    }
+  }
+}
+
+// Captures issue_group into a graph on st (which must not be capturing).
+hipGraphExec_t capture_group(const GroupPlan& gp, void* base, hipStream_t st) {
+  hipGraph_t graph = nullptr;
+  NK_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  try {
+    issue_group(gp, base, st);
+  } catch (...) {
+    (void)hipStreamEndCapture(st, &graph);
+    if (graph) (void)hipGraphDestroy(graph);
+    throw;
+  }
+  NK_HIP(hipStreamEndCapture(st, &graph));
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) throw nk::HipError(NKREG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  return ex;
+}
+
+// Milliseconds per replay of the group's launches (one warm-up, then two timed).
+float time_group(const GroupPlan& gp, hipStream_t st) {
+  std::vector<unsigned char> host;
+  GroupPlan g = gp;
+  add_tables(g, host);
+  void* dev = nullptr;
+  if (!host.empty()) {
+    NK_HIP(hipMalloc(&dev, host.size()));
+    NK_HIP(hipMemcpy(dev, host.data(), host.size(), hipMemcpyHostToDevice));
+  }
+  hipGraphExec_t ex = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  float ms = 0.f;
+  try {
+    ex = capture_group(g, dev, st);
+    NK_HIP(hipEventCreate(&e0));
+    NK_HIP(hipEventCreate(&e1));
+    NK_HIP(hipGraphLaunch(ex, st));
+    NK_HIP(hipEventRecord(e0, st));
+    NK_HIP(hipGraphLaunch(ex, st));
+    NK_HIP(hipGraphLaunch(ex, st));
+    NK_HIP(hipEventRecord(e1, st));
+    NK_HIP(hipEventSynchronize(e1));
+    NK_HIP(hipEventElapsedTime(&ms, e0, e1));
+  } catch (...) {
+    (void)hipStreamSynchronize(st);
+    if (ex) (void)hipGraphExecDestroy(ex);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (dev) (void)hipFree(dev);
+    throw;
+  }
+  (void)hipGraphExecDestroy(ex);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (dev) (void)hipFree(dev);
+  return ms / 2.f;
+}
+
 }  // namespace
 
 extern "C" {
@@ -325,6 +417,12 @@ int nkreg_batch_hessian_matvec(nkreg_batch* b, const void* const* vt, void* cons
   return guarded([&]() {
     const size_t cnt = b->items.size();
     if (cnt == 0) return (int)NKREG_OK;
+    // the batch stream waits for every caller stream (and so for all earlier work
+    // on the items), also before a rebuild replays a group to time it
+    for (size_t i = 0; i < cnt; ++i) {
+      NK_HIP(hipEventRecord(b->waits[i], b->items[i]->impl->caller_stream()));
+      NK_HIP(hipStreamWaitEvent(b->s, b->waits[i], 0));
+    }
     bool stale = !b->exec || b->key_in.size() != cnt;
     for (size_t i = 0; i < cnt && !stale; ++i)
       stale = b->key_in[i] != vt[i] || b->key_out[i] != out[i] || b->key_gen[i] != b->items[i]->impl->generation;
@@ -337,53 +435,62 @@ int nkreg_batch_hessian_matvec(nkreg_batch* b, const void* const* vt, void* cons
       // record every item's matvec and group equal-shaped sequences
       std::vector<nk::Recorder> recs(cnt);
       for (size_t i = 0; i < cnt; ++i) b->items[i]->impl->record_matvec(vt[i], out[i], recs[i]);
-      std::vector<std::vector<size_t>> groups;
+      std::vector<GroupPlan> plans;
       for (size_t i = 0; i < cnt; ++i) {
         bool placed = false;
-        for (auto& g : groups) {
-          if (same_sequence(recs[g[0]].recs, recs[i].recs)) { g.push_back(i); placed = true; break; }
+        for (auto& gp : plans) {
+          if (same_sequence(gp.recs[0].recs, recs[i].recs)) {
+            gp.items.push_back(i);
+            gp.recs.push_back(std::move(recs[i]));
+            placed = true;
+            break;
+          }
         }
-        if (!placed) groups.push_back({i});
+        if (!placed) {
+          plans.emplace_back();
+          plans.back().items.push_back(i);
+          plans.back().recs.push_back(std::move(recs[i]));
+        }
       }
-      // argument tables: for each group and launch position, the items' entries side by side
+      // a group's launches are G times larger than one item's: where the tiled
+      // column pass applies, time both column passes (identical values) at the
+      // group's scale and keep the faster
+      b->variants.clear();
+      for (auto& gp : plans) {
+        nk::ProblemBase* first = b->items[gp.items[0]]->impl;
+        int chosen = first->col_variant();
+        if (gp.items.size() > 1 && first->tiled_pass_applies() && (chosen == 8 || chosen == 0)) {
+          float best = 0.f;
+          GroupPlan bestp;
+          for (int cv : {8, 0}) {
+            GroupPlan c;
+            c.items = gp.items;
+            c.recs.resize(gp.items.size());
+            for (size_t k = 0; k < gp.items.size(); ++k)
+              b->items[gp.items[k]]->impl->record_matvec(vt[gp.items[k]], out[gp.items[k]], c.recs[k], cv);
+            const float ms = time_group(c, b->s);
+            if (cv == 8 || ms < best) { best = ms; bestp = std::move(c); chosen = cv; }
+          }
+          gp = std::move(bestp);
+        }
+        b->variants.push_back(chosen);
+      }
       std::vector<unsigned char> host;
-      std::vector<std::vector<size_t>> offs(groups.size());
-      for (size_t gi = 0; gi < groups.size(); ++gi) {
-        const auto& g = groups[gi];
-        const auto& seq = recs[g[0]].recs;
-        offs[gi].resize(seq.size());
-        for (size_t p = 0; p < seq.size(); ++p) {
-          if (seq[p].kind == nk::LaunchRec::COPY) continue;
-          host.resize((host.size() + 255) / 256 * 256);
-          offs[gi][p] = host.size();
-          for (size_t i : g) host.insert(host.end(), recs[i].recs[p].entry.begin(), recs[i].recs[p].entry.end());
-        }
-      }
+      for (auto& gp : plans) add_tables(gp, host);
       if (!host.empty()) {
         NK_HIP(hipMalloc(&b->tables, host.size()));
         NK_HIP(hipMemcpy(b->tables, host.data(), host.size(), hipMemcpyHostToDevice));
       }
       b->group_sizes.clear();
-      for (auto& g : groups) b->group_sizes.push_back((int)g.size());
+      for (auto& gp : plans) b->group_sizes.push_back((int)gp.items.size());
       hipGraph_t graph = nullptr;
       NK_HIP(hipStreamBeginCapture(b->s, hipStreamCaptureModeThreadLocal));
       try {
         NK_HIP(hipEventRecord(b->fork, b->s));
-        for (size_t gi = 0; gi < groups.size(); ++gi) {
-          const auto& g = groups[gi];
-          hipStream_t st = b->items[g[0]]->impl->stream();
+        for (size_t gi = 0; gi < plans.size(); ++gi) {
+          hipStream_t st = b->items[plans[gi].items[0]]->impl->stream();
           NK_HIP(hipStreamWaitEvent(st, b->fork, 0));
-          const auto& seq = recs[g[0]].recs;
-          for (size_t p = 0; p < seq.size(); ++p) {
-            if (seq[p].kind == nk::LaunchRec::COPY) {
-              for (size_t i : g) {
-                const auto& r = recs[i].recs[p];
-                NK_HIP(hipMemcpyAsync(r.dst, r.src, r.bytes, hipMemcpyDeviceToDevice, st));
-              }
-            } else {
-              launch_group(seq[p], (int)g.size(), (unsigned char*)b->tables + offs[gi][p], st);
-            }
-          }
+          issue_group(plans[gi], b->tables, st);
           NK_HIP(hipEventRecord(b->joins[gi], st));
           NK_HIP(hipStreamWaitEvent(b->s, b->joins[gi], 0));
         }
@@ -404,11 +511,7 @@ int nkreg_batch_hessian_matvec(nkreg_batch* b, const void* const* vt, void* cons
       b->key_gen.resize(cnt);
       for (size_t i = 0; i < cnt; ++i) b->key_gen[i] = b->items[i]->impl->generation;
     }
-    // the batch stream waits for every caller stream; every caller stream waits for the batch
-    for (size_t i = 0; i < cnt; ++i) {
-      NK_HIP(hipEventRecord(b->waits[i], b->items[i]->impl->caller_stream()));
-      NK_HIP(hipStreamWaitEvent(b->s, b->waits[i], 0));
-    }
+    // every caller stream waits for the batch
     NK_HIP(hipGraphLaunch(b->exec, b->s));
     NK_HIP(hipEventRecord(b->done, b->s));
     for (size_t i = 0; i < cnt; ++i) NK_HIP(hipStreamWaitEvent(b->items[i]->impl->caller_stream(), b->done, 0));
@@ -416,11 +519,13 @@ int nkreg_batch_hessian_matvec(nkreg_batch* b, const void* const* vt, void* cons
   });
 }
 
-int nkreg_batch_groups(nkreg_batch* b, int* groups, int* sizes, int cap) {
+int nkreg_batch_groups(nkreg_batch* b, int* groups, int* sizes, int* tiled, int cap) {
   NEED(b); NEED(groups);
   *groups = (int)b->group_sizes.size();
-  if (sizes)
-    for (int i = 0; i < cap && i < (int)b->group_sizes.size(); ++i) sizes[i] = b->group_sizes[i];
+  for (int i = 0; i < cap && i < (int)b->group_sizes.size(); ++i) {
+    if (sizes) sizes[i] = b->group_sizes[i];
+    if (tiled) tiled[i] = b->variants[i] == 0;
+  }
   return NKREG_OK;
 }
 

@@ -140,7 +140,11 @@ class ProblemBase {
   // captures several problems into one graph); checks the cached state.
   virtual void matvec_launches(const void* vt, void* out) = 0;
   // Records one matvec's launches (nothing is issued); checks the cached state.
-  virtual void record_matvec(const void* vt, void* out, Recorder& r) = 0;
+  // col_variant >= 0 records with that column pass (8 or 0 = tiled, which give
+  // identical values) instead of the handle's own choice.
+  virtual void record_matvec(const void* vt, void* out, Recorder& r, int col_variant = -1) = 0;
+  virtual bool tiled_pass_applies() const = 0;
+  virtual int col_variant() const = 0;
   virtual hipStream_t caller_stream() const = 0;
   // bumped whenever captured graphs become stale (beta change, graph switch, timer)
   unsigned generation = 0;
@@ -314,17 +318,25 @@ class ProblemT final : public ProblemBase {
   // Recording for batch groups: while rec is set, the matvec's launches are
   // recorded (here and in both spectral engines) instead of issued.
   Recorder* rec = nullptr;
-  void record_matvec(const void* vt, void* out, Recorder& r) override {
+  void record_matvec(const void* vt, void* out, Recorder& r, int col_variant) override {
     if (!state_valid) throw HipError(NKREG_ESTATE, "no gradient computed at the current velocity");
+    const int keep = sp.colE, keep64 = sp64.colE;
+    if (col_variant >= 0) sp.colE = sp64.colE = col_variant;
     rec = sp.rec = sp64.rec = &r;
     try {
       matvec_body(vt, out);
     } catch (...) {
       rec = sp.rec = sp64.rec = nullptr;
+      sp.colE = keep;
+      sp64.colE = keep64;
       throw;
     }
     rec = sp.rec = sp64.rec = nullptr;
+    sp.colE = keep;
+    sp64.colE = keep64;
   }
+  bool tiled_pass_applies() const override { return sp.any_tiled_pass(); }
+  int col_variant() const override { return sp.colE; }
 
   void copy(void* dst, const void* src, size_t bytes) {
     if (rec) {
@@ -627,14 +639,15 @@ class ProblemT final : public ProblemBase {
     return exec;
   }
 
-  // Tile autotuner, run once per handle at creation, before any result is
-  // computed: the column transforms run with 8 complex elements per lane (one
-  // wavefront per 512-point column) or 4 (two wavefronts per column). For each
-  // candidate a HIP graph of kTuneReps derivative and divergence column passes
-  // over zeroed spectra is captured on the internal stream and replayed under
-  // HIP events; the fastest candidate is kept. The choice is shared by every
-  // handle of the same grid and precision in the process, so they all compute
-  // bit-identical results. NKREG_COL_E in the environment fixes the choice.
+  // Column-pass autotuner, run once per handle at creation: the candidates are
+  // the one-workgroup-per-column-group pass with 8 complex elements per lane and,
+  // where an axis allows it, the LDS-tiled pass. Both run the same register FFT
+  // on the same values, so the choice changes the schedule and never a result.
+  // For each candidate a HIP graph of kTuneReps derivative and divergence column
+  // passes over zeroed spectra is captured on the internal stream and replayed
+  // under HIP events; the fastest is kept and shared by every handle of the same
+  // grid and precision in the process. NKREG_COL_E in the environment fixes the
+  // choice (8, 4 or tiled; 4 elements per lane rounds differently).
   static constexpr int kTuneReps = 16;
   static std::string col_variant_name(int ce) { return ce == 0 ? "col=tiled" : "col_E=" + std::to_string(ce); }
   std::string tuning;
@@ -660,8 +673,14 @@ class ProblemT final : public ProblemBase {
     NK_HIP(hipEventCreate(&e1));
     float best = 1e30f;
     int bestE = sp.colE;
-    std::vector<int> cands = {8, 4};
+    std::vector<int> cands = {8};
     if (sp.any_tiled_pass()) cands.push_back(0);
+    if (cands.size() == 1) {
+      sp.colE = 8;
+      tt.col_e[tune_key()] = 8;
+      tuning = "col_E=8 (no tiled pass applies to this grid)";
+      return;
+    }
     for (int ce : cands) {
       sp.colE = ce;
       hipGraph_t graph = nullptr;

@@ -226,7 +226,11 @@ def test_batch_matches_single_items(nk):
         B.hessian_matvec(ws, outs)
         for o, r in zip(outs, refs):
             assert np.array_equal(host(o), r)
-    assert sorted(B.groups()) == [1, 1, 2, 2, 3]
+    # five groups; the 64 x 32 pair may take the tiled column pass (timed at group scale),
+    # the others have no axis it applies to
+    plan = B.group_plan()
+    assert sorted(n for n, _ in plan) == [1, 1, 2, 2, 3]
+    assert sum(t for _, t in plan) <= 1
     # a beta change invalidates the graph; the rebuilt batch uses the new beta for that item
     probs[1].beta = 5e-3
     ref1 = host(probs[1].hessian_matvec(ws[1]))
@@ -375,3 +379,22 @@ def test_column_variants_match_oracle(nk, monkeypatch, shape, nt, gamma, variant
     assert rel_inf(gu, osp.grad(u)) < (1e-12 if prec == 64 else 2e-5)
     assert rel_l2(gu, osp.grad(u)) < (1e-12 if prec == 64 else 1e-5)
     G.close()
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("shape,nt,gamma", [((64, 128), 6, 0), ((128, 64, 64), 3, 1)])
+def test_tiled_and_wave_column_passes_are_bit_identical(nk, monkeypatch, shape, nt, gamma, prec):
+    """The tiled column pass and the 8-per-lane pass run the same register FFT on the same
+    values, so the autotuner's choice between them never changes a result."""
+    mT, mR, vstar, w = smooth_inputs(shape, nt, divfree=bool(gamma))
+    outs = []
+    for variant in ("8", "tiled"):
+        monkeypatch.setenv("NKREG_COL_E", variant)
+        G = nk.Problem(shape, nt, reg=2, incompressible=bool(gamma), beta=1e-3, precision=prec)
+        G.set_images(dev_t(mT, prec), dev_t(mR, prec))
+        J, _, _, g = G.objective_gradient(dev_v(0.5 * vstar))
+        outs.append((J, host(g), host(G.hessian_matvec(dev_v(w)))))
+        G.close()
+    assert outs[0][0] == outs[1][0]
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert np.array_equal(outs[0][2], outs[1][2])
