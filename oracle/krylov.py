@@ -112,6 +112,7 @@ class SolveReport:
     gnorm_inf: List[float] = field(default_factory=list)
     n_pde: int = 0
     matvecs: int = 0
+    gnorm0_inf: float = 0.0
     converged: bool = False
     line_search_failed: bool = False
     reason: str = ""
@@ -119,9 +120,12 @@ class SolveReport:
 
 def gauss_newton(P: rd.Problem, v0: Optional[np.ndarray] = None, gtol: float = 1e-3,
                  max_outer: int = 50, rule: str = "relgrad", tau_J: float = 1e-3,
-                 cfl_max: Optional[float] = None, pcg_maxit: Optional[int] = None
-                 ) -> Tuple[np.ndarray, SolveReport, rd.State]:
-    """Algorithm a:outer-iteration with GN-PCG search directions."""
+                 cfl_max: Optional[float] = None, pcg_maxit: Optional[int] = None,
+                 gref_inf: Optional[float] = None) -> Tuple[np.ndarray, SolveReport, rd.State]:
+    """Algorithm a:outer-iteration with GN-PCG search directions.
+
+    gref_inf: gradient scale of the relative-gradient rule (default: this solve's
+    ||g_0||_inf). A continuation passes its first level's value (see continuation)."""
     vl = np.zeros(P.vshape()) if v0 is None else v0.copy()
     n = int(np.prod(P.vshape()))
     maxit = n if pcg_maxit is None else pcg_maxit
@@ -130,7 +134,8 @@ def gauss_newton(P: rd.Problem, v0: Optional[np.ndarray] = None, gtol: float = 1
     rep.n_pde += 2
     J0 = S.J
     g0_2 = float(np.sqrt(np.sum(S.g * S.g)))
-    g0_inf = float(np.abs(S.g).max())
+    g0_inf = float(np.abs(S.g).max()) if not gref_inf else float(gref_inf)
+    rep.gnorm0_inf = float(np.abs(S.g).max())
     rep.J.append(S.J)
     rep.gnorm_inf.append(g0_inf)
     J_prev: Optional[float] = None
@@ -188,11 +193,133 @@ def gauss_newton(P: rd.Problem, v0: Optional[np.ndarray] = None, gtol: float = 1
 def continuation(P: rd.Problem, betas: Sequence[float], gtol: float = 1e-3,
                  max_outer: int = 50, cfl_max: Optional[float] = None
                  ) -> Tuple[np.ndarray, List[SolveReport]]:
-    """Solve for each beta in turn, warm-starting from the previous level."""
+    """Solve for each beta in turn, warm-starting from the previous level.
+
+    Reading: every level's relative-gradient rule is measured against the first
+    level's ||g_0||_inf (a warm-started level's own g_0 is already small)."""
     vl = np.zeros(P.vshape())
     reports = []
+    gref = None
     for b in betas:
         Pb = rd.Problem(P.mT, P.mR, P.nt, P.nc, P.reg, P.gamma, b)
-        vl, rep, _ = gauss_newton(Pb, vl, gtol=gtol, max_outer=max_outer, cfl_max=cfl_max)
+        vl, rep, _ = gauss_newton(Pb, vl, gtol=gtol, max_outer=max_outer, cfl_max=cfl_max, gref_inf=gref)
+        if gref is None:
+            gref = rep.gnorm0_inf
         reports.append(rep)
     return vl, reports
+
+
+@dataclass
+class BetaTrial:
+    beta: float
+    min_det: float
+    l2_rel: float
+    accepted: bool
+
+
+@dataclass
+class BetaSearchReport:
+    trials: List[BetaTrial] = field(default_factory=list)
+    beta_star: float = float("nan")
+    min_det_star: float = float("nan")
+    l2_rel_star: float = float("nan")
+    dbeta_min: float = 0.0
+    breached: bool = False
+    reason: str = ""
+
+    @property
+    def steps(self) -> int:
+        return len(self.trials)
+
+
+def beta_search_logic(evaluate: Callable[[float, Optional[np.ndarray]], Tuple[np.ndarray, float, float]],
+                      eps_F: float, beta_start: float = 1.0, beta_min: float = 1e-6,
+                      dbeta_rel: float = 0.05, l2_rel_min: float = 1e-2, max_steps: int = 64
+                      ) -> Tuple[Optional[np.ndarray], BetaSearchReport]:
+    """Parameter continuation in beta with a lower bound eps_F on det F_1.
+
+    Section "Parameter Selection" (parameter continuation) and Table t:para-cont:
+    solve at a large beta (underfitting), reduce beta by one order of magnitude
+    while min det F_1 >= eps_F, then bisect between the last accepted and the
+    breaching beta; stop when the change in beta drops below 5% of the beta at
+    which eps_F was breached. beta is bounded below by 1e-6, and the descent
+    also stops when the relative change of the L2 distance drops below 1e-2.
+
+    evaluate(beta, v_warm) solves at beta (warm-started from v_warm, None = zero)
+    and returns (v, min det F_1, ||m_R - m_1|| / ||m_R - m_T||).
+
+    Readings: the bisection midpoint is the arithmetic mean; every trial is
+    warm-started from the last accepted solution; the bisection step is half the
+    bracket, and it stops once that is below dbeta_rel times the first breaching
+    beta (these reproduce the steps, beta* and dbeta_min of Table t:para-cont).
+    """
+    rep = BetaSearchReport()
+    v_ok: Optional[np.ndarray] = None
+    beta_ok: Optional[float] = None
+    det_ok = l2_ok = float("nan")
+
+    def trial(beta: float):
+        v, d, l2 = evaluate(beta, v_ok)
+        acc = d >= eps_F
+        rep.trials.append(BetaTrial(beta, d, l2, acc))
+        return v, d, l2, acc
+
+    beta = beta_start
+    breach: Optional[float] = None
+    while True:
+        v, d, l2, acc = trial(beta)
+        if not acc:
+            breach = beta
+            break
+        prev_l2 = l2_ok if beta_ok is not None else None
+        v_ok, beta_ok, det_ok, l2_ok = v, beta, d, l2
+        if rep.steps >= max_steps:
+            rep.reason = "step limit"
+            break
+        if prev_l2 is not None and abs(prev_l2 - l2) < l2_rel_min * prev_l2:
+            rep.reason = "L2 distance stagnates"
+            break
+        if beta / 10.0 < beta_min:
+            rep.reason = "lower bound on beta"
+            break
+        beta = beta / 10.0
+    if breach is not None:
+        rep.breached = True
+        if beta_ok is None:
+            rep.reason = "bound breached at the first beta"
+            return None, rep
+        lo, hi = breach, beta_ok
+        rep.dbeta_min = dbeta_rel * breach
+        rep.reason = "bisection converged"
+        while (hi - lo) / 2.0 >= rep.dbeta_min:
+            if rep.steps >= max_steps:
+                rep.reason = "step limit"
+                break
+            mid = (lo + hi) / 2.0
+            v, d, l2, acc = trial(mid)
+            if acc:
+                v_ok, beta_ok, det_ok, l2_ok = v, mid, d, l2
+                hi = mid
+            else:
+                lo = mid
+    rep.beta_star, rep.min_det_star, rep.l2_rel_star = beta_ok, det_ok, l2_ok
+    return v_ok, rep
+
+
+def beta_search(P: rd.Problem, eps_F: float, beta_start: float = 1.0, gtol: float = 1e-3,
+                max_outer: int = 50, **kw) -> Tuple[Optional[np.ndarray], BetaSearchReport]:
+    """beta_search_logic with GN-PCG solves (relative-gradient rule against the first
+    solve's ||g_0||_inf) and det F_1 from the deformation-gradient solve."""
+    from . import defgrad as dg
+    r0 = float(np.sqrt(np.sum((P.mR - P.mT) ** 2)))
+    gref: List[Optional[float]] = [None]
+
+    def evaluate(beta: float, v_warm: Optional[np.ndarray]):
+        Pb = rd.Problem(P.mT, P.mR, P.nt, P.nc, P.reg, P.gamma, beta)
+        v, rep, S = gauss_newton(Pb, v_warm, gtol=gtol, max_outer=max_outer, gref_inf=gref[0])
+        if gref[0] is None:
+            gref[0] = rep.gnorm0_inf
+        _, stats = dg.det_stats(v, P.nt)
+        return v, stats[0], math.sqrt(2.0 * S.J_dist / P.hd) / r0
+
+    return beta_search_logic(evaluate, eps_F, beta_start, **kw)

@@ -105,6 +105,78 @@ def test_continuation_warm_starts():
     assert len(reps) == 3 and all(r.converged for r in reps)
 
 
+def test_continuation_measures_every_level_against_the_first_gradient():
+    """Reading of the continuation's stopping rule: a warm-started level stops when its
+    gradient falls below gtol times the first level's ||g_0||_inf."""
+    P, _ = small_problem(shape=(16, 16), nt=8, reg=2, beta=1e-3)
+    v, reps = kr.continuation(P, [1e-1, 1e-2])
+    g0 = reps[0].gnorm0_inf
+    assert reps[1].gnorm0_inf < g0
+    assert reps[1].gnorm_inf[-1] <= 1e-3 * g0
+    # a level that starts converged against that scale takes no step
+    v2, reps2 = kr.continuation(P, [1e-1, 1e-1])
+    assert reps2[1].iterations == 0
+
+
+GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden", "beta_search_table.json")
+
+
+@pytest.mark.parametrize("row,beta_c", [(0, 0.31), (1, 0.021), (2, 0.0335), (3, 2.65e-4)])
+def test_beta_search_reproduces_table_para_cont(row, beta_c):
+    """The search's control flow against Table t:para-cont: with a monotone det F_1(beta)
+    that crosses eps_F at beta_c (any value between the last rejected and the accepted
+    trial of that row), the steps, beta* and dbeta_min are the table's."""
+    import json
+    r = json.load(open(GOLDEN))["rows"][row]
+    eps = r["eps_F"]
+
+    def evaluate(beta, v_warm):
+        return np.array([beta]), eps * beta / beta_c, 1.0 / (1.0 + np.log10(1.0 / beta))
+
+    v, rep = kr.beta_search_logic(evaluate, eps)
+    assert rep.steps == r["steps"], [t.beta for t in rep.trials]
+    assert abs(rep.beta_star - r["beta_star"]) <= 1e-12 * r["beta_star"]
+    assert abs(rep.dbeta_min - r["dbeta_min"]) <= 1e-12 * r["dbeta_min"]
+    assert rep.breached and rep.min_det_star >= eps
+    assert v[0] == rep.beta_star
+
+
+def test_beta_search_warm_starts_from_the_last_accepted_solution_and_honours_bounds():
+    calls = []
+
+    def evaluate(beta, v_warm):
+        calls.append((beta, None if v_warm is None else float(v_warm[0])))
+        return np.array([beta]), 1.0, 0.5   # never breaches, L2 distance flat
+
+    _, rep = kr.beta_search_logic(evaluate, 0.5)
+    assert [c[0] for c in calls] == [1.0, 0.1]          # L2 distance stagnates after one decade
+    assert calls[1][1] == 1.0 and rep.reason.startswith("L2")
+    _, rep = kr.beta_search_logic(lambda b, w: (np.array([b]), 1.0, b), 0.5)
+    assert rep.trials[-1].beta >= 1e-6 and rep.reason == "lower bound on beta"
+    assert not rep.breached and rep.beta_star == rep.trials[-1].beta
+    _, rep = kr.beta_search_logic(lambda b, w: (np.array([b]), 0.0, b), 0.5)
+    assert rep.breached and rep.steps == 1 and np.isnan(rep.beta_star)
+
+
+def test_beta_search_on_a_registration_problem():
+    """Real solves: min det F_1 falls as beta falls; accepted trials satisfy the bound,
+    rejected ones break it, and beta* lies within dbeta_min of a rejected beta."""
+    shape, nt = (16, 16), 8
+    mT = synth.smooth_image(shape, 3, 0.6 * 16 ** 2 / 16)
+    vstar = synth.bandlimited_velocity(shape, 77, 2, 0.5, norm="linf")
+    P = rd.Problem(mT, tr.forward_only(mT, vstar, nt), nt, 1, 1, 0, 1.0)
+    v, rep = kr.beta_search(P, 0.8, max_outer=10)
+    assert rep.breached and rep.reason == "bisection converged"
+    for t in rep.trials:
+        assert (t.min_det >= 0.8) == t.accepted
+    acc = sorted((t.beta, t.min_det) for t in rep.trials)
+    assert all(a[1] <= b[1] + 1e-9 for a, b in zip(acc, acc[1:]))   # det F_1 grows with beta
+    rejected = [t.beta for t in rep.trials if not t.accepted]
+    assert min(abs(rep.beta_star - b) for b in rejected) < 2 * rep.dbeta_min
+    _, st = dg.det_stats(v, nt)
+    assert st[0] == rep.min_det_star
+
+
 def test_deformation_gradient_constant_velocity_is_identity():
     v = np.zeros((1, 2, 16, 16))
     v[0, 0], v[0, 1] = 0.4, -0.9
