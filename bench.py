@@ -224,6 +224,39 @@ def cube_section(nk, synth, torch, reps, kernel, precisions=(32, 64)):
     return out
 
 
+def beta_search_section(nk, synth, torch, precisions=(32, 64)):
+    """Parameter continuation in beta with a lower bound on det F_1 (decade descent from
+    beta = 1, then bisection), 256^2, H1, nt = 64: time to beta*, FP32 and FP64."""
+    dev = torch.device("cuda:0")
+    spec = synth.CONFIGS["c2beta"]
+    shape, nt, eps = spec.shape, spec.nt, spec.extra["eps_F"]
+    mT, vstar = synth.make_inputs(spec)
+    gen = nk.Problem(shape, nt, 1, spec.reg, False, 1.0, precision=64)
+    gen.set_images(torch.from_numpy(mT).to(dev), torch.zeros(shape, dtype=torch.float64, device=dev))
+    mR = gen.forward(torch.from_numpy(vstar).to(dev))
+    _, st = gen.det_grad_y(torch.from_numpy(vstar).to(dev))
+    gen.close()
+    out = {"grid": list(shape), "nt": nt, "reg": "H1", "eps_F": eps, "min_det_of_true_velocity": st[0]}
+    for prec in precisions:
+        dt = torch.float32 if prec == 32 else torch.float64
+        G = nk.Problem(shape, nt, 1, spec.reg, False, 1.0, precision=prec)
+        G.set_images(torch.from_numpy(mT).to(dev).to(dt), mR.to(dt))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        v, res = G.beta_search(eps, gtol=1e-3, max_outer=50)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        out[f"fp{prec}"] = {"seconds": secs, "steps": res.steps, "beta_star": res.beta_star,
+                            "min_det_star": res.min_det_star, "l2_rel_star": res.l2_rel_star,
+                            "dbeta_min": res.dbeta_min, "reason": res.reason,
+                            "newton_iterations": res.newton_iterations, "matvecs": res.cg_iterations,
+                            "trials": [[t.beta, t.min_det, t.accepted] for t in res.trials]}
+        log(f"beta search FP{prec}: {secs:.2f} s, {res.steps} solves, beta* = {res.beta_star:.5g}, "
+            f"min det F_1 = {res.min_det_star:.4f}, {res.cg_iterations} matvecs")
+        G.close()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -239,6 +272,7 @@ def main() -> int:
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration) and exit")
     ap.add_argument("--no-3d", action="store_true", help="skip the 256^3 workload")
+    ap.add_argument("--no-beta-search", action="store_true", help="skip the det F_1-bounded beta search")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -347,6 +381,8 @@ def main() -> int:
         out["roofline"] = roofline(k["name"], sym, k, measured_traffic(sym))
     if not args.no_batch:
         out["batch"] = batch_section(nk, synth, torch, reps=10)
+    if not args.no_beta_search:
+        out["beta_search"] = beta_search_section(nk, synth, torch, (32,) if args.no_fp64 else (32, 64))
     if not args.no_3d:
         out["cube_256"] = cube_section(nk, synth, torch, reps=4, kernel=args.kernel,
                                        precisions=(32,) if args.no_fp64 else (32, 64))

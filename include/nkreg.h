@@ -182,6 +182,56 @@ int nkreg_det_grad_y(nkreg_problem* p, const void* d_v, void* d_detF, double* h_
 int nkreg_newton_solve(nkreg_problem* p, void* d_v, const nkreg_solve_opts* opts,
                        nkreg_solve_report* report);
 
+/* Beta continuation (Section "Parameter Selection"): Newton solves at each
+ * beta of h_betas[0..levels) in turn, each warm-started from the previous
+ * level's solution in d_v (overwritten with the last level's). The relative
+ * gradient rule of every level uses opts->gref_inf if positive, else the first
+ * level's ||g_0||_inf (a warm-started level's own g_0 is already small).
+ * h_reports receives one report per level. The handle keeps the last beta.
+ * Returns ENOCONV if a level did not converge. Synchronises. */
+int nkreg_continuation(nkreg_problem* p, void* d_v, const double* h_betas, int levels,
+                       const nkreg_solve_opts* opts, nkreg_solve_report* h_reports);
+
+/* Parameter continuation in beta with a lower bound eps_F on det F_1
+ * (Section "Parameter Selection", Table t:para-cont). Solves at beta_start
+ * and divides beta by ten while min det F_1 >= eps_F; after the first beta
+ * that breaks the bound, bisects (arithmetic midpoint) between the last
+ * accepted and the breaching beta until half the bracket is below dbeta_rel
+ * times the first breaching beta. The descent also stops below beta_min or
+ * when ||m_R - m_1|| changes by less than l2_rel_min (relative) between two
+ * accepted betas. Every trial is warm-started from the last accepted solution
+ * (the first from d_v); the solves use opts->solve, whose gref_inf <= 0 means
+ * the first solve's ||g_0||_inf. On return d_v holds the solution at beta*,
+ * the smallest accepted beta, and the handle's beta is beta*. Returns ENOCONV
+ * if the bound is broken already at beta_start (d_v then holds that solve).
+ * Synchronises. */
+#define NKREG_MAX_BETA_TRIALS 64
+typedef struct {
+  double eps_F;         /* lower bound on min det F_1, in (0, 1) */
+  double beta_start;    /* first beta; <= 0: 1 */
+  double beta_min;      /* lower bound on beta; <= 0: 1e-6 */
+  double dbeta_rel;     /* bisection tolerance relative to the first breaching beta; <= 0: 0.05 */
+  double l2_rel_min;    /* stagnation bound on the relative change of ||m_R - m_1||; <= 0: 1e-2 */
+  int max_steps;        /* Newton solves at most; <= 0 or > NKREG_MAX_BETA_TRIALS: the maximum */
+  nkreg_solve_opts solve;
+} nkreg_beta_search_opts;
+
+typedef struct {
+  int steps;            /* Newton solves (trials) */
+  int breached;         /* 1 if some trial broke the bound */
+  int reason;           /* 1 bisection converged, 2 L2 distance stagnates, 3 lower bound on beta,
+                           4 step limit, 5 bound broken at beta_start */
+  double beta_star, min_det_star, l2_rel_star;  /* l2_rel = ||m_R - m_1|| / ||m_R - m_T|| */
+  double dbeta_min;     /* dbeta_rel x first breaching beta (0 without a breach) */
+  int newton_iterations, cg_iterations;
+  double seconds;
+  double trial_beta[NKREG_MAX_BETA_TRIALS], trial_min_det[NKREG_MAX_BETA_TRIALS],
+      trial_l2_rel[NKREG_MAX_BETA_TRIALS];
+  int trial_accepted[NKREG_MAX_BETA_TRIALS];
+} nkreg_beta_search_report;
+int nkreg_beta_search(nkreg_problem* p, void* d_v, const nkreg_beta_search_opts* opts,
+                      nkreg_beta_search_report* report);
+
 /* Building blocks exposed for testing the spectral machinery. */
 /* d_g (d*n) = spectral gradient of the scalar field d_u (n). */
 int nkreg_gradient(nkreg_problem* p, const void* d_u, void* d_g);

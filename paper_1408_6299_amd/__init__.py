@@ -8,7 +8,8 @@ from ._lib import NkregError, load as _load
 
 _load()
 
-from .api import Batch, Problem, SolveResult  # noqa: E402
+from .api import Batch, BetaSearchResult, BetaTrial, Problem, SolveResult  # noqa: E402
 from .autograd import RegistrationObjective, objective  # noqa: E402
 
-__all__ = ["Problem", "Batch", "SolveResult", "NkregError", "RegistrationObjective", "objective"]
+__all__ = ["Problem", "Batch", "SolveResult", "BetaSearchResult", "BetaTrial", "NkregError", "RegistrationObjective",
+           "objective"]

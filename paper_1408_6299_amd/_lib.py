@@ -30,6 +30,22 @@ class SolveReport(Structure):
                 ("gnorm_inf", c_double), ("seconds", c_double)]
 
 
+MAX_BETA_TRIALS = 64
+
+
+class BetaSearchOpts(Structure):
+    _fields_ = [("eps_F", c_double), ("beta_start", c_double), ("beta_min", c_double), ("dbeta_rel", c_double),
+                ("l2_rel_min", c_double), ("max_steps", c_int), ("solve", SolveOpts)]
+
+
+class BetaSearchReport(Structure):
+    _fields_ = [("steps", c_int), ("breached", c_int), ("reason", c_int), ("beta_star", c_double),
+                ("min_det_star", c_double), ("l2_rel_star", c_double), ("dbeta_min", c_double),
+                ("newton_iterations", c_int), ("cg_iterations", c_int), ("seconds", c_double),
+                ("trial_beta", c_double * MAX_BETA_TRIALS), ("trial_min_det", c_double * MAX_BETA_TRIALS),
+                ("trial_l2_rel", c_double * MAX_BETA_TRIALS), ("trial_accepted", c_int * MAX_BETA_TRIALS)]
+
+
 # name -> (restype, argtypes); every symbol declared in include/nkreg.h
 SIGNATURES = {
     "nkreg_version": (c_char_p, []),
@@ -53,6 +69,9 @@ SIGNATURES = {
                           POINTER(c_double)]),
     "nkreg_det_grad_y": (c_int, [c_void_p, c_void_p, c_void_p, POINTER(c_double)]),
     "nkreg_newton_solve": (c_int, [c_void_p, c_void_p, POINTER(SolveOpts), POINTER(SolveReport)]),
+    "nkreg_continuation": (c_int, [c_void_p, c_void_p, POINTER(c_double), c_int, POINTER(SolveOpts),
+                                   POINTER(SolveReport)]),
+    "nkreg_beta_search": (c_int, [c_void_p, c_void_p, POINTER(BetaSearchOpts), POINTER(BetaSearchReport)]),
     "nkreg_gradient": (c_int, [c_void_p, c_void_p, c_void_p]),
     "nkreg_divergence": (c_int, [c_void_p, c_void_p, c_void_p]),
     "nkreg_apply_reg": (c_int, [c_void_p, c_void_p, c_void_p]),

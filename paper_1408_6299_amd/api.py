@@ -40,6 +40,37 @@ class SolveResult:
     status: int
 
 
+@dataclass
+class BetaTrial:
+    beta: float
+    min_det: float
+    l2_rel: float
+    accepted: bool
+
+
+BETA_SEARCH_REASONS = {1: "bisection converged", 2: "L2 distance stagnates", 3: "lower bound on beta",
+                       4: "step limit", 5: "bound breached at the first beta"}
+
+
+@dataclass
+class BetaSearchResult:
+    trials: List[BetaTrial]
+    beta_star: float
+    min_det_star: float
+    l2_rel_star: float
+    dbeta_min: float
+    breached: bool
+    reason: str
+    newton_iterations: int
+    cg_iterations: int
+    seconds: float
+    status: int
+
+    @property
+    def steps(self) -> int:
+        return len(self.trials)
+
+
 class Problem:
     """One registration problem (images, grid, time steps, regulariser) on the current GPU.
 
@@ -225,32 +256,70 @@ class Problem:
         """
         v = self.zeros_v() if v is None else v.clone()
         self._check(v, self.vshape, "v")
-        o = SolveOpts()
-        o.max_outer, o.gtol, o.tau_J = int(max_outer), float(gtol), float(tau_J)
-        o.pcg_maxit, o.cfl_guard, o.verbose = int(pcg_maxit), int(cfl_guard), int(verbose)
-        o.gref_inf = float(gref_inf)
+        o = self._solve_opts(gtol, max_outer, tau_J, pcg_maxit, cfl_guard, verbose, gref_inf)
         rep = SolveReport()
         st = self.lib.nkreg_newton_solve(self._h, _ptr(v), byref(o), byref(rep))
         if st not in (_lib.OK, _lib.ENOCONV):
             check(st, "nkreg_newton_solve")
-        res = SolveResult(rep.iterations, rep.cg_iterations, rep.n_pde, bool(rep.line_search_failed),
-                          bool(rep.converged), rep.J0, rep.J, rep.J_dist, rep.J_reg, rep.gnorm0_inf,
-                          rep.gnorm_inf, rep.seconds, st)
-        return v, res
+        return v, self._result(rep, st)
+
+    @staticmethod
+    def _solve_opts(gtol=1e-3, max_outer=50, tau_J=1e-3, pcg_maxit=0, cfl_guard=False, verbose=False,
+                    gref_inf=0.0) -> SolveOpts:
+        o = SolveOpts()
+        o.max_outer, o.gtol, o.tau_J = int(max_outer), float(gtol), float(tau_J)
+        o.pcg_maxit, o.cfl_guard, o.verbose = int(pcg_maxit), int(cfl_guard), int(verbose)
+        o.gref_inf = float(gref_inf)
+        return o
+
+    @staticmethod
+    def _result(rep: SolveReport, st: int) -> "SolveResult":
+        return SolveResult(rep.iterations, rep.cg_iterations, rep.n_pde, bool(rep.line_search_failed),
+                           bool(rep.converged), rep.J0, rep.J, rep.J_dist, rep.J_reg, rep.gnorm0_inf,
+                           rep.gnorm_inf, rep.seconds, st)
 
     def continuation(self, betas: Sequence[float], v: Optional[torch.Tensor] = None, gtol: float = 1e-3,
                      max_outer: int = 50, **kw) -> Tuple[torch.Tensor, list]:
         """Solve for each beta in turn, warm-starting from the previous level; the relative
-        gradient rule of every level is measured against the first level's ||g_0||_inf."""
-        reports = []
-        gref = 0.0
-        for b in betas:
-            self.beta = b
-            v, rep = self.newton_solve(v, gtol=gtol, max_outer=max_outer, gref_inf=gref, **kw)
-            if gref == 0.0:
-                gref = rep.gnorm0_inf
-            reports.append(rep)
-        return v, reports
+        gradient rule of every level is measured against the first level's ||g_0||_inf
+        (nkreg_continuation). Returns (v, one report per level)."""
+        v = self.zeros_v() if v is None else v.clone()
+        self._check(v, self.vshape, "v")
+        n = len(betas)
+        bs = (c_double * max(1, n))(*[float(b) for b in betas])
+        reps = (SolveReport * max(1, n))()
+        o = self._solve_opts(gtol=gtol, max_outer=max_outer, **kw)
+        st = self.lib.nkreg_continuation(self._h, _ptr(v), bs, n, byref(o), reps)
+        if st not in (_lib.OK, _lib.ENOCONV):
+            check(st, "nkreg_continuation")
+        if n:
+            self._beta = float(betas[-1])
+        return v, [self._result(reps[i], st) for i in range(n)]
+
+    def beta_search(self, eps_F: float, v: Optional[torch.Tensor] = None, beta_start: float = 1.0,
+                    beta_min: float = 1e-6, dbeta_rel: float = 0.05, l2_rel_min: float = 1e-2,
+                    max_steps: int = 0, gtol: float = 1e-3, max_outer: int = 50, **kw
+                    ) -> Tuple[torch.Tensor, "BetaSearchResult"]:
+        """Parameter continuation in beta with the lower bound eps_F on det F_1
+        (nkreg_beta_search); returns (solution at beta*, result with every trial)."""
+        v = self.zeros_v() if v is None else v.clone()
+        self._check(v, self.vshape, "v")
+        o = _lib.BetaSearchOpts()
+        o.eps_F, o.beta_start, o.beta_min = float(eps_F), float(beta_start), float(beta_min)
+        o.dbeta_rel, o.l2_rel_min, o.max_steps = float(dbeta_rel), float(l2_rel_min), int(max_steps)
+        o.solve = self._solve_opts(gtol=gtol, max_outer=max_outer, **kw)
+        r = _lib.BetaSearchReport()
+        st = self.lib.nkreg_beta_search(self._h, _ptr(v), byref(o), byref(r))
+        if st not in (_lib.OK, _lib.ENOCONV):
+            check(st, "nkreg_beta_search")
+        if r.steps and r.beta_star == r.beta_star:
+            self._beta = float(r.beta_star)
+        trials = [BetaTrial(r.trial_beta[i], r.trial_min_det[i], r.trial_l2_rel[i], bool(r.trial_accepted[i]))
+                  for i in range(r.steps)]
+        res = BetaSearchResult(trials, r.beta_star, r.min_det_star, r.l2_rel_star, r.dbeta_min, bool(r.breached),
+                               BETA_SEARCH_REASONS.get(r.reason, str(r.reason)), r.newton_iterations,
+                               r.cg_iterations, r.seconds, st)
+        return v, res
 
     def gradient(self, u: torch.Tensor) -> torch.Tensor:
         self._check(u, self.shape, "u")

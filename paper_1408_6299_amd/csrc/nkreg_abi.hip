@@ -218,6 +218,18 @@ int nkreg_newton_solve(nkreg_problem* p, void* v, const nkreg_solve_opts* opts, 
   return guarded([&]() { Join j_(p->impl); return p->impl->newton(v, opts, rep); });
 }
 
+int nkreg_continuation(nkreg_problem* p, void* v, const double* betas, int levels, const nkreg_solve_opts* opts,
+                       nkreg_solve_report* reports) {
+  NEED(p); NEED(v);
+  if (levels < 0 || (levels > 0 && !betas)) return fail(NKREG_EINVAL, "bad beta levels");
+  return guarded([&]() { Join j_(p->impl); return p->impl->continuation(v, betas, levels, opts, reports); });
+}
+
+int nkreg_beta_search(nkreg_problem* p, void* v, const nkreg_beta_search_opts* opts, nkreg_beta_search_report* rep) {
+  NEED(p); NEED(v); NEED(opts);
+  return guarded([&]() { Join j_(p->impl); return p->impl->beta_search(v, opts, rep); });
+}
+
 int nkreg_gradient(nkreg_problem* p, const void* u, void* g) {
   NEED(p); NEED(u); NEED(g);
   return guarded([&]() { Join j_(p->impl); p->impl->gradient(u, g); return (int)NKREG_OK; });

@@ -128,6 +128,9 @@ class ProblemBase {
   virtual int pcg(const void* rhs, void* s, double rtol, int maxit, int* iters, double* relres) = 0;
   virtual void det_grad_y(const void* v, void* detF, double* stats) = 0;
   virtual int newton(void* v, const nkreg_solve_opts* o, nkreg_solve_report* rep) = 0;
+  virtual int continuation(void* v, const double* betas, int levels, const nkreg_solve_opts* o,
+                           nkreg_solve_report* reps) = 0;
+  virtual int beta_search(void* v, const nkreg_beta_search_opts* o, nkreg_beta_search_report* rep) = 0;
   virtual void gradient(const void* u, void* g) = 0;
   virtual void divergence(const void* w, void* s) = 0;
   virtual void apply_reg(const void* x, void* out) = 0;
@@ -897,6 +900,127 @@ class ProblemT final : public ProblemBase {
   }
 
   // ---- deformation gradient in FP64 ----
+  // ---- beta continuation (Section "Parameter Selection") ----
+  int continuation(void* vio, const double* betas, int levels, const nkreg_solve_opts* o,
+                   nkreg_solve_report* reps) override {
+    if (levels < 0 || (levels > 0 && !betas)) throw HipError(NKREG_EINVAL, "bad beta levels");
+    for (int i = 0; i < levels; ++i)
+      if (!(betas[i] > 0)) throw HipError(NKREG_EINVAL, "beta must be positive");
+    nkreg_solve_opts so{};
+    so.max_outer = 50; so.gtol = 1e-3; so.tau_J = 1e-3;
+    if (o) so = *o;
+    double gref = so.gref_inf;
+    int status = NKREG_OK;
+    for (int i = 0; i < levels; ++i) {
+      set_beta(betas[i]);
+      so.gref_inf = gref;
+      nkreg_solve_report r{};
+      if (newton(vio, &so, &r) != NKREG_OK) status = NKREG_ENOCONV;
+      if (gref <= 0) gref = r.gnorm0_inf;
+      if (reps) reps[i] = r;
+    }
+    return status;
+  }
+
+  // Parameter continuation in beta with a lower bound on det F_1 (Table
+  // t:para-cont): decade descent, then arithmetic bisection between the last
+  // accepted and the breaching beta; every trial warm-starts from the last
+  // accepted solution.
+  int beta_search(void* vio, const nkreg_beta_search_opts* oin, nkreg_beta_search_report* out) override {
+    need_images();
+    if (!oin) throw HipError(NKREG_EINVAL, "beta search options are required");
+    nkreg_beta_search_opts o = *oin;
+    if (!(o.eps_F > 0.0 && o.eps_F < 1.0)) throw HipError(NKREG_EINVAL, "eps_F must lie in (0, 1)");
+    if (o.beta_start <= 0) o.beta_start = 1.0;
+    if (o.beta_min <= 0) o.beta_min = 1e-6;
+    if (o.dbeta_rel <= 0) o.dbeta_rel = 0.05;
+    if (o.l2_rel_min <= 0) o.l2_rel_min = 1e-2;
+    if (o.max_steps <= 0 || o.max_steps > NKREG_MAX_BETA_TRIALS) o.max_steps = NKREG_MAX_BETA_TRIALS;
+    const auto t0 = std::chrono::steady_clock::now();
+    nkreg_beta_search_report r{};
+    double* v = (double*)vio;
+    DevBuf<double> vstart(nv), vok(nv);
+    copy(vstart.p, v, nv * sizeof(double));
+    red.enqueue<R>(RED_SUMSQDIFF, mR.p, mT.p, n, 0);
+    red.fetch(1);
+    const double r0 = std::sqrt(red.host[0]);
+    bool have_ok = false;
+    double beta_ok = 0, det_ok = 0, l2_ok = 0;
+    double gref = o.solve.gref_inf;
+    auto trial = [&](double beta) -> bool {
+      set_beta(beta);
+      copy(v, have_ok ? vok.p : vstart.p, nv * sizeof(double));
+      nkreg_solve_opts so = o.solve;
+      so.gref_inf = gref;
+      nkreg_solve_report nr{};
+      newton(v, &so, &nr);
+      if (gref <= 0) gref = nr.gnorm0_inf;
+      double st[4];
+      det_grad_y(v, nullptr, st);
+      const double l2 = r0 > 0 ? std::sqrt(2.0 * nr.J_dist / g.hd) / r0 : 0.0;
+      const bool acc = st[0] >= o.eps_F;
+      const int k = r.steps++;
+      r.trial_beta[k] = beta;
+      r.trial_min_det[k] = st[0];
+      r.trial_l2_rel[k] = l2;
+      r.trial_accepted[k] = acc;
+      r.newton_iterations += nr.iterations;
+      r.cg_iterations += nr.cg_iterations;
+      if (acc) {
+        copy(vok.p, v, nv * sizeof(double));
+        have_ok = true;
+        beta_ok = beta;
+        det_ok = st[0];
+        l2_ok = l2;
+      }
+      return acc;
+    };
+    double beta = o.beta_start, breach = 0.0;
+    while (true) {
+      const double prev_l2 = l2_ok;
+      const bool had_ok = have_ok;
+      if (!trial(beta)) {
+        breach = beta;
+        break;
+      }
+      if (r.steps >= o.max_steps) { r.reason = 4; break; }
+      if (had_ok && std::fabs(prev_l2 - l2_ok) < o.l2_rel_min * prev_l2) { r.reason = 2; break; }
+      if (beta / 10.0 < o.beta_min) { r.reason = 3; break; }
+      beta /= 10.0;
+    }
+    int status = NKREG_OK;
+    if (breach > 0.0) {
+      r.breached = 1;
+      if (!have_ok) {
+        r.reason = 5;
+        status = NKREG_ENOCONV;
+      } else {
+        double lo = breach, hi = beta_ok;
+        r.dbeta_min = o.dbeta_rel * breach;
+        r.reason = 1;
+        while ((hi - lo) / 2.0 >= r.dbeta_min) {
+          if (r.steps >= o.max_steps) { r.reason = 4; break; }
+          const double mid = (lo + hi) / 2.0;
+          if (trial(mid)) hi = mid;
+          else lo = mid;
+        }
+      }
+    }
+    if (have_ok) {
+      copy(v, vok.p, nv * sizeof(double));
+      set_beta(beta_ok);
+      r.beta_star = beta_ok;
+      r.min_det_star = det_ok;
+      r.l2_rel_star = l2_ok;
+    } else {
+      r.beta_star = r.min_det_star = r.l2_rel_star = std::nan("");
+    }
+    NK_HIP(hipStreamSynchronize(s));
+    r.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (out) *out = r;
+    return status;
+  }
+
   void det_grad_y(const void* vin, void* detF, double* stats) override {
     Spectral<double>& q = sp64;
     const long long dd = (long long)d * d;

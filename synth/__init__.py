@@ -214,6 +214,9 @@ def _spec_table() -> Dict[str, ProblemSpec]:
                              (512, 512), 32, 1, 2, 0, 1e-4, 32, 2, 400.0, "band", vel_seed=102,
                              vel_kmax=16, vel_target=cfl_literal_linf(512, 32), vel_norm="linf",
                              beta_levels=(1e-1, 1e-2, 1e-3, 1e-4))
+    c["c2beta"] = ProblemSpec("c2beta: 2D 256x256, H1, nt=64 (CFL 0.095), beta search with eps_F = 0.85",
+                              (256, 256), 64, 1, 1, 0, 1.0, 32, 2, 400.0, "band", vel_seed=211, vel_kmax=4,
+                              vel_target=0.15, vel_norm="linf", extra={"eps_F": 0.85})
     c["c4"] = ProblemSpec("c4: 3D 256^3 FP32, H2 + Stokes, beta=1e-3, nt=32 (CFL 0.1), checkpoint 8",
                           (256, 256, 256), 32, 1, 2, 1, 1e-3, 32, 4, 256.0, "band", vel_seed=104,
                           vel_kmax=8, vel_target=cfl_literal_linf(256, 32), vel_norm="linf",

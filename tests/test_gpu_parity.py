@@ -398,3 +398,62 @@ def test_tiled_and_wave_column_passes_are_bit_identical(nk, monkeypatch, shape, 
     assert outs[0][0] == outs[1][0]
     assert np.array_equal(outs[0][1], outs[1][1])
     assert np.array_equal(outs[0][2], outs[1][2])
+
+
+def beta_search_problem():
+    shape, nt = (16, 16), 8
+    mT = synth.smooth_image(shape, 3, 0.6 * 16 ** 2 / 16)
+    vstar = synth.bandlimited_velocity(shape, 77, 2, 0.5, norm="linf")
+    return shape, nt, mT, otr.forward_only(mT, vstar, nt)
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_beta_search_matches_oracle(nk, prec):
+    """nkreg_beta_search (decade descent, then bisection on the det F_1 bound) against the
+    oracle's search: in FP64 the same trials, decisions, beta* and solution; in FP32 the
+    decisions follow the bound and beta* lies within one bisection step of the oracle's."""
+    shape, nt, mT, mR = beta_search_problem()
+    P = ord_.Problem(mT, mR, nt, 1, 1, 0, 1.0)
+    v_ref, rep_ref = okr.beta_search(P, 0.8, max_outer=10)
+    G = nk.Problem(shape, nt, reg=1, beta=1.0, precision=prec)
+    G.set_images(dev_t(mT, prec), dev_t(mR, prec))
+    v, res = G.beta_search(0.8, max_outer=10)
+    assert res.breached and res.reason == "bisection converged" and res.status == 0
+    for t in res.trials:
+        assert (t.min_det >= 0.8) == t.accepted
+    assert G.beta == res.beta_star
+    if prec == 64:
+        assert [t.beta for t in res.trials] == [t.beta for t in rep_ref.trials]
+        assert [t.accepted for t in res.trials] == [t.accepted for t in rep_ref.trials]
+        for a, b in zip(res.trials, rep_ref.trials):
+            assert abs(a.min_det - b.min_det) < 1e-8 and abs(a.l2_rel - b.l2_rel) < 1e-8
+        assert res.beta_star == rep_ref.beta_star and res.dbeta_min == rep_ref.dbeta_min
+        assert rel_inf(host(v), v_ref) < 1e-6
+    else:
+        assert abs(res.beta_star - rep_ref.beta_star) <= 2 * rep_ref.dbeta_min
+    _, st = G.det_grad_y(v)
+    assert abs(st[0] - res.min_det_star) < 1e-12
+    G.close()
+
+
+def test_continuation_matches_oracle(nk):
+    """nkreg_continuation: each level warm-started, every level's relative-gradient rule
+    against the first level's ||g_0||_inf; FP64 against the oracle."""
+    P, G, _, _ = make_pair(nk, (32, 32), 8, 1, 2, 0, 1e-1, 64)
+    betas = [1e-1, 1e-2, 1e-3]
+    v_ref, reps_ref = okr.continuation(P, betas)
+    v, reps = G.continuation(betas)
+    assert [r.iterations for r in reps] == [r.iterations for r in reps_ref]
+    assert all(r.converged for r in reps)
+    assert abs(reps[0].gnorm0_inf - reps_ref[0].gnorm0_inf) <= 1e-10 * reps_ref[0].gnorm0_inf
+    # inexact PCG stops can fall one iteration apart across warm-started levels, so the
+    # solutions agree to the solve's tolerance (relative gradient 1e-3), not to rounding
+    assert rel_l2(host(v), v_ref) < 1e-4
+    Jd_ref = rd_objective_dist(P, v_ref, 1e-3)
+    assert abs(reps[-1].J_dist - Jd_ref) <= 1e-4 * Jd_ref
+    assert G.beta == 1e-3
+
+
+def rd_objective_dist(P, v, beta):
+    Pb = ord_.Problem(P.mT, P.mR, P.nt, P.nc, P.reg, P.gamma, beta)
+    return ord_.objective(Pb, v)[1]
