@@ -112,6 +112,16 @@ def hessian_matvec(P: Problem, S: State, vtl: np.ndarray) -> np.ndarray:
     return P.beta * sp.apply_A(vtl, P.reg, P.d) + P.project(Ft)
 
 
+def newton_hessian_matvec(P: Problem, S: State, vtl: np.ndarray) -> np.ndarray:
+    """Full-Newton Hessian matvec H v~ = beta A v~ + K[F~] with the lambda terms of
+    e:sec-order-iadj and the incremental body force lam~ grad m + lam grad m~ kept
+    (e:second-order-opt-cond); the Gauss-Newton matvec drops them."""
+    mt1, gmt, gmts = tr.incremental_state_trajectory(S.vl, vtl, S.traj, P.nt)
+    adj = tr.adjoint_trajectory(P.mR - S.traj.m1, S.vl, P.nt)
+    Ft = tr.newton_adjoint_with_force(-mt1, S.vl, vtl, S.traj, adj, gmt, gmts, P.nt)
+    return P.beta * sp.apply_A(vtl, P.reg, P.d) + P.project(Ft)
+
+
 def precond(P: Problem, r: np.ndarray) -> np.ndarray:
     """(beta A)^-1 with the zero mode unscaled, per coefficient and component."""
     return sp.apply_Pinv(r, P.reg, P.beta, P.d)

@@ -137,3 +137,77 @@ def incremental_state(vl: np.ndarray, vtl: np.ndarray, traj: Trajectory, nt: int
         r2 = -_dot(v1, sp.grad(mts)) - _dot(w1, traj.grad_ms[j])
         mt = mt + 0.5 * h * (r1 + r2)
     return mt
+
+
+def adjoint_trajectory(lam1: np.ndarray, vl: np.ndarray, nt: int) -> List[Tuple[np.ndarray, np.ndarray]]:
+    """The adjoint states of the gradient's backward solve from lam(1) = lam1:
+    entry j is (lam^{j+1}, lam*_j), j = 0..nt-1 (what the full-Newton matvec reads)."""
+    h = 1.0 / nt
+    out: List[Tuple[np.ndarray, np.ndarray]] = [None] * nt
+    lam = lam1.copy()
+    for j in range(nt - 1, -1, -1):
+        lam_next, lams = adjoint_step(lam, velocity_at(vl, j * h), velocity_at(vl, (j + 1) * h), h)
+        out[j] = (lam.copy(), lams)
+        lam = lam_next
+    return out
+
+
+def incremental_state_trajectory(vl: np.ndarray, vtl: np.ndarray, traj: Trajectory, nt: int
+                                 ) -> Tuple[np.ndarray, List[np.ndarray], List[np.ndarray]]:
+    """incremental_state that also keeps grad m~^j and grad m~*_j, j = 0..nt-1."""
+    h = 1.0 / nt
+    mt = np.zeros(traj.m1.shape)
+    g_list, gs_list = [], []
+    for j in range(nt):
+        v0 = velocity_at(vl, j * h)
+        v1 = velocity_at(vl, (j + 1) * h)
+        w0 = velocity_at(vtl, j * h)
+        w1 = velocity_at(vtl, (j + 1) * h)
+        gmt = sp.grad(mt)
+        r1 = -_dot(v0, gmt) - _dot(w0, traj.grad_m[j])
+        mts = mt + h * r1
+        gmts = sp.grad(mts)
+        r2 = -_dot(v1, gmts) - _dot(w1, traj.grad_ms[j])
+        g_list.append(gmt)
+        gs_list.append(gmts)
+        mt = mt + 0.5 * h * (r1 + r2)
+    return mt, g_list, gs_list
+
+
+def newton_adjoint_with_force(lamt1: np.ndarray, vl: np.ndarray, vtl: np.ndarray, traj: Trajectory,
+                              adj: List[Tuple[np.ndarray, np.ndarray]], grad_mt: List[np.ndarray],
+                              grad_mts: List[np.ndarray], nt: int) -> np.ndarray:
+    """Full-Newton incremental adjoint (e:sec-order-iadj) with its body force.
+
+    The second variations keep the terms in lambda that the Gauss-Newton system
+    drops: the incremental adjoint -dt lam~ - div(v lam~) - div(v~ lam) = 0 from
+    lam~(1) = -m~_1, and the incremental body force f~ = lam~ grad m + lam grad m~.
+    Discretised as the directional derivative of the gradient's Heun-adjoint step
+    and quadrature (so that the matvec is the exact Hessian of the discrete
+    objective): with lam = lam^{j+1}, lam* = lam*_j of the gradient's solve,
+        s1~ = div(v(t_{j+1}) lam~ + v~(t_{j+1}) lam),   lam~* = lam~ + h s1~,
+        s2~ = div(v(t_j) lam~* + v~(t_j) lam*),         lam~ <- lam~ + h/2 (s1~ + s2~),
+        F~_l += (h/2) [ b_l(t_j) (lam~* grad m^j + lam* grad m~^j)
+                        + b_l(t_{j+1}) (lam~ grad m*_j + lam grad m~*_j) ].
+    """
+    h = 1.0 / nt
+    nc = vl.shape[0]
+    lt = lamt1.copy()
+    F = np.zeros_like(vl)
+    for j in range(nt - 1, -1, -1):
+        v0 = velocity_at(vl, j * h)
+        v1 = velocity_at(vl, (j + 1) * h)
+        w0 = velocity_at(vtl, j * h)
+        w1 = velocity_at(vtl, (j + 1) * h)
+        b0 = basis_values(nc, j * h)
+        b1 = basis_values(nc, (j + 1) * h)
+        lam, lams = adj[j]
+        s1 = sp.div(v1 * lt + w1 * lam)
+        lts = lt + h * s1
+        s2 = sp.div(v0 * lts + w0 * lams)
+        for l in range(nc):
+            F[l] += 0.5 * h * (b0[l] * (lts * traj.grad_m[j] + lams * grad_mt[j])
+                               + b1[l] * (lt * traj.grad_ms[j] + lam * grad_mts[j]))
+        lt = lt + 0.5 * h * (s1 + s2)
+    return F
+

@@ -167,3 +167,43 @@ def test_hessian_rayleigh_quotient_at_corner_mode_matches_paper(reg, gamma, key)
     w = np.stack([corner, 0.0 * corner])[None]
     rq = P.inner(w, rd.hessian_matvec(P, S, w)) / P.inner(w, w)
     assert rq == pytest.approx(gold["max_real"], rel=5e-7)
+
+
+@pytest.mark.parametrize("nc,reg,gamma", [(1, 1, 0), (2, 2, 0), (1, 2, 1)])
+def test_newton_matvec_is_the_derivative_of_the_gradient_at_nonzero_residual(nc, reg, gamma):
+    """Full-Newton matvec (e:second-order-opt-cond) against central differences of the
+    exact discrete gradient at a point with a nonzero residual (lambda != 0): the error
+    decays as eps^2 and reaches rounding level; the GN matvec misses the lambda terms."""
+    P, vstar = make_problem(nc=nc, reg=reg, gamma=gamma)
+    v = 0.6 * vstar
+    S = rd.objective_gradient(P, v)
+    w = direction(P.shape, nc, 105, bool(gamma))
+    Hw = rd.newton_hessian_matvec(P, S, w)
+    errs = []
+    for eps in (1e-2, 1e-3, 1e-4):
+        fd = (rd.objective_gradient(P, v + eps * w).g - rd.objective_gradient(P, v - eps * w).g) / (2 * eps)
+        errs.append(np.abs(fd - Hw).max() / np.abs(Hw).max())
+    assert errs[0] / errs[1] > 50 and errs[2] < 1e-8, errs
+    gn = rd.hessian_matvec(P, S, w)
+    assert np.abs(gn - Hw).max() > 1e3 * errs[2] * np.abs(Hw).max()
+
+
+@pytest.mark.parametrize("nc,reg,gamma", [(1, 1, 0), (3, 2, 1)])
+def test_newton_matvec_is_symmetric(nc, reg, gamma):
+    P, vstar = make_problem(nc=nc, reg=reg, gamma=gamma)
+    S = rd.objective_gradient(P, 0.6 * vstar)
+    u = direction(P.shape, nc, 106, bool(gamma))
+    w = direction(P.shape, nc, 107, bool(gamma))
+    a = P.inner(u, rd.newton_hessian_matvec(P, S, w))
+    b = P.inner(rd.newton_hessian_matvec(P, S, u), w)
+    assert abs(a - b) <= 1e-12 * abs(a)
+
+
+def test_newton_matvec_equals_gn_at_zero_residual():
+    """lambda = m_R - m_1 vanishes at the true velocity, and with it every term that
+    separates the full-Newton from the Gauss-Newton matvec."""
+    P, vstar = make_problem(nc=1, reg=1, gamma=0, zero_residual=True)
+    S = rd.objective_gradient(P, vstar)
+    w = direction(P.shape, 1, 108, False)
+    Hn, Hg = rd.newton_hessian_matvec(P, S, w), rd.hessian_matvec(P, S, w)
+    assert np.abs(Hn - Hg).max() <= 1e-10 * np.abs(Hg).max()
