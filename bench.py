@@ -349,6 +349,28 @@ def main() -> int:
                            "grad_rel": rep.gnorm_inf / reps[0].gnorm0_inf if reps[0].gnorm0_inf else 0.0}
             log(f"FP{prec}: Newton solve {tsol:.3f} s, {tot_it} outer / {tot_cg} matvecs, mismatch {mis:.3e}")
             G.beta = spec.beta
+            # the same with the full-Newton Hessian (e:second-order-opt-cond)
+            G.hessian = "newton"
+            _, _, _, gN = G.objective_gradient(G.zeros_v())
+            rhsN = (-gN).contiguous()
+            nsteps = max(10, steps // 2)
+            timed_pcg_steps(G, rhsN, 3, torch)
+            secsN = timed_pcg_steps(G, rhsN, nsteps, torch)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            vN, repsN = G.continuation(spec.beta_levels, G.zeros_v(), gtol=1e-3, max_outer=50)
+            torch.cuda.synchronize()
+            tN = time.perf_counter() - t0
+            misN = 2.0 * repsN[-1].J_dist / (G.hd * float(np.sum((mR_h - mT_h) ** 2)))
+            r["full_newton"] = {"matvecs_per_s": nsteps / secsN, "ms_per_step": 1e3 * secsN / nsteps,
+                                "seconds": tN, "outer_iterations": sum(x.iterations for x in repsN),
+                                "matvecs": sum(x.cg_iterations for x in repsN), "relative_mismatch": misN,
+                                "converged": all(x.converged for x in repsN)}
+            log(f"FP{prec}: full Newton {nsteps / secsN:.1f} matvecs/s; solve {tN:.3f} s, "
+                f"{r['full_newton']['outer_iterations']} outer / {r['full_newton']['matvecs']} matvecs, "
+                f"mismatch {misN:.3e}")
+            G.hessian = "gn"
+            G.beta = spec.beta
         results[prec] = r
         G.close()
 
@@ -375,6 +397,7 @@ def main() -> int:
     if not args.no_solve:
         for prec in results:
             out[f"newton_fp{prec}"] = results[prec]["newton"]
+            out[f"full_newton_fp{prec}"] = results[prec]["full_newton"]
     k = results[32]["kernel"]
     if k["launches"] > 0 and k["avg_us"] > 0:
         sym = symbol_of(k["name"], results[32]["launch"])

@@ -116,6 +116,18 @@ int nkreg_destroy(nkreg_problem* p);
 /* Change beta (continuation; Section "Parameter Selection"). Keeps the cached state. */
 int nkreg_set_beta(nkreg_problem* p, double beta);
 
+/* Hessian used by nkreg_hessian_matvec, nkreg_pcg and nkreg_newton_solve:
+ * mode 0 = Gauss-Newton (e:gauss-newton, the default), 1 = full Newton
+ * (e:second-order-opt-cond: the incremental adjoint keeps -div(v~ lam) and the
+ * incremental body force keeps lam grad m~). Full Newton keeps lam^{j+1},
+ * lam*_j of every gradient evaluation and grad m~ of every matvec (2 nt + 2 nt d
+ * fields) and needs checkpoint_every = 0 (else ENOTIMPL). Switching modes
+ * invalidates the cached state (a new gradient is needed before a matvec). The
+ * full-Newton Hessian can be indefinite away from a minimiser: PCG stops at
+ * non-positive curvature and, if that happens in its first iteration, returns
+ * the preconditioned right-hand side P^-1 rhs (a descent direction). */
+int nkreg_set_hessian(nkreg_problem* p, int mode);
+
 /* Hessian matvecs are captured into a HIP graph per (input, output) pointer
  * pair and replayed (the default); enable = 0 launches every kernel eagerly.
  * The library runs on an internal stream joined to the caller's stream at every

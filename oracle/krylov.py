@@ -38,6 +38,12 @@ def pcg(apply_H: Callable[[np.ndarray], np.ndarray],
         rhs: np.ndarray, rtol: float, maxit: int) -> Tuple[np.ndarray, int, float, bool]:
     """Solve H x = rhs from x0 = 0; stop when ||r||_2 <= rtol ||rhs||_2.
 
+    Non-positive curvature <p, H p> <= 0 ends the iteration (Section "GN
+    Approximation": terminate the inner iteration on negative curvature). Reading:
+    when that happens in the first iteration, x is the preconditioned residual
+    direction p = P^-1 rhs (a descent direction) rather than zero, as in truncated
+    Newton methods.
+
     Returns (x, iterations, ||r||/||rhs||, converged).
     """
     x = np.zeros_like(rhs)
@@ -57,6 +63,8 @@ def pcg(apply_H: Callable[[np.ndarray], np.ndarray],
         Hp = apply_H(p)
         pHp = float(np.sum(p * Hp))
         if pHp <= 0.0:
+            if it == 0:
+                x = p.copy()
             break
         alpha = rz / pHp
         x = x + alpha * p
@@ -121,11 +129,14 @@ class SolveReport:
 def gauss_newton(P: rd.Problem, v0: Optional[np.ndarray] = None, gtol: float = 1e-3,
                  max_outer: int = 50, rule: str = "relgrad", tau_J: float = 1e-3,
                  cfl_max: Optional[float] = None, pcg_maxit: Optional[int] = None,
-                 gref_inf: Optional[float] = None) -> Tuple[np.ndarray, SolveReport, rd.State]:
+                 gref_inf: Optional[float] = None, hessian: str = "gn"
+                 ) -> Tuple[np.ndarray, SolveReport, rd.State]:
     """Algorithm a:outer-iteration with GN-PCG search directions.
 
     gref_inf: gradient scale of the relative-gradient rule (default: this solve's
-    ||g_0||_inf). A continuation passes its first level's value (see continuation)."""
+    ||g_0||_inf). A continuation passes its first level's value (see continuation).
+    hessian: "gn" (e:gauss-newton) or "newton" (e:second-order-opt-cond)."""
+    matvec = rd.newton_hessian_matvec if hessian == "newton" else rd.hessian_matvec
     vl = np.zeros(P.vshape()) if v0 is None else v0.copy()
     n = int(np.prod(P.vshape()))
     maxit = n if pcg_maxit is None else pcg_maxit
@@ -165,8 +176,7 @@ def gauss_newton(P: rd.Problem, v0: Optional[np.ndarray] = None, gtol: float = 1
             break
         g2 = float(np.sqrt(np.sum(S.g * S.g)))
         eta = min(0.5, math.sqrt(g2 / g0_2))
-        s, its, _, _ = pcg(lambda w: rd.hessian_matvec(P, S, w), lambda r: rd.precond(P, r),
-                           -S.g, eta, maxit)
+        s, its, _, _ = pcg(lambda w: matvec(P, S, w), lambda r: rd.precond(P, r), -S.g, eta, maxit)
         rep.cg_iterations.append(its)
         rep.matvecs += its
         rep.n_pde += 2 * its

@@ -54,6 +54,7 @@ SIGNATURES = {
     "nkreg_create": (c_int, [POINTER(Config), c_void_p, POINTER(c_void_p)]),
     "nkreg_destroy": (c_int, [c_void_p]),
     "nkreg_set_beta": (c_int, [c_void_p, c_double]),
+    "nkreg_set_hessian": (c_int, [c_void_p, c_int]),
     "nkreg_use_graphs": (c_int, [c_void_p, c_int]),
     "nkreg_describe": (c_int, [c_void_p, ctypes.c_char_p, c_int]),
     "nkreg_set_images": (c_int, [c_void_p, c_void_p, c_void_p]),

@@ -144,6 +144,18 @@ class Problem:
         check(self.lib.nkreg_set_beta(self._h, c_double(value)), "nkreg_set_beta")
         self._beta = float(value)
 
+    @property
+    def hessian(self) -> str:
+        """"gn" (Gauss-Newton, default) or "newton" (full Newton, e:second-order-opt-cond)."""
+        return getattr(self, "_hessian", "gn")
+
+    @hessian.setter
+    def hessian(self, mode: str) -> None:
+        if mode not in ("gn", "newton"):
+            raise ValueError("hessian must be 'gn' or 'newton'")
+        check(self.lib.nkreg_set_hessian(self._h, c_int(1 if mode == "newton" else 0)), "nkreg_set_hessian")
+        self._hessian = mode
+
     def describe(self) -> dict:
         """Launch configuration of the handle (tile choices, autotuner timings)."""
         import json

@@ -48,8 +48,20 @@ enum StageKind {
   ST_R2C = 7,    // plain R2C of a batch of real fields
   ST_C2R = 8,    // plain C2R of a batch of row spectra (times scale)
   ST_GRAD = 9,   // write the gradient of a batch of scalar fields
-  ST_DIV = 10    // write the divergence (already summed spectrum) as a real field
+  ST_DIV = 10,   // write the divergence (already summed spectrum) as a real field
+  // Full-Newton incremental adjoint (e:sec-order-iadj): the adjoint kinds with the
+  // lambda terms kept. Outputs v lam~ + v~ lam (lam from the gradient's adjoint
+  // solve); stage 1 adds lam* grad m~^j + lam grad m~*_j to the body force.
+  ST_NADJINIT = 11,
+  ST_NADJ1 = 12,
+  ST_NADJ2 = 13
 };
+
+// The adjoint kind a full-Newton kind extends (identity for the others).
+__host__ __device__ constexpr int base_kind(int k) {
+  return k == ST_NADJINIT ? ST_ADJINIT : (k == ST_NADJ1 ? ST_ADJ1 : (k == ST_NADJ2 ? ST_ADJ2 : k));
+}
+__host__ __device__ constexpr bool newton_kind(int k) { return k >= ST_NADJINIT && k <= ST_NADJ2; }
 
 template <typename R>
 struct StageArgs {
@@ -63,8 +75,14 @@ struct StageArgs {
   const R* vtl;              // incremental velocity coefficients [nc][d][n]
   const R* g0;               // grad m^j   [d][n]
   const R* g1;               // grad m*_j  [d][n]
-  R* g0w;                    // where FWD1 stores grad m^j
-  R* g1w;                    // where FWD2 stores grad m*_j
+  R* g0w;                    // where FWD1 stores grad m^j (INC1: grad m~^j)
+  R* g1w;                    // where FWD2 stores grad m*_j (INC2: grad m~*_j)
+  R* lamw0;                  // ADJ1, if set: stores lam^{j+1} here ...
+  R* lamw1;                  // ... and lam*_j here (the full-Newton matvec reads them)
+  const R* lt0;              // full-Newton kinds: lam of the gradient's solve at the output time
+  const R* lt1;              //   (NADJ1: lt0 = lam^{j+1}, lt1 = lam*_j; NADJINIT, NADJ2: lt0 only)
+  const R* gt0;              // NADJ1: grad m~^j  [d][n]
+  const R* gt1;              // NADJ1: grad m~*_j [d][n]
   R* acc;                    // Heun accumulator [n]
   R* lam;                    // adjoint state [n]
   R* F;                      // body force accumulators [nc][d][n]
@@ -87,8 +105,9 @@ struct StageArgs {
   R bv[kMaxNc];              // weights of the velocity used for the outputs (ADJINIT/ADJ1/ADJ2)
 };
 
-template <int KIND, int D>
+template <int KIND0, int D>
 struct StageShape {
+  static constexpr int KIND = base_kind(KIND0);
   // KIN: input row spectra after C2R; KOUT: real rows transformed by R2C.
   // The transport stages need only the gradient of the transported field: the
   // field itself travels as a real array (stage 2 stores it, stage 1 reads it).

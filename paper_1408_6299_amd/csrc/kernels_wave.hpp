@@ -56,15 +56,17 @@ __device__ __forceinline__ cplx<R> comb2(const R* __restrict__ f, const R* w, in
   return s;
 }
 
-template <typename R, int L, int E, int KIND, int D, bool NC1>
+template <typename R, int L, int E, int KIND0, int D, bool NC1>
 __device__ __forceinline__ void row_body(const StageArgs<R>& a, const cplx<R>* __restrict__ tw, int lmax) {
+  constexpr int KIND = base_kind(KIND0);    // full-Newton kinds run their adjoint kind's code ...
+  constexpr bool NEWT = newton_kind(KIND0);  // ... plus the lambda terms
   constexpr int M = L / 2;
   using P = WavePlan<M, E>;
   constexpr int LS = P::LS;
   constexpr int SPW = 64 / LS;
   constexpr int PADM = padded_e<E>(M);
   constexpr int H = E / 2;
-  using SH = StageShape<KIND, D>;
+  using SH = StageShape<KIND0, D>;
   constexpr int KIN = SH::KIN, KOUT = SH::KOUT, KMAX = SH::KMAX;
   constexpr bool FWDK = (KIND == ST_FWD1 || KIND == ST_FWD2);
   constexpr bool INCK = (KIND == ST_INC1 || KIND == ST_INC2);
@@ -104,10 +106,12 @@ __device__ __forceinline__ void row_body(const StageArgs<R>& a, const cplx<R>* _
 
   // ---- prefetch the epilogue's operands (natural layout, point pairs) ----
   constexpr int DV = (FWDK || INCK || ADJOUT) ? D : 1;
-  constexpr int DW = INCK ? D : 1;
+  constexpr int DW = (INCK || NEWT) ? D : 1;
   constexpr int DG = (INCK || KIND == ST_ADJ1) ? D : 1;
   constexpr int DF = (KIND == ST_ADJ1 && NC1) ? D : 1;
+  constexpr int DT = (NEWT && KIND == ST_ADJ1) ? D : 1;
   cplx<R> V[DV][E], W[DW][E], G0[DG][E], G1[DG][E], FV[DF][E], X1[E], X2[E];
+  cplx<R> LT0[E], LT1[E], GT0[DT][E], GT1[DT][E];
   const R* wv = (KIND == ST_FWD1 || KIND == ST_INC1) ? a.b0 : ((KIND == ST_FWD2 || KIND == ST_INC2) ? a.b1 : a.bv);
   const bool need_v = !(KIND == ST_ADJ2 && a.skip_out);
 #pragma unroll
@@ -133,6 +137,21 @@ __device__ __forceinline__ void row_body(const StageArgs<R>& a, const cplx<R>* _
         if constexpr (NC1) FV[c][e] = ld2(a.F + (long long)c * n, e);
       }
       X1[e] = ld2(a.lam, e);
+    }
+    if constexpr (NEWT) {
+      if (need_v) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) W[c][e] = comb2<R, D, NC1>(a.vtl, wv, a.nc, c, n, pidx(e));
+        LT0[e] = ld2(a.lt0, e);
+      }
+      if constexpr (KIND == ST_ADJ1) {
+        LT1[e] = ld2(a.lt1, e);
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          GT0[c][e] = ld2(a.gt0 + (long long)c * n, e);
+          GT1[c][e] = ld2(a.gt1 + (long long)c * n, e);
+        }
+      }
     }
     if constexpr (KIND == ST_FWD2 || KIND == ST_INC2 || KIND == ST_ADJ2) X1[e] = ld2(a.acc, e);
     if constexpr (KIND == ST_FWD1) X2[e] = ld2(a.mreal, e);
@@ -220,9 +239,12 @@ __device__ __forceinline__ void row_body(const StageArgs<R>& a, const cplx<R>* _
       }
     } else if constexpr (INCK) {
       cplx<R> r = {R(0), R(0)};
-      if (!zero_in) {
+      R* gw = (KIND == ST_INC1) ? a.g0w : a.g1w;   // grad m~ of this stage, for the full-Newton matvec
 #pragma unroll
-        for (int c = 0; c < D; ++c) r = csub(r, pmul(V[c][e], cscale(A[c][e], invL)));
+      for (int c = 0; c < D; ++c) {
+        const cplx<R> gc = zero_in ? cplx<R>{R(0), R(0)} : cscale(A[c][e], invL);
+        if (gw) st2(gw + (long long)c * n, e, gc);
+        r = csub(r, pmul(V[c][e], gc));
       }
 #pragma unroll
       for (int c = 0; c < D; ++c) r = csub(r, pmul(W[c][e], G0[c][e]));
@@ -239,16 +261,29 @@ __device__ __forceinline__ void row_body(const StageArgs<R>& a, const cplx<R>* _
       const cplx<R> lam = cadd(cscale(X1[e], a.ca), cscale(X2[e], a.cb));
       st2(a.lam, e, lam);
 #pragma unroll
-      for (int c = 0; c < D; ++c) O[c][e] = pmul(V[c][e], lam);
+      for (int c = 0; c < D; ++c) {
+        O[c][e] = pmul(V[c][e], lam);
+        if constexpr (NEWT) O[c][e] = pfma(W[c][e], LT0[e], O[c][e]);
+      }
     } else if constexpr (KIND == ST_ADJ1) {
       const cplx<R> s1 = cscale(A[0][e], invL);
       const cplx<R> lam = X1[e];
       const cplx<R> lams = cadd(lam, cscale(s1, h));
       st2(a.acc, e, cadd(lam, cscale(s1, hh)));
+      if constexpr (!NEWT) {
+        if (a.lamw0) {
+          st2(a.lamw0, e, lam);
+          st2(a.lamw1, e, lams);
+        }
+      }
 #pragma unroll
       for (int c = 0; c < D; ++c) {
-        const cplx<R> t0 = pmul(lams, G0[c][e]);
-        const cplx<R> t1 = pmul(lam, G1[c][e]);
+        cplx<R> t0 = pmul(lams, G0[c][e]);
+        cplx<R> t1 = pmul(lam, G1[c][e]);
+        if constexpr (NEWT) {
+          t0 = pfma(LT1[e], GT0[c][e], t0);   // lam*_j grad m~^j
+          t1 = pfma(LT0[e], GT1[c][e], t1);   // lam^{j+1} grad m~*_j
+        }
         if constexpr (NC1) {
           const cplx<R> f = cadd(FV[c][e], cscale(cadd(cscale(t0, a.b0[0]), cscale(t1, a.b1[0])), hh));
           st2(a.F + (long long)c * n, e, f);
@@ -260,6 +295,7 @@ __device__ __forceinline__ void row_body(const StageArgs<R>& a, const cplx<R>* _
           }
         }
         O[c][e] = pmul(V[c][e], lams);
+        if constexpr (NEWT) O[c][e] = pfma(W[c][e], LT1[e], O[c][e]);   // + v~(t_j) lam*_j
       }
     } else if constexpr (KIND == ST_ADJ2) {
       const cplx<R> s2 = cscale(A[0][e], invL);
@@ -267,7 +303,10 @@ __device__ __forceinline__ void row_body(const StageArgs<R>& a, const cplx<R>* _
       st2(a.lam, e, lam);
       if (!a.skip_out) {
 #pragma unroll
-        for (int c = 0; c < D; ++c) O[c][e] = pmul(V[c][e], lam);
+        for (int c = 0; c < D; ++c) {
+          O[c][e] = pmul(V[c][e], lam);
+          if constexpr (NEWT) O[c][e] = pfma(W[c][e], LT0[e], O[c][e]);   // + v~(t_j) lam^j
+        }
       }
     } else if constexpr (KIND == ST_R2C) {
       O[0][e] = X1[e];

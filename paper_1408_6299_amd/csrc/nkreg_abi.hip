@@ -218,6 +218,11 @@ int nkreg_newton_solve(nkreg_problem* p, void* v, const nkreg_solve_opts* opts, 
   return guarded([&]() { Join j_(p->impl); return p->impl->newton(v, opts, rep); });
 }
 
+int nkreg_set_hessian(nkreg_problem* p, int mode) {
+  NEED(p);
+  return guarded([&]() { Join j_(p->impl); p->impl->set_hessian(mode); return (int)NKREG_OK; });
+}
+
 int nkreg_continuation(nkreg_problem* p, void* v, const double* betas, int levels, const nkreg_solve_opts* opts,
                        nkreg_solve_report* reports) {
   NEED(p); NEED(v);

@@ -137,6 +137,8 @@ class ProblemBase {
   virtual double dot(const void* a, const void* b, long long cnt) = 0;
   virtual hipStream_t stream() const = 0;
   virtual void set_beta(double beta) = 0;
+  virtual void set_hessian(int mode) = 0;
+  virtual int hessian_mode() const = 0;
   virtual void use_graph_capture(bool on) = 0;
   virtual std::string describe() = 0;
   // One matvec as eager launches on the internal stream (used when a batch
@@ -258,6 +260,28 @@ class ProblemT final : public ProblemBase {
     NK_HIP(hipEventRecord(ev_out, s));
     NK_HIP(hipStreamWaitEvent(user_s, ev_out, 0));
   }
+
+  // ---- Hessian: Gauss-Newton (default) or full Newton (e:second-order-opt-cond) ----
+  // The full-Newton matvec reads the gradient's adjoint states (lam^{j+1}, lam*_j
+  // per step, kept by the gradient's adjoint sweep) and its own incremental
+  // state gradients (grad m~^j, grad m~*_j, kept by its incremental sweep).
+  bool full_newton = false;
+  DevBuf<R> ltraj, mtraj;
+  R* ltp(int j, int k) { return ltraj.p + ((size_t)(2 * j + k)) * n; }
+  R* mtp(int j, int k) { return mtraj.p + ((size_t)(2 * j + k)) * d * n; }
+  void set_hessian(int mode) override {
+    if (mode != 0 && mode != 1) throw HipError(NKREG_EINVAL, "Hessian mode must be 0 (GN) or 1 (full Newton)");
+    if (mode == 1 && K) throw HipError(NKREG_ENOTIMPL, "the full-Newton matvec needs the full trajectory (checkpoint_every = 0)");
+    NK_HIP(hipStreamSynchronize(s));
+    if (mode == 1 && !ltraj.p) {
+      ltraj.alloc((size_t)2 * nt * n);
+      mtraj.alloc((size_t)2 * nt * d * n);
+    }
+    if ((mode == 1) != full_newton) state_valid = false;  // the adjoint states must be recorded
+    full_newton = mode == 1;
+    drop_graphs();
+  }
+  int hessian_mode() const override { return full_newton ? 1 : 0; }
 
   // ---- HIP graph of the Hessian matvec, keyed by its (input, output) pointers ----
   bool use_graphs = true;
@@ -474,7 +498,18 @@ class ProblemT final : public ProblemBase {
 
   // ---- adjoint (conservative, backward Heun) with body-force accumulation ----
   // lam(1) = ca*src_a + cb*src_b; F (nc*d fields) = time-integrated lam grad m.
-  void adjoint_sweep(const R* vl, R ca, const R* src_a, R cb, const R* src_b, R* Fout) {
+  // record_lam keeps lam^{j+1} and lam*_j per step (for the full-Newton matvec).
+  void adjoint_sweep(const R* vl, R ca, const R* src_a, R cb, const R* src_b, R* Fout, bool record_lam = false) {
+    adjoint_sweep_k<false>(vl, nullptr, ca, src_a, cb, src_b, Fout, record_lam);
+  }
+  // NEWT: the full-Newton incremental adjoint (e:sec-order-iadj), with v~ = vtl and
+  // the gradient's adjoint states and this matvec's grad m~ trajectories.
+  template <bool NEWT>
+  void adjoint_sweep_k(const R* vl, const R* vtl, R ca, const R* src_a, R cb, const R* src_b, R* Fout,
+                       bool record_lam) {
+    constexpr int KI = NEWT ? ST_NADJINIT : ST_ADJINIT;
+    constexpr int K1 = NEWT ? ST_NADJ1 : ST_ADJ1;
+    constexpr int K2 = NEWT ? ST_NADJ2 : ST_ADJ2;
     const R h = R(1.0 / nt);
     const long long ns = g.nspec;
     cplx<R>* U0 = U.p;
@@ -485,8 +520,9 @@ class ProblemT final : public ProblemBase {
     a.vl = vl; a.nc = nc; a.h = h;
     a.src_a = src_a; a.src_b = src_b; a.ca = ca; a.cb = cb;
     a.lam = lam.p; a.out0 = U0; a.out1 = U1; a.out2 = U2;
+    if (NEWT) { a.vtl = vtl; a.lt0 = ltp(nt - 1, 0); }
     basis(1.0, a.bv);
-    sp.template row<ST_ADJINIT>(a, 1);
+    sp.template row<KI>(a, 1);
     for (int j = nt - 1; j >= 0; --j) {
       if (K && (j == nt - 1 || (j + 1) % K == 0)) load_segment(vl, j / K);
       sp.div_cols(U0, U1, U2, S2.p, Dsp.p);
@@ -494,19 +530,22 @@ class ProblemT final : public ProblemBase {
       b.spec = Dsp.p; b.vl = vl; b.nc = nc; b.h = h;
       b.lam = lam.p; b.acc = acc.p; b.F = Fout;
       b.g0 = trajp(j, 0); b.g1 = trajp(j, 1);
+      if (record_lam) { b.lamw0 = ltp(j, 0); b.lamw1 = ltp(j, 1); }
+      if (NEWT) { b.vtl = vtl; b.lt0 = ltp(j, 0); b.lt1 = ltp(j, 1); b.gt0 = mtp(j, 0); b.gt1 = mtp(j, 1); }
       basis(j * (double)h, b.b0);
       basis((j + 1) * (double)h, b.b1);
       basis(j * (double)h, b.bv);
       b.out0 = U0; b.out1 = U1; b.out2 = U2;
-      sp.template row<ST_ADJ1>(b, 1);
+      sp.template row<K1>(b, 1);
       sp.div_cols(U0, U1, U2, S2.p, Dsp.p);
       StageArgs<R> c{};
       c.spec = Dsp.p; c.vl = vl; c.nc = nc; c.h = h;
       c.lam = lam.p; c.acc = acc.p;
       basis(j * (double)h, c.bv);
       c.skip_out = (j == 0);
+      if (NEWT) { c.vtl = vtl; c.lt0 = j > 0 ? ltp(j - 1, 0) : nullptr; }   // lam^j
       c.out0 = U0; c.out1 = U1; c.out2 = U2;
-      sp.template row<ST_ADJ2>(c, 1);
+      sp.template row<K2>(c, 1);
     }
   }
 
@@ -520,6 +559,7 @@ class ProblemT final : public ProblemBase {
       a.spec = T.p; a.s1 = S1.p; a.s2 = S2.p; a.out0 = Ts.p;
       a.vl = vl; a.vtl = vtl; a.nc = nc; a.h = h; a.acc = acc.p;
       a.g0 = trajp(j, 0);
+      if (full_newton) a.g0w = mtp(j, 0);
       a.zero_state = (j == 0);
       a.mreal = mt1.p;
       basis(j * (double)h, a.b0);
@@ -529,6 +569,7 @@ class ProblemT final : public ProblemBase {
       b.spec = Ts.p; b.s1 = S1.p; b.s2 = S2.p; b.out0 = T.p;
       b.vl = vl; b.vtl = vtl; b.nc = nc; b.h = h; b.acc = acc.p;
       b.g1 = trajp(j, 1);
+      if (full_newton) b.g1w = mtp(j, 1);
       basis((j + 1) * (double)h, b.b1);
       b.out_real = mt1.p;  // m~^{j+1}; m~_1 after the last step
       sp.template row<ST_INC2>(b, 1);
@@ -598,7 +639,7 @@ class ProblemT final : public ProblemBase {
     forward_sweep(vl, true, m1.p);
     double jd, jr;
     objective_terms(v.p, &jd, &jr);
-    adjoint_sweep(vl, R(1), mR.p, R(-1), m1.p, F.p);
+    adjoint_sweep(vl, R(1), mR.p, R(-1), m1.p, F.p, full_newton);
     double* gdst = gout ? (double*)gout : gbuf.p;
     sp64.vecop(OP_HESS, v.p, force64(), gdst, nc, cfg.reg, cfg.incompressible, cfg.beta, Xs.p, Ys.p);
     state_valid = true;
@@ -732,8 +773,10 @@ class ProblemT final : public ProblemBase {
   void matvec_body(const void* vtin, void* out) {
     const double* vt = (const double*)vtin;
     const R* vl = kF64 ? (const R*)v.p : vR.p;
-    incremental_sweep(vl, to_transport(vt, vtR));
-    adjoint_sweep(vl, R(-1), mt1.p, R(0), nullptr, F.p);
+    const R* vtl = to_transport(vt, vtR);
+    incremental_sweep(vl, vtl);
+    if (full_newton) adjoint_sweep_k<true>(vl, vtl, R(-1), mt1.p, R(0), nullptr, F.p, false);
+    else adjoint_sweep(vl, R(-1), mt1.p, R(0), nullptr, F.p);
     sp64.vecop(OP_HESS, vt, force64(), (double*)out, nc, cfg.reg, cfg.incompressible, cfg.beta, Xs.p, Ys.p);
   }
 
@@ -792,7 +835,10 @@ class ProblemT final : public ProblemBase {
       hessian_matvec(kp.p, kq.p);
       const double pq = red.one<double>(RED_DOT, kp.p, kq.p, nv);
       if (!std::isfinite(pq)) throw HipError(NKREG_ENONFINITE, "p.Hp is not finite");
-      if (pq <= 0.0) break;  // non-positive curvature
+      if (pq <= 0.0) {  // non-positive curvature ends the iteration
+        if (it == 0) copy(x, kp.p, nv * sizeof(double));  // then x = P^-1 rhs, a descent direction
+        break;
+      }
       const double alpha = rz / pq;
       axpby(nv, alpha, kp.p, 1.0, x);
       axpby(nv, -alpha, kq.p, 1.0, kr.p);

@@ -476,8 +476,9 @@ class Spectral {
     constexpr int E = (L / 2 >= kRowE) ? kRowE : (L / 2 >= 4 ? 4 : 2);
     constexpr int SPW = 64 / WavePlan<L / 2, E>::LS;
     dim3 grid((unsigned)((g.rows + SPW - 1) / SPW), (unsigned)nf);
-    constexpr bool uses_nc = (KIND == ST_FWD1 || KIND == ST_FWD2 || KIND == ST_INC1 || KIND == ST_INC2 ||
-                              KIND == ST_ADJINIT || KIND == ST_ADJ1 || KIND == ST_ADJ2);
+    constexpr int BK = base_kind(KIND);
+    constexpr bool uses_nc = (BK == ST_FWD1 || BK == ST_FWD2 || BK == ST_INC1 || BK == ST_INC2 ||
+                              BK == ST_ADJINIT || BK == ST_ADJ1 || BK == ST_ADJ2);
     if (rec) {
       LaunchRec r;
       r.kind = LaunchRec::ROW;
@@ -507,11 +508,14 @@ class Spectral {
     switch (KIND) {
       case ST_FWD1: return D + 1 + v + (a.g0w ? D : 0) + 2;
       case ST_FWD2: return D + v + 1 + (a.g1w ? D : 0) + 2;
-      case ST_INC1: return (a.zero_state ? 0 : D + 1) + 2 * v + D + 2;
-      case ST_INC2: return D + 2 * v + D + 1 + 2;
+      case ST_INC1: return (a.zero_state ? 0 : D + 1) + 2 * v + D + 2 + (a.g0w ? D : 0);
+      case ST_INC2: return D + 2 * v + D + 1 + 2 + (a.g1w ? D : 0);
       case ST_ADJINIT: return (a.src_b ? 2 : 1) + v + 1 + D;
-      case ST_ADJ1: return 1 + 1 + 2 * D + 2 * v + 1 + D + v;
+      case ST_ADJ1: return 1 + 1 + 2 * D + 2 * v + 1 + D + v + (a.lamw0 ? 2 : 0);
       case ST_ADJ2: return a.skip_out ? 3 : 2 + v + 1 + D;
+      case ST_NADJINIT: return (a.src_b ? 2 : 1) + 2 * v + 2 + D;
+      case ST_NADJ1: return 1 + 1 + 4 * D + 2 * v + 1 + D + 2 * v + 2;
+      case ST_NADJ2: return a.skip_out ? 3 : 2 + 2 * v + 2 + D;
       case ST_R2C: case ST_C2R: case ST_DIV: return 2;
       case ST_GRAD: return D + D;
       default: return 0;

@@ -457,3 +457,85 @@ def test_continuation_matches_oracle(nk):
 def rd_objective_dist(P, v, beta):
     Pb = ord_.Problem(P.mT, P.mR, P.nt, P.nc, P.reg, P.gamma, beta)
     return ord_.objective(Pb, v)[1]
+
+
+NEWTON_CASES = [((32, 32), 8, 1, 1, 0, 1e-2), ((32, 64), 8, 3, 2, 1, 1e-3), ((16, 8, 16), 6, 1, 2, 1, 1e-3)]
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("case", NEWTON_CASES)
+def test_full_newton_matvec_matches_oracle(nk, case, prec):
+    """Full-Newton matvec (e:second-order-opt-cond) at a nonzero residual against the
+    oracle's; it differs from the GN matvec there, and is symmetric."""
+    shape, nt, nc, reg, gamma, beta = case
+    P, G, v, w = make_pair(nk, shape, nt, nc, reg, gamma, beta, prec)
+    G.hessian = "newton"
+    S = ord_.objective_gradient(P, v)
+    ref = ord_.newton_hessian_matvec(P, S, w)
+    G.objective_gradient(dev_v(v))
+    hw = host(G.hessian_matvec(dev_v(w)))
+    # FP32: lambda = m_R - m_1 carries the cancellation error of the FP32 transport
+    kappa = np.sqrt(np.sum(P.mT ** 2) / np.sum((P.mR - P.mT) ** 2))
+    tol = TOL[prec] if prec == 64 else TOL[32] * max(1.0, kappa / 10.0)
+    assert rel_l2(hw, ref) < tol
+    gn = ord_.hessian_matvec(P, S, w)
+    assert rel_l2(gn, ref) > 100 * tol
+    if prec == 64:
+        u = synth.bandlimited_velocity(shape, 301, 3, 0.2, divfree=bool(gamma), nc=nc)
+        hu = host(G.hessian_matvec(dev_v(u)))
+        a, b = float(np.sum(u * hw)), float(np.sum(hu * w))
+        assert abs(a - b) <= 1e-11 * abs(a)
+    G.close()
+
+
+def test_full_newton_mode_errors_and_state(nk):
+    """Switching the Hessian needs a new gradient; checkpointing is not supported with it."""
+    shape, nt = (16, 16), 4
+    mT, mR, vstar, w = smooth_inputs(shape, nt)
+    G = nk.Problem(shape, nt, precision=64)
+    G.set_images(dev_t(mT, 64), dev_t(mR, 64))
+    G.objective_gradient(dev_v(0.5 * vstar))
+    G.hessian = "newton"
+    with pytest.raises(nk.NkregError) as ei:
+        G.hessian_matvec(dev_v(w))
+    assert ei.value.status == -5   # ESTATE
+    G.objective_gradient(dev_v(0.5 * vstar))
+    G.hessian_matvec(dev_v(w))
+    G.close()
+    C = nk.Problem(shape, nt, precision=64, checkpoint_every=2)
+    with pytest.raises(nk.NkregError) as ei:
+        C.hessian = "newton"
+    assert ei.value.status == -9   # ENOTIMPL
+    C.close()
+
+
+def test_full_newton_batch_matches_single_items(nk):
+    items = []
+    for seed in (21, 22):
+        mT, mR, vstar, w = smooth_inputs((32, 32), 6, seed=seed)
+        G = nk.Problem((32, 32), 6, precision=32)
+        G.hessian = "newton"
+        G.set_images(dev_t(mT, 32), dev_t(mR, 32))
+        G.objective_gradient(dev_v(0.5 * vstar))
+        items.append((G, dev_v(w)))
+    refs = [host(G.hessian_matvec(w)) for G, w in items]
+    B = nk.Batch([G for G, _ in items])
+    outs = B.hessian_matvec([w for _, w in items])
+    assert B.groups() == [2]
+    for o, r in zip(outs, refs):
+        assert np.array_equal(host(o), r)
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_full_newton_solve_matches_oracle(nk, prec):
+    shape, nt, reg, beta = (32, 32), 8, 2, 1e-2
+    P, G, _, _ = make_pair(nk, shape, nt, 1, reg, 0, beta, prec)
+    G.hessian = "newton"
+    v_ref, rep_ref, S_ref = okr.gauss_newton(P, gtol=1e-3, max_outer=20, hessian="newton")
+    v, rep = G.newton_solve(gtol=1e-3, max_outer=20)
+    assert rep.converged and rep_ref.converged
+    mis0 = np.sum((P.mR - P.mT) ** 2)
+    assert abs(2 * rep.J_dist / (P.hd * mis0) - 2 * S_ref.J_dist / (P.hd * mis0)) <= 1e-4
+    if prec == 64:
+        assert rep.iterations == rep_ref.iterations
+        assert rel_l2(host(v), v_ref) < 1e-6
