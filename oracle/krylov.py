@@ -200,6 +200,72 @@ def gauss_newton(P: rd.Problem, v0: Optional[np.ndarray] = None, gtol: float = 1
     return vl, rep, S
 
 
+def scale_memory(alpha_tilde: float, alpha: float) -> float:
+    """Step-scale memory of the Picard scheme (Section "Parameter Selection",
+    "Optimization"): the next direction is scaled by alpha~ before the line search;
+    if the line search had to backtrack (alpha < 1), alpha~ shrinks by alpha,
+    and if alpha = 1 was accepted, alpha~ doubles."""
+    return alpha_tilde * alpha if alpha < 1.0 else 2.0 * alpha_tilde
+
+
+def picard(P: rd.Problem, v0: Optional[np.ndarray] = None, gtol: float = 1e-3, max_outer: int = 500,
+           memory: bool = True, stagnation: Tuple[int, float] = (10, 1e-6),
+           gref_inf: Optional[float] = None) -> Tuple[np.ndarray, SolveReport, rd.State]:
+    """Globalised Picard iteration (preconditioned gradient descent), e:picard.
+
+    The Picard iterate -(beta A)^-1 [gamma grad p + f] is used as a search direction
+    by subtracting the current iterate; with the eliminated pressure that is
+    s_k = -P^-1 g_k, P = beta A with the zero mode unscaled (Section "Picard
+    Method"). s_k is scaled by the memory alpha~ (scale_memory) and enters the
+    Armijo line search from alpha = 1. Stops on the relative-gradient rule, after
+    max_outer iterations, or when the objective changed by at most stagnation[1]
+    (relative to 1 + J_0) in each of stagnation[0] consecutive iterations (the
+    rule of Section "Convergence Study" for the Picard method).
+    """
+    vl = np.zeros(P.vshape()) if v0 is None else v0.copy()
+    rep = SolveReport()
+    S = rd.objective_gradient(P, vl)
+    rep.n_pde += 2
+    rep.gnorm0_inf = float(np.abs(S.g).max())
+    g0 = rep.gnorm0_inf if not gref_inf else float(gref_inf)
+    J0 = S.J
+    rep.J.append(S.J)
+    rep.gnorm_inf.append(rep.gnorm0_inf)
+    at = 1.0
+    flat = 0
+    k = 0
+    while True:
+        ginf = float(np.abs(S.g).max())
+        if ginf <= gtol * g0 or g0 == 0.0:
+            rep.converged, rep.reason = True, "relative gradient"
+            break
+        if flat >= stagnation[0]:
+            rep.converged, rep.reason = True, "objective stagnates"
+            break
+        if k >= max_outer:
+            rep.reason = "max outer iterations"
+            break
+        s = -(at if memory else 1.0) * rd.precond(P, S.g)
+        alpha, ok, trials = armijo(P, vl, S.J, S.g, s)
+        rep.n_pde += trials
+        if not ok:
+            rep.line_search_failed, rep.reason = True, "line search failed"
+            break
+        rep.alphas.append(alpha)
+        if memory:
+            at = scale_memory(at, alpha)
+        J_prev = S.J
+        vl = vl + alpha * s
+        S = rd.objective_gradient(P, vl)
+        rep.n_pde += 2
+        rep.J.append(S.J)
+        rep.gnorm_inf.append(float(np.abs(S.g).max()))
+        flat = flat + 1 if abs(J_prev - S.J) <= stagnation[1] * (1.0 + J0) else 0
+        k += 1
+    rep.iterations = k
+    return vl, rep, S
+
+
 def continuation(P: rd.Problem, betas: Sequence[float], gtol: float = 1e-3,
                  max_outer: int = 50, cfl_max: Optional[float] = None
                  ) -> Tuple[np.ndarray, List[SolveReport]]:

@@ -214,3 +214,46 @@ def test_det_compressible_matches_jacobi_transport():
         det1, _ = dg.det_stats(v, nt)
         res.append(np.abs(det1 - J).max())
     assert res[1] < 1e-3 and res[0] / res[1] > 3.0
+
+
+def test_picard_step_memory_follows_the_paper():
+    """alpha~ shrinks by alpha when the line search backtracks and doubles when alpha = 1."""
+    assert kr.scale_memory(1.0, 1.0) == 2.0
+    assert kr.scale_memory(4.0, 0.25) == 1.0
+    assert kr.scale_memory(0.5, 0.5) == 0.25
+
+
+def test_picard_first_direction_is_the_picard_iterate_minus_v():
+    """e:picard: the direction is -(beta A)^-1 [K f] - v on every nonzero mode (the
+    Picard iterate minus the current iterate); the zero mode is left unscaled."""
+    P, vstar = small_problem(shape=(16, 16), nt=6, reg=2, gamma=1, beta=1e-2)
+    v = 0.4 * vstar
+    S = rd.objective_gradient(P, v)
+    f = S.g - P.beta * sp.apply_A(v, P.reg, P.d)          # K[f] (the projected body force)
+    s = -rd.precond(P, S.g)
+    kx = np.fft.fftfreq(16, 1.0 / 16)
+    a = (kx[:, None] ** 2 + kx[None, :] ** 2) ** 2        # |k|^4 for H2
+    for c in range(2):
+        F = np.fft.fft2(f[0, c])
+        V = np.fft.fft2(v[0, c])
+        Sh = np.fft.fft2(s[0, c])
+        nz = a > 0
+        assert np.abs(Sh[nz] - (-F[nz] / (P.beta * a[nz]) - V[nz])).max() <= 1e-10 * np.abs(Sh).max()
+
+
+def test_picard_reaches_the_gauss_newton_solution_with_more_iterations():
+    """Both minimise J^h: the Picard (preconditioned gradient descent) solution agrees with
+    the GN-PCG one to the solve tolerance, with far more outer iterations and PDE solves;
+    the objective decreases monotonically."""
+    P, _ = small_problem(shape=(16, 16), nt=8, reg=1, beta=1e-1)
+    v_gn, rep_gn, S_gn = kr.gauss_newton(P, gtol=1e-4, max_outer=30)
+    never = (10 ** 9, 0.0)   # no stagnation stop: only the gradient rule ends the iteration
+    v_p, rep_p, S_p = kr.picard(P, gtol=1e-4, max_outer=2000, stagnation=never)
+    assert rep_gn.converged and rep_p.converged and rep_p.reason == "relative gradient"
+    assert np.abs(v_p - v_gn).max() <= 5e-3 * np.abs(v_gn).max()
+    assert rep_p.iterations > 3 * rep_gn.iterations and rep_p.n_pde > rep_gn.n_pde
+    assert all(b <= a for a, b in zip(rep_p.J, rep_p.J[1:]))
+    _, rep_nm, _ = kr.picard(P, gtol=1e-4, max_outer=5000, memory=False, stagnation=never)
+    assert rep_nm.iterations > rep_p.iterations       # the step-scale memory pays off
+    _, rep_st, _ = kr.picard(P, gtol=1e-4, max_outer=2000)
+    assert rep_st.reason == "objective stagnates" and rep_st.iterations < rep_p.iterations
