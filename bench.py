@@ -257,6 +257,39 @@ def beta_search_section(nk, synth, torch, precisions=(32, 64)):
     return out
 
 
+def solver_section(nk, torch, spec, mT_h, mR_h, precisions=(32, 64), beta=1e-2):
+    """GN-PCG against the globalised Picard iteration (preconditioned gradient descent with
+    the step-scale memory) on the headline grid at one beta, from v = 0 to a relative
+    gradient of 1e-3: wall time, outer iterations and hyperbolic PDE solves."""
+    dev = torch.device("cuda:0")
+    out = {"beta": beta, "gtol": 1e-3}
+    for prec in precisions:
+        dt = torch.float32 if prec == 32 else torch.float64
+        G = nk.Problem(spec.shape, spec.nt, 1, spec.reg, False, beta, precision=prec)
+        G.set_images(torch.from_numpy(mT_h).to(dev).to(dt), torch.from_numpy(mR_h).to(dev).to(dt))
+        r = {}
+        for name, run in (("gn_pcg", lambda: G.newton_solve(G.zeros_v(), gtol=1e-3, max_outer=50)),
+                          ("picard", lambda: G.picard_solve(G.zeros_v(), gtol=1e-3, max_outer=2000)),
+                          ("picard_no_stagnation_stop",
+                           lambda: G.picard_solve(G.zeros_v(), gtol=1e-3, max_outer=2000, stagnation=(0, 0.0)))):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, rep = run()
+            torch.cuda.synchronize()
+            r[name] = {"seconds": time.perf_counter() - t0, "outer_iterations": rep.iterations,
+                       "matvecs": rep.cg_iterations, "n_pde": rep.n_pde, "converged": rep.converged,
+                       "grad_rel": rep.gnorm_inf / rep.gnorm0_inf if rep.gnorm0_inf else 0.0}
+        log(f"FP{prec} beta={beta}: GN-PCG {r['gn_pcg']['seconds']:.3f} s ({r['gn_pcg']['n_pde']} PDE solves), "
+            f"Picard {r['picard']['seconds']:.3f} s ({r['picard']['n_pde']} PDE solves, "
+            f"{r['picard']['outer_iterations']} iterations, stops on stagnation at |g|/|g0| = "
+            f"{r['picard']['grad_rel']:.2e}); to the gradient tolerance: "
+            f"{r['picard_no_stagnation_stop']['seconds']:.3f} s, {r['picard_no_stagnation_stop']['n_pde']} PDE "
+            f"solves, converged {r['picard_no_stagnation_stop']['converged']}")
+        out[f"fp{prec}"] = r
+        G.close()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -404,6 +437,8 @@ def main() -> int:
         out["roofline"] = roofline(k["name"], sym, k, measured_traffic(sym))
     if not args.no_batch:
         out["batch"] = batch_section(nk, synth, torch, reps=10)
+    if not args.no_solve:
+        out["solvers"] = solver_section(nk, torch, spec, mT_h, mR_h, (32,) if args.no_fp64 else (32, 64))
     if not args.no_beta_search:
         out["beta_search"] = beta_search_section(nk, synth, torch, (32,) if args.no_fp64 else (32, 64))
     if not args.no_3d:

@@ -244,6 +244,25 @@ typedef struct {
 int nkreg_beta_search(nkreg_problem* p, void* d_v, const nkreg_beta_search_opts* opts,
                       nkreg_beta_search_report* report);
 
+/* Globalised Picard iteration (Section "Picard Method", e:picard): the Picard
+ * iterate -(beta A)^-1 [gamma grad p + f] minus the current iterate gives the
+ * direction s_k = -P^-1 g_k (a preconditioned gradient descent); it is scaled by
+ * the step memory alpha~ (memory = 1: alpha~ starts at 1, shrinks by alpha
+ * after a backtracking line search and doubles after alpha = 1) and enters the
+ * Armijo line search from alpha = 1. Stops on the relative gradient rule of
+ * opts (gtol > 0 required; opts->gref_inf as for Newton), after opts->max_outer
+ * iterations, or when J changed by at most stagnation_tol (1 + J_0) in each of
+ * stagnation_count consecutive iterations (<= 0: never). The report's
+ * cg_iterations is 0. popts may be NULL (memory on, 10 iterations, 1e-6).
+ * Returns ENOCONV without convergence. Synchronises. */
+typedef struct {
+  int memory;
+  int stagnation_count;
+  double stagnation_tol;
+} nkreg_picard_opts;
+int nkreg_picard_solve(nkreg_problem* p, void* d_v, const nkreg_solve_opts* opts, const nkreg_picard_opts* popts,
+                       nkreg_solve_report* report);
+
 /* Building blocks exposed for testing the spectral machinery. */
 /* d_g (d*n) = spectral gradient of the scalar field d_u (n). */
 int nkreg_gradient(nkreg_problem* p, const void* d_u, void* d_g);

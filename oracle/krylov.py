@@ -100,12 +100,14 @@ def cfl_number(vl: np.ndarray, nt: int) -> float:
 
 def armijo(P: rd.Problem, vl: np.ndarray, J: float, g: np.ndarray, s: np.ndarray,
            c1: float = 1e-4, max_halvings: int = 20) -> Tuple[float, bool, int]:
-    """Backtracking from alpha = 1; returns (alpha, success, trial count)."""
+    """Backtracking from alpha = 1; returns (alpha, success, trial count). A trial whose
+    transport overflows (non-finite J) is rejected like one that does not decrease J."""
     slope = P.inner(g, s)
     alpha = 1.0
     for trial in range(max_halvings + 1):
-        Jt, _, _ = rd.objective(P, vl + alpha * s)
-        if Jt <= J + c1 * alpha * slope:
+        with np.errstate(over="ignore", invalid="ignore"):
+            Jt, _, _ = rd.objective(P, vl + alpha * s)
+        if math.isfinite(Jt) and Jt <= J + c1 * alpha * slope:
             return alpha, True, trial + 1
         alpha *= 0.5
     return 0.0, False, max_halvings + 1

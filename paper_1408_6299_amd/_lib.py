@@ -30,6 +30,10 @@ class SolveReport(Structure):
                 ("gnorm_inf", c_double), ("seconds", c_double)]
 
 
+class PicardOpts(Structure):
+    _fields_ = [("memory", c_int), ("stagnation_count", c_int), ("stagnation_tol", c_double)]
+
+
 MAX_BETA_TRIALS = 64
 
 
@@ -70,6 +74,8 @@ SIGNATURES = {
                           POINTER(c_double)]),
     "nkreg_det_grad_y": (c_int, [c_void_p, c_void_p, c_void_p, POINTER(c_double)]),
     "nkreg_newton_solve": (c_int, [c_void_p, c_void_p, POINTER(SolveOpts), POINTER(SolveReport)]),
+    "nkreg_picard_solve": (c_int, [c_void_p, c_void_p, POINTER(SolveOpts), POINTER(PicardOpts),
+                                   POINTER(SolveReport)]),
     "nkreg_continuation": (c_int, [c_void_p, c_void_p, POINTER(c_double), c_int, POINTER(SolveOpts),
                                    POINTER(SolveReport)]),
     "nkreg_beta_search": (c_int, [c_void_p, c_void_p, POINTER(BetaSearchOpts), POINTER(BetaSearchReport)]),

@@ -290,6 +290,23 @@ class Problem:
                            bool(rep.converged), rep.J0, rep.J, rep.J_dist, rep.J_reg, rep.gnorm0_inf,
                            rep.gnorm_inf, rep.seconds, st)
 
+    def picard_solve(self, v: Optional[torch.Tensor] = None, gtol: float = 1e-3, max_outer: int = 500,
+                     memory: bool = True, stagnation: Tuple[int, float] = (10, 1e-6), **kw
+                     ) -> Tuple[torch.Tensor, SolveResult]:
+        """Globalised Picard iteration (preconditioned gradient descent with the step-scale
+        memory) from v (zero if None); returns (v, report). stagnation = (count, tol),
+        count <= 0 disables the objective-stagnation stop."""
+        v = self.zeros_v() if v is None else v.clone()
+        self._check(v, self.vshape, "v")
+        o = self._solve_opts(gtol=gtol, max_outer=max_outer, **kw)
+        po = _lib.PicardOpts()
+        po.memory, po.stagnation_count, po.stagnation_tol = int(memory), int(stagnation[0]), float(stagnation[1])
+        rep = SolveReport()
+        st = self.lib.nkreg_picard_solve(self._h, _ptr(v), byref(o), byref(po), byref(rep))
+        if st not in (_lib.OK, _lib.ENOCONV):
+            check(st, "nkreg_picard_solve")
+        return v, self._result(rep, st)
+
     def continuation(self, betas: Sequence[float], v: Optional[torch.Tensor] = None, gtol: float = 1e-3,
                      max_outer: int = 50, **kw) -> Tuple[torch.Tensor, list]:
         """Solve for each beta in turn, warm-starting from the previous level; the relative

@@ -218,6 +218,12 @@ int nkreg_newton_solve(nkreg_problem* p, void* v, const nkreg_solve_opts* opts, 
   return guarded([&]() { Join j_(p->impl); return p->impl->newton(v, opts, rep); });
 }
 
+int nkreg_picard_solve(nkreg_problem* p, void* v, const nkreg_solve_opts* opts, const nkreg_picard_opts* popts,
+                       nkreg_solve_report* rep) {
+  NEED(p); NEED(v);
+  return guarded([&]() { Join j_(p->impl); return p->impl->picard(v, opts, popts, rep); });
+}
+
 int nkreg_set_hessian(nkreg_problem* p, int mode) {
   NEED(p);
   return guarded([&]() { Join j_(p->impl); p->impl->set_hessian(mode); return (int)NKREG_OK; });

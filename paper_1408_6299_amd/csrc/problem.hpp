@@ -128,6 +128,7 @@ class ProblemBase {
   virtual int pcg(const void* rhs, void* s, double rtol, int maxit, int* iters, double* relres) = 0;
   virtual void det_grad_y(const void* v, void* detF, double* stats) = 0;
   virtual int newton(void* v, const nkreg_solve_opts* o, nkreg_solve_report* rep) = 0;
+  virtual int picard(void* v, const nkreg_solve_opts* o, const nkreg_picard_opts* po, nkreg_solve_report* rep) = 0;
   virtual int continuation(void* v, const double* betas, int levels, const nkreg_solve_opts* o,
                            nkreg_solve_report* reps) = 0;
   virtual int beta_search(void* v, const nkreg_beta_search_opts* o, nkreg_beta_search_report* rep) = 0;
@@ -609,14 +610,26 @@ class ProblemT final : public ProblemBase {
   }
 
   // J_dist (FP64 reduction of the transport-precision mismatch) and J_reg (FP64).
-  void objective_terms(const double* vl, double* Jd, double* Jr) {
+  void objective_terms(const double* vl, double* Jd, double* Jr, bool require_finite = true) {
     sp64.vecop(OP_A, vl, nullptr, tmpv.p, nc, cfg.reg, 0, cfg.beta, Xs.p, Ys.p);
     red.enqueue<R>(RED_SUMSQDIFF, mR.p, m1.p, n, 0);
     red.enqueue<double>(RED_DOT, vl, tmpv.p, nv, 1);
     red.fetch(2);
     *Jd = 0.5 * g.hd * red.host[0];
     *Jr = 0.5 * cfg.beta * g.hd * red.host[1];
-    if (!std::isfinite(*Jd) || !std::isfinite(*Jr)) throw HipError(NKREG_ENONFINITE, "objective is not finite");
+    if (require_finite && (!std::isfinite(*Jd) || !std::isfinite(*Jr)))
+      throw HipError(NKREG_ENONFINITE, "objective is not finite");
+  }
+
+  // J at a line-search trial point; +inf if the trial's transport overflowed,
+  // which rejects the trial (the line search then halves the step).
+  double trial_objective(const double* vl) {
+    forward_sweep(to_transport(vl, vtR), false, m1.p);
+    state_valid = false;
+    double jd, jr;
+    objective_terms(vl, &jd, &jr, false);
+    const double J = jd + jr;
+    return std::isfinite(J) ? J : HUGE_VAL;
   }
 
   void objective(const void* vin, double* J, double* Jd, double* Jr) override {
@@ -857,6 +870,91 @@ class ProblemT final : public ProblemBase {
     if (relres) *relres = rn / nb;
     return ok ? NKREG_OK : NKREG_ENOCONV;
   }
+  // Armijo backtracking along sbuf from alpha = 1 (c1 = 1e-4, at most 20
+  // halvings; Section "Numerical Optimization"); gbuf holds the gradient at vk.
+  bool armijo(const double* vk, double J, double* alpha_out, int* n_pde) {
+    const double slope = g.hd * red.one<double>(RED_DOT, gbuf.p, sbuf.p, nv);
+    double alpha = 1.0;
+    for (int trial = 0; trial <= 20; ++trial) {
+      lincomb(nv, 1.0, vk, alpha, sbuf.p, vtrial.p);
+      const double Jt = trial_objective(vtrial.p);
+      *n_pde += 1;
+      if (Jt <= J + 1e-4 * alpha * slope) {
+        *alpha_out = alpha;
+        return true;
+      }
+      alpha *= 0.5;
+    }
+    *alpha_out = 0.0;
+    return false;
+  }
+  // Halves sbuf until vk + sbuf satisfies the CFL bound (before the line search).
+  void cfl_guard(const double* vk) {
+    if (cfg.cfl_max <= 0) return;
+    for (int h = 0; h < 30; ++h) {
+      lincomb(nv, 1.0, vk, 1.0, sbuf.p, vtrial.p);
+      if (cfl_number(vtrial.p) <= cfg.cfl_max) break;
+      axpby(nv, 0.0, sbuf.p, 0.5, sbuf.p);
+    }
+  }
+
+  // ---- globalised Picard iteration (preconditioned gradient descent, e:picard) ----
+  // s_k = -alpha~ P^-1 g_k (the Picard iterate minus v_k), Armijo from alpha = 1;
+  // alpha~ shrinks by alpha after backtracking and doubles after alpha = 1.
+  int picard(void* vio, const nkreg_solve_opts* o, const nkreg_picard_opts* po, nkreg_solve_report* rep) override {
+    need_images();
+    auto t0 = std::chrono::steady_clock::now();
+    nkreg_solve_opts opt{};
+    opt.max_outer = 500; opt.gtol = 1e-3;
+    if (o) opt = *o;
+    if (!(opt.gtol > 0)) throw HipError(NKREG_EINVAL, "the Picard iteration stops on the relative gradient rule (gtol > 0)");
+    nkreg_picard_opts pop{};
+    pop.memory = 1; pop.stagnation_count = 10; pop.stagnation_tol = 1e-6;
+    if (po) pop = *po;
+    nkreg_solve_report r{};
+    double* vk = (double*)vio;
+    double J, Jd, Jr;
+    objective_gradient(vk, &J, &Jd, &Jr, gbuf.p);
+    r.n_pde += 2;
+    r.J0 = J;
+    double ginf = red.one<double>(RED_MAXABS, gbuf.p, nullptr, nv);
+    r.gnorm0_inf = ginf;
+    const double g0inf = opt.gref_inf > 0 ? opt.gref_inf : ginf;
+    double at = 1.0;
+    int flat = 0, k = 0;
+    bool conv = false;
+    while (true) {
+      if (ginf <= opt.gtol * g0inf || g0inf == 0.0) { conv = true; break; }
+      if (pop.stagnation_count > 0 && flat >= pop.stagnation_count) { conv = true; break; }
+      if (k >= opt.max_outer) break;
+      precond(gbuf.p, sbuf.p);
+      axpby(nv, 0.0, sbuf.p, pop.memory ? -at : -1.0, sbuf.p);
+      if (cfg.incompressible) project(sbuf.p, sbuf.p);
+      if (opt.cfl_guard) cfl_guard(vk);
+      double alpha = 0.0;
+      if (!armijo(vk, J, &alpha, &r.n_pde)) { r.line_search_failed = 1; break; }
+      if (pop.memory) at = alpha < 1.0 ? at * alpha : 2.0 * at;
+      axpby(nv, alpha, sbuf.p, 1.0, vk);
+      const double Jprev = J;
+      objective_gradient(vk, &J, &Jd, &Jr, gbuf.p);
+      r.n_pde += 2;
+      flat = std::fabs(Jprev - J) <= pop.stagnation_tol * (1.0 + r.J0) ? flat + 1 : 0;
+      ginf = red.one<double>(RED_MAXABS, gbuf.p, nullptr, nv);
+      ++k;
+      if (opt.verbose)
+        fprintf(stderr, "[nkreg] picard k=%d J=%.6e |g|inf=%.3e rel=%.3e alpha=%g scale=%g\n", k, J, ginf,
+                ginf / g0inf, alpha, at);
+    }
+    NK_HIP(hipStreamSynchronize(s));
+    r.iterations = k;
+    r.converged = conv ? 1 : 0;
+    r.J = J; r.J_dist = Jd; r.J_reg = Jr;
+    r.gnorm_inf = ginf;
+    r.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (rep) *rep = r;
+    return conv && !r.line_search_failed ? NKREG_OK : NKREG_ENOCONV;
+  }
+
   // ---- outer iteration (GN-PCG, Armijo, relative-gradient or C1-C5 rule) ----
   int newton(void* vio, const nkreg_solve_opts* o, nkreg_solve_report* rep) override {
     need_images();
@@ -902,26 +1000,9 @@ class ProblemT final : public ProblemBase {
       r.cg_iterations += its;
       r.n_pde += 2 * its;
       if (cfg.incompressible) project(sbuf.p, sbuf.p);
-      if (opt.cfl_guard && cfg.cfl_max > 0) {
-        for (int h = 0; h < 30; ++h) {
-          lincomb(nv, 1.0, vk, 1.0, sbuf.p, vtrial.p);
-          if (cfl_number(vtrial.p) <= cfg.cfl_max) break;
-          axpby(nv, 0.0, sbuf.p, 0.5, sbuf.p);
-        }
-      }
-      // Armijo backtracking from alpha = 1, c1 = 1e-4, at most 20 halvings
-      const double slope = g.hd * red.one<double>(RED_DOT, gbuf.p, sbuf.p, nv);
-      double alpha = 1.0;
-      bool accepted = false;
-      for (int trial = 0; trial <= 20; ++trial) {
-        lincomb(nv, 1.0, vk, alpha, sbuf.p, vtrial.p);
-        double Jt;
-        objective(vtrial.p, &Jt, nullptr, nullptr);
-        r.n_pde += 1;
-        if (Jt <= J + 1e-4 * alpha * slope) { accepted = true; break; }
-        alpha *= 0.5;
-      }
-      if (!accepted) { r.line_search_failed = 1; break; }
+      if (opt.cfl_guard) cfl_guard(vk);
+      double alpha = 0.0;
+      if (!armijo(vk, J, &alpha, &r.n_pde)) { r.line_search_failed = 1; break; }
       axpby(nv, alpha, sbuf.p, 1.0, vk);
       axpby(nv, 0.0, sbuf.p, alpha, sbuf.p);  // keep alpha*s for C2
       Jprev = J;

@@ -539,3 +539,30 @@ def test_full_newton_solve_matches_oracle(nk, prec):
     if prec == 64:
         assert rep.iterations == rep_ref.iterations
         assert rel_l2(host(v), v_ref) < 1e-6
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_picard_matches_oracle(nk, prec):
+    """Globalised Picard iteration (preconditioned gradient descent with the step-scale
+    memory) against the oracle's: FP64 the same iterations, PDE solves and iterate; FP32
+    converges to the same solution."""
+    mT = synth.smooth_image((16, 16), 5, 8.0)
+    vstar = synth.bandlimited_velocity((16, 16), 77, 3, 0.8)
+    mR = otr.forward_only(mT, vstar, 8)
+    P = ord_.Problem(mT, mR, 8, 1, 1, 0, 1e-1)
+    never = (0, 0.0)
+    v_ref, rep_ref, _ = okr.picard(P, gtol=1e-4, max_outer=500, stagnation=(10 ** 9, 0.0))
+    G = nk.Problem((16, 16), 8, reg=1, beta=1e-1, precision=prec)
+    G.set_images(dev_t(mT, prec), dev_t(mR, prec))
+    v, rep = G.picard_solve(gtol=1e-4, max_outer=500, stagnation=never)
+    assert rep.converged and rep.cg_iterations == 0
+    if prec == 64:
+        assert rep.iterations == rep_ref.iterations and rep.n_pde == rep_ref.n_pde
+        assert rel_inf(host(v), v_ref) < 1e-8
+    else:
+        assert rel_l2(host(v), v_ref) < 1e-3
+    _, rep_st = G.picard_solve(gtol=1e-4, max_outer=500)
+    _, rep_st_ref, _ = okr.picard(P, gtol=1e-4, max_outer=500)
+    if prec == 64:
+        assert rep_st.iterations == rep_st_ref.iterations
+    G.close()
