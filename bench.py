@@ -290,6 +290,41 @@ def solver_section(nk, torch, spec, mT_h, mR_h, precisions=(32, 64), beta=1e-2):
     return out
 
 
+def analysis_section(nk, synth, torch, spec, mT_h, mR_h):
+    """Hessian analysis: the dense 64^2 Hessian (n = 8192) by unit-vector matvecs, and a
+    100-step Lanczos estimate of the extreme eigenvalues and condition number of the
+    headline Hessian (FP32 transport) at v = 0."""
+    dev = torch.device("cuda:0")
+    out = {}
+    shape, nt = (64, 64), 8
+    mT = synth.smooth_image(shape, 5, 0.6 * 64 ** 2 / 16)
+    vstar = synth.bandlimited_velocity(shape, 77, 4, synth.cfl_literal_linf(64, nt), norm="linf")
+    G = nk.Problem(shape, nt, 1, 2, False, 1e-3, precision=64)
+    G.set_images(torch.from_numpy(mT).to(dev), torch.from_numpy(mT).to(dev))
+    G.objective_gradient(torch.from_numpy(vstar).to(dev))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H = G.hessian_matrix()
+    torch.cuda.synchronize()
+    out["assemble_64sq"] = {"n": int(H.shape[0]), "seconds": time.perf_counter() - t0}
+    del H
+    G.close()
+    G = nk.Problem(spec.shape, spec.nt, 1, spec.reg, False, spec.beta, precision=32)
+    G.set_images(torch.from_numpy(mT_h).to(dev).float(), torch.from_numpy(mR_h).to(dev).float())
+    G.objective_gradient(G.zeros_v())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ritz = G.lanczos(100)
+    secs = time.perf_counter() - t0
+    out["lanczos_headline"] = {"steps": len(ritz), "seconds": secs, "ritz_min": ritz[0], "ritz_max": ritz[-1],
+                               "condition_estimate": ritz[-1] / ritz[0] if ritz[0] > 0 else None}
+    log(f"Hessian analysis: 64^2 assembly ({out['assemble_64sq']['n']} matvecs) "
+        f"{out['assemble_64sq']['seconds']:.2f} s; Lanczos(100) at 512^2 {secs:.2f} s, "
+        f"Ritz values [{ritz[0]:.4g}, {ritz[-1]:.4g}]")
+    G.close()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -306,6 +341,7 @@ def main() -> int:
                     help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration) and exit")
     ap.add_argument("--no-3d", action="store_true", help="skip the 256^3 workload")
     ap.add_argument("--no-beta-search", action="store_true", help="skip the det F_1-bounded beta search")
+    ap.add_argument("--no-analysis", action="store_true", help="skip the Hessian assembly and Lanczos estimate")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -439,6 +475,8 @@ def main() -> int:
         out["batch"] = batch_section(nk, synth, torch, reps=10)
     if not args.no_solve:
         out["solvers"] = solver_section(nk, torch, spec, mT_h, mR_h, (32,) if args.no_fp64 else (32, 64))
+    if not args.no_analysis:
+        out["hessian_analysis"] = analysis_section(nk, synth, torch, spec, mT_h, mR_h)
     if not args.no_beta_search:
         out["beta_search"] = beta_search_section(nk, synth, torch, (32,) if args.no_fp64 else (32, 64))
     if not args.no_3d:

@@ -263,6 +263,17 @@ typedef struct {
 int nkreg_picard_solve(nkreg_problem* p, void* d_v, const nkreg_solve_opts* opts, const nkreg_picard_opts* popts,
                        nkreg_solve_report* report);
 
+/* Hessian analysis at the cached state (Section "Spectral Analysis", Table
+ * t:eigenvalues). nkreg_hessian_assemble writes the n x n matrix (n = nc*d*prod N_i,
+ * doubles, row j = H e_j; H is symmetric) by n matvecs with the current Hessian
+ * mode. nkreg_hessian_lanczos runs up to `steps` (1..512) Lanczos steps on H with
+ * full reorthogonalisation from a fixed pseudo-random start and writes the Ritz
+ * values in ascending order to h_ritz (capacity >= steps) and their number to
+ * h_count; the extreme Ritz values estimate H's extreme eigenvalues and condition
+ * number (Section "Parameter Selection", Regularization). Synchronise. */
+int nkreg_hessian_assemble(nkreg_problem* p, void* d_H);
+int nkreg_hessian_lanczos(nkreg_problem* p, int steps, double* h_ritz, int* h_count);
+
 /* Building blocks exposed for testing the spectral machinery. */
 /* d_g (d*n) = spectral gradient of the scalar field d_u (n). */
 int nkreg_gradient(nkreg_problem* p, const void* d_u, void* d_g);

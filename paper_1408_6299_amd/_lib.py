@@ -59,6 +59,8 @@ SIGNATURES = {
     "nkreg_destroy": (c_int, [c_void_p]),
     "nkreg_set_beta": (c_int, [c_void_p, c_double]),
     "nkreg_set_hessian": (c_int, [c_void_p, c_int]),
+    "nkreg_hessian_assemble": (c_int, [c_void_p, c_void_p]),
+    "nkreg_hessian_lanczos": (c_int, [c_void_p, c_int, POINTER(c_double), POINTER(c_int)]),
     "nkreg_use_graphs": (c_int, [c_void_p, c_int]),
     "nkreg_describe": (c_int, [c_void_p, ctypes.c_char_p, c_int]),
     "nkreg_set_images": (c_int, [c_void_p, c_void_p, c_void_p]),

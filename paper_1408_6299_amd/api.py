@@ -156,6 +156,21 @@ class Problem:
         check(self.lib.nkreg_set_hessian(self._h, c_int(1 if mode == "newton" else 0)), "nkreg_set_hessian")
         self._hessian = mode
 
+    def hessian_matrix(self) -> torch.Tensor:
+        """The dense Hessian at the cached state, (n, n) float64 with n = nc*d*prod(shape);
+        row j is H e_j (n matvecs)."""
+        nvals = self.nc * self.d * int(torch.tensor(self.shape).prod())
+        H = torch.empty((nvals, nvals), dtype=torch.float64, device=self.device)
+        check(self.lib.nkreg_hessian_assemble(self._h, _ptr(H)), "nkreg_hessian_assemble")
+        return H
+
+    def lanczos(self, steps: int = 100) -> List[float]:
+        """Ritz values (ascending) of up to ``steps`` Lanczos steps on the Hessian."""
+        ritz = (c_double * max(1, steps))()
+        cnt = c_int()
+        check(self.lib.nkreg_hessian_lanczos(self._h, c_int(steps), ritz, byref(cnt)), "nkreg_hessian_lanczos")
+        return [ritz[i] for i in range(cnt.value)]
+
     def describe(self) -> dict:
         """Launch configuration of the handle (tile choices, autotuner timings)."""
         import json

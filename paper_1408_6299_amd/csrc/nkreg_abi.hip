@@ -224,6 +224,16 @@ int nkreg_picard_solve(nkreg_problem* p, void* v, const nkreg_solve_opts* opts, 
   return guarded([&]() { Join j_(p->impl); return p->impl->picard(v, opts, popts, rep); });
 }
 
+int nkreg_hessian_assemble(nkreg_problem* p, void* H) {
+  NEED(p); NEED(H);
+  return guarded([&]() { Join j_(p->impl); p->impl->assemble_hessian(H); return (int)NKREG_OK; });
+}
+
+int nkreg_hessian_lanczos(nkreg_problem* p, int steps, double* ritz, int* count) {
+  NEED(p); NEED(ritz);
+  return guarded([&]() { Join j_(p->impl); return p->impl->lanczos(steps, ritz, count); });
+}
+
 int nkreg_set_hessian(nkreg_problem* p, int mode) {
   NEED(p);
   return guarded([&]() { Join j_(p->impl); p->impl->set_hessian(mode); return (int)NKREG_OK; });

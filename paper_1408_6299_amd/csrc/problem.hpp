@@ -139,6 +139,8 @@ class ProblemBase {
   virtual hipStream_t stream() const = 0;
   virtual void set_beta(double beta) = 0;
   virtual void set_hessian(int mode) = 0;
+  virtual void assemble_hessian(void* H) = 0;
+  virtual int lanczos(int steps, double* ritz, int* count) = 0;
   virtual int hessian_mode() const = 0;
   virtual void use_graph_capture(bool on) = 0;
   virtual std::string describe() = 0;
@@ -1024,6 +1026,97 @@ class ProblemT final : public ProblemBase {
     if (rep) *rep = r;
     if (r.line_search_failed) return NKREG_ENOCONV;
     return conv ? NKREG_OK : NKREG_ENOCONV;
+  }
+
+  // ---- Hessian analysis (Section "Spectral Analysis", Table t:eigenvalues) ----
+  // Row j of H (nv x nv doubles) = H e_j, by nv matvecs at the cached state.
+  void assemble_hessian(void* Hout) override {
+    if (!state_valid) throw HipError(NKREG_ESTATE, "no gradient computed at the current velocity");
+    double* H = (double*)Hout;
+    DevBuf<double> e(nv), col(nv);
+    for (long long j = 0; j < nv; ++j) {
+      hipLaunchKernelGGL((k_unit<double>), dim3(launch_blocks(nv)), dim3(256), 0, s, nv, j, e.p);
+      NK_LAUNCHED();
+      hessian_matvec(e.p, col.p);
+      NK_HIP(hipMemcpyAsync(H + (size_t)j * nv, col.p, nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    NK_HIP(hipStreamSynchronize(s));
+  }
+
+  // Lanczos on H (Euclidean inner product; H is symmetric) with full
+  // reorthogonalisation, from a fixed pseudo-random start; returns the Ritz
+  // values (ascending) of the tridiagonal matrix after at most `steps` steps.
+  static constexpr int kMaxLanczos = 512;
+  int lanczos(int steps, double* ritz, int* count) override {
+    if (!state_valid) throw HipError(NKREG_ESTATE, "no gradient computed at the current velocity");
+    if (steps <= 0 || steps > kMaxLanczos) throw HipError(NKREG_EINVAL, "Lanczos steps must lie in [1, 512]");
+    const int m = (int)std::min<long long>(steps, nv);
+    DevBuf<double> Q((size_t)(m + 1) * nv), w(nv), qin(nv), c(m + 1);
+    auto q = [&](int i) { return Q.p + (size_t)i * nv; };
+    hipLaunchKernelGGL(k_hash_fill, dim3(launch_blocks(nv)), dim3(256), 0, s, nv, q(0));
+    NK_LAUNCHED();
+    axpby(nv, 0.0, q(0), 1.0 / std::sqrt(red.one<double>(RED_SUMSQ, q(0), nullptr, nv)), q(0));
+    std::vector<double> a, b;
+    double anorm = 0.0;
+    for (int k = 0; k < m; ++k) {
+      copy(qin.p, q(k), nv * sizeof(double));
+      hessian_matvec(qin.p, w.p);
+      const double ak = red.one<double>(RED_DOT, q(k), w.p, nv);
+      a.push_back(ak);
+      // w -= a_k q_k + b_k q_{k-1}, then twice Gram-Schmidt against q_0..q_k
+      lincomb(nv, 1.0, w.p, -ak, q(k), w.p);
+      if (k > 0) axpby(nv, -b.back(), q(k - 1), 1.0, w.p);
+      for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL(k_multidot, dim3(k + 1), dim3(256), 0, s, Q.p, (long long)nv, w.p, c.p);
+        hipLaunchKernelGGL(k_multi_axpy, dim3(launch_blocks(nv)), dim3(256), 0, s, Q.p, k + 1, (long long)nv, c.p,
+                           w.p);
+        NK_LAUNCHED();
+      }
+      const double bk = std::sqrt(red.one<double>(RED_SUMSQ, w.p, nullptr, nv));
+      anorm = std::max(anorm, std::fabs(ak) + bk + (b.empty() ? 0.0 : b.back()));
+      if (k + 1 == m || !(bk > 1e-13 * anorm)) break;   // done, or an invariant subspace
+      b.push_back(bk);
+      lincomb(nv, 1.0 / bk, w.p, 0.0, w.p, q(k + 1));
+    }
+    const std::vector<double> ev = tridiagonal_eigenvalues(a, b);
+    for (size_t i = 0; i < ev.size(); ++i) ritz[i] = ev[i];
+    if (count) *count = (int)ev.size();
+    return NKREG_OK;
+  }
+  // Eigenvalues (ascending) of the symmetric tridiagonal matrix with diagonal a
+  // and off-diagonal b, by bisection on Sturm sequence counts.
+  static std::vector<double> tridiagonal_eigenvalues(const std::vector<double>& a, const std::vector<double>& b) {
+    const int m = (int)a.size();
+    double lo = 1e300, hi = -1e300;
+    for (int i = 0; i < m; ++i) {
+      const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(b[i]) : 0.0);
+      lo = std::min(lo, a[i] - r);
+      hi = std::max(hi, a[i] + r);
+    }
+    // number of eigenvalues below x: negative pivots of the LDL^T factorisation of T - x I
+    auto below = [&](double x) {
+      int cnt = 0;
+      double dprev = 1.0;
+      for (int i = 0; i < m; ++i) {
+        double di = a[i] - x - (i > 0 ? b[i - 1] * b[i - 1] / dprev : 0.0);
+        if (di == 0.0) di = -1e-300;
+        if (di < 0) ++cnt;
+        dprev = di;
+      }
+      return cnt;
+    };
+    std::vector<double> ev(m);
+    const double tol = 4e-16 * std::max(std::fabs(lo), std::fabs(hi));
+    for (int i = 0; i < m; ++i) {
+      double l = lo, h = hi;
+      for (int it = 0; it < 200 && h - l > tol; ++it) {
+        const double mid = 0.5 * (l + h);
+        if (below(mid) > i) h = mid;
+        else l = mid;
+      }
+      ev[i] = 0.5 * (l + h);
+    }
+    return ev;
   }
 
   // ---- deformation gradient in FP64 ----

@@ -566,3 +566,92 @@ def test_picard_matches_oracle(nk, prec):
     if prec == 64:
         assert rep_st.iterations == rep_st_ref.iterations
     G.close()
+
+
+def test_hessian_matrix_matches_oracle_columns_and_lanczos_matches_its_spectrum(nk):
+    """Dense Hessian by unit-vector matvecs (16^2, n = 512) against the oracle's matvecs,
+    symmetric; the Lanczos Ritz values reach its extreme eigenvalues."""
+    P, G, v, _ = make_pair(nk, (16, 16), 6, 1, 2, 0, 1e-2, 64)
+    S = ord_.objective_gradient(P, v)
+    G.objective_gradient(dev_v(v))
+    H = G.hessian_matrix()
+    Hh = host(H)
+    n = Hh.shape[0]
+    assert n == 512
+    for j in (0, 17, 300, 511):
+        e = np.zeros(n)
+        e[j] = 1.0
+        ref = ord_.hessian_matvec(P, S, e.reshape(P.vshape())).reshape(-1)
+        assert np.abs(Hh[j] - ref).max() <= 1e-10 * np.abs(ref).max()
+    assert np.abs(Hh - Hh.T).max() <= 1e-12 * np.abs(Hh).max()
+    ev = np.linalg.eigvalsh(0.5 * (Hh + Hh.T))
+    ritz = G.lanczos(200)
+    assert len(ritz) == 200
+    assert abs(ritz[-1] - ev[-1]) <= 1e-10 * ev[-1]
+    assert abs(ritz[0] - ev[0]) <= 1e-6 * ev[-1]
+    assert ritz[0] >= ev[0] - 1e-9 * ev[-1] and ritz[-1] <= ev[-1] * (1 + 1e-12)
+    G.close()
+
+
+GOLDEN_EIG = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden", "eigen_extremes.json")
+
+
+def test_hessian_spectrum_extremes_match_table_t_eigenvalues(nk):
+    """64^2, n_c = 1 (n = 8192), at the true velocity (zero residual): the spectrum of the
+    assembled Hessian reproduces the data-independent extremes of Table t:eigenvalues.
+
+    gamma = 0: H is symmetric; its largest eigenvalue is beta a(k) at the corner wavenumber.
+    gamma = 1: H = beta A + K M (M symmetric) is not symmetric on the full space, but block
+    lower-triangular in (curl-free, divergence-free) coordinates: on curl-free fields it is
+    beta A (eigenvalues beta a(k), the smallest beta at |k| = 1) and on divergence-free
+    fields it is the symmetric K H K. Its eigenvalues are the union of the two blocks'."""
+    import json
+    shape, nt = (64, 64), 8
+    n = 8192
+    mT = synth.smooth_image(shape, 5, 0.6 * 64 ** 2 / 16)
+    k = np.fft.fftfreq(64, 1.0 / 64)
+    for ent in json.load(open(GOLDEN_EIG))["entries"]:
+        gamma, reg, beta = ent["gamma"], ent["reg"], ent["beta"]
+        vstar = synth.bandlimited_velocity(shape, 77, 4, synth.cfl_literal_linf(64, nt), divfree=bool(gamma),
+                                           norm="linf")
+        mR = otr.forward_only(mT, vstar, nt)
+        G = nk.Problem(shape, nt, reg=reg, incompressible=bool(gamma), beta=beta, precision=64)
+        G.set_images(dev_t(mT, 64), dev_t(mR, 64))
+        G.objective_gradient(dev_v(vstar))
+        H = G.hessian_matrix()
+        assert H.shape == (n, n)
+        if not gamma:
+            assert float((H - H.T).abs().max()) <= 1e-12 * float(H.abs().max())
+            ev = torch.linalg.eigvalsh(0.5 * (H + H.T)).cpu().numpy()
+            lo, hi = ev[0], ev[-1]
+        else:
+            # divergence-free block: K H K with K assembled column by column by nkreg_project
+            Km = torch.empty((n, n), dtype=torch.float64, device="cuda")
+            e = G.zeros_v()
+            for j in range(n):
+                e.view(-1).zero_()
+                e.view(-1)[j] = 1.0
+                Km[j] = G.project(e).view(-1)
+            Hd = Km @ H.T @ Km      # rows of H are H e_j, so H.T is the operator's matrix
+            evd = torch.linalg.eigvalsh(0.5 * (Hd + Hd.T)).cpu().numpy()
+            rank = n - int(round(float(torch.trace(Km))))      # curl-free dimension
+            evd = evd[rank:]                                    # drop the curl-free null directions
+            # curl-free block: beta a(k) on the curl-free Fourier modes (k != 0)
+            kk = k[:, None] ** 2 + k[None, :] ** 2
+            a = (kk if reg == 1 else kk ** 2)[kk > 0]
+            lo, hi = min(evd[0], beta * a.min()), max(evd[-1], beta * a.max())
+            # the curl-free block is exactly beta A: (I - K) H w = beta A w for w = grad cos(x1)
+            x1 = 2 * np.pi * np.arange(64) / 64
+            w = np.zeros(G.vshape)
+            w[0, 0] = -np.sin(x1)[:, None] * np.ones(64)[None, :]
+            Hw = host(G.hessian_matvec(dev_v(w)))
+            cf = Hw - host(G.project(dev_v(Hw)))
+            assert np.abs(cf - beta * w).max() <= 1e-9 * beta
+            del Km, Hd
+        if "max_real" in ent:
+            assert abs(hi - ent["max_real"]) <= 1e-9 * ent["max_real"], (ent, hi)
+        if "min_real" in ent:
+            assert abs(lo - ent["min_real"]) <= 1e-9 * ent["min_real"], (ent, lo)
+        assert lo > 0
+        del H
+        G.close()
