@@ -655,3 +655,45 @@ def test_hessian_spectrum_extremes_match_table_t_eigenvalues(nk):
         assert lo > 0
         del H
         G.close()
+
+
+EDGE_SHAPES = [((8, 8), 1, 1, 1, 0), ((512, 8), 3, 1, 2, 0), ((8, 512), 3, 2, 1, 1),
+               ((512, 8, 8), 2, 1, 2, 1), ((8, 512, 8), 2, 1, 1, 0), ((8, 8, 512), 2, 1, 2, 0),
+               ((8, 8, 8), 1, 2, 1, 1)]
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("shape,nt,nc,reg,gamma", EDGE_SHAPES)
+def test_extreme_shapes_match_oracle(nk, shape, nt, nc, reg, gamma, prec):
+    """Smallest (8) and largest (512) axis lengths on every axis position, one time step,
+    several Chebyshev coefficients: gradient and GN matvec against the oracle.
+
+    On a 512-point axis the H2 symbol reaches 256^4, so the problem itself amplifies FP64
+    rounding: the FP64 bound is 20 times the oracle's own change under a 1e-16 relative
+    perturbation of v (and of w for the matvec), at least 1e-10. FP32 (FFTs of length 512, CFL-0.1 steps with only
+    one to three time steps) is held to 3e-5 here."""
+    mT, mR, vstar, w = smooth_inputs(shape, max(nt, 2), nc=nc, divfree=bool(gamma))
+    mR = otr.forward_only(mT, vstar, nt)
+    P = ord_.Problem(mT, mR, nt, nc, reg, gamma, 1e-2)
+    v = 0.5 * vstar
+    S = ord_.objective_gradient(P, v)
+    Hw = ord_.hessian_matvec(P, S, w)
+    G = nk.Problem(shape, nt, nc=nc, reg=reg, incompressible=bool(gamma), beta=1e-2, precision=prec)
+    G.set_images(dev_t(mT, prec), dev_t(mR, prec))
+    J, _, _, g = G.objective_gradient(dev_v(v))
+    hw = host(G.hessian_matvec(dev_v(w)))
+    if prec == 64:
+        rng = np.random.default_rng(0)
+        vp = v * (1 + 1e-16 * rng.standard_normal(v.shape))
+        Sp = ord_.objective_gradient(P, vp)
+        sens_g = rel_inf(Sp.g, S.g)
+        wp = w * (1 + 1e-16 * rng.standard_normal(w.shape))
+        sens_h = rel_inf(ord_.hessian_matvec(P, Sp, wp), Hw)
+        assert abs(J - S.J) <= 1e-10 * abs(S.J)
+        assert rel_inf(host(g), S.g) < max(1e-10, 20 * sens_g)
+        assert rel_inf(hw, Hw) < max(1e-10, 20 * sens_h)
+    else:
+        kappa = np.sqrt(np.sum(P.mT ** 2) / max(np.sum((P.mR - P.mT) ** 2), 1e-300))
+        assert rel_l2(host(g), S.g) < 3e-5 * max(1.0, kappa / 10.0)
+        assert rel_l2(hw, Hw) < 3e-5
+    G.close()
