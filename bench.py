@@ -93,6 +93,27 @@ def symbol_of(kernel: str, launch: dict) -> str:
     return kernel
 
 
+def matvec_roofline(G, vt, ms_per_matvec: float) -> dict:
+    """The whole matvec against the HBM roofline: algorithmic bytes of all its launches
+    (the library's tally) over the graph-replayed matvec time."""
+    b, launches = G.matvec_bytes(vt)
+    ach = b / (ms_per_matvec * 1e-3) / 1e9
+    return {"bound": "hbm", "bytes_per_matvec": b, "launches": launches, "matvec_ms": ms_per_matvec,
+            "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}
+
+
+def time_matvecs(G, vt, reps, torch) -> float:
+    """Milliseconds per graph-replayed Hessian matvec (one warm-up replay)."""
+    out = G.empty_v()
+    G.hessian_matvec(vt, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        G.hessian_matvec(vt, out)
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0) / reps
+
+
 def roofline(kernel: str, symbol: str, rec: dict, traffic=None) -> dict:
     ach = rec["bytes_per_launch"] / (rec["avg_us"] * 1e-6) / 1e9
     return {"bound": "hbm", "kernel": kernel, "symbol": symbol, "launches": rec["launches"], "matvecs": rec["matvecs"],
@@ -213,6 +234,7 @@ def cube_section(nk, synth, torch, reps, kernel, precisions=(32, 64)):
         t = (time.perf_counter() - t0) / n
         out[f"fp{prec}"] = {"matvec_ms": 1e3 * t, "matvecs_per_s": 1.0 / t}
         log(f"256^3 FP{prec}: {1e3 * t:.1f} ms per matvec")
+        out[f"fp{prec}"]["matvec_roofline"] = matvec_roofline(G, wt, 1e3 * t)
         if prec == 32:
             k = kernel_pass(G, kernel, wt, o, 1, torch)
             if k["launches"]:
@@ -394,8 +416,9 @@ def main() -> int:
         secs = timed_pcg_steps(G, rhs, steps, torch)   # matvecs replay their captured HIP graph
         r = {"steps": steps, "seconds": secs, "matvecs_per_s": steps / secs, "ms_per_step": 1e3 * secs / steps,
              "launch": G.describe()}
+        r["matvec_roofline"] = matvec_roofline(G, rhs, time_matvecs(G, rhs, max(20, steps // 2), torch))
         if prec == 32:
-            # second timed region, same workload: HIP events around every launch of the
+            # second timed region, same workload: HIP events stamped by every launch of the
             # dominant kernel (the library launches eagerly while its timer is armed)
             r["kernel"] = kernel_pass(G, args.kernel, rhs, G.empty_v(), 20, torch)
         log(f"FP{prec}: {r['matvecs_per_s']:.1f} matvecs/s ({r['ms_per_step']:.3f} ms per PCG iteration)")
@@ -460,9 +483,11 @@ def main() -> int:
                    "beta": spec.beta, "incompressible": False, "step": "one GN-PCG iteration (matvec-dominated)"},
         "launch": results[32]["launch"],
     }
+    out["matvec_roofline"] = results[32]["matvec_roofline"]
     if 64 in results:
         out["fp64"] = {"matvecs_per_s": results[64]["matvecs_per_s"], "ms_per_step": results[64]["ms_per_step"],
-                       "fp32_speedup": results[32]["matvecs_per_s"] / results[64]["matvecs_per_s"]}
+                       "fp32_speedup": results[32]["matvecs_per_s"] / results[64]["matvecs_per_s"],
+                       "matvec_roofline": results[64]["matvec_roofline"]}
     if not args.no_solve:
         for prec in results:
             out[f"newton_fp{prec}"] = results[prec]["newton"]

@@ -297,6 +297,10 @@ int nkreg_dot(nkreg_problem* p, const void* d_a, const void* d_b, long long cnt,
  * disarms the timer. While the timer is armed, Hessian matvecs launch eagerly
  * instead of replaying their HIP graph (graph-recorded events cannot be timed). */
 int nkreg_timer_arm(nkreg_problem* p, int kernel_id, int capacity);
+/* One Hessian matvec (eager launches) that adds up the algorithmic bytes of all
+ * its launches (fields each kernel reads plus fields it writes); divided by a
+ * matvec's duration it gives the whole matvec's achieved bandwidth. Synchronises. */
+int nkreg_matvec_bytes(nkreg_problem* p, const void* d_vt, void* d_Hvt, double* h_bytes, int* h_launches);
 int nkreg_timer_read(nkreg_problem* p, int* launches, double* avg_ms, double* bytes_per_launch);
 
 /* Batched Gauss-Newton matvecs over independent problems of uneven sizes

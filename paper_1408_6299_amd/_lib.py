@@ -86,6 +86,7 @@ SIGNATURES = {
     "nkreg_apply_reg": (c_int, [c_void_p, c_void_p, c_void_p]),
     "nkreg_dot": (c_int, [c_void_p, c_void_p, c_void_p, c_longlong, POINTER(c_double)]),
     "nkreg_timer_arm": (c_int, [c_void_p, c_int, c_int]),
+    "nkreg_matvec_bytes": (c_int, [c_void_p, c_void_p, c_void_p, POINTER(c_double), POINTER(c_int)]),
     "nkreg_timer_read": (c_int, [c_void_p, POINTER(c_int), POINTER(c_double), POINTER(c_double)]),
     "nkreg_batch_create": (c_int, [c_int, POINTER(c_void_p), POINTER(c_void_p)]),
     "nkreg_batch_groups": (c_int, [c_void_p, POINTER(c_int), POINTER(c_int), POINTER(c_int), c_int]),

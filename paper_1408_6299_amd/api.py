@@ -385,6 +385,14 @@ class Problem:
         """Time each of the next ``capacity`` launches of ``kernel`` with dispatch-stamped HIP events."""
         check(self.lib.nkreg_timer_arm(self._h, c_int(self.KERNELS[kernel]), c_int(capacity)), "nkreg_timer_arm")
 
+    def matvec_bytes(self, vt: torch.Tensor) -> Tuple[float, int]:
+        """(algorithmic bytes, launches) of one Hessian matvec at the cached state."""
+        self._check(vt, self.vshape, "vt")
+        out = self.empty_v()
+        b, n = c_double(), c_int()
+        check(self.lib.nkreg_matvec_bytes(self._h, _ptr(vt), _ptr(out), byref(b), byref(n)), "nkreg_matvec_bytes")
+        return b.value, n.value
+
     def timer_read(self) -> Tuple[int, float, float]:
         """(launches, average ms per launch, algorithmic bytes per launch); disarms."""
         n, ms, b = c_int(), c_double(), c_double()

@@ -278,6 +278,11 @@ int nkreg_timer_arm(nkreg_problem* p, int kernel_id, int capacity) {
   return guarded([&]() { Join j_(p->impl); p->impl->timer_arm(kernel_id, capacity); return (int)NKREG_OK; });
 }
 
+int nkreg_matvec_bytes(nkreg_problem* p, const void* vt, void* out, double* bytes, int* launches) {
+  NEED(p); NEED(vt); NEED(out);
+  return guarded([&]() { Join j_(p->impl); p->impl->matvec_bytes(vt, out, bytes, launches); return (int)NKREG_OK; });
+}
+
 int nkreg_timer_read(nkreg_problem* p, int* launches, double* avg_ms, double* bytes_per_launch) {
   NEED(p);
   return guarded([&]() { Join j_(p->impl); p->impl->timer_read(launches, avg_ms, bytes_per_launch); return (int)NKREG_OK; });

@@ -160,6 +160,7 @@ class ProblemBase {
   // the caller's stream, leave() makes the caller's stream wait for it.
   virtual void enter() = 0;
   virtual void leave() = 0;
+  virtual void matvec_bytes(const void* vt, void* out, double* bytes, int* launches) = 0;
   virtual void timer_arm(int id, int capacity) = 0;
   virtual void timer_read(int* launches, double* avg_ms, double* bytes) = 0;
 };
@@ -321,6 +322,22 @@ class ProblemT final : public ProblemBase {
   }
 
   KernelTimer timer;
+  // One eager matvec that adds up the algorithmic bytes of all its launches.
+  void matvec_bytes(const void* vt, void* out, double* bytes, int* launches) override {
+    if (!state_valid) throw HipError(NKREG_ESTATE, "no gradient computed at the current velocity");
+    ByteTally t;
+    sp.tally = sp64.tally = &t;
+    try {
+      matvec_body(vt, out);
+    } catch (...) {
+      sp.tally = sp64.tally = nullptr;
+      throw;
+    }
+    sp.tally = sp64.tally = nullptr;
+    NK_HIP(hipStreamSynchronize(s));
+    if (bytes) *bytes = t.bytes;
+    if (launches) *launches = (int)t.launches;
+  }
   void timer_arm(int id, int capacity) override {
     NK_HIP(hipStreamSynchronize(s));
     timer.arm(id, capacity);
@@ -393,6 +410,7 @@ class ProblemT final : public ProblemBase {
       rec->recs.push_back(r);
       return;
     }
+    if (sp.tally) sp.tally->add((double)cnt * (sizeof(RS) + sizeof(RD)));
     hipLaunchKernelGGL((k_convert<RS, RD>), dim3(launch_blocks(cnt)), dim3(256), 0, s, cnt, x, y);
     NK_LAUNCHED();
   }
@@ -410,6 +428,7 @@ class ProblemT final : public ProblemBase {
       rec->recs.push_back(r);
       return;
     }
+    if (sp.tally) sp.tally->add((double)cnt * sizeof(R));
     hipLaunchKernelGGL((k_fill<R>), dim3(launch_blocks(cnt)), dim3(256), 0, s, cnt, v, y);
     NK_LAUNCHED();
   }

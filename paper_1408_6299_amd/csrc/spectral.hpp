@@ -150,6 +150,16 @@ struct Recorder {
   std::vector<LaunchRec> recs;
 };
 
+// Algorithmic bytes (fields read plus fields written) of every launch while set.
+struct ByteTally {
+  double bytes = 0.0;
+  long long launches = 0;
+  void add(double b) {
+    bytes += b;
+    ++launches;
+  }
+};
+
 template <typename R>
 class Spectral {
  public:
@@ -158,6 +168,7 @@ class Spectral {
   cplx<R>* tw = nullptr;  // exp(-2 pi i m / lmax), m < lmax
   KernelTimer* timer = nullptr;
   Recorder* rec = nullptr;  // when set, launches are recorded instead of issued
+  ByteTally* tally = nullptr;  // when set, every launch adds its algorithmic bytes
   // Column-pass variant, chosen by the autotuner: 8 or 4 = one workgroup per
   // column group with that many complex elements per lane (8: one wavefront per
   // 512-point column, 4: two); 0 = tiled through LDS (k_col_t) wherever the
@@ -355,6 +366,7 @@ class Spectral {
       r.set_entry(a);
       rec->recs.push_back(r);
     } else {
+      if (tally) tally->add((double)nf * g.nspec * sizeof(cplx<R>) * (Y ? 3 : 2));
       if (g.d == 2) hipLaunchKernelGGL((k_spec_mul<R, 2>), dim3(blocks), dim3(256), 0, s, a, op);
       else hipLaunchKernelGGL((k_spec_mul<R, 3>), dim3(blocks), dim3(256), 0, s, a, op);
       NK_LAUNCHED();
@@ -415,6 +427,7 @@ class Spectral {
       return;
     }
     const bool timed = timer && timer->want(kColIdBase + mode);
+    if (tally) tally->add((double)nf * g.nspec * sizeof(cplx<R>) * (add ? 3 : 2));
     const cplx<R>* twc = tw;
     switch (mode) {
       case COL_FWD: launch(k_col_t<R, N, CT, COL_FWD>, grid, dim3(TileShape<R, N, CT>::NT), timed, in, add, out, a, scale, twc, twb); break;
@@ -442,6 +455,7 @@ class Spectral {
       return;
     }
     const bool timed = timer && timer->want(kColIdBase + mode);
+    if (tally) tally->add((double)nf * g.nspec * sizeof(cplx<R>) * (add ? 3 : 2));
     switch (mode) {
       case COL_FWD:
         launch(k_col_w<R, N, E, COL_FWD>, grid, dim3(CS::NT), timed, in, add, out, a, scale, (const cplx<R>*)tw, twb);
@@ -493,6 +507,7 @@ class Spectral {
       return;
     }
     const bool timed = timer && timer->want(KIND);
+    if (tally) tally->add((double)nf * stage_fields<KIND>(a, D) * g.npts * sizeof(R));
     if (!uses_nc || a.nc <= 1)
       launch(k_row_w<R, L, E, KIND, D, true>, grid, dim3(64), timed, a, (const cplx<R>*)tw, g.lmax);
     else if constexpr (uses_nc)
