@@ -499,14 +499,22 @@ class ProblemT final : public ProblemBase {
   }
 
   // Forward solve from m_T; m1out receives m_1. With record, the trajectory is
-  // kept in full or, when checkpointing, only m at the segment starts.
+  // kept in full or, when checkpointing, as m at the segment starts plus the
+  // whole last segment, which the adjoint sweep needs first. The last segment
+  // restarts from its checkpoint exactly as a recomputation does, so the
+  // buffer holds the same values either way.
   void forward_sweep(const R* vl, bool record, R* m1out) {
     if (!K) {
       traj_base = 0;
       state_steps(vl, 0, nt, mT.p, m1out, main_bufs(), record, false);
+    } else if (!record) {
+      state_steps(vl, 0, nt, mT.p, m1out, main_bufs(), false, false);
     } else {
-      if (record) copy(ckpt.p, mT.p, n * sizeof(R));
-      state_steps(vl, 0, nt, mT.p, m1out, main_bufs(), false, record);
+      const int jl = (nseg - 1) * K;
+      copy(ckpt.p, mT.p, n * sizeof(R));
+      state_steps(vl, 0, jl, mT.p, m1out, main_bufs(), false, true);
+      traj_base = jl;
+      state_steps(vl, jl, nt, m1out, m1out, main_bufs(), true, false);
     }
   }
 
@@ -521,14 +529,13 @@ class ProblemT final : public ProblemBase {
   // ---- adjoint (conservative, backward Heun) with body-force accumulation ----
   // lam(1) = ca*src_a + cb*src_b; F (nc*d fields) = time-integrated lam grad m.
   // record_lam keeps lam^{j+1} and lam*_j per step (for the full-Newton matvec).
-  void adjoint_sweep(const R* vl, R ca, const R* src_a, R cb, const R* src_b, R* Fout, bool record_lam = false) {
-    adjoint_sweep_k<false>(vl, nullptr, ca, src_a, cb, src_b, Fout, record_lam);
-  }
   // NEWT: the full-Newton incremental adjoint (e:sec-order-iadj), with v~ = vtl and
   // the gradient's adjoint states and this matvec's grad m~ trajectories.
+  // ring_has_last: the trajectory buffer already holds the last segment (the
+  // incremental sweep of the same matvec ended there), so it is not recomputed.
   template <bool NEWT>
   void adjoint_sweep_k(const R* vl, const R* vtl, R ca, const R* src_a, R cb, const R* src_b, R* Fout,
-                       bool record_lam) {
+                       bool record_lam, bool ring_has_last = false) {
     constexpr int KI = NEWT ? ST_NADJINIT : ST_ADJINIT;
     constexpr int K1 = NEWT ? ST_NADJ1 : ST_ADJ1;
     constexpr int K2 = NEWT ? ST_NADJ2 : ST_ADJ2;
@@ -546,7 +553,7 @@ class ProblemT final : public ProblemBase {
     basis(1.0, a.bv);
     sp.template row<KI>(a, 1);
     for (int j = nt - 1; j >= 0; --j) {
-      if (K && (j == nt - 1 || (j + 1) % K == 0)) load_segment(vl, j / K);
+      if (K && (j == nt - 1 ? !ring_has_last : (j + 1) % K == 0)) load_segment(vl, j / K);
       sp.div_cols(U0, U1, U2, S2.p, Dsp.p);
       StageArgs<R> b{};
       b.spec = Dsp.p; b.vl = vl; b.nc = nc; b.h = h;
@@ -572,10 +579,15 @@ class ProblemT final : public ProblemBase {
   }
 
   // ---- incremental state (GN), m~(0) = 0; writes m~_1 to mt1 ----
+  // With checkpointing, segment 0 is taken from the trajectory buffer as the
+  // last adjoint sweep left it: that sweep (of the gradient or of the previous
+  // matvec, both at the current velocity) ends by recomputing segment 0, and
+  // nothing else writes the buffer while the gradient state is valid.
   void incremental_sweep(const R* vl, const R* vtl) {
     const R h = R(1.0 / nt);
+    if (K) traj_base = 0;
     for (int j = 0; j < nt; ++j) {
-      if (K && j % K == 0) load_segment(vl, j / K);
+      if (K && j % K == 0 && j > 0) load_segment(vl, j / K);
       if (j > 0) sp.deriv_cols(T.p, S1.p, S2.p);
       StageArgs<R> a{};
       a.spec = T.p; a.s1 = S1.p; a.s2 = S2.p; a.out0 = Ts.p;
@@ -673,7 +685,7 @@ class ProblemT final : public ProblemBase {
     forward_sweep(vl, true, m1.p);
     double jd, jr;
     objective_terms(v.p, &jd, &jr);
-    adjoint_sweep(vl, R(1), mR.p, R(-1), m1.p, F.p, full_newton);
+    adjoint_sweep_k<false>(vl, nullptr, R(1), mR.p, R(-1), m1.p, F.p, full_newton, true);
     double* gdst = gout ? (double*)gout : gbuf.p;
     sp64.vecop(OP_HESS, v.p, force64(), gdst, nc, cfg.reg, cfg.incompressible, cfg.beta, Xs.p, Ys.p);
     state_valid = true;
@@ -808,9 +820,14 @@ class ProblemT final : public ProblemBase {
     const double* vt = (const double*)vtin;
     const R* vl = kF64 ? (const R*)v.p : vR.p;
     const R* vtl = to_transport(vt, vtR);
-    incremental_sweep(vl, vtl);
-    if (full_newton) adjoint_sweep_k<true>(vl, vtl, R(-1), mt1.p, R(0), nullptr, F.p, false);
-    else adjoint_sweep(vl, R(-1), mt1.p, R(0), nullptr, F.p);
+    try {
+      incremental_sweep(vl, vtl);
+      if (full_newton) adjoint_sweep_k<true>(vl, vtl, R(-1), mt1.p, R(0), nullptr, F.p, false, true);
+      else adjoint_sweep_k<false>(vl, nullptr, R(-1), mt1.p, R(0), nullptr, F.p, false, true);
+    } catch (...) {
+      state_valid = false;  // the trajectory buffer may no longer hold segment 0
+      throw;
+    }
     sp64.vecop(OP_HESS, vt, force64(), (double*)out, nc, cfg.reg, cfg.incompressible, cfg.beta, Xs.p, Ys.p);
   }
 

@@ -306,7 +306,10 @@ def test_graph_replays_match_eager_matvec(nk, prec):
 @pytest.mark.parametrize("shape,nt,nc,gamma", [((32, 32), 8, 1, 0), ((8, 16, 8), 6, 2, 1)])
 def test_checkpointed_trajectory_is_bit_identical(nk, shape, nt, nc, gamma, prec):
     """Keeping m every K steps and recomputing segments reproduces the full-trajectory
-    gradient and matvec exactly (same kernels, same order), also when K does not divide nt."""
+    gradient and matvec exactly (same kernels, same order), also when K does not divide nt.
+    A matvec takes segment 0 from the buffer as the previous adjoint sweep left it, so
+    matvecs in a row (eager, captured and replayed), a PCG solve, and a new gradient at
+    another velocity followed by a matvec must all stay exact."""
     mT, mR, vstar, w = smooth_inputs(shape, nt, nc=nc, divfree=bool(gamma))
     outs = []
     for K in (0, 3, 2):
@@ -314,13 +317,24 @@ def test_checkpointed_trajectory_is_bit_identical(nk, shape, nt, nc, gamma, prec
                        checkpoint_every=K)
         G.set_images(dev_t(mT, prec), dev_t(mR, prec))
         J, _, _, g = G.objective_gradient(dev_v(0.5 * vstar))
-        hw = G.hessian_matvec(dev_v(w))
-        outs.append((J, host(g), host(hw)))
+        res = [J, host(g), host(G.hessian_matvec(dev_v(w)))]
+        wt, out = dev_v(0.3 * w + 0.1 * vstar), G.empty_v()
+        for _ in range(3):                        # capture, then two replays
+            G.hessian_matvec(wt, out)
+            res.append(host(out))
+            G.precond(dev_v(w))
+        G.use_graphs(False)
+        res.append(host(G.hessian_matvec(dev_v(-w))))
+        G.use_graphs(True)
+        s, it, rel, _ = G.pcg(g, 1e-6, maxit=6)
+        res += [host(s), it, rel]
+        J2, _, _, g2 = G.objective_gradient(dev_v(0.25 * vstar))
+        res += [J2, host(g2), host(G.hessian_matvec(dev_v(w)))]
+        outs.append(res)
         G.close()
-    for J, g, hw in outs[1:]:
-        assert J == outs[0][0]
-        assert np.array_equal(g, outs[0][1])
-        assert np.array_equal(hw, outs[0][2])
+    for res in outs[1:]:
+        for a, b in zip(res, outs[0]):
+            assert np.array_equal(np.asarray(a), np.asarray(b))
 
 
 @pytest.mark.parametrize("prec", [32, 64])
