@@ -244,10 +244,43 @@ def cube_section(nk, synth, torch, reps, kernel, precisions=(32, 64)):
             if k["launches"]:
                 sym = symbol_of(kernel, G.describe())
                 out["roofline"] = roofline(kernel, sym, k, measured_traffic(sym))
+            ref = o.clone()
         G.close()
+        if prec == 32:
+            out["fp32"]["trajectory_slots"] = slots_sweep(nk, spec, mT, mR, wt, ref, reps, torch)
     if "fp64" in out:
         out["fp32_speedup"] = out["fp64"]["matvec_ms"] / out["fp32"]["matvec_ms"]
     return out
+
+
+def slots_sweep(nk, spec, mT, mR, wt, ref, reps, torch, slots=(2, 4)):
+    """FP32 matvec time with more K-step trajectory segments kept in memory (the default
+    keeps one); every setting must reproduce the one-slot matvec bit for bit."""
+    dev = torch.device("cuda:0")
+    shape, nt, K = spec.shape, spec.nt, spec.checkpoint_every
+    field = 4 * int(np.prod(shape))
+    res = []
+    for S in slots:
+        G = nk.Problem(shape, nt, 1, spec.reg, True, spec.beta, precision=32, checkpoint_every=K,
+                       trajectory_slots=S)
+        G.set_images(torch.from_numpy(mT).to(dev).to(torch.float32), mR.to(torch.float32))
+        G.objective_gradient(G.zeros_v())
+        o = G.empty_v()
+        G.hessian_matvec(wt, o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            G.hessian_matvec(wt, o)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / reps
+        nseg = -(-nt // K)
+        res.append({"slots": S, "matvec_ms": 1e3 * t, "segment_recomputes_per_matvec": 2 * max(0, nseg - S),
+                    "trajectory_gib": 2 * min(S, nseg) * K * len(shape) * field / 2**30,
+                    "bit_identical": bool(torch.equal(o, ref))})
+        log(f"256^3 FP32, {S} trajectory slots: {1e3 * t:.1f} ms per matvec, "
+            f"bit-identical {res[-1]['bit_identical']}")
+        G.close()
+    return res
 
 
 def beta_search_section(nk, synth, torch, precisions=(32, 64)):

@@ -72,6 +72,11 @@ typedef struct {
                            every K-th step and recompute a K-step segment inside each adjoint
                            and incremental sweep (2 K d fields; one extra state solve per sweep) */
   double cfl_max;       /* CFL bound checked by nkreg_objective_gradient; <= 0 disables */
+  int trajectory_slots; /* with K > 0: K-step segments of the trajectory kept in memory (2 S K d
+                           fields), 0 or 1 = one. Segment s lives in slot s % S; a sweep recomputes
+                           a segment only when its slot holds another one, so a matvec recomputes
+                           2 (nseg - S) segments (nseg = ceil(nt / K)) and none once S >= nseg.
+                           Results do not depend on S. */
 } nkreg_config;
 
 typedef struct nkreg_problem nkreg_problem;
@@ -130,8 +135,9 @@ int nkreg_set_hessian(nkreg_problem* p, int mode);
 
 /* Hessian matvecs are captured into a HIP graph per (input, output) pointer
  * pair and replayed (the default); enable = 0 launches every kernel eagerly.
- * The library runs on an internal stream joined to the caller's stream at every
- * call, so capture works also when the caller uses the null stream. */
+ * All work runs on the caller's stream; graphs are captured on a stream of the
+ * handle's own (capture is not possible on the null stream) and replayed on the
+ * caller's. */
 int nkreg_use_graphs(nkreg_problem* p, int enable);
 
 /* Writes a JSON object describing the handle's launch configuration (transport
@@ -291,7 +297,7 @@ int nkreg_dot(nkreg_problem* p, const void* d_a, const void* d_b, long long cnt,
  * 7 R2C, 8 C2R, 9 gradient, 10 divergence; column passes: 20 forward, 21 inverse,
  * 22 derivative) and times each of its next `capacity` launches with a pair of
  * HIP events that the dispatch itself stamps (hipExtLaunchKernelGGL on the
- * handle's internal stream). nkreg_timer_read synchronises, returns the
+ * caller's stream). nkreg_timer_read synchronises, returns the
  * number of recorded launches, their average duration in milliseconds and the
  * average algorithmic bytes per launch (fields read plus fields written), and
  * disarms the timer. While the timer is armed, Hessian matvecs launch eagerly
@@ -312,7 +318,9 @@ int nkreg_timer_read(nkreg_problem* p, int* launches, double* avg_ms, double* by
  * are bit-identical to the items' own nkreg_hessian_matvec. The graph and its
  * tables are built on the first call and replayed while the pointer sets and
  * the items' configurations are unchanged. The batch does not own its items.
- * Where the LDS-tiled column pass applies, each group times it against the
+ * When all items were created on one stream the graph replays on it; otherwise
+ * on a stream of the batch that waits for every item's stream, and every item's
+ * stream waits for the batch. Where the LDS-tiled column pass applies, each group times it against the
  * per-column pass at the group's scale and keeps the faster (both give the
  * same values). nkreg_batch_groups reports the last built graph: the number of
  * groups and, for up to cap groups, their sizes and whether they use the tiled

@@ -15,7 +15,8 @@ OK, EINVAL, ESHAPE, ENOMEM, EHIP, ESTATE, ENONFINITE, ECFL, ENOCONV, ENOTIMPL = 
 class Config(Structure):
     _fields_ = [("dim", c_int), ("n", c_int * 3), ("nt", c_int), ("nc", c_int), ("reg", c_int),
                 ("incompressible", c_int), ("beta", c_double), ("precision", c_int),
-                ("checkpoint_every", c_int), ("cfl_max", c_double)]
+                ("checkpoint_every", c_int), ("cfl_max", c_double),
+                ("trajectory_slots", c_int)]
 
 
 class SolveOpts(Structure):

@@ -79,12 +79,17 @@ class Problem:
     float64 (``precision=64``). Velocity-shaped arrays (velocity coefficients,
     gradients, Hessian products, Krylov vectors) have shape (nc, d, *shape) and
     are float64 in both modes.
+
+    ``checkpoint_every=K`` keeps the state every K steps instead of the whole
+    trajectory of gradients; ``trajectory_slots=S`` keeps S K-step segments of
+    that trajectory, so a Hessian matvec recomputes 2 (ceil(nt/K) - S) segments.
+    Neither changes any result.
     """
 
     def __init__(self, shape: Sequence[int], nt: int, nc: int = 1, reg: int = 1,
                  incompressible: bool = False, beta: float = 1e-2, precision: int = 32,
                  cfl_max: float = 0.0, stream: Optional[torch.cuda.Stream] = None,
-                 checkpoint_every: int = 0):
+                 checkpoint_every: int = 0, trajectory_slots: int = 1):
         self.lib = _lib.load()
         self.shape = tuple(int(s) for s in shape)
         self.d = len(self.shape)
@@ -104,6 +109,7 @@ class Problem:
         cfg.beta = float(beta)
         cfg.precision = self.precision
         cfg.checkpoint_every = int(checkpoint_every)
+        cfg.trajectory_slots = int(trajectory_slots)
         cfg.cfl_max = float(cfl_max)
         self._beta = float(beta)
         h = c_void_p()

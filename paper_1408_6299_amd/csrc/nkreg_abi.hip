@@ -18,6 +18,7 @@ struct nkreg_problem {
 struct nkreg_batch {
   std::vector<nkreg_problem*> items;
   hipStream_t s = nullptr;
+  std::vector<hipStream_t> branch;  // capture branches, one per group
   hipEvent_t fork = nullptr, done = nullptr;
   std::vector<hipEvent_t> joins, waits;
   hipGraphExec_t exec = nullptr;
@@ -34,6 +35,10 @@ struct nkreg_batch {
     for (hipEvent_t e : waits) (void)hipEventDestroy(e);
     if (fork) (void)hipEventDestroy(fork);
     if (done) (void)hipEventDestroy(done);
+    for (hipStream_t st : branch) {
+      (void)hipStreamSynchronize(st);
+      (void)hipStreamDestroy(st);
+    }
     if (s) (void)hipStreamDestroy(s);
   }
 };
@@ -74,22 +79,11 @@ int validate(const nkreg_config* c) {
   if (c->precision != 32 && c->precision != 64) return fail(NKREG_EINVAL, "precision must be 32 or 64");
   if (c->incompressible != 0 && c->incompressible != 1) return fail(NKREG_EINVAL, "incompressible must be 0 or 1");
   if (c->checkpoint_every < 0) return fail(NKREG_EINVAL, "checkpoint_every must be >= 0");
+  if (c->trajectory_slots < 0) return fail(NKREG_EINVAL, "trajectory_slots must be >= 0");
   for (int i = 0; i < c->dim; ++i)
     if (!pow2_in_range(c->n[i])) return fail(NKREG_ESHAPE, "grid sizes must be powers of two in [8, 512]");
   return NKREG_OK;
 }
-
-// Joins the library's internal stream to the caller's stream around a call.
-struct Join {
-  nk::ProblemBase* p;
-  explicit Join(nk::ProblemBase* q) : p(q) { p->enter(); }
-  ~Join() {
-    try {
-      p->leave();
-    } catch (...) {
-    }
-  }
-};
 
 #define NEED(ptr)                                                        \
   do {                                                                   \
@@ -148,12 +142,12 @@ int nkreg_destroy(nkreg_problem* p) {
 int nkreg_set_beta(nkreg_problem* p, double beta) {
   NEED(p);
   if (!(beta > 0.0)) return fail(NKREG_EINVAL, "beta must be positive");
-  return guarded([&]() { Join j_(p->impl); p->impl->set_beta(beta); return (int)NKREG_OK; });
+  return guarded([&]() { p->impl->set_beta(beta); return (int)NKREG_OK; });
 }
 
 int nkreg_use_graphs(nkreg_problem* p, int enable) {
   NEED(p);
-  return guarded([&]() { Join j_(p->impl); p->impl->use_graph_capture(enable != 0); return (int)NKREG_OK; });
+  return guarded([&]() { p->impl->use_graph_capture(enable != 0); return (int)NKREG_OK; });
 }
 
 int nkreg_describe(nkreg_problem* p, char* buf, int len) {
@@ -168,124 +162,124 @@ int nkreg_describe(nkreg_problem* p, char* buf, int len) {
 
 int nkreg_set_images(nkreg_problem* p, const void* mT, const void* mR) {
   NEED(p); NEED(mT); NEED(mR);
-  return guarded([&]() { Join j_(p->impl); p->impl->set_images(mT, mR); return (int)NKREG_OK; });
+  return guarded([&]() { p->impl->set_images(mT, mR); return (int)NKREG_OK; });
 }
 
 int nkreg_forward(nkreg_problem* p, const void* v, void* m1) {
   NEED(p); NEED(v);
-  return guarded([&]() { Join j_(p->impl); p->impl->forward(v, m1); return (int)NKREG_OK; });
+  return guarded([&]() { p->impl->forward(v, m1); return (int)NKREG_OK; });
 }
 
 int nkreg_objective(nkreg_problem* p, const void* v, double* J, double* Jd, double* Jr) {
   NEED(p); NEED(v);
-  return guarded([&]() { Join j_(p->impl); p->impl->objective(v, J, Jd, Jr); return (int)NKREG_OK; });
+  return guarded([&]() { p->impl->objective(v, J, Jd, Jr); return (int)NKREG_OK; });
 }
 
 int nkreg_objective_gradient(nkreg_problem* p, const void* v, double* J, double* Jd, double* Jr, void* g) {
   NEED(p); NEED(v);
-  return guarded([&]() { Join j_(p->impl); p->impl->objective_gradient(v, J, Jd, Jr, g); return (int)NKREG_OK; });
+  return guarded([&]() { p->impl->objective_gradient(v, J, Jd, Jr, g); return (int)NKREG_OK; });
 }
 
 int nkreg_hessian_matvec(nkreg_problem* p, const void* vt, void* out) {
   NEED(p); NEED(vt); NEED(out);
   if (vt == out) return fail(NKREG_EINVAL, "input and output may not alias");
-  return guarded([&]() { Join j_(p->impl); p->impl->hessian_matvec(vt, out); return (int)NKREG_OK; });
+  return guarded([&]() { p->impl->hessian_matvec(vt, out); return (int)NKREG_OK; });
 }
 
 int nkreg_precond_apply(nkreg_problem* p, const void* r, void* z) {
   NEED(p); NEED(r); NEED(z);
-  return guarded([&]() { Join j_(p->impl); p->impl->precond(r, z); return (int)NKREG_OK; });
+  return guarded([&]() { p->impl->precond(r, z); return (int)NKREG_OK; });
 }
 
 int nkreg_project(nkreg_problem* p, const void* f, void* out) {
   NEED(p); NEED(f); NEED(out);
-  return guarded([&]() { Join j_(p->impl); p->impl->project(f, out); return (int)NKREG_OK; });
+  return guarded([&]() { p->impl->project(f, out); return (int)NKREG_OK; });
 }
 
 int nkreg_pcg(nkreg_problem* p, const void* rhs, void* s, double rtol, int maxit, int* iters, double* relres) {
   NEED(p); NEED(rhs); NEED(s);
   if (!(rtol >= 0.0)) return fail(NKREG_EINVAL, "rtol must be >= 0");
-  return guarded([&]() { Join j_(p->impl); return p->impl->pcg(rhs, s, rtol, maxit, iters, relres); });
+  return guarded([&]() { return p->impl->pcg(rhs, s, rtol, maxit, iters, relres); });
 }
 
 int nkreg_det_grad_y(nkreg_problem* p, const void* v, void* detF, double* stats) {
   NEED(p); NEED(v);
-  return guarded([&]() { Join j_(p->impl); p->impl->det_grad_y(v, detF, stats); return (int)NKREG_OK; });
+  return guarded([&]() { p->impl->det_grad_y(v, detF, stats); return (int)NKREG_OK; });
 }
 
 int nkreg_newton_solve(nkreg_problem* p, void* v, const nkreg_solve_opts* opts, nkreg_solve_report* rep) {
   NEED(p); NEED(v);
-  return guarded([&]() { Join j_(p->impl); return p->impl->newton(v, opts, rep); });
+  return guarded([&]() { return p->impl->newton(v, opts, rep); });
 }
 
 int nkreg_picard_solve(nkreg_problem* p, void* v, const nkreg_solve_opts* opts, const nkreg_picard_opts* popts,
                        nkreg_solve_report* rep) {
   NEED(p); NEED(v);
-  return guarded([&]() { Join j_(p->impl); return p->impl->picard(v, opts, popts, rep); });
+  return guarded([&]() { return p->impl->picard(v, opts, popts, rep); });
 }
 
 int nkreg_hessian_assemble(nkreg_problem* p, void* H) {
   NEED(p); NEED(H);
-  return guarded([&]() { Join j_(p->impl); p->impl->assemble_hessian(H); return (int)NKREG_OK; });
+  return guarded([&]() { p->impl->assemble_hessian(H); return (int)NKREG_OK; });
 }
 
 int nkreg_hessian_lanczos(nkreg_problem* p, int steps, double* ritz, int* count) {
   NEED(p); NEED(ritz);
-  return guarded([&]() { Join j_(p->impl); return p->impl->lanczos(steps, ritz, count); });
+  return guarded([&]() { return p->impl->lanczos(steps, ritz, count); });
 }
 
 int nkreg_set_hessian(nkreg_problem* p, int mode) {
   NEED(p);
-  return guarded([&]() { Join j_(p->impl); p->impl->set_hessian(mode); return (int)NKREG_OK; });
+  return guarded([&]() { p->impl->set_hessian(mode); return (int)NKREG_OK; });
 }
 
 int nkreg_continuation(nkreg_problem* p, void* v, const double* betas, int levels, const nkreg_solve_opts* opts,
                        nkreg_solve_report* reports) {
   NEED(p); NEED(v);
   if (levels < 0 || (levels > 0 && !betas)) return fail(NKREG_EINVAL, "bad beta levels");
-  return guarded([&]() { Join j_(p->impl); return p->impl->continuation(v, betas, levels, opts, reports); });
+  return guarded([&]() { return p->impl->continuation(v, betas, levels, opts, reports); });
 }
 
 int nkreg_beta_search(nkreg_problem* p, void* v, const nkreg_beta_search_opts* opts, nkreg_beta_search_report* rep) {
   NEED(p); NEED(v); NEED(opts);
-  return guarded([&]() { Join j_(p->impl); return p->impl->beta_search(v, opts, rep); });
+  return guarded([&]() { return p->impl->beta_search(v, opts, rep); });
 }
 
 int nkreg_gradient(nkreg_problem* p, const void* u, void* g) {
   NEED(p); NEED(u); NEED(g);
-  return guarded([&]() { Join j_(p->impl); p->impl->gradient(u, g); return (int)NKREG_OK; });
+  return guarded([&]() { p->impl->gradient(u, g); return (int)NKREG_OK; });
 }
 
 int nkreg_divergence(nkreg_problem* p, const void* w, void* s) {
   NEED(p); NEED(w); NEED(s);
-  return guarded([&]() { Join j_(p->impl); p->impl->divergence(w, s); return (int)NKREG_OK; });
+  return guarded([&]() { p->impl->divergence(w, s); return (int)NKREG_OK; });
 }
 
 int nkreg_apply_reg(nkreg_problem* p, const void* x, void* out) {
   NEED(p); NEED(x); NEED(out);
-  return guarded([&]() { Join j_(p->impl); p->impl->apply_reg(x, out); return (int)NKREG_OK; });
+  return guarded([&]() { p->impl->apply_reg(x, out); return (int)NKREG_OK; });
 }
 
 int nkreg_dot(nkreg_problem* p, const void* a, const void* b, long long cnt, double* out) {
   NEED(p); NEED(a); NEED(b); NEED(out);
   if (cnt < 0) return fail(NKREG_EINVAL, "negative count");
-  return guarded([&]() { Join j_(p->impl); *out = p->impl->dot(a, b, cnt); return (int)NKREG_OK; });
+  return guarded([&]() { *out = p->impl->dot(a, b, cnt); return (int)NKREG_OK; });
 }
 
 int nkreg_timer_arm(nkreg_problem* p, int kernel_id, int capacity) {
   NEED(p);
   if (capacity < 1 || capacity > (1 << 16)) return fail(NKREG_EINVAL, "capacity must be in [1, 65536]");
-  return guarded([&]() { Join j_(p->impl); p->impl->timer_arm(kernel_id, capacity); return (int)NKREG_OK; });
+  return guarded([&]() { p->impl->timer_arm(kernel_id, capacity); return (int)NKREG_OK; });
 }
 
 int nkreg_matvec_bytes(nkreg_problem* p, const void* vt, void* out, double* bytes, int* launches) {
   NEED(p); NEED(vt); NEED(out);
-  return guarded([&]() { Join j_(p->impl); p->impl->matvec_bytes(vt, out, bytes, launches); return (int)NKREG_OK; });
+  return guarded([&]() { p->impl->matvec_bytes(vt, out, bytes, launches); return (int)NKREG_OK; });
 }
 
 int nkreg_timer_read(nkreg_problem* p, int* launches, double* avg_ms, double* bytes_per_launch) {
   NEED(p);
-  return guarded([&]() { Join j_(p->impl); p->impl->timer_read(launches, avg_ms, bytes_per_launch); return (int)NKREG_OK; });
+  return guarded([&]() { p->impl->timer_read(launches, avg_ms, bytes_per_launch); return (int)NKREG_OK; });
 }
 
 int nkreg_batch_create(int count, nkreg_problem* const* items, nkreg_batch** out) {
@@ -455,15 +449,22 @@ int nkreg_batch_hessian_matvec(nkreg_batch* b, const void* const* vt, void* cons
   return guarded([&]() {
     const size_t cnt = b->items.size();
     if (cnt == 0) return (int)NKREG_OK;
-    // the batch stream waits for every caller stream (and so for all earlier work
-    // on the items), also before a rebuild replays a group to time it
-    for (size_t i = 0; i < cnt; ++i) {
-      NK_HIP(hipEventRecord(b->waits[i], b->items[i]->impl->caller_stream()));
-      NK_HIP(hipStreamWaitEvent(b->s, b->waits[i], 0));
-    }
+    // items on one caller stream: the graph replays on that stream, ordered like
+    // any other call; otherwise on the batch stream, joined to every caller stream
+    const hipStream_t cs = b->items[0]->impl->caller_stream();
+    bool one_stream = true;
+    for (size_t i = 1; i < cnt; ++i) one_stream = one_stream && b->items[i]->impl->caller_stream() == cs;
     bool stale = !b->exec || b->key_in.size() != cnt;
     for (size_t i = 0; i < cnt && !stale; ++i)
       stale = b->key_in[i] != vt[i] || b->key_out[i] != out[i] || b->key_gen[i] != b->items[i]->impl->generation;
+    if (stale || !one_stream) {
+      // the batch stream waits for every caller stream (and so for all earlier
+      // work on the items), also before a rebuild replays a group to time it
+      for (size_t i = 0; i < cnt; ++i) {
+        NK_HIP(hipEventRecord(b->waits[i], b->items[i]->impl->caller_stream()));
+        NK_HIP(hipStreamWaitEvent(b->s, b->waits[i], 0));
+      }
+    }
     if (stale) {
       NK_HIP(hipStreamSynchronize(b->s));
       if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -521,12 +522,19 @@ int nkreg_batch_hessian_matvec(nkreg_batch* b, const void* const* vt, void* cons
       }
       b->group_sizes.clear();
       for (auto& gp : plans) b->group_sizes.push_back((int)gp.items.size());
+      // groups become parallel branches of the graph: each is captured on a
+      // stream of its own, forked from and joined back into the batch stream
+      while (b->branch.size() < plans.size()) {
+        hipStream_t st = nullptr;
+        NK_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));  // default priority
+        b->branch.push_back(st);
+      }
       hipGraph_t graph = nullptr;
       NK_HIP(hipStreamBeginCapture(b->s, hipStreamCaptureModeThreadLocal));
       try {
         NK_HIP(hipEventRecord(b->fork, b->s));
         for (size_t gi = 0; gi < plans.size(); ++gi) {
-          hipStream_t st = b->items[plans[gi].items[0]]->impl->stream();
+          hipStream_t st = b->branch[gi];
           NK_HIP(hipStreamWaitEvent(st, b->fork, 0));
           issue_group(plans[gi], b->tables, st);
           NK_HIP(hipEventRecord(b->joins[gi], st));
@@ -548,6 +556,10 @@ int nkreg_batch_hessian_matvec(nkreg_batch* b, const void* const* vt, void* cons
       b->key_out.assign(out, out + cnt);
       b->key_gen.resize(cnt);
       for (size_t i = 0; i < cnt; ++i) b->key_gen[i] = b->items[i]->impl->generation;
+    }
+    if (one_stream) {
+      NK_HIP(hipGraphLaunch(b->exec, cs));
+      return (int)NKREG_OK;
     }
     // every caller stream waits for the batch
     NK_HIP(hipGraphLaunch(b->exec, b->s));

@@ -156,10 +156,6 @@ class ProblemBase {
   virtual hipStream_t caller_stream() const = 0;
   // bumped whenever captured graphs become stale (beta change, graph switch, timer)
   unsigned generation = 0;
-  // Every call runs on the library's internal stream: enter() makes it wait for
-  // the caller's stream, leave() makes the caller's stream wait for it.
-  virtual void enter() = 0;
-  virtual void leave() = 0;
   virtual void matvec_bytes(const void* vt, void* out, double* bytes, int* launches) = 0;
   virtual void timer_arm(int id, int capacity) = 0;
   virtual void timer_read(int* launches, double* avg_ms, double* bytes) = 0;
@@ -190,8 +186,12 @@ class ProblemT final : public ProblemBase {
  public:
   static constexpr bool kF64 = std::is_same<R, double>::value;
   Grid g;
-  hipStream_t user_s;      // the caller's stream (may be the null stream)
-  hipStream_t s;           // internal stream: all work, capturable into graphs
+  // Every call runs on the caller's stream (which may be the null stream, where
+  // capture is not possible); graphs are captured on a stream of the handle's own
+  // and replayed on the caller's.
+  hipStream_t user_s;      // the caller's stream
+  hipStream_t cap_s;       // used only while capturing or autotuning
+  hipStream_t s;           // where launches go: user_s, or cap_s while capturing
   Spectral<R> sp;          // transport precision
   Spectral<double> sp64;   // control space
   Reducer red;
@@ -204,8 +204,11 @@ class ProblemT final : public ProblemBase {
   DevBuf<R> mT, mR, traj, acc, lam, m1, mt1, vR, vtR, F;
   DevBuf<cplx<R>> T, Ts, S1, S2, U, Dsp;
   // trajectory checkpointing: m at the start of every K-step segment, and the
-  // scratch of the segment recomputation (disjoint from the sweeps' buffers)
-  int K = 0, nseg = 1, seglen = 0, traj_base = 0;
+  // scratch of the segment recomputation (disjoint from the sweeps' buffers).
+  // The trajectory buffer has S slots of one segment each; segment s lives in
+  // slot s % S, and held[slot] names the segment a slot currently holds.
+  int K = 0, nseg = 1, seglen = 0, S = 1;
+  std::vector<int> held;
   DevBuf<R> ckpt, accr, mr;
   DevBuf<cplx<R>> Tr, Tsr, S1r, S2r;
   // control space (FP64)
@@ -219,9 +222,8 @@ class ProblemT final : public ProblemBase {
   }
 
   ProblemT(const nkreg_config& c, hipStream_t stream)
-      : g(make_grid(c.dim, c.n)), user_s(stream), s(make_stream()), sp(g, s), sp64(g, s) {
-    NK_HIP(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
-    NK_HIP(hipEventCreateWithFlags(&ev_out, hipEventDisableTiming));
+      : g(make_grid(c.dim, c.n)), user_s(stream), cap_s(make_stream()), s(stream), sp(g, stream),
+        sp64(g, stream) {
     const char* ng = std::getenv("NKREG_NO_GRAPHS");
     use_graphs = !(ng && ng[0] == '1');
     cfg = c;
@@ -235,7 +237,9 @@ class ProblemT final : public ProblemBase {
     K = (c.checkpoint_every > 0 && c.checkpoint_every < nt) ? c.checkpoint_every : 0;
     nseg = K ? (nt + K - 1) / K : 1;
     seglen = K ? K : nt;
-    traj.alloc((size_t)2 * seglen * d * n);
+    S = K ? std::max(1, std::min(c.trajectory_slots, nseg)) : 1;
+    held.assign(S, -1);
+    traj.alloc((size_t)2 * S * seglen * d * n);
     if (K) {
       ckpt.alloc((size_t)nseg * n);
       accr.alloc(n); mr.alloc(n);
@@ -253,17 +257,21 @@ class ProblemT final : public ProblemBase {
     tune_columns();
   }
 
-  hipStream_t stream() const override { return s; }
+  hipStream_t stream() const override { return user_s; }
 
-  hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  void enter() override {
-    NK_HIP(hipEventRecord(ev_in, user_s));
-    NK_HIP(hipStreamWaitEvent(s, ev_in, 0));
+  // Sends every launch of this handle (both spectral engines and the reducer) to st.
+  void route(hipStream_t st) {
+    s = st;
+    sp.s = st;
+    sp64.s = st;
+    red.s = st;
   }
-  void leave() override {
-    NK_HIP(hipEventRecord(ev_out, s));
-    NK_HIP(hipStreamWaitEvent(user_s, ev_out, 0));
-  }
+  // Launches go to the capture stream while an object of this type lives.
+  struct OnCaptureStream {
+    ProblemT& p;
+    explicit OnCaptureStream(ProblemT& q) : p(q) { p.route(p.cap_s); }
+    ~OnCaptureStream() { p.route(p.user_s); }
+  };
 
   // ---- Hessian: Gauss-Newton (default) or full Newton (e:second-order-opt-cond) ----
   // The full-Newton matvec reads the gradient's adjoint states (lam^{j+1}, lam*_j
@@ -305,11 +313,10 @@ class ProblemT final : public ProblemBase {
   }
   hipStream_t caller_stream() const override { return user_s; }
   ~ProblemT() override {
-    (void)hipStreamSynchronize(s);
+    (void)hipStreamSynchronize(user_s);
+    (void)hipStreamSynchronize(cap_s);
     drop_graphs();
-    if (ev_in) (void)hipEventDestroy(ev_in);
-    if (ev_out) (void)hipEventDestroy(ev_out);
-    (void)hipStreamDestroy(s);
+    (void)hipStreamDestroy(cap_s);
   }
   void use_graph_capture(bool on) override {
     NK_HIP(hipStreamSynchronize(s));
@@ -354,7 +361,11 @@ class ProblemT final : public ProblemBase {
   }
 
   // grad m^j (stage 0) and grad m*_j (stage 1) of the steps held in the trajectory buffer
-  R* trajp(int j, int stage) { return traj.p + ((size_t)(2 * (j - traj_base) + stage)) * d * n; }
+  R* trajp(int j, int stage) {
+    const size_t slot = K ? (size_t)((j / K) % S) : 0;
+    const int jj = K ? j % K : j;
+    return traj.p + (slot * 2 * seglen + (size_t)(2 * jj + stage)) * d * n;
+  }
 
   void basis(double t, R* out) {
     double b[kMaxNc];
@@ -500,30 +511,34 @@ class ProblemT final : public ProblemBase {
 
   // Forward solve from m_T; m1out receives m_1. With record, the trajectory is
   // kept in full or, when checkpointing, as m at the segment starts plus the
-  // whole last segment, which the adjoint sweep needs first. The last segment
+  // last S segments, which the adjoint sweep needs first. The recorded part
   // restarts from its checkpoint exactly as a recomputation does, so the
   // buffer holds the same values either way.
   void forward_sweep(const R* vl, bool record, R* m1out) {
     if (!K) {
-      traj_base = 0;
       state_steps(vl, 0, nt, mT.p, m1out, main_bufs(), record, false);
     } else if (!record) {
       state_steps(vl, 0, nt, mT.p, m1out, main_bufs(), false, false);
     } else {
-      const int jl = (nseg - 1) * K;
+      const int s0 = nseg - S, jl = s0 * K;
+      held.assign(S, -1);
       copy(ckpt.p, mT.p, n * sizeof(R));
-      state_steps(vl, 0, jl, mT.p, m1out, main_bufs(), false, true);
-      traj_base = jl;
-      state_steps(vl, jl, nt, m1out, m1out, main_bufs(), true, false);
+      if (jl > 0) state_steps(vl, 0, jl, mT.p, m1out, main_bufs(), false, true);
+      state_steps(vl, jl, nt, jl > 0 ? m1out : mT.p, m1out, main_bufs(), true, true);
+      for (int sg = s0; sg < nseg; ++sg) held[sg % S] = sg;
     }
   }
 
-  // Makes the trajectory of segment sgi available (recomputed from its checkpoint).
+  // Makes the trajectory of segment sgi available: recomputed from its
+  // checkpoint unless its slot still holds it. After every adjoint sweep the
+  // slots hold the segments 0..S-1 (the sweep ends there), and a matvec leaves
+  // them so, whether it runs eagerly or as a captured graph.
   void load_segment(const R* vl, int sgi) {
-    if (!K) return;
+    if (!K || held[sgi % S] == sgi) return;
     const int j0 = sgi * K, j1 = std::min(nt, j0 + K);
-    traj_base = j0;
+    held[sgi % S] = -1;
     state_steps(vl, j0, j1, ckpt.p + (size_t)sgi * n, mr.p, recompute_bufs(), true, false);
+    held[sgi % S] = sgi;
   }
 
   // ---- adjoint (conservative, backward Heun) with body-force accumulation ----
@@ -531,11 +546,9 @@ class ProblemT final : public ProblemBase {
   // record_lam keeps lam^{j+1} and lam*_j per step (for the full-Newton matvec).
   // NEWT: the full-Newton incremental adjoint (e:sec-order-iadj), with v~ = vtl and
   // the gradient's adjoint states and this matvec's grad m~ trajectories.
-  // ring_has_last: the trajectory buffer already holds the last segment (the
-  // incremental sweep of the same matvec ended there), so it is not recomputed.
   template <bool NEWT>
   void adjoint_sweep_k(const R* vl, const R* vtl, R ca, const R* src_a, R cb, const R* src_b, R* Fout,
-                       bool record_lam, bool ring_has_last = false) {
+                       bool record_lam) {
     constexpr int KI = NEWT ? ST_NADJINIT : ST_ADJINIT;
     constexpr int K1 = NEWT ? ST_NADJ1 : ST_ADJ1;
     constexpr int K2 = NEWT ? ST_NADJ2 : ST_ADJ2;
@@ -553,7 +566,7 @@ class ProblemT final : public ProblemBase {
     basis(1.0, a.bv);
     sp.template row<KI>(a, 1);
     for (int j = nt - 1; j >= 0; --j) {
-      if (K && (j == nt - 1 ? !ring_has_last : (j + 1) % K == 0)) load_segment(vl, j / K);
+      if (K && (j == nt - 1 || (j + 1) % K == 0)) load_segment(vl, j / K);
       sp.div_cols(U0, U1, U2, S2.p, Dsp.p);
       StageArgs<R> b{};
       b.spec = Dsp.p; b.vl = vl; b.nc = nc; b.h = h;
@@ -579,15 +592,14 @@ class ProblemT final : public ProblemBase {
   }
 
   // ---- incremental state (GN), m~(0) = 0; writes m~_1 to mt1 ----
-  // With checkpointing, segment 0 is taken from the trajectory buffer as the
-  // last adjoint sweep left it: that sweep (of the gradient or of the previous
-  // matvec, both at the current velocity) ends by recomputing segment 0, and
-  // nothing else writes the buffer while the gradient state is valid.
+  // With checkpointing, the segments still held from the last adjoint sweep
+  // (of the gradient or of the previous matvec, both at the current velocity)
+  // are not recomputed; nothing else writes the trajectory buffer while the
+  // gradient state is valid.
   void incremental_sweep(const R* vl, const R* vtl) {
     const R h = R(1.0 / nt);
-    if (K) traj_base = 0;
     for (int j = 0; j < nt; ++j) {
-      if (K && j % K == 0 && j > 0) load_segment(vl, j / K);
+      if (K && j % K == 0) load_segment(vl, j / K);
       if (j > 0) sp.deriv_cols(T.p, S1.p, S2.p);
       StageArgs<R> a{};
       a.spec = T.p; a.s1 = S1.p; a.s2 = S2.p; a.out0 = Ts.p;
@@ -685,7 +697,7 @@ class ProblemT final : public ProblemBase {
     forward_sweep(vl, true, m1.p);
     double jd, jr;
     objective_terms(v.p, &jd, &jr);
-    adjoint_sweep_k<false>(vl, nullptr, R(1), mR.p, R(-1), m1.p, F.p, full_newton, true);
+    adjoint_sweep_k<false>(vl, nullptr, R(1), mR.p, R(-1), m1.p, F.p, full_newton);
     double* gdst = gout ? (double*)gout : gbuf.p;
     sp64.vecop(OP_HESS, v.p, force64(), gdst, nc, cfg.reg, cfg.incompressible, cfg.beta, Xs.p, Ys.p);
     state_valid = true;
@@ -711,17 +723,19 @@ class ProblemT final : public ProblemBase {
     NK_HIP(hipGraphLaunch(mv_graph.exec, s));
   }
 
+  // Captures one matvec on the capture stream; nothing runs until the graph is launched.
   hipGraphExec_t capture_matvec(const void* vtin, void* out) {
     hipGraph_t graph = nullptr;
-    NK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    OnCaptureStream on(*this);
+    NK_HIP(hipStreamBeginCapture(cap_s, hipStreamCaptureModeThreadLocal));
     try {
       matvec_body(vtin, out);
     } catch (...) {
-      (void)hipStreamEndCapture(s, &graph);
+      (void)hipStreamEndCapture(cap_s, &graph);
       if (graph) (void)hipGraphDestroy(graph);
       throw;
     }
-    NK_HIP(hipStreamEndCapture(s, &graph));
+    NK_HIP(hipStreamEndCapture(cap_s, &graph));
     hipGraphExec_t exec = nullptr;
     const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
@@ -755,14 +769,6 @@ class ProblemT final : public ProblemBase {
       return;
     }
     const long long ns = g.nspec;
-    hipLaunchKernelGGL((k_fill<R>), dim3(launch_blocks(2 * ns)), dim3(256), 0, s, 2 * ns, R(0), (R*)T.p);
-    hipLaunchKernelGGL((k_fill<R>), dim3(launch_blocks(6 * ns)), dim3(256), 0, s, 6 * ns, R(0), (R*)U.p);
-    NK_LAUNCHED();
-    hipEvent_t e0, e1;
-    NK_HIP(hipEventCreate(&e0));
-    NK_HIP(hipEventCreate(&e1));
-    float best = 1e30f;
-    int bestE = sp.colE;
     std::vector<int> cands = {8};
     if (sp.any_tiled_pass()) cands.push_back(0);
     if (cands.size() == 1) {
@@ -771,6 +777,16 @@ class ProblemT final : public ProblemBase {
       tuning = "col_E=8 (no tiled pass applies to this grid)";
       return;
     }
+    // timed on the capture stream, which the host waits for before returning
+    OnCaptureStream on(*this);
+    hipLaunchKernelGGL((k_fill<R>), dim3(launch_blocks(2 * ns)), dim3(256), 0, s, 2 * ns, R(0), (R*)T.p);
+    hipLaunchKernelGGL((k_fill<R>), dim3(launch_blocks(6 * ns)), dim3(256), 0, s, 6 * ns, R(0), (R*)U.p);
+    NK_LAUNCHED();
+    hipEvent_t e0, e1;
+    NK_HIP(hipEventCreate(&e0));
+    NK_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    int bestE = sp.colE;
     for (int ce : cands) {
       sp.colE = ce;
       hipGraph_t graph = nullptr;
@@ -822,10 +838,11 @@ class ProblemT final : public ProblemBase {
     const R* vtl = to_transport(vt, vtR);
     try {
       incremental_sweep(vl, vtl);
-      if (full_newton) adjoint_sweep_k<true>(vl, vtl, R(-1), mt1.p, R(0), nullptr, F.p, false, true);
-      else adjoint_sweep_k<false>(vl, nullptr, R(-1), mt1.p, R(0), nullptr, F.p, false, true);
+      if (full_newton) adjoint_sweep_k<true>(vl, vtl, R(-1), mt1.p, R(0), nullptr, F.p, false);
+      else adjoint_sweep_k<false>(vl, nullptr, R(-1), mt1.p, R(0), nullptr, F.p, false);
     } catch (...) {
-      state_valid = false;  // the trajectory buffer may no longer hold segment 0
+      state_valid = false;  // the slots may no longer hold what the next matvec expects
+      held.assign(S, -1);
       throw;
     }
     sp64.vecop(OP_HESS, vt, force64(), (double*)out, nc, cfg.reg, cfg.incompressible, cfg.beta, Xs.p, Ys.p);

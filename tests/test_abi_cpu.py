@@ -48,6 +48,7 @@ def make_cfg(**kw):
     c.beta = kw.get("beta", 1e-2)
     c.precision = kw.get("precision", 32)
     c.checkpoint_every = kw.get("checkpoint_every", 0)
+    c.trajectory_slots = kw.get("trajectory_slots", 1)
     c.cfl_max = 0.0
     return c
 
@@ -67,6 +68,7 @@ def make_cfg(**kw):
     (dict(n=(1024, 64, 1)), _lib.ESHAPE),
     (dict(dim=3, n=(64, 64, 12)), _lib.ESHAPE),
     (dict(checkpoint_every=-1), _lib.EINVAL),
+    (dict(checkpoint_every=2, trajectory_slots=-1), _lib.EINVAL),
 ])
 def test_invalid_configs_are_rejected_before_any_device_work(kw, code):
     lib = _lib.load()

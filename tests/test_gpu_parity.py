@@ -244,6 +244,61 @@ def test_batch_matches_single_items(nk):
         p.close()
 
 
+def test_handle_on_a_side_stream_matches_the_default_stream(nk):
+    """A handle runs on the stream it was created with: work queued there (gradient,
+    eager and replayed matvecs, PCG) gives the same bits as on the default stream."""
+    shape, nt = (64, 32), 8
+    mT, mR, vstar, w = smooth_inputs(shape, nt)
+    ins = [dev_t(mT, 32), dev_t(mR, 32), dev_v(0.5 * vstar), dev_v(w)]
+    res = []
+    side = torch.cuda.Stream()
+    for st in (torch.cuda.current_stream(), side):
+        st.wait_stream(torch.cuda.current_stream())      # inputs were made on the default stream
+        with torch.cuda.stream(st):
+            G = nk.Problem(shape, nt, reg=2, beta=1e-3, precision=32, stream=st)
+            G.set_images(ins[0], ins[1])
+            J, _, _, g = G.objective_gradient(ins[2])
+            outs = [G.hessian_matvec(ins[3]) for _ in range(3)]
+            s, it, rel, _ = G.pcg(g, 1e-8, maxit=5)
+        torch.cuda.current_stream().wait_stream(st)
+        res.append([J, host(g)] + [host(o) for o in outs] + [host(s), it, rel])
+        G.close()
+    for a, b in zip(res[0], res[1]):
+        assert np.array_equal(np.asarray(a), np.asarray(b))
+
+
+def test_batch_items_on_two_streams(nk):
+    """Items created on different streams: the batch joins every item's stream and matches
+    each item's own matvec bit for bit."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    probs, ws, refs = [], [], []
+    for i, (shape, nt, prec, beta, seed, ck) in enumerate(BATCH_ITEMS[:5]):
+        st = side if i % 2 else torch.cuda.current_stream()
+        mT, mR, vstar, w = smooth_inputs(shape, nt, seed=seed)
+        ins = [dev_t(mT, prec), dev_t(mR, prec), dev_v(0.5 * vstar), dev_v(w)]
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            G = nk.Problem(shape, nt, reg=1, beta=beta, precision=prec, stream=st)
+            G.set_images(ins[0], ins[1])
+            G.objective_gradient(ins[2])
+            refs.append(G.hessian_matvec(ins[3]))
+        probs.append(G)
+        ws.append(ins[3])
+    torch.cuda.current_stream().wait_stream(side)
+    refs = [host(r) for r in refs]
+    B = nk.Batch(probs)
+    outs = [p.empty_v() for p in probs]
+    for _ in range(2):
+        B.hessian_matvec(ws, outs)
+        torch.cuda.current_stream().wait_stream(side)
+        for o, r in zip(outs, refs):
+            assert np.array_equal(host(o), r)
+    B.close()
+    for p in probs:
+        p.close()
+
+
 @pytest.mark.parametrize("prec", [64, 32])
 def test_newton_solve_matches_oracle(nk, prec):
     shape, nt, reg, beta = (32, 32), 8, 2, 1e-2
@@ -307,14 +362,15 @@ def test_graph_replays_match_eager_matvec(nk, prec):
 def test_checkpointed_trajectory_is_bit_identical(nk, shape, nt, nc, gamma, prec):
     """Keeping m every K steps and recomputing segments reproduces the full-trajectory
     gradient and matvec exactly (same kernels, same order), also when K does not divide nt.
-    A matvec takes segment 0 from the buffer as the previous adjoint sweep left it, so
-    matvecs in a row (eager, captured and replayed), a PCG solve, and a new gradient at
-    another velocity followed by a matvec must all stay exact."""
+    With S trajectory slots a sweep reuses the segments the previous sweep left in
+    them, so matvecs in a row (eager, captured and replayed), a PCG solve, and a new
+    gradient at another velocity followed by a matvec must all stay exact for every S,
+    including S at or above the segment count."""
     mT, mR, vstar, w = smooth_inputs(shape, nt, nc=nc, divfree=bool(gamma))
     outs = []
-    for K in (0, 3, 2):
+    for K, S in ((0, 1), (3, 1), (2, 1), (2, 2), (3, 2), (2, 3), (2, 8)):
         G = nk.Problem(shape, nt, nc=nc, reg=2, incompressible=bool(gamma), beta=1e-3, precision=prec,
-                       checkpoint_every=K)
+                       checkpoint_every=K, trajectory_slots=S)
         G.set_images(dev_t(mT, prec), dev_t(mR, prec))
         J, _, _, g = G.objective_gradient(dev_v(0.5 * vstar))
         res = [J, host(g), host(G.hessian_matvec(dev_v(w)))]
