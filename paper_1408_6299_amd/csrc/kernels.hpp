@@ -357,6 +357,23 @@ __global__ void k_axpby(long long cnt, R a, const R* __restrict__ x, R b, R* __r
     y[i] = a * x[i] + b * y[i];
 }
 
+// One PCG update with the step length taken on the device: alpha = rz / pq from
+// the reduction slots, then x += alpha p and r -= alpha q, written as the two
+// axpby launches would (a x + b y with b = 1). Curvature pq <= 0 (or NaN) leaves
+// x and r unchanged; the host sees pq at its next read and stops there.
+__global__ void k_pcg_step(long long cnt, const double* __restrict__ rz, const double* __restrict__ pq,
+                           const double* __restrict__ p, const double* __restrict__ q, double* __restrict__ x,
+                           double* __restrict__ r) {
+  const double c = *pq;
+  if (!(c > 0.0)) return;
+  const double a = *rz / c;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+       i += (long long)gridDim.x * blockDim.x) {
+    x[i] = a * p[i] + 1.0 * x[i];
+    r[i] = -a * q[i] + 1.0 * r[i];
+  }
+}
+
 // z = a*x + b*y
 template <typename R>
 __global__ void k_lincomb(long long cnt, R a, const R* __restrict__ x, R b, const R* __restrict__ y,

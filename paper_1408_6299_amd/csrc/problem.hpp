@@ -895,26 +895,32 @@ class ProblemT final : public ProblemBase {
     const double tol = rtol * nb;
     precond(kr.p, kz.p);
     copy(kp.p, kz.p, nv * sizeof(double));
-    double rz = red.one<double>(RED_DOT, kr.p, kz.p, nv);
+    // reduction slots: 0 = |r|^2, 1 = r.z (read by the next step), 2 = p.Hp
+    red.enqueue<double>(RED_DOT, kr.p, kz.p, nv, 1);
+    red.fetch(2);
+    double rz = red.host[1];
     double rn = nb;
     int it = 0;
     bool ok = rn <= tol;
+    // One host read per iteration: the step length is formed on the device from
+    // p.Hp and r.z, and p.Hp is checked when the new residual is read.
     while (!ok && it < maxit) {
       hessian_matvec(kp.p, kq.p);
-      const double pq = red.one<double>(RED_DOT, kp.p, kq.p, nv);
-      if (!std::isfinite(pq)) throw HipError(NKREG_ENONFINITE, "p.Hp is not finite");
-      if (pq <= 0.0) {  // non-positive curvature ends the iteration
-        if (it == 0) copy(x, kp.p, nv * sizeof(double));  // then x = P^-1 rhs, a descent direction
-        break;
-      }
-      const double alpha = rz / pq;
-      axpby(nv, alpha, kp.p, 1.0, x);
-      axpby(nv, -alpha, kq.p, 1.0, kr.p);
-      ++it;
+      red.enqueue<double>(RED_DOT, kp.p, kq.p, nv, 2);
+      hipLaunchKernelGGL(k_pcg_step, dim3(launch_blocks(nv)), dim3(256), 0, s, nv, (const double*)red.result.p + 1,
+                         (const double*)red.result.p + 2, (const double*)kp.p, (const double*)kq.p, x, kr.p);
+      NK_LAUNCHED();
       precond(kr.p, kz.p);
       red.enqueue<double>(RED_SUMSQ, kr.p, nullptr, nv, 0);
       red.enqueue<double>(RED_DOT, kr.p, kz.p, nv, 1);
-      red.fetch(2);
+      red.fetch(3);
+      const double pq = red.host[2];
+      if (!std::isfinite(pq)) throw HipError(NKREG_ENONFINITE, "p.Hp is not finite");
+      if (pq <= 0.0) {  // non-positive curvature ends the iteration (x and r were left unchanged)
+        if (it == 0) copy(x, kp.p, nv * sizeof(double));  // then x = P^-1 rhs, a descent direction
+        break;
+      }
+      ++it;
       rn = std::sqrt(red.host[0]);
       const double rz_new = red.host[1];
       if (rn <= tol) { ok = true; break; }
