@@ -186,6 +186,11 @@ def batch_section(nk, synth, torch, reps):
         torch.cuda.synchronize()
         tb = (time.perf_counter() - t0) / reps
         r = {"batched_ms": 1e3 * tb, "item_matvecs_per_s": len(specs) / tb, "mpoints_per_s": pts * 1e-6 / tb}
+        # the whole batch against the HBM roofline: the items' algorithmic bytes over the batch time
+        nbytes = sum(G.matvec_bytes(w)[0] for G, w in zip(probs, ws))
+        ach = nbytes / tb / 1e9
+        r["roofline"] = {"bound": "hbm", "bytes_per_batched_matvec": nbytes, "achieved": ach, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}
         if prec == 32:
             for G, w, o in zip(probs, ws, outs):
                 G.hessian_matvec(w, o)
@@ -199,8 +204,8 @@ def batch_section(nk, synth, torch, reps):
             r["sequential_ms"] = 1e3 * ts
             r["batched_speedup_vs_sequential"] = ts / tb
         out[f"fp{prec}"] = r
-        log(f"batch FP{prec}: {r['batched_ms']:.3f} ms per batched matvec ({r['item_matvecs_per_s']:.0f} item-matvecs/s)"
-            + (f", sequential {r['sequential_ms']:.3f} ms" if prec == 32 else ""))
+        log(f"batch FP{prec}: {r['batched_ms']:.3f} ms per batched matvec ({r['item_matvecs_per_s']:.0f} item-matvecs/s, "
+            f"{ach / 1e3:.2f} TB/s)" + (f", sequential {r['sequential_ms']:.3f} ms" if prec == 32 else ""))
         B.close()
         for G in probs:
             G.close()

@@ -14,7 +14,7 @@ struct nkreg_problem {
 // have the same shape (same grid, steps, scheme and precision) form a group;
 // every launch of a group's sequence becomes one launch over all its items,
 // whose per-item arguments come from a device table. Groups are independent
-// branches of the graph, each on the internal stream of its first item.
+// branches of the graph, each captured on a branch stream of the batch.
 struct nkreg_batch {
   std::vector<nkreg_problem*> items;
   hipStream_t s = nullptr;

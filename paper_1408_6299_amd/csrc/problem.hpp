@@ -144,9 +144,6 @@ class ProblemBase {
   virtual int hessian_mode() const = 0;
   virtual void use_graph_capture(bool on) = 0;
   virtual std::string describe() = 0;
-  // One matvec as eager launches on the internal stream (used when a batch
-  // captures several problems into one graph); checks the cached state.
-  virtual void matvec_launches(const void* vt, void* out) = 0;
   // Records one matvec's launches (nothing is issued); checks the cached state.
   // col_variant >= 0 records with that column pass (8 or 0 = tiled, which give
   // identical values) instead of the handle's own choice.
@@ -306,10 +303,6 @@ class ProblemT final : public ProblemBase {
     if (mv_graph.exec) (void)hipGraphExecDestroy(mv_graph.exec);
     mv_graph = GraphEntry{};
     ++generation;
-  }
-  void matvec_launches(const void* vt, void* out) override {
-    if (!state_valid) throw HipError(NKREG_ESTATE, "no gradient computed at the current velocity");
-    matvec_body(vt, out);
   }
   hipStream_t caller_stream() const override { return user_s; }
   ~ProblemT() override {
@@ -748,7 +741,7 @@ class ProblemT final : public ProblemBase {
   // where an axis allows it, the LDS-tiled pass. Both run the same register FFT
   // on the same values, so the choice changes the schedule and never a result.
   // For each candidate a HIP graph of kTuneReps derivative and divergence column
-  // passes over zeroed spectra is captured on the internal stream and replayed
+  // passes over zeroed spectra is captured on the capture stream and replayed
   // under HIP events; the fastest is kept and shared by every handle of the same
   // grid and precision in the process. NKREG_COL_E in the environment fixes the
   // choice (8, 4 or tiled; 4 elements per lane rounds differently).
@@ -831,7 +824,7 @@ class ProblemT final : public ProblemBase {
            "\"}";
   }
 
-  // One Gauss-Newton matvec as a sequence of launches on the internal stream.
+  // One Gauss-Newton matvec as a sequence of launches on the current launch stream.
   void matvec_body(const void* vtin, void* out) {
     const double* vt = (const double*)vtin;
     const R* vl = kF64 ? (const R*)v.p : vR.p;
