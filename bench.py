@@ -146,6 +146,32 @@ def timed_pcg_steps(prob, rhs, steps, torch):
     return time.perf_counter() - t0
 
 
+def counter_pass(nk, synth, torch, name: str) -> int:
+    """Three eager FP32 matvecs of one workload, launched one kernel at a time, for the
+    FETCH_SIZE / WRITE_SIZE runs. The column pass follows the autotuner unless
+    NKREG_COL_E pins it."""
+    dev = torch.device("cuda:0")
+    spec = synth.CONFIGS[name]
+    stokes = name == "c4"
+    mT, vstar = synth.make_inputs(spec)
+    G = nk.Problem(spec.shape, spec.nt, 1, spec.reg, stokes, spec.beta, precision=32,
+                   checkpoint_every=spec.checkpoint_every)
+    G.use_graphs(False)
+    mTd = torch.from_numpy(mT).to(dev).to(torch.float32)
+    G.set_images(mTd, mTd)
+    mR = G.forward(torch.from_numpy(vstar).to(dev))
+    G.set_images(mTd, mR)
+    G.objective_gradient(G.zeros_v())
+    w = torch.from_numpy(synth.bandlimited_velocity(spec.shape, 52, 6, 0.05, divfree=stokes)).to(dev)
+    out = G.empty_v()
+    for _ in range(3):
+        G.hessian_matvec(w, out)
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": name, "matvecs": 3, "launch": G.describe()}), flush=True)
+    G.close()
+    return 0
+
+
 def batch_section(nk, synth, torch, reps):
     """64 independent 2D pairs of uneven grid sizes (64^2..512^2), H1, beta 1e-2, nt = 16:
     one graph-captured batched matvec (items of one grid size share every kernel launch)
@@ -406,6 +432,9 @@ def main() -> int:
     ap.add_argument("--no-3d", action="store_true", help="skip the 256^3 workload")
     ap.add_argument("--no-beta-search", action="store_true", help="skip the det F_1-bounded beta search")
     ap.add_argument("--no-analysis", action="store_true", help="skip the Hessian assembly and Lanczos estimate")
+    ap.add_argument("--counter-pass", choices=("c2lit", "c4"), default=None,
+                    help="only run three eager FP32 Hessian matvecs of the workload (no graphs, no timers; for "
+                         "HBM counters) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -429,6 +458,8 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_each_way": 4 * n, "launches": 3}), flush=True)
         return 0
+    if args.counter_pass:
+        return counter_pass(nk, synth, torch, args.counter_pass)
     spec = synth.CONFIGS["c2lit"]
     shape, nt = spec.shape, spec.nt
     mT_h, vstar_h = synth.make_inputs(spec)
