@@ -126,7 +126,7 @@ int nkreg_set_beta(nkreg_problem* p, double beta);
  * (e:second-order-opt-cond: the incremental adjoint keeps -div(v~ lam) and the
  * incremental body force keeps lam grad m~). Full Newton keeps lam^{j+1},
  * lam*_j of every gradient evaluation and grad m~ of every matvec (2 nt + 2 nt d
- * fields) and needs checkpoint_every = 0 (else ENOTIMPL). Switching modes
+ * fields, also when the state trajectory is checkpointed). Switching modes
  * invalidates the cached state (a new gradient is needed before a matvec). The
  * full-Newton Hessian can be indefinite away from a minimiser: PCG stops at
  * non-positive curvature and, if that happens in its first iteration, returns

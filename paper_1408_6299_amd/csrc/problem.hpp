@@ -280,7 +280,6 @@ class ProblemT final : public ProblemBase {
   R* mtp(int j, int k) { return mtraj.p + ((size_t)(2 * j + k)) * d * n; }
   void set_hessian(int mode) override {
     if (mode != 0 && mode != 1) throw HipError(NKREG_EINVAL, "Hessian mode must be 0 (GN) or 1 (full Newton)");
-    if (mode == 1 && K) throw HipError(NKREG_ENOTIMPL, "the full-Newton matvec needs the full trajectory (checkpoint_every = 0)");
     NK_HIP(hipStreamSynchronize(s));
     if (mode == 1 && !ltraj.p) {
       ltraj.alloc((size_t)2 * nt * n);

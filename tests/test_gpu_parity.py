@@ -559,7 +559,7 @@ def test_full_newton_matvec_matches_oracle(nk, case, prec):
 
 
 def test_full_newton_mode_errors_and_state(nk):
-    """Switching the Hessian needs a new gradient; checkpointing is not supported with it."""
+    """Switching the Hessian needs a new gradient."""
     shape, nt = (16, 16), 4
     mT, mR, vstar, w = smooth_inputs(shape, nt)
     G = nk.Problem(shape, nt, precision=64)
@@ -572,11 +572,31 @@ def test_full_newton_mode_errors_and_state(nk):
     G.objective_gradient(dev_v(0.5 * vstar))
     G.hessian_matvec(dev_v(w))
     G.close()
-    C = nk.Problem(shape, nt, precision=64, checkpoint_every=2)
-    with pytest.raises(nk.NkregError) as ei:
-        C.hessian = "newton"
-    assert ei.value.status == -9   # ENOTIMPL
-    C.close()
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+def test_full_newton_with_checkpointing_is_bit_identical(nk, prec):
+    """The full-Newton matvec with a checkpointed state trajectory (any number of slots)
+    reproduces the full-trajectory one bit for bit: matvecs in a row, a PCG solve, and a
+    matvec after a new gradient."""
+    shape, nt = (32, 16), 7
+    mT, mR, vstar, w = smooth_inputs(shape, nt, nc=2)
+    outs = []
+    for K, S in ((0, 1), (2, 1), (3, 2), (2, 4)):
+        G = nk.Problem(shape, nt, nc=2, reg=2, beta=1e-3, precision=prec, checkpoint_every=K, trajectory_slots=S)
+        G.hessian = "newton"
+        G.set_images(dev_t(mT, prec), dev_t(mR, prec))
+        J, _, _, g = G.objective_gradient(dev_v(0.5 * vstar))
+        res = [J, host(g)] + [host(G.hessian_matvec(dev_v(c * w))) for c in (1.0, -0.5)]
+        s, it, rel, _ = G.pcg(g, 1e-6, maxit=5)
+        res += [host(s), it, rel]
+        G.objective_gradient(dev_v(0.25 * vstar))
+        res.append(host(G.hessian_matvec(dev_v(w))))
+        outs.append(res)
+        G.close()
+    for res in outs[1:]:
+        for a, b in zip(res, outs[0]):
+            assert np.array_equal(np.asarray(a), np.asarray(b))
 
 
 def test_full_newton_batch_matches_single_items(nk):
