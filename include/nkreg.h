@@ -271,8 +271,12 @@ int nkreg_picard_solve(nkreg_problem* p, void* d_v, const nkreg_solve_opts* opts
 
 /* Hessian analysis at the cached state (Section "Spectral Analysis", Table
  * t:eigenvalues). nkreg_hessian_assemble writes the n x n matrix (n = nc*d*prod N_i,
- * doubles, row j = H e_j; H is symmetric) by n matvecs with the current Hessian
- * mode. nkreg_hessian_lanczos runs up to `steps` (1..512) Lanczos steps on H with
+ * doubles, row j = H e_j; H is symmetric unless the Leray projection is on) by n
+ * matvecs with the current Hessian mode. It runs them G at a time (G <= 32, fewer
+ * on large grids) as one captured batch group of the handle and G - 1 temporary
+ * clones (same configuration, images, velocity and mode; their matvecs are
+ * bit-identical to the handle's), so it allocates G - 1 handles' workspace and
+ * 2 G n doubles while it runs. nkreg_hessian_lanczos runs up to `steps` (1..512) Lanczos steps on H with
  * full reorthogonalisation from a fixed pseudo-random start and writes the Ritz
  * values in ascending order to h_ritz (capacity >= steps) and their number to
  * h_count; the extreme Ritz values estimate H's extreme eigenvalues and condition

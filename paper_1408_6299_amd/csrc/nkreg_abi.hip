@@ -218,11 +218,6 @@ int nkreg_picard_solve(nkreg_problem* p, void* v, const nkreg_solve_opts* opts, 
   return guarded([&]() { return p->impl->picard(v, opts, popts, rep); });
 }
 
-int nkreg_hessian_assemble(nkreg_problem* p, void* H) {
-  NEED(p); NEED(H);
-  return guarded([&]() { p->impl->assemble_hessian(H); return (int)NKREG_OK; });
-}
-
 int nkreg_hessian_lanczos(nkreg_problem* p, int steps, double* ritz, int* count) {
   NEED(p); NEED(ritz);
   return guarded([&]() { return p->impl->lanczos(steps, ritz, count); });
@@ -439,9 +434,102 @@ float time_group(const GroupPlan& gp, hipStream_t st) {
   return ms / 2.f;
 }
 
+// Y[i] = e_{j0 + i} for i < G (G vectors of length cnt, one after another); a
+// column index at or beyond cnt gives a zero vector.
+__global__ void k_unit_block(long long cnt, int G, long long j0, double* __restrict__ Y) {
+  const long long tot = cnt * G;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot;
+       t += (long long)gridDim.x * blockDim.x)
+    Y[t] = (t % cnt) == j0 + t / cnt ? 1.0 : 0.0;
+}
+
+// Columns of the dense Hessian assembled per graph replay: up to this many, and
+// fewer on large grids, where one matvec already fills the GPU.
+constexpr int kAssembleGroup = 32;
+
+// Dense Hessian by unit-vector matvecs, G columns per replay. The handle and G - 1
+// clones of it (same configuration, images, velocity and Hessian mode, so every
+// clone's matvec is bit-identical to the handle's) form one batch group whose
+// launch sequence is captured once; each replay takes G unit vectors and yields
+// G adjacent columns of H (column-major, nv x nv).
+void assemble_grouped(nk::ProblemBase* src, double* H) {
+  if (!src->state_ready()) throw nk::HipError(NKREG_ESTATE, "no gradient computed at the current velocity");
+  const nkreg_config c = src->cfg;
+  const long long npts = (long long)c.n[0] * c.n[1] * (c.dim == 3 ? c.n[2] : 1);
+  const long long nv = (long long)c.nc * c.dim * npts;
+  const int G = (int)std::min<long long>(std::min<long long>(kAssembleGroup, nv),
+                                         std::max<long long>(1, (1LL << 20) / npts));
+  if (G <= 1) {
+    src->assemble_hessian(H);
+    return;
+  }
+  const hipStream_t st = src->stream();
+  std::vector<std::unique_ptr<nk::ProblemBase>> clones;
+  std::vector<nk::ProblemBase*> items{src};
+  const void *mT = nullptr, *mR = nullptr;
+  src->images(&mT, &mR);
+  for (int i = 1; i < G; ++i) {
+    nk::ProblemBase* q;
+    if (c.precision == 32) q = new nk::ProblemT<float>(c, st);
+    else q = new nk::ProblemT<double>(c, st);
+    clones.emplace_back(q);
+    q->set_hessian(src->hessian_mode());
+    q->set_images(mT, mR);
+    q->objective_gradient(src->velocity(), nullptr, nullptr, nullptr, nullptr);
+    items.push_back(q);
+  }
+  nk::DevBuf<double> E((size_t)G * nv), C((size_t)G * nv);
+  GroupPlan gp;
+  gp.recs.resize(G);
+  for (int i = 0; i < G; ++i) {
+    gp.items.push_back((size_t)i);
+    items[i]->record_matvec(E.p + (size_t)i * nv, C.p + (size_t)i * nv, gp.recs[i]);
+    if (!same_sequence(gp.recs[0].recs, gp.recs[i].recs))
+      throw nk::HipError(NKREG_EHIP, "clone's matvec differs from the handle's");
+  }
+  std::vector<unsigned char> host;
+  add_tables(gp, host);
+  nk::DevBuf<unsigned char> tab(host.size());
+  if (!host.empty()) NK_HIP(hipMemcpy(tab.p, host.data(), host.size(), hipMemcpyHostToDevice));
+  // captured on a stream of its own (the caller's may be the null stream), replayed on st
+  hipStream_t cap = nullptr;
+  NK_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));  // default priority
+  hipGraphExec_t ex = nullptr;
+  try {
+    ex = capture_group(gp, tab.p, cap);
+  } catch (...) {
+    (void)hipStreamDestroy(cap);
+    throw;
+  }
+  (void)hipStreamDestroy(cap);
+  try {
+    const long long tot = (long long)G * nv;
+    const int blocks = (int)std::min<long long>((tot + 255) / 256, 8192);
+    for (long long j0 = 0; j0 < nv; j0 += G) {
+      hipLaunchKernelGGL(k_unit_block, dim3(blocks), dim3(256), 0, st, nv, G, j0, E.p);
+      NK_LAUNCHED();
+      NK_HIP(hipGraphLaunch(ex, st));
+      const long long cols = std::min<long long>(G, nv - j0);
+      NK_HIP(hipMemcpyAsync(H + (size_t)j0 * nv, C.p, (size_t)cols * nv * sizeof(double), hipMemcpyDeviceToDevice,
+                            st));
+    }
+    NK_HIP(hipStreamSynchronize(st));
+  } catch (...) {
+    (void)hipStreamSynchronize(st);
+    (void)hipGraphExecDestroy(ex);
+    throw;
+  }
+  (void)hipGraphExecDestroy(ex);
+}
+
 }  // namespace
 
 extern "C" {
+
+int nkreg_hessian_assemble(nkreg_problem* p, void* H) {
+  NEED(p); NEED(H);
+  return guarded([&]() { assemble_grouped(p->impl, (double*)H); return (int)NKREG_OK; });
+}
 
 int nkreg_batch_hessian_matvec(nkreg_batch* b, const void* const* vt, void* const* out) {
   NEED(b);

@@ -140,6 +140,11 @@ class ProblemBase {
   virtual void set_beta(double beta) = 0;
   virtual void set_hessian(int mode) = 0;
   virtual void assemble_hessian(void* H) = 0;
+  // The cached state a matvec is taken at: valid flag, velocity (FP64) and images
+  // (transport precision), for handles that replicate it.
+  virtual bool state_ready() const = 0;
+  virtual const double* velocity() const = 0;
+  virtual void images(const void** mT, const void** mR) const = 0;
   virtual int lanczos(int steps, double* ritz, int* count) = 0;
   virtual int hessian_mode() const = 0;
   virtual void use_graph_capture(bool on) = 0;
@@ -1081,6 +1086,13 @@ class ProblemT final : public ProblemBase {
 
   // ---- Hessian analysis (Section "Spectral Analysis", Table t:eigenvalues) ----
   // Row j of H (nv x nv doubles) = H e_j, by nv matvecs at the cached state.
+  bool state_ready() const override { return state_valid; }
+  const double* velocity() const override { return v.p; }
+  void images(const void** a, const void** b) const override {
+    *a = mT.p;
+    *b = mR.p;
+  }
+
   void assemble_hessian(void* Hout) override {
     if (!state_valid) throw HipError(NKREG_ESTATE, "no gradient computed at the current velocity");
     double* H = (double*)Hout;

@@ -683,6 +683,29 @@ def test_hessian_matrix_matches_oracle_columns_and_lanczos_matches_its_spectrum(
     G.close()
 
 
+@pytest.mark.parametrize("prec,mode,K", [(32, "gn", 0), (64, "newton", 0), (32, "gn", 2)])
+def test_assembled_columns_equal_single_matvecs(nk, prec, mode, K):
+    """The assembly runs its unit-vector matvecs as one batch group of the handle and its
+    clones (16^2: n = 512 columns, 16 replays of 32); every column equals the handle's own
+    matvec of that unit vector bit for bit, also in the full-Newton mode and with a
+    checkpointed trajectory."""
+    nt = 6
+    mT, mR, vstar, w = smooth_inputs((16, 16), nt)
+    G = nk.Problem((16, 16), nt, reg=2, beta=1e-2, precision=prec, checkpoint_every=K)
+    G.hessian = mode
+    G.set_images(dev_t(mT, prec), dev_t(mR, prec))
+    G.objective_gradient(dev_v(0.5 * vstar))
+    Hh = host(G.hessian_matrix())
+    n = Hh.shape[0]
+    assert n == 512
+    for j in (0, 1, 31, 32, 257, 480, 511):
+        e = np.zeros(n)
+        e[j] = 1.0
+        col = host(G.hessian_matvec(dev_v(e.reshape(G.vshape))))
+        assert np.array_equal(Hh[j], col.reshape(-1)), j
+    G.close()
+
+
 GOLDEN_EIG = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden", "eigen_extremes.json")
 
 
