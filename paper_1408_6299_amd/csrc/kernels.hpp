@@ -397,50 +397,6 @@ __global__ void k_convert(long long cnt, const RS* __restrict__ x, RD* __restric
     y[i] = (RD)x[i];
 }
 
-// y = e_j (unit vector), for assembling the Hessian column by column.
-template <typename R>
-__global__ void k_unit(long long cnt, long long j, R* __restrict__ y) {
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
-       i += (long long)gridDim.x * blockDim.x)
-    y[i] = i == j ? R(1) : R(0);
-}
-
-// Deterministic start vector in [-1, 1] (a fixed integer hash of the index).
-__global__ void k_hash_fill(long long cnt, double* __restrict__ y) {
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
-       i += (long long)gridDim.x * blockDim.x) {
-    unsigned long long x = (unsigned long long)i * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
-    x ^= x >> 31;
-    x *= 0xBF58476D1CE4E5B9ull;
-    x ^= x >> 29;
-    y[i] = (double)(x >> 11) * (2.0 / 9007199254740992.0) - 1.0;
-  }
-}
-
-// c[i] = <Q_i, w> for the k vectors Q_0..Q_{k-1} (stride nv), one workgroup per vector.
-__global__ __launch_bounds__(256) void k_multidot(const double* __restrict__ Q, long long nv,
-                                                  const double* __restrict__ w, double* __restrict__ c) {
-  const double* q = Q + (long long)blockIdx.x * nv;
-  double sum = 0.0;
-  for (long long t = threadIdx.x; t < nv; t += blockDim.x) sum += q[t] * w[t];
-  __shared__ double part[4];
-  for (int o = 32; o > 0; o >>= 1) sum += __shfl_down(sum, o, 64);
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = sum;
-  __syncthreads();
-  if (threadIdx.x == 0) c[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
-}
-
-// w -= sum_i c[i] Q_i over the k vectors.
-__global__ void k_multi_axpy(const double* __restrict__ Q, int k, long long nv, const double* __restrict__ c,
-                             double* __restrict__ w) {
-  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < nv;
-       t += (long long)gridDim.x * blockDim.x) {
-    double acc = w[t];
-    for (int i = 0; i < k; ++i) acc -= c[i] * Q[(long long)i * nv + t];
-    w[t] = acc;
-  }
-}
-
 // Batch-group forms: item blockIdx.z takes its pointers from the table.
 template <typename R>
 __global__ void k_fill_t(long long cnt, R v, R* const* __restrict__ tab) {

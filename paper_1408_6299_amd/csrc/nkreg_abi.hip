@@ -434,15 +434,6 @@ float time_group(const GroupPlan& gp, hipStream_t st) {
   return ms / 2.f;
 }
 
-// Y[i] = e_{j0 + i} for i < G (G vectors of length cnt, one after another); a
-// column index at or beyond cnt gives a zero vector.
-__global__ void k_unit_block(long long cnt, int G, long long j0, double* __restrict__ Y) {
-  const long long tot = cnt * G;
-  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot;
-       t += (long long)gridDim.x * blockDim.x)
-    Y[t] = (t % cnt) == j0 + t / cnt ? 1.0 : 0.0;
-}
-
 // Columns of the dense Hessian assembled per graph replay: up to this many, and
 // fewer on large grids, where one matvec already fills the GPU.
 constexpr int kAssembleGroup = 32;
@@ -506,7 +497,7 @@ void assemble_grouped(nk::ProblemBase* src, double* H) {
     const long long tot = (long long)G * nv;
     const int blocks = (int)std::min<long long>((tot + 255) / 256, 8192);
     for (long long j0 = 0; j0 < nv; j0 += G) {
-      hipLaunchKernelGGL(k_unit_block, dim3(blocks), dim3(256), 0, st, nv, G, j0, E.p);
+      hipLaunchKernelGGL(nk::k_unit_block, dim3(blocks), dim3(256), 0, st, nv, G, j0, E.p);
       NK_LAUNCHED();
       NK_HIP(hipGraphLaunch(ex, st));
       const long long cols = std::min<long long>(G, nv - j0);

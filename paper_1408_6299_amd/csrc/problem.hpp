@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "../../include/nkreg.h"
+#include "kernels_analysis.hpp"
 #include "spectral.hpp"
 
 namespace nk {
@@ -1114,7 +1115,7 @@ class ProblemT final : public ProblemBase {
     if (!state_valid) throw HipError(NKREG_ESTATE, "no gradient computed at the current velocity");
     if (steps <= 0 || steps > kMaxLanczos) throw HipError(NKREG_EINVAL, "Lanczos steps must lie in [1, 512]");
     const int m = (int)std::min<long long>(steps, nv);
-    DevBuf<double> Q((size_t)(m + 1) * nv), w(nv), qin(nv), c(m + 1);
+    DevBuf<double> Q((size_t)(m + 1) * nv), w(nv), qin(nv), c(m + 1), part((size_t)(m + 1) * kDotParts);
     auto q = [&](int i) { return Q.p + (size_t)i * nv; };
     hipLaunchKernelGGL(k_hash_fill, dim3(launch_blocks(nv)), dim3(256), 0, s, nv, q(0));
     NK_LAUNCHED();
@@ -1130,7 +1131,9 @@ class ProblemT final : public ProblemBase {
       lincomb(nv, 1.0, w.p, -ak, q(k), w.p);
       if (k > 0) axpby(nv, -b.back(), q(k - 1), 1.0, w.p);
       for (int pass = 0; pass < 2; ++pass) {
-        hipLaunchKernelGGL(k_multidot, dim3(k + 1), dim3(256), 0, s, Q.p, (long long)nv, w.p, c.p);
+        hipLaunchKernelGGL(k_multidot_part, dim3(k + 1, kDotParts), dim3(256), 0, s, Q.p, (long long)nv, w.p,
+                           part.p);
+        hipLaunchKernelGGL(k_multidot_sum, dim3((k + 1 + 63) / 64), dim3(64), 0, s, part.p, kDotParts, k + 1, c.p);
         hipLaunchKernelGGL(k_multi_axpy, dim3(launch_blocks(nv)), dim3(256), 0, s, Q.p, k + 1, (long long)nv, c.p,
                            w.p);
         NK_LAUNCHED();
