@@ -240,3 +240,52 @@ def test_c4_256cube_properties(nk):
     assert abs(stats[0] - 1) < 1e-3 and abs(stats[1] - 1) < 1e-3 and abs(stats[2] - 1) < 1e-4
     G32.close()
     G64.close()
+
+
+def test_largest_grid_512cube_closed_form_and_symmetry(nk):
+    """The largest grid the library takes (512^3, FP32, nt = 2). A constant velocity moves
+    each Fourier mode by the Heun factor G(z) = 1 + z + z^2/2 per step, z = -i h (k . v),
+    so m_T = sin(x1) + cos(3 x3) under v = (a1, 0, a3) ends as
+    Im(G(-i h a1)^nt e^{i x1}) + Re(G(-3 i h a3)^nt e^{3 i x3}) at every point (the
+    constant-velocity closed form the oracle is pinned to). The GN Hessian at that state is
+    symmetric for two smooth directions to FP32 rounding."""
+    n, nt = 512, 2
+    shape = (n, n, n)
+    h = 1.0 / nt
+    a1, a3 = 0.004, -0.003
+    x = torch.arange(n, dtype=torch.float64, device="cuda") * (2 * np.pi / n)
+    X1 = x.view(n, 1, 1)
+    X3 = x.view(1, 1, n)
+    mT = (torch.sin(X1) + torch.cos(3 * X3)).expand(shape).contiguous()
+    G = nk.Problem(shape, nt, 1, 1, False, 1e-2, precision=32)
+    v = torch.zeros(G.vshape, dtype=torch.float64, device="cuda")
+    v[0, 0] = a1
+    v[0, 2] = a3
+    G.set_images(mT.float(), mT.float())
+    m1 = G.forward(v)
+    heun = lambda z: (1 + z + z * z / 2) ** nt
+    g1, g3 = heun(-1j * h * a1), heun(-3j * h * a3)
+    ref = (abs(g1) * torch.sin(X1 + np.angle(g1)) + abs(g3) * torch.cos(3 * X3 + np.angle(g3))).expand(shape)
+    err = float((m1.double() - ref).abs().max())
+    moved = float((ref - mT).abs().max())   # how far the closed form is from the template
+    assert err < 5e-6 and moved > 1e-3, (err, moved)
+    del ref, m1
+    # reference image: the template moved by the velocity (library forward, input synthesis)
+    mR = G.forward(2.0 * v)
+    G.set_images(mT.float(), mR)
+    G.objective_gradient(v)
+    X2 = x.view(1, n, 1)
+    u = torch.zeros_like(v)
+    u[0, 0] = 0.01 * torch.sin(X2)
+    u[0, 1] = 0.01 * torch.cos(X3)
+    u[0, 2] = 0.01 * torch.sin(X1)
+    w = u.clone()                       # w = u + r keeps <u, Hw> away from zero (H is SPD)
+    w[0, 0] += 0.005 * torch.cos(2 * X3)
+    w[0, 1] += 0.005 * torch.sin(X1)
+    w[0, 2] += 0.005 * torch.cos(X2)
+    Hw = G.hessian_matvec(w)
+    Hu = G.hessian_matvec(u)
+    s1, s2 = float((u * Hw).sum()), float((Hu * w).sum())
+    assert abs(s1 - s2) <= 1e-5 * abs(s1), (s1, s2)
+    assert torch.isfinite(Hw).all()
+    G.close()
