@@ -15,12 +15,17 @@
 
 namespace nk {
 
-// All LDS traffic of this wavefront completes before execution continues, and
-// the memory clobber keeps the compiler from moving memory accesses across
-// this point. Only LDS (lgkm) traffic is waited on, so global prefetches stay
-// in flight. Other waves are not involved.
+// Orders this wavefront's LDS accesses across an exchange: the LDS unit runs a
+// wavefront's instructions in issue order, so a read issued after the writes of
+// the other lanes sees them, and a later write cannot overtake an earlier read;
+// what must not happen is the compiler moving an access across this point, which
+// the wavefront-scope fences forbid. No wait is issued here: the LDS writes of an
+// exchange overlap the reads that follow them, and results are waited for only
+// where registers use them. Other waves are not involved.
 __device__ __forceinline__ void wave_lds_sync() {
-  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <typename R, bool INV>
