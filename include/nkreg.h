@@ -37,7 +37,11 @@
  *   synchronise that stream; the others are asynchronous.
  * - A handle is not thread-safe. No exception crosses the ABI.
  * - The library owns its workspace (trajectory, spectra, Krylov vectors), which
- *   it allocates in nkreg_create and frees in nkreg_destroy.
+ *   it allocates in nkreg_create and frees in nkreg_destroy. The gradient, the
+ *   Hessian matvec, PCG and the Newton and Picard drivers allocate nothing; the
+ *   beta search, det(grad y), the Hessian assembly and Lanczos allocate their own
+ *   temporaries for the duration of the call, and a batch allocates its argument
+ *   tables when it (re)builds its graph.
  */
 #ifndef NKREG_H
 #define NKREG_H
