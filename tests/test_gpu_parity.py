@@ -617,6 +617,34 @@ def test_full_newton_batch_matches_single_items(nk):
         assert np.array_equal(host(o), r)
 
 
+def test_pcg_negative_curvature_in_the_first_step_returns_the_preconditioned_rhs(nk):
+    """Full Newton far from a minimiser (an unrelated reference image, small beta) is
+    indefinite. With rhs = P u for an eigenvector u of a negative eigenvalue, the first
+    search direction P^-1 rhs = u has negative curvature: PCG stops before any update
+    (0 iterations, not converged) and returns P^-1 rhs, as the step length formed on the
+    device leaves x untouched."""
+    shape, nt, beta = (16, 16), 4, 1e-4
+    width = 0.6 * 16 ** 2 / 16.0
+    mT = synth.smooth_image(shape, 5, width)
+    mR = synth.smooth_image(shape, 9, width)
+    G = nk.Problem(shape, nt, reg=1, beta=beta, precision=64)
+    G.hessian = "newton"
+    G.set_images(dev_t(mT, 64), dev_t(mR, 64))
+    G.objective_gradient(G.zeros_v())
+    H = host(G.hessian_matrix())
+    lam, U = np.linalg.eigh(0.5 * (H + H.T))
+    assert lam[0] < 0, lam[:3]
+    ud = dev_v(U[:, 0].reshape(G.vshape))
+    assert float((ud * G.hessian_matvec(ud)).sum()) < 0
+    rhs = beta * G.apply_reg(ud) + ud.mean(dim=(-2, -1), keepdim=True)   # P u, the mean kept
+    pinv = host(G.precond(rhs))
+    assert rel_inf(pinv, host(ud)) < 1e-8
+    s, it, rel, converged = G.pcg(rhs, 1e-8)
+    assert it == 0 and not converged
+    assert np.array_equal(host(s), pinv)
+    G.close()
+
+
 @pytest.mark.parametrize("prec", [64, 32])
 def test_full_newton_solve_matches_oracle(nk, prec):
     shape, nt, reg, beta = (32, 32), 8, 2, 1e-2
