@@ -94,6 +94,26 @@ def test_c2lit_512_autograd_fd_five_directions(nk, c2lit):
     G.close()
 
 
+def test_c2lit_512_fp32_solve_final_mismatch_matches_fp64(nk, c2lit):
+    """The bench's time-to-solution run: beta continuation 1e-1 -> 1e-4 at 512^2, nt = 32,
+    to a relative gradient of 1e-3 per level. The FP32 transport's final relative mismatch
+    ||m_1 - m_R||^2 / ||m_T - m_R||^2 lies within 1e-4 (absolute) of the FP64 solve's. The
+    FP64 library stands in for the oracle here (a CPU continuation at this size takes
+    minutes); every FP64 operation of the path is pinned to the oracle to 1e-10 above."""
+    spec, P, vstar, S0, w, Hw = c2lit
+    mis = {}
+    for prec in (64, 32):
+        G = nk.Problem(spec.shape, spec.nt, 1, spec.reg, False, spec.beta, precision=prec)
+        G.set_images(dev_t(P.mT, prec), dev_t(P.mR, prec))
+        v, reps = G.continuation(spec.beta_levels, G.zeros_v(), gtol=1e-3, max_outer=50)
+        assert all(r.converged for r in reps), prec
+        m1 = host(G.forward(v))
+        mis[prec] = float(np.sum((m1 - P.mR) ** 2) / np.sum((P.mT - P.mR) ** 2))
+        G.close()
+    assert mis[64] < 1e-2
+    assert abs(mis[32] - mis[64]) <= 1e-4, mis
+
+
 def test_c0_64_gauss_newton_solve_matches_oracle(nk):
     """64^2 FP64, H1, beta = 1e-2, nt = 16: the whole GN-PCG solve to relative gradient 1e-3."""
     spec = synth.CONFIGS["c0"]
