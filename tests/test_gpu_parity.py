@@ -403,7 +403,7 @@ def test_handles_of_one_grid_share_the_tile_choice(nk, prec):
     for _ in range(2):
         G = nk.Problem(shape, nt, reg=2, beta=1e-3, precision=prec)
         desc = G.describe()
-        assert desc["col_E"] in (4, 8) and "col_E" in desc["autotune"], desc
+        assert desc["col_E"] in (0, 4, 8) and "col_E" in desc["autotune"], desc   # 0 = tiled
         G.set_images(dev_t(mT, prec), dev_t(mR, prec))
         J, _, _, g = G.objective_gradient(dev_v(0.5 * vstar))
         res.append((desc["col_E"], J, host(g), host(G.hessian_matvec(dev_v(w)))))
