@@ -418,8 +418,8 @@ def analysis_section(nk, synth, torch, spec, mT_h, mR_h):
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--kernel", default="col_deriv",
                     help="kernel whose launches are timed for the roofline (see Problem.KERNELS)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
