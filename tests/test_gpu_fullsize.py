@@ -114,6 +114,31 @@ def test_c2lit_512_fp32_solve_final_mismatch_matches_fp64(nk, c2lit):
     assert abs(mis[32] - mis[64]) <= 1e-4, mis
 
 
+GOLDEN_C2 = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden", "c2lit_solve.json")
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+def test_c2lit_512_solve_matches_the_oracle_solve(nk, c2lit, prec):
+    """The bench's time-to-solution run against the FP64 oracle's continuation of the same
+    512^2 workload (stored by tests/golden/make_c2lit_solve.py, which calls only the
+    oracle): every level converges with the oracle's outer iterations to within one, and the
+    final relative mismatch lies within 1e-4 (absolute) of the oracle's."""
+    import json
+    ref = json.load(open(GOLDEN_C2))
+    spec, P, vstar, S0, w, Hw = c2lit
+    assert list(spec.beta_levels) == ref["beta_levels"]
+    G = nk.Problem(spec.shape, spec.nt, 1, spec.reg, False, spec.beta, precision=prec)
+    G.set_images(dev_t(P.mT, prec), dev_t(P.mR, prec))
+    v, reps = G.continuation(spec.beta_levels, G.zeros_v(), gtol=ref["gtol"], max_outer=50)
+    for r, lv in zip(reps, ref["levels"]):
+        assert r.converged and lv["converged"]
+        assert abs(r.iterations - lv["iterations"]) <= 1, (r.iterations, lv)
+    m1 = host(G.forward(v))
+    mis = float(np.sum((m1 - P.mR) ** 2) / np.sum((P.mT - P.mR) ** 2))
+    assert abs(mis - ref["relative_mismatch"]) <= 1e-4, (mis, ref["relative_mismatch"])
+    G.close()
+
+
 def test_c0_64_gauss_newton_solve_matches_oracle(nk):
     """64^2 FP64, H1, beta = 1e-2, nt = 16: the whole GN-PCG solve to relative gradient 1e-3."""
     spec = synth.CONFIGS["c0"]
