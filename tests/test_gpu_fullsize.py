@@ -139,6 +139,38 @@ def test_c2lit_512_solve_matches_the_oracle_solve(nk, c2lit, prec):
     G.close()
 
 
+GOLDEN_BS = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden", "c2beta_search.json")
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_c2beta_256_beta_search_matches_the_oracle_search(nk, prec):
+    """The bench's beta search (256^2, nt = 64, H1, bound eps_F on det F_1) against the FP64
+    oracle's search of the same workload (stored by tests/golden/make_c2beta_search.py, which
+    calls only the oracle). FP64: the same trials and decisions, min det F_1 per trial within
+    1e-8 and the same beta*. FP32: every decision follows the bound and beta* lies within two
+    bisection steps of the oracle's."""
+    import json
+    ref = json.load(open(GOLDEN_BS))
+    spec = synth.CONFIGS["c2beta"]
+    mT, vstar = synth.make_inputs(spec)
+    mR = otr.forward_only(mT, vstar, spec.nt)   # the reference image, as the stored search used
+    G = nk.Problem(spec.shape, spec.nt, 1, spec.reg, False, 1.0, precision=prec)
+    G.set_images(dev_t(mT, prec), dev_t(mR, prec))
+    v, res = G.beta_search(ref["eps_F"], gtol=ref["gtol"], max_outer=50)
+    assert res.breached == ref["breached"] and res.reason == ref["reason"]
+    for t in res.trials:
+        assert (t.min_det >= ref["eps_F"]) == t.accepted
+    if prec == 64:
+        assert [t.beta for t in res.trials] == [r["beta"] for r in ref["trials"]]
+        assert [t.accepted for t in res.trials] == [r["accepted"] for r in ref["trials"]]
+        for t, r in zip(res.trials, ref["trials"]):
+            assert abs(t.min_det - r["min_det"]) < 1e-8, (t, r)
+        assert res.beta_star == ref["beta_star"]
+    else:
+        assert abs(res.beta_star - ref["beta_star"]) <= 2 * ref["dbeta_min"]
+    G.close()
+
+
 def test_c0_64_gauss_newton_solve_matches_oracle(nk):
     """64^2 FP64, H1, beta = 1e-2, nt = 16: the whole GN-PCG solve to relative gradient 1e-3."""
     spec = synth.CONFIGS["c0"]
