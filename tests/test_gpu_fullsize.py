@@ -207,6 +207,32 @@ def test_c2lit_512_gn_and_picard_match_the_oracle(nk, c2lit, prec):
     G.close()
 
 
+GOLDEN_NEWTON = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden",
+                                           "c2lit_newton_solve.json")
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_c2lit_512_full_newton_solve_matches_the_oracle_solve(nk, c2lit, prec):
+    """The bench's full-Newton continuation (512^2, nt = 32) against the FP64 oracle's
+    (stored by tests/golden/make_c2lit_newton_solve.py, oracle calls only): every level
+    converges with the oracle's outer iterations to within one, and the final relative
+    mismatch lies within 1e-4 (absolute) of the oracle's."""
+    import json
+    ref = json.load(open(GOLDEN_NEWTON))
+    spec, P, vstar, S0, w, Hw = c2lit
+    G = nk.Problem(spec.shape, spec.nt, 1, spec.reg, False, spec.beta, precision=prec)
+    G.hessian = "newton"
+    G.set_images(dev_t(P.mT, prec), dev_t(P.mR, prec))
+    v, reps = G.continuation(spec.beta_levels, G.zeros_v(), gtol=ref["gtol"], max_outer=50)
+    for r, lv in zip(reps, ref["levels"]):
+        assert r.converged and lv["converged"]
+        assert abs(r.iterations - lv["iterations"]) <= 1, (r.iterations, lv)
+    m1 = host(G.forward(v))
+    mis = float(np.sum((m1 - P.mR) ** 2) / np.sum((P.mT - P.mR) ** 2))
+    assert abs(mis - ref["relative_mismatch"]) <= 1e-4, (mis, ref["relative_mismatch"])
+    G.close()
+
+
 def test_c0_64_gauss_newton_solve_matches_oracle(nk):
     """64^2 FP64, H1, beta = 1e-2, nt = 16: the whole GN-PCG solve to relative gradient 1e-3."""
     spec = synth.CONFIGS["c0"]
