@@ -287,7 +287,8 @@ def test_c1_256_det_grad_y_of_divergence_free_velocity(nk):
 
 def test_c3_batch_subset(nk):
     """Batched workload: every grid size of the 64-item batch, one graph launch, equal to
-    single-item matvecs bit for bit; the smallest item against the oracle."""
+    single-item matvecs bit for bit; one item of every grid size (64^2 to 512^2) against the
+    oracle."""
     specs = synth.batch_specs()
     picks, seen = [], set()
     for i, sp in enumerate(specs):
@@ -316,11 +317,15 @@ def test_c3_batch_subset(nk):
         outs = B.hessian_matvec(ws)
         for o, r in zip(outs, refs):
             assert np.array_equal(host(o), r)
-    k = int(np.argmin([sp.shape[0] for (_, _, _, sp) in host_items]))
-    mT, mR, w, sp = host_items[k]
-    P = ord_.Problem(mT, mR, sp.nt, 1, sp.reg, 0, sp.beta)
-    S0 = ord_.objective_gradient(P, np.zeros(P.vshape()))
-    assert rel_l2(refs[k], ord_.hessian_matvec(P, S0, w)) < 1e-5
+    # The items transport in FP32: lambda = m_R - m_1 carries the FP32 transport error
+    # amplified by the mismatch cancellation kappa = |m_T| / |m_R - m_T| (about 10 at 64^2,
+    # 140 at 512^2), hence 1e-5 * max(1, kappa / 10) as for the other FP32 oracle checks.
+    for k in range(len(seen)):                  # the first pick of each grid size
+        mT, mR, w, sp = host_items[k]
+        P = ord_.Problem(mT, mR, sp.nt, 1, sp.reg, 0, sp.beta)
+        S0 = ord_.objective_gradient(P, np.zeros(P.vshape()))
+        kappa = np.linalg.norm(mT) / np.linalg.norm(mR - mT)
+        assert rel_l2(refs[k], ord_.hessian_matvec(P, S0, w)) < 1e-5 * max(1.0, kappa / 10.0), sp.shape
 
 
 def test_c4_64cube_oracle_parity(nk):
