@@ -228,8 +228,7 @@ __device__ __forceinline__ void row_body(const StageArgs<R>& a, const cplx<R>* _
 #pragma unroll
         for (int e = 0; e < E; ++e) A[k][e] = S[k * PADM + pad_e<E>(j + LS * e)];
       wave_lds_sync();
-#pragma unroll
-      for (int k = 0; k < KIN; ++k) wave_fft<R, M, E, true>(A[k], j, S + k * PADM, T);
+      wave_fft_multi<R, M, E, true, KIN>(A, j, S, PADM, T);
     }
   }
 
@@ -342,8 +341,7 @@ __device__ __forceinline__ void row_body(const StageArgs<R>& a, const cplx<R>* _
   // ---- forward FFT of the new rows -> R2C unpacking -> store in pair layout ----
   if constexpr (KOUT > 0) {
     if (KIND == ST_ADJ2 && a.skip_out) return;  // uniform across the workgroup
-#pragma unroll
-    for (int k = 0; k < KOUT; ++k) wave_fft<R, M, E, false>(O[k], j, S + k * PADM, T);
+    wave_fft_multi<R, M, E, false, KOUT>(O, j, S, PADM, T);
 #pragma unroll
     for (int k = 0; k < KOUT; ++k)
 #pragma unroll

@@ -144,70 +144,119 @@ __device__ __forceinline__ int pad_e(int i) { return i + i / E; }
 template <int E>
 constexpr int padded_e(int m) { return m + m / E + 1; }
 
+// Butterflies of Stockham pass p on one lane's E elements (a[b + r * BPL] is
+// input r of butterfly b). Passes after the first take their twiddles from T in
+// pass order, E - 1 (or RLAST - 1) per butterfly.
+template <typename R, int M, int E, bool INV>
+__device__ __forceinline__ void fft_pass(cplx<R> (&a)[E], int p, const WaveTwiddles<R, M, E>& T) {
+  using P = WavePlan<M, E>;
+  const bool rem = (P::REM > 0) && (p == P::NP - 1);
+  const int RR = rem ? P::RLAST : E;
+  const int BPL = E / RR;
+  int c = p > 0 ? (p - 1) * (E - 1) : 0;
+#pragma unroll
+  for (int b = 0; b < BPL; ++b) {
+    if (RR == E) {
+      cplx<R> v[E];
+#pragma unroll
+      for (int r = 0; r < E; ++r) v[r] = a[b + r * BPL];
+      if (p > 0) {
+#pragma unroll
+        for (int r = 1; r < E; ++r) {
+          cplx<R> w = T.w[c++];
+          if (INV) w.y = -w.y;
+          v[r] = cmul(v[r], w);
+        }
+      }
+      dft_small<R, INV, E>(v);
+#pragma unroll
+      for (int r = 0; r < E; ++r) a[b + r * BPL] = v[r];
+    } else {
+      constexpr int RL = P::RLAST;
+      cplx<R> v[RL];
+#pragma unroll
+      for (int r = 0; r < RL; ++r) v[r] = a[b + r * BPL];
+      if (p > 0) {
+#pragma unroll
+        for (int r = 1; r < RL; ++r) {
+          cplx<R> w = T.w[c++];
+          if (INV) w.y = -w.y;
+          v[r] = cmul(v[r], w);
+        }
+      }
+      dft_small<R, INV, RL>(v);
+#pragma unroll
+      for (int r = 0; r < RL; ++r) a[b + r * BPL] = v[r];
+    }
+  }
+}
+
+// Scatter of pass p's outputs into the sequence's scratch: the outputs of
+// butterfly k = j + b * LS go to (k / Ns) * RR * Ns + k % Ns + r * Ns.
+template <typename R, int M, int E>
+__device__ __forceinline__ void fft_scatter(const cplx<R> (&a)[E], int p, int j, cplx<R>* s) {
+  using P = WavePlan<M, E>;
+  constexpr int LS = P::LS;
+  const bool rem = (P::REM > 0) && (p == P::NP - 1);
+  const int RR = rem ? P::RLAST : E;
+  const int BPL = E / RR;
+  const int Ns = P::ns(p);
+#pragma unroll
+  for (int b = 0; b < BPL; ++b) {
+    const int k = j + b * LS;
+    const int kk = k % Ns;
+    const int base = (k - kk) * RR + kk;
+#pragma unroll
+    for (int r = 0; r < RR; ++r) s[pad_e<E>(base + r * Ns)] = a[b + r * BPL];
+  }
+}
+
+// Lane j's elements j + LS * e of the sequence in scratch.
+template <typename R, int M, int E>
+__device__ __forceinline__ void fft_gather(cplx<R> (&a)[E], int j, const cplx<R>* s) {
+  constexpr int LS = WavePlan<M, E>::LS;
+#pragma unroll
+  for (int e = 0; e < E; ++e) a[e] = s[pad_e<E>(j + LS * e)];
+}
+
 // BLOCK = true when a sequence spans several wavefronts of the workgroup
 // (M / E > 64 lanes): exchanges then synchronise the whole workgroup.
 template <typename R, int M, int E, bool INV, bool BLOCK = false>
 __device__ __forceinline__ void wave_fft(cplx<R> (&a)[E], int j, cplx<R>* s, const WaveTwiddles<R, M, E>& T) {
   using P = WavePlan<M, E>;
-  constexpr int LS = P::LS;
-  int c = 0;
 #pragma unroll
   for (int p = 0; p < P::NP; ++p) {
-    const bool rem = (P::REM > 0) && (p == P::NP - 1);
-    const int RR = rem ? P::RLAST : E;
-    const int BPL = E / RR;
-    const int Ns = P::ns(p);
-    const bool last = (p == P::NP - 1);
-    // butterflies of this pass: b < BPL, inputs a[b + r * BPL]
-#pragma unroll
-    for (int b = 0; b < BPL; ++b) {
-      if (RR == E) {
-        cplx<R> v[E];
-#pragma unroll
-        for (int r = 0; r < E; ++r) v[r] = a[b + r * BPL];
-        if (p > 0) {
-#pragma unroll
-          for (int r = 1; r < E; ++r) {
-            cplx<R> w = T.w[c++];
-            if (INV) w.y = -w.y;
-            v[r] = cmul(v[r], w);
-          }
-        }
-        dft_small<R, INV, E>(v);
-#pragma unroll
-        for (int r = 0; r < E; ++r) a[b + r * BPL] = v[r];
-      } else {
-        constexpr int RL = P::RLAST;
-        cplx<R> v[RL];
-#pragma unroll
-        for (int r = 0; r < RL; ++r) v[r] = a[b + r * BPL];
-        if (p > 0) {
-#pragma unroll
-          for (int r = 1; r < RL; ++r) {
-            cplx<R> w = T.w[c++];
-            if (INV) w.y = -w.y;
-            v[r] = cmul(v[r], w);
-          }
-        }
-        dft_small<R, INV, RL>(v);
-#pragma unroll
-        for (int r = 0; r < RL; ++r) a[b + r * BPL] = v[r];
-      }
+    fft_pass<R, M, E, INV>(a, p, T);
+    if (p != P::NP - 1) {
+      fft_scatter<R, M, E>(a, p, j, s);
+      if (BLOCK) __syncthreads(); else wave_lds_sync();
+      fft_gather<R, M, E>(a, j, s);
+      if (BLOCK) __syncthreads(); else wave_lds_sync();
     }
-    if (!last) {
-      // outputs of butterfly k = j + b*LS go to (k / Ns) * RR * Ns + k % Ns + r * Ns
+  }
+}
+
+// NK independent sequences of one wavefront (a[k], scratch s + k * pitch)
+// transformed in lockstep: each pass runs on every sequence before the one
+// exchange wait, so the LDS round trips of the sequences overlap. Per sequence
+// the arithmetic is that of wave_fft.
+template <typename R, int M, int E, bool INV, int NK, int KA>
+__device__ __forceinline__ void wave_fft_multi(cplx<R> (&a)[KA][E], int j, cplx<R>* s, int pitch,
+                                               const WaveTwiddles<R, M, E>& T) {
+  static_assert(NK >= 1 && NK <= KA, "sequence count");
+  using P = WavePlan<M, E>;
+  static_assert(P::LS <= 64, "a sequence fits one wavefront");
 #pragma unroll
-      for (int b = 0; b < BPL; ++b) {
-        const int k = j + b * LS;
-        const int kk = k % Ns;
-        const int base = (k - kk) * RR + kk;
+  for (int p = 0; p < P::NP; ++p) {
 #pragma unroll
-        for (int r = 0; r < RR; ++r) s[pad_e<E>(base + r * Ns)] = a[b + r * BPL];
-      }
-      if (BLOCK) __syncthreads(); else wave_lds_sync();
+    for (int k = 0; k < NK; ++k) fft_pass<R, M, E, INV>(a[k], p, T);
+    if (p != P::NP - 1) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) a[e] = s[pad_e<E>(j + LS * e)];
-      if (BLOCK) __syncthreads(); else wave_lds_sync();
+      for (int k = 0; k < NK; ++k) fft_scatter<R, M, E>(a[k], p, j, s + k * pitch);
+      wave_lds_sync();
+#pragma unroll
+      for (int k = 0; k < NK; ++k) fft_gather<R, M, E>(a[k], j, s + k * pitch);
+      wave_lds_sync();
     }
   }
 }
