@@ -16,8 +16,9 @@ Readings where the paper is silent:
 * Armijo: alpha starts at 1, sufficient decrease J(v + a s) <= J(v) + c1 a <g, s>_h
   with c1 = 1e-4, alpha halved at most 20 times, then failure is reported.
 * Convergence studies use ||g_k||_inf <= gtol * ||g_0||_inf ("relative change of
-  the gradient of three orders", gtol = 1e-3) or the paper's full rule
-  ((C1 and C2 and C3) or C4 or C5) with tau_J.
+  the gradient of three orders", gtol = 1e-3), capped at max_outer iterations, or the
+  paper's full rule ((C1 and C2 and C3) or C4 or C5) with tau_J (stopping_rule), where
+  n_opt = max_outer and C5 reads k > n_opt literally (at most n_opt + 1 iterations).
 * Continuation: a list of beta levels solved in turn, each warm-started from
   the previous level's solution, each with its own relative-gradient rule.
 """
@@ -160,22 +161,15 @@ def gauss_newton(P: rd.Problem, v0: Optional[np.ndarray] = None, gtol: float = 1
             if ginf <= gtol * g0_inf or g0_inf == 0.0:
                 rep.converged, rep.reason = True, "relative gradient"
                 break
-        else:
-            eps = np.finfo(np.float64).eps
-            c4 = ginf < 1e3 * eps
-            if k > 0:
-                c1 = (J_prev - S.J) < tau_J * (1.0 + J0)
-                c2 = float(np.abs(v_prev - vl).max()) < math.sqrt(tau_J) * (1.0 + float(np.abs(vl).max()))
-                c3 = ginf < tau_J ** (1.0 / 3.0) * (1.0 + J0)
-                if (c1 and c2 and c3) or c4:
-                    rep.converged, rep.reason = True, "C1-C3/C4"
-                    break
-            elif c4:
-                rep.converged, rep.reason = True, "C4"
+            if k >= max_outer:
+                rep.reason = "max outer iterations"
                 break
-        if k >= max_outer:
-            rep.reason = "max outer iterations"
-            break
+        else:
+            stop, crit = stopping_rule(k, J0, J_prev, S.J, v_prev, vl, S.g, tau_J, max_outer)
+            if stop:
+                rep.converged = bool(crit["C4"] or (crit["C1"] and crit["C2"] and crit["C3"]))
+                rep.reason = "C1-C3" if crit["C1"] and crit["C2"] and crit["C3"] else ("C4" if crit["C4"] else "C5")
+                break
         g2 = float(np.sqrt(np.sum(S.g * S.g)))
         eta = min(0.5, math.sqrt(g2 / g0_2))
         s, its, _, _ = pcg(lambda w: matvec(P, S, w), lambda r: rd.precond(P, r), -S.g, eta, maxit)
@@ -200,6 +194,34 @@ def gauss_newton(P: rd.Problem, v0: Optional[np.ndarray] = None, gtol: float = 1
         k += 1
     rep.iterations = k
     return vl, rep, S
+
+
+def stopping_rule(k: int, J0: float, J_prev: Optional[float], J: float, v_prev: Optional[np.ndarray],
+                  v: np.ndarray, g: np.ndarray, tau_J: float, n_opt: int,
+                  eps_mach: float = float(np.finfo(np.float64).eps)) -> Tuple[bool, dict]:
+    """Termination rule of the outer iteration, e:stopping-criteria combined as in
+    e:converged: stop if (C1 and C2 and C3) or C4 or C5, with
+
+      C1  J(v_{k-1}) - J(v_k)        < tau_J (1 + J(v_0))
+      C2  ||v_{k-1} - v_k||_inf      < sqrt(tau_J) (1 + ||v_k||_inf)
+      C3  ||g_k||_inf                < tau_J^(1/3) (1 + J(v_0))
+      C4  ||g_k||_inf                < 1e3 eps_mach
+      C5  k                          > n_opt
+
+    evaluated at the top of the loop of Algorithm a:outer-iteration, k being the number
+    of completed outer iterations. C1-C3 compare two iterates and are false at k = 0.
+    eps_mach is FP64's for both transport precisions (the reductions are FP64).
+    Returns (stop, {"C1": .., ..., "C5": ..})."""
+    ginf = float(np.abs(g).max())
+    crit = {"C1": False, "C2": False, "C3": False,
+            "C4": ginf < 1e3 * eps_mach,
+            "C5": k > n_opt}
+    if k > 0:
+        crit["C1"] = (J_prev - J) < tau_J * (1.0 + J0)
+        crit["C2"] = float(np.abs(v_prev - v).max()) < math.sqrt(tau_J) * (1.0 + float(np.abs(v).max()))
+        crit["C3"] = ginf < tau_J ** (1.0 / 3.0) * (1.0 + J0)
+    stop = (crit["C1"] and crit["C2"] and crit["C3"]) or crit["C4"] or crit["C5"]
+    return bool(stop), crit
 
 
 def scale_memory(alpha_tilde: float, alpha: float) -> float:
