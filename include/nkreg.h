@@ -87,8 +87,10 @@ typedef struct nkreg_problem nkreg_problem;
 
 /* Options of the outer iteration (Algorithm a:outer-iteration). */
 typedef struct {
-  int max_outer;        /* n_opt (e:stopping-criteria C5) */
-  double gtol;          /* relative gradient rule ||g_k||_inf <= gtol ||g_0||_inf; <= 0: use C1-C5 */
+  int max_outer;        /* relative gradient rule: at most max_outer iterations; C1-C5 rule: n_opt of
+                           (C5) k > n_opt, i.e. at most max_outer + 1 iterations */
+  double gtol;          /* relative gradient rule ||g_k||_inf <= gtol ||g_0||_inf; <= 0: the paper's
+                           rule (C1 and C2 and C3) or C4 or C5 of e:stopping-criteria / e:converged */
   double tau_J;         /* tolerance of C1-C3 */
   int pcg_maxit;        /* cap on PCG iterations per Newton step; <= 0: n (system size) */
   int cfl_guard;        /* 1: halve the step until h_t max|v^i|/h_x^i <= cfl_max before the line search */
@@ -108,6 +110,9 @@ typedef struct {
   double J_dist, J_reg; /* data term and regulariser at the end */
   double gnorm0_inf, gnorm_inf;
   double seconds;       /* wall-clock of the whole solve */
+  int stop_reason;      /* 1 relative gradient rule, 2 (C1 and C2 and C3), 3 C4, 4 iteration limit
+                           (relative rule: max_outer iterations; C1-C5 rule: C5, k > max_outer),
+                           5 line search failed, 6 objective stagnation (Picard) */
 } nkreg_solve_report;
 
 /* Library version string, e.g. "nkreg 1.0 gfx950". */

@@ -28,7 +28,7 @@ class SolveReport(Structure):
     _fields_ = [("iterations", c_int), ("cg_iterations", c_int), ("n_pde", c_int),
                 ("line_search_failed", c_int), ("converged", c_int), ("J0", c_double), ("J", c_double),
                 ("J_dist", c_double), ("J_reg", c_double), ("gnorm0_inf", c_double),
-                ("gnorm_inf", c_double), ("seconds", c_double)]
+                ("gnorm_inf", c_double), ("seconds", c_double), ("stop_reason", c_int)]
 
 
 class PicardOpts(Structure):

@@ -38,6 +38,11 @@ class SolveResult:
     gnorm_inf: float
     seconds: float
     status: int
+    stop_reason: str = ""
+
+
+STOP_REASONS = {1: "relative gradient", 2: "C1-C3", 3: "C4", 4: "iteration limit", 5: "line search failed",
+                6: "objective stagnation"}
 
 
 @dataclass
@@ -309,7 +314,7 @@ class Problem:
     def _result(rep: SolveReport, st: int) -> "SolveResult":
         return SolveResult(rep.iterations, rep.cg_iterations, rep.n_pde, bool(rep.line_search_failed),
                            bool(rep.converged), rep.J0, rep.J, rep.J_dist, rep.J_reg, rep.gnorm0_inf,
-                           rep.gnorm_inf, rep.seconds, st)
+                           rep.gnorm_inf, rep.seconds, st, STOP_REASONS.get(rep.stop_reason, ""))
 
     def picard_solve(self, v: Optional[torch.Tensor] = None, gtol: float = 1e-3, max_outer: int = 500,
                      memory: bool = True, stagnation: Tuple[int, float] = (10, 1e-6), **kw

@@ -328,7 +328,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_final(const double* __re
 }
 
 // min / max / sum / sum of squares about a shift, of an FP64 field (det F statistics)
-__global__ __launch_bounds__(kRedThreads) void k_stats(const double* __restrict__ x, long long cnt, double shift,
+static __global__ __launch_bounds__(kRedThreads) void k_stats(const double* __restrict__ x, long long cnt, double shift,
                                                        double* partial /* [4][blocks] */) {
   double mn = INFINITY, mx = -INFINITY, s = 0.0, s2 = 0.0;
   for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < cnt;
@@ -361,7 +361,7 @@ __global__ void k_axpby(long long cnt, R a, const R* __restrict__ x, R b, R* __r
 // the reduction slots, then x += alpha p and r -= alpha q, written as the two
 // axpby launches would (a x + b y with b = 1). Curvature pq <= 0 (or NaN) leaves
 // x and r unchanged; the host sees pq at its next read and stops there.
-__global__ void k_pcg_step(long long cnt, const double* __restrict__ rz, const double* __restrict__ pq,
+static __global__ void k_pcg_step(long long cnt, const double* __restrict__ rz, const double* __restrict__ pq,
                            const double* __restrict__ p, const double* __restrict__ q, double* __restrict__ x,
                            double* __restrict__ r) {
   const double c = *pq;

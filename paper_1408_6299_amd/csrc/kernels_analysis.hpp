@@ -17,7 +17,7 @@ __global__ void k_unit(long long cnt, long long j, R* __restrict__ y) {
 
 // Y[i] = e_{j0 + i} for i < G (G vectors of length cnt, one after another); a
 // column index at or beyond cnt gives a zero vector.
-__global__ void k_unit_block(long long cnt, int G, long long j0, double* __restrict__ Y) {
+static __global__ void k_unit_block(long long cnt, int G, long long j0, double* __restrict__ Y) {
   const long long tot = cnt * G;
   for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot;
        t += (long long)gridDim.x * blockDim.x)
@@ -25,7 +25,7 @@ __global__ void k_unit_block(long long cnt, int G, long long j0, double* __restr
 }
 
 // Deterministic start vector in [-1, 1] (a fixed integer hash of the index).
-__global__ void k_hash_fill(long long cnt, double* __restrict__ y) {
+static __global__ void k_hash_fill(long long cnt, double* __restrict__ y) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
        i += (long long)gridDim.x * blockDim.x) {
     unsigned long long x = (unsigned long long)i * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
@@ -41,7 +41,7 @@ __global__ void k_hash_fill(long long cnt, double* __restrict__ y) {
 // into part[i * P + p], P = gridDim.y. Many workgroups per vector keep the
 // whole GPU streaming where one per vector would leave it mostly idle.
 constexpr int kDotParts = 64;
-__global__ __launch_bounds__(256) void k_multidot_part(const double* __restrict__ Q, long long nv,
+static __global__ __launch_bounds__(256) void k_multidot_part(const double* __restrict__ Q, long long nv,
                                                        const double* __restrict__ w, double* __restrict__ part) {
   const double* q = Q + (long long)blockIdx.x * nv;
   const long long stride = (long long)gridDim.y * blockDim.x;
@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void k_multidot_part(const double* __restrict_
   if (threadIdx.x == 0) part[(long long)blockIdx.x * gridDim.y + blockIdx.y] = red[0] + red[1] + red[2] + red[3];
 }
 // c[i] = sum of vector i's P partials, in order.
-__global__ void k_multidot_sum(const double* __restrict__ part, int P, int k, double* __restrict__ c) {
+static __global__ void k_multidot_sum(const double* __restrict__ part, int P, int k, double* __restrict__ c) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= k) return;
   double s = 0.0;
@@ -63,7 +63,7 @@ __global__ void k_multidot_sum(const double* __restrict__ part, int P, int k, do
 }
 
 // w -= sum_i c[i] Q_i over the k vectors.
-__global__ void k_multi_axpy(const double* __restrict__ Q, int k, long long nv, const double* __restrict__ c,
+static __global__ void k_multi_axpy(const double* __restrict__ Q, int k, long long nv, const double* __restrict__ c,
                              double* __restrict__ w) {
   for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < nv;
        t += (long long)gridDim.x * blockDim.x) {

@@ -122,8 +122,7 @@ int nkreg_create(const nkreg_config* cfg, void* hip_stream, nkreg_problem** out)
   return guarded([&]() {
     hipStream_t s = (hipStream_t)hip_stream;
     nk::ProblemBase* impl;
-    if (cfg->precision == 32) impl = new nk::ProblemT<float>(*cfg, s);
-    else impl = new nk::ProblemT<double>(*cfg, s);
+    impl = nk::make_problem(*cfg, s);
     *out = new nkreg_problem{impl};
     return (int)NKREG_OK;
   });
@@ -460,9 +459,7 @@ void assemble_grouped(nk::ProblemBase* src, double* H) {
   const void *mT = nullptr, *mR = nullptr;
   src->images(&mT, &mR);
   for (int i = 1; i < G; ++i) {
-    nk::ProblemBase* q;
-    if (c.precision == 32) q = new nk::ProblemT<float>(c, st);
-    else q = new nk::ProblemT<double>(c, st);
+    nk::ProblemBase* q = nk::make_problem(c, st);
     clones.emplace_back(q);
     q->set_hessian(src->hessian_mode());
     q->set_images(mT, mR);

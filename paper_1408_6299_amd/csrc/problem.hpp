@@ -983,15 +983,15 @@ class ProblemT final : public ProblemBase {
     int flat = 0, k = 0;
     bool conv = false;
     while (true) {
-      if (ginf <= opt.gtol * g0inf || g0inf == 0.0) { conv = true; break; }
-      if (pop.stagnation_count > 0 && flat >= pop.stagnation_count) { conv = true; break; }
-      if (k >= opt.max_outer) break;
+      if (ginf <= opt.gtol * g0inf || g0inf == 0.0) { conv = true; r.stop_reason = 1; break; }
+      if (pop.stagnation_count > 0 && flat >= pop.stagnation_count) { conv = true; r.stop_reason = 6; break; }
+      if (k >= opt.max_outer) { r.stop_reason = 4; break; }
       precond(gbuf.p, sbuf.p);
       axpby(nv, 0.0, sbuf.p, pop.memory ? -at : -1.0, sbuf.p);
       if (cfg.incompressible) project(sbuf.p, sbuf.p);
       if (opt.cfl_guard) cfl_guard(vk);
       double alpha = 0.0;
-      if (!armijo(vk, J, &alpha, &r.n_pde)) { r.line_search_failed = 1; break; }
+      if (!armijo(vk, J, &alpha, &r.n_pde)) { r.line_search_failed = 1; r.stop_reason = 5; break; }
       if (pop.memory) at = alpha < 1.0 ? at * alpha : 2.0 * at;
       axpby(nv, alpha, sbuf.p, 1.0, vk);
       const double Jprev = J;
@@ -1031,26 +1031,33 @@ class ProblemT final : public ProblemBase {
     const double g0inf = opt.gref_inf > 0 ? opt.gref_inf : gstart;
     const double g0two = std::sqrt(red.one<double>(RED_SUMSQ, gbuf.p, nullptr, nv));
     r.gnorm0_inf = gstart;
-    double ginf = g0inf, gtwo = g0two;
+    double ginf = gstart, gtwo = g0two;
     double Jprev = J;
     int k = 0;
     bool conv = false;
-    const double eps = 2.220446049250313e-16;
+    const double eps = 2.220446049250313e-16;  // FP64 machine precision in C4 for both transports
     while (true) {
       if (opt.gtol > 0) {
-        if (ginf <= opt.gtol * g0inf || g0inf == 0.0) { conv = true; break; }
+        // relative gradient rule, at most max_outer iterations
+        if (ginf <= opt.gtol * g0inf || g0inf == 0.0) { conv = true; r.stop_reason = 1; break; }
+        if (k >= opt.max_outer) { r.stop_reason = 4; break; }
       } else {
+        // e:stopping-criteria combined as e:converged, n_opt = max_outer:
+        // (C1 and C2 and C3) or C4 or C5; C1-C3 compare two iterates
         const bool c4 = ginf < 1e3 * eps;
+        const bool c5 = k > opt.max_outer;
+        bool c123 = false;
         if (k > 0) {
           const double dv = red.one<double>(RED_MAXABS, sbuf.p, nullptr, nv);  // |v_{k-1} - v_k| = alpha |s|
           const double vinf = red.one<double>(RED_MAXABS, vk, nullptr, nv);
           const bool c1 = (Jprev - J) < opt.tau_J * (1.0 + r.J0);
           const bool c2 = dv < std::sqrt(opt.tau_J) * (1.0 + vinf);
           const bool c3 = ginf < std::cbrt(opt.tau_J) * (1.0 + r.J0);
-          if ((c1 && c2 && c3) || c4) { conv = true; break; }
-        } else if (c4) { conv = true; break; }
+          c123 = c1 && c2 && c3;
+        }
+        if (c123 || c4) { conv = true; r.stop_reason = c123 ? 2 : 3; break; }
+        if (c5) { r.stop_reason = 4; break; }
       }
-      if (k >= opt.max_outer) break;
       const double eta = std::min(0.5, std::sqrt(gtwo / g0two));
       lincomb(nv, -1.0, gbuf.p, 0.0, gbuf.p, rhsbuf.p);
       int its = 0;
@@ -1061,7 +1068,7 @@ class ProblemT final : public ProblemBase {
       if (cfg.incompressible) project(sbuf.p, sbuf.p);
       if (opt.cfl_guard) cfl_guard(vk);
       double alpha = 0.0;
-      if (!armijo(vk, J, &alpha, &r.n_pde)) { r.line_search_failed = 1; break; }
+      if (!armijo(vk, J, &alpha, &r.n_pde)) { r.line_search_failed = 1; r.stop_reason = 5; break; }
       axpby(nv, alpha, sbuf.p, 1.0, vk);
       axpby(nv, 0.0, sbuf.p, alpha, sbuf.p);  // keep alpha*s for C2
       Jprev = J;
@@ -1369,5 +1376,13 @@ class ProblemT final : public ProblemBase {
     NK_HIP(hipStreamSynchronize(s));
   }
 };
+
+// Handle factories, one per transport precision, each defined (and its kernels
+// instantiated) in a translation unit of its own so the two compile in parallel.
+ProblemBase* make_problem_f32(const nkreg_config& c, hipStream_t s);
+ProblemBase* make_problem_f64(const nkreg_config& c, hipStream_t s);
+inline ProblemBase* make_problem(const nkreg_config& c, hipStream_t s) {
+  return c.precision == 32 ? make_problem_f32(c, s) : make_problem_f64(c, s);
+}
 
 }  // namespace nk
