@@ -146,10 +146,19 @@ def timed_pcg_steps(prob, rhs, steps, torch):
     return time.perf_counter() - t0
 
 
+# Column pass of each counter workload: the autotuner's choice on the GPU (per-column at
+# 512^2, tiled at 256^3), fixed here so a counter run never captures or times a graph.
+COUNTER_COLUMN_PASS = {"c2lit": "8", "c4": "tiled"}
+
+
 def counter_pass(nk, synth, torch, name: str) -> int:
     """Three eager FP32 matvecs of one workload, launched one kernel at a time, for the
-    FETCH_SIZE / WRITE_SIZE runs. The column pass follows the autotuner unless
-    NKREG_COL_E pins it."""
+    FETCH_SIZE / WRITE_SIZE runs. The column pass is pinned (NKREG_COL_E, before the first
+    handle exists) so the autotuner never runs, and the handle never captures or replays a
+    HIP graph: a counter-collection run once ended in a host segmentation fault at the
+    point where the autotuner captures and event-times its column-pass graphs."""
+    os.environ["NKREG_COL_E"] = os.environ.get("NKREG_COL_E") or COUNTER_COLUMN_PASS[name]
+    os.environ["NKREG_NO_GRAPHS"] = "1"
     dev = torch.device("cuda:0")
     spec = synth.CONFIGS[name]
     stokes = name == "c4"

@@ -155,7 +155,12 @@ int nkreg_use_graphs(nkreg_problem* p, int enable);
  * buf (len bytes, NUL-terminated, truncated if needed). */
 int nkreg_describe(nkreg_problem* p, char* buf, int len);
 
-/* Copy the template m_T and reference m_R (each n values) into the handle. */
+/* Copy the template m_T and reference m_R (each n values) into the handle. Both are
+ * stored with the template's mean c subtracted: a constant is transported exactly
+ * and J, g and H depend only on differences and gradients of the images, so the
+ * shift changes nothing but the round-off of the transforms (which scales with a
+ * field's norm, mean included); nkreg_forward adds c back to m_1. Synchronises.
+ * Errors: ENONFINITE (m_T not finite). */
 int nkreg_set_images(nkreg_problem* p, const void* d_mT, const void* d_mR);
 
 /* State equation e:first-order-forward: Heun from m(0) = m_T under velocity
@@ -322,27 +327,52 @@ int nkreg_timer_arm(nkreg_problem* p, int kernel_id, int capacity);
 int nkreg_matvec_bytes(nkreg_problem* p, const void* d_vt, void* d_Hvt, double* h_bytes, int* h_launches);
 int nkreg_timer_read(nkreg_problem* p, int* launches, double* avg_ms, double* bytes_per_launch);
 
-/* Batched Gauss-Newton matvecs over independent problems of uneven sizes
- * (each a handle with a cached state). One call applies H_i to vt_i for every
- * item i as a single HIP-graph launch. Items with the same grid, time steps,
- * scheme and precision form a group: each kernel of the matvec runs once for
- * the whole group, reading every item's pointers and scalars (beta included)
- * from a device table, and groups run as independent graph branches. Results
- * are bit-identical to the items' own nkreg_hessian_matvec. The graph and its
- * tables are built on the first call and replayed while the pointer sets and
- * the items' configurations are unchanged. The batch does not own its items.
- * When all items were created on one stream the graph replays on it; otherwise
- * on a stream of the batch that waits for every item's stream, and every item's
- * stream waits for the batch. Where the LDS-tiled column pass applies, each group times it against the
- * per-column pass at the group's scale and keeps the faster (both give the
- * same values). nkreg_batch_groups reports the last built graph: the number of
- * groups and, for up to cap groups, their sizes and whether they use the tiled
- * pass (sizes, tiled may be NULL). */
+/* Batches of independent problems of uneven sizes (the batched form of the path:
+ * many image pairs, each its own problem of Algorithm a:outer-iteration).
+ *
+ * nkreg_batch_create makes count problem handles from cfgs[0..count) on one HIP
+ * stream (NULL = the null stream), owned by the batch and destroyed with it;
+ * nkreg_batch_item returns item i's handle, through which the caller sets its
+ * images (nkreg_set_images) and runs any single-problem call. nkreg_batch_wrap
+ * makes a batch over existing handles instead (the batch does not own them; they
+ * may live on different streams).
+ *
+ * Batched calls apply one operation to every item as a single HIP-graph launch:
+ * - nkreg_batch_objective_gradient: each item's objective and reduced gradient at
+ *   d_v[i], exactly as nkreg_objective_gradient (forward sweep keeping the
+ *   trajectory, adjoint sweep, g = beta A v + K[f]); g[i] receives the gradient
+ *   (g or g[i] NULL: not written), and J, J_dist, J_reg (host arrays of count
+ *   doubles, each may be NULL) the objective terms. Each item's CFL bound is
+ *   checked first (ECFL). Leaves every item's state ready for Hessian matvecs.
+ *   Synchronises.
+ * - nkreg_batch_set_state: the same without outputs (each item's forward and
+ *   adjoint sweeps at d_v[i]). Synchronises.
+ * - nkreg_batch_hessian_matvec: H_i vt_i for every item at its cached state
+ *   (ESTATE if an item has none). Asynchronous.
+ * Items with the same grid, time steps, scheme and precision form a group: each
+ * kernel of the operation runs once for the whole group, reading every item's
+ * pointers and scalars (beta included) from a device table, and groups run as
+ * independent graph branches. Results are bit-identical to the items' own calls.
+ * The graph of each operation and its tables are built on the first call and
+ * replayed while the pointer sets and the items' configurations are unchanged.
+ * When all items live on one stream the graph replays on it; otherwise on a
+ * stream of the batch that waits for every item's stream, and every item's stream
+ * waits for the batch. Where the LDS-tiled column pass applies, each group times it
+ * against the per-column pass at the group's scale and keeps the faster (both give
+ * the same values). nkreg_batch_groups reports the last built matvec graph: the
+ * number of groups and, for up to cap groups, their sizes and whether they use the
+ * tiled pass (sizes, tiled may be NULL). Errors: EINVAL, ESHAPE (a configuration),
+ * ENOMEM, EHIP, ESTATE, ECFL, ENONFINITE. */
 typedef struct nkreg_batch nkreg_batch;
-int nkreg_batch_create(int count, nkreg_problem* const* items, nkreg_batch** out);
+int nkreg_batch_create(int count, const nkreg_config* cfgs, void* hip_stream, nkreg_batch** out);
+int nkreg_batch_wrap(int count, nkreg_problem* const* items, nkreg_batch** out);
+int nkreg_batch_item(nkreg_batch* b, int i, nkreg_problem** out);
+int nkreg_batch_objective_gradient(nkreg_batch* b, const void* const* d_v, double* h_J, double* h_J_dist,
+                                   double* h_J_reg, void* const* d_g);
+int nkreg_batch_set_state(nkreg_batch* b, const void* const* d_v);
+int nkreg_batch_hessian_matvec(nkreg_batch* b, const void* const* d_vt, void* const* d_Hvt);
 int nkreg_batch_groups(nkreg_batch* b, int* groups, int* sizes, int* tiled, int cap);
 int nkreg_batch_destroy(nkreg_batch* b);
-int nkreg_batch_hessian_matvec(nkreg_batch* b, const void* const* d_vt, void* const* d_Hvt);
 
 #ifdef __cplusplus
 }

@@ -95,6 +95,16 @@ class Problem:
                  incompressible: bool = False, beta: float = 1e-2, precision: int = 32,
                  cfl_max: float = 0.0, stream: Optional[torch.cuda.Stream] = None,
                  checkpoint_every: int = 0, trajectory_slots: int = 1):
+        cfg = self._setup(shape, nt, nc, reg, incompressible, beta, precision, cfl_max, stream, checkpoint_every,
+                          trajectory_slots)
+        h = c_void_p()
+        check(self.lib.nkreg_create(byref(cfg), c_void_p(self.stream.cuda_stream), byref(h)), "nkreg_create")
+        self._h = h
+        self._owned = True
+
+    def _setup(self, shape, nt, nc, reg, incompressible, beta, precision, cfl_max, stream, checkpoint_every,
+               trajectory_slots) -> Config:
+        """Records the configuration on the object and returns it as the C struct."""
         self.lib = _lib.load()
         self.shape = tuple(int(s) for s in shape)
         self.d = len(self.shape)
@@ -117,14 +127,22 @@ class Problem:
         cfg.trajectory_slots = int(trajectory_slots)
         cfg.cfl_max = float(cfl_max)
         self._beta = float(beta)
-        h = c_void_p()
-        check(self.lib.nkreg_create(byref(cfg), c_void_p(self.stream.cuda_stream), byref(h)), "nkreg_create")
-        self._h = h
+        return cfg
+
+    @classmethod
+    def _borrowed(cls, handle: c_void_p, **kw) -> "Problem":
+        """A view of a handle owned elsewhere (a batch's item); closing it does nothing."""
+        p = cls.__new__(cls)
+        p._setup(**kw)
+        p._h = handle
+        p._owned = False
+        return p
 
     # -- lifetime --
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:
-            self.lib.nkreg_destroy(self._h)
+            if getattr(self, "_owned", True):
+                self.lib.nkreg_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -421,15 +439,74 @@ class Problem:
 
 
 class Batch:
-    """Several independent problems whose Hessian matvecs are applied in one call."""
+    """Several independent problems whose gradients and Hessian matvecs are applied in one
+    call each (one HIP-graph launch over all items; items of one configuration share every
+    kernel launch).
+
+    ``Batch(problems)`` batches existing problems (which stay owned by the caller);
+    ``Batch.create(configs)`` makes the problems itself (``items`` gives them; they are
+    destroyed with the batch).
+    """
 
     def __init__(self, problems: Sequence[Problem]):
         self.lib = _lib.load()
         self.problems = list(problems)
         arr = (c_void_p * len(self.problems))(*[p._h.value for p in self.problems])
         h = c_void_p()
-        check(self.lib.nkreg_batch_create(len(self.problems), arr, byref(h)), "nkreg_batch_create")
+        check(self.lib.nkreg_batch_wrap(len(self.problems), arr, byref(h)), "nkreg_batch_wrap")
         self._h = h
+
+    @classmethod
+    def create(cls, configs: Sequence[dict], stream: Optional[torch.cuda.Stream] = None) -> "Batch":
+        """configs: keyword dicts of Problem (shape, nt, nc, reg, incompressible, beta,
+        precision, cfl_max, checkpoint_every, trajectory_slots)."""
+        b = cls.__new__(cls)
+        b.lib = _lib.load()
+        st = stream if stream is not None else torch.cuda.current_stream()
+        defaults = dict(nc=1, reg=1, incompressible=False, beta=1e-2, precision=32, cfl_max=0.0,
+                        checkpoint_every=0, trajectory_slots=1)
+        kws, cfgs = [], (Config * max(1, len(configs)))()
+        for i, c in enumerate(configs):
+            kw = dict(defaults, **c)
+            kw["stream"] = st
+            tmp = Problem.__new__(Problem)
+            cfgs[i] = tmp._setup(**kw)
+            kws.append(kw)
+        h = c_void_p()
+        check(b.lib.nkreg_batch_create(len(configs), cfgs, c_void_p(st.cuda_stream), byref(h)), "nkreg_batch_create")
+        b._h = h
+        b.problems = []
+        for i, kw in enumerate(kws):
+            ih = c_void_p()
+            check(b.lib.nkreg_batch_item(h, i, byref(ih)), "nkreg_batch_item")
+            b.problems.append(Problem._borrowed(ih, **kw))
+        return b
+
+    @property
+    def items(self) -> List[Problem]:
+        return self.problems
+
+    def objective_gradient(self, vs: Sequence[torch.Tensor], gs: Optional[Sequence[torch.Tensor]] = None):
+        """Every item's objective and gradient at vs[i]; returns (J, J_dist, J_reg, gs)."""
+        n = len(self.problems)
+        if gs is None:
+            gs = [p.empty_v() for p in self.problems]
+        for p, a, b in zip(self.problems, vs, gs):
+            p._check(a, p.vshape, "v")
+            p._check(b, p.vshape, "g")
+        ins = (c_void_p * n)(*[t.data_ptr() for t in vs])
+        os_ = (c_void_p * n)(*[t.data_ptr() for t in gs])
+        J, Jd, Jr = (c_double * n)(), (c_double * n)(), (c_double * n)()
+        check(self.lib.nkreg_batch_objective_gradient(self._h, ins, J, Jd, Jr, os_), "nkreg_batch_objective_gradient")
+        return list(J), list(Jd), list(Jr), gs
+
+    def set_state(self, vs: Sequence[torch.Tensor]) -> None:
+        """Every item's forward and adjoint sweeps at vs[i] (the state its matvecs use)."""
+        n = len(self.problems)
+        for p, a in zip(self.problems, vs):
+            p._check(a, p.vshape, "v")
+        ins = (c_void_p * n)(*[t.data_ptr() for t in vs])
+        check(self.lib.nkreg_batch_set_state(self._h, ins), "nkreg_batch_set_state")
 
     def hessian_matvec(self, vts: Sequence[torch.Tensor], outs: Optional[Sequence[torch.Tensor]] = None):
         if outs is None:
@@ -457,6 +534,9 @@ class Batch:
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
+            for p in getattr(self, "problems", []):
+                if not getattr(p, "_owned", True):
+                    p._h = None       # the batch destroys the items it owns
             self.lib.nkreg_batch_destroy(self._h)
             self._h = None
 

@@ -304,8 +304,8 @@ enum RedOp { RED_DOT = 0, RED_SUMSQ = 1, RED_MAXABS = 2, RED_SUM = 3, RED_SUMSQD
 // propagates into the sum (and is caught on the host); RED_MAXABS also turns a
 // NaN into +inf so that it is detected.
 template <typename R, int OP>
-__global__ __launch_bounds__(kRedThreads) void k_reduce(const R* __restrict__ x, const R* __restrict__ y,
-                                                        long long cnt, double* partial) {
+__device__ __forceinline__ void reduce_body(const R* __restrict__ x, const R* __restrict__ y, long long cnt,
+                                            double* partial) {
   double acc = 0.0;
   for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < cnt;
        i += (long long)gridDim.x * kRedThreads) {
@@ -318,13 +318,46 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const R* __restrict__ x,
   }
   block_reduce_store<OP == RED_MAXABS>(acc, partial + blockIdx.x);
 }
+template <typename R, int OP>
+__global__ __launch_bounds__(kRedThreads) void k_reduce(const R* __restrict__ x, const R* __restrict__ y,
+                                                        long long cnt, double* partial) {
+  reduce_body<R, OP>(x, y, cnt, partial);
+}
 
 template <bool MAX>
-__global__ __launch_bounds__(kRedThreads) void k_reduce_final(const double* __restrict__ partial, int np,
-                                                              double* out) {
+__device__ __forceinline__ void reduce_final_body(const double* __restrict__ partial, int np, double* out) {
   double acc = 0.0;
   for (int i = threadIdx.x; i < np; i += kRedThreads) acc = MAX ? fmax(acc, partial[i]) : acc + partial[i];
   block_reduce_store<MAX>(acc, out);
+}
+template <bool MAX>
+__global__ __launch_bounds__(kRedThreads) void k_reduce_final(const double* __restrict__ partial, int np,
+                                                              double* out) {
+  reduce_final_body<MAX>(partial, np, out);
+}
+
+// Batch-group forms of the two reduction stages: each item takes its pointers
+// from the table (blockIdx.z); the per-item grid and summation order are those of the
+// plain forms.
+template <typename R>
+struct RedPtrs {
+  const R* x;
+  const R* y;
+  double* partial;
+};
+struct RedFinalPtrs {
+  const double* partial;
+  double* out;
+};
+template <typename R, int OP>
+__global__ __launch_bounds__(kRedThreads) void k_reduce_t(long long cnt, const RedPtrs<R>* __restrict__ tab) {
+  const RedPtrs<R> p = tab[blockIdx.z];
+  reduce_body<R, OP>(p.x, p.y, cnt, p.partial);
+}
+template <bool MAX>
+__global__ __launch_bounds__(kRedThreads) void k_reduce_final_t(int np, const RedFinalPtrs* __restrict__ tab) {
+  const RedFinalPtrs p = tab[blockIdx.z];
+  reduce_final_body<MAX>(p.partial, np, p.out);
 }
 
 // min / max / sum / sum of squares about a shift, of an FP64 field (det F statistics)
@@ -381,6 +414,14 @@ __global__ void k_lincomb(long long cnt, R a, const R* __restrict__ x, R b, cons
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
        i += (long long)gridDim.x * blockDim.x)
     z[i] = a * x[i] + b * y[i];
+}
+
+// y = x + c (c a host scalar); x and y may alias
+template <typename R>
+__global__ void k_shift(long long cnt, R c, const R* x, R* y) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+       i += (long long)gridDim.x * blockDim.x)
+    y[i] = x[i] + c;
 }
 
 template <typename R>

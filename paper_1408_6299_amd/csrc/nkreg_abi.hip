@@ -10,27 +10,40 @@ struct nkreg_problem {
   nk::ProblemBase* impl;
 };
 
-// A batch replays one HIP graph. Items whose recorded matvec launch sequences
-// have the same shape (same grid, steps, scheme and precision) form a group;
-// every launch of a group's sequence becomes one launch over all its items,
-// whose per-item arguments come from a device table. Groups are independent
-// branches of the graph, each captured on a branch stream of the batch.
-struct nkreg_batch {
-  std::vector<nkreg_problem*> items;
-  hipStream_t s = nullptr;
-  std::vector<hipStream_t> branch;  // capture branches, one per group
-  hipEvent_t fork = nullptr, done = nullptr;
-  std::vector<hipEvent_t> joins, waits;
+// A batch replays one HIP graph per operation (the Hessian matvec and the objective
+// and gradient). Items whose recorded launch sequences have the same shape (same
+// grid, steps, scheme and precision) form a group; every launch of a group's sequence
+// becomes one launch over all its items, whose per-item arguments come from a device
+// table. Groups are independent branches of the graph, each captured on a branch
+// stream of the batch.
+struct BatchGraph {
   hipGraphExec_t exec = nullptr;
   void* tables = nullptr;  // device argument tables of the captured graph
   std::vector<int> group_sizes, variants;  // per group: items, column pass (8 or 0 = tiled)
   std::vector<const void*> key_in;
   std::vector<void*> key_out;
   std::vector<unsigned> key_gen;
-  ~nkreg_batch() {
-    if (s) (void)hipStreamSynchronize(s);
+  void reset() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (tables) (void)hipFree(tables);
+    exec = nullptr;
+    tables = nullptr;
+  }
+  ~BatchGraph() { reset(); }
+};
+
+struct nkreg_batch {
+  std::vector<nkreg_problem*> items;
+  bool owns_items = false;  // created by nkreg_batch_create (destroyed with the batch)
+  hipStream_t s = nullptr;
+  std::vector<hipStream_t> branch;  // capture branches, one per group
+  hipEvent_t fork = nullptr, done = nullptr;
+  std::vector<hipEvent_t> joins, waits;
+  BatchGraph matvec, gradient;
+  ~nkreg_batch() {
+    if (s) (void)hipStreamSynchronize(s);
+    matvec.reset();
+    gradient.reset();
     for (hipEvent_t e : joins) (void)hipEventDestroy(e);
     for (hipEvent_t e : waits) (void)hipEventDestroy(e);
     if (fork) (void)hipEventDestroy(fork);
@@ -40,6 +53,14 @@ struct nkreg_batch {
       (void)hipStreamDestroy(st);
     }
     if (s) (void)hipStreamDestroy(s);
+    if (owns_items) {
+      for (nkreg_problem* p : items) {
+        if (!p) continue;
+        (void)hipStreamSynchronize(p->impl->stream());
+        delete p->impl;
+        delete p;
+      }
+    }
   }
 };
 
@@ -51,6 +72,14 @@ int fail(int code, const std::string& msg) {
   g_last_error = msg;
   return code;
 }
+
+}  // namespace
+
+namespace nk {
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace nk
+
+namespace {
 
 template <typename F>
 int guarded(F&& f) {
@@ -276,7 +305,51 @@ int nkreg_timer_read(nkreg_problem* p, int* launches, double* avg_ms, double* by
   return guarded([&]() { p->impl->timer_read(launches, avg_ms, bytes_per_launch); return (int)NKREG_OK; });
 }
 
-int nkreg_batch_create(int count, nkreg_problem* const* items, nkreg_batch** out) {
+}  // extern "C"
+
+namespace {
+
+// The batch's own stream and events for count items.
+void batch_init(nkreg_batch* b, int count) {
+  NK_HIP(hipStreamCreateWithFlags(&b->s, hipStreamNonBlocking));  // default priority
+  NK_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+  NK_HIP(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
+  b->joins.resize(count);
+  b->waits.resize(count);
+  for (int i = 0; i < count; ++i) {
+    NK_HIP(hipEventCreateWithFlags(&b->joins[i], hipEventDisableTiming));
+    NK_HIP(hipEventCreateWithFlags(&b->waits[i], hipEventDisableTiming));
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int nkreg_batch_create(int count, const nkreg_config* cfgs, void* hip_stream, nkreg_batch** out) {
+  NEED(out);
+  *out = nullptr;
+  if (count < 0 || (count > 0 && !cfgs)) return fail(NKREG_EINVAL, "bad batch");
+  for (int i = 0; i < count; ++i) {
+    const int st = validate(cfgs + i);
+    if (st != NKREG_OK) return st;
+  }
+  return guarded([&]() {
+    std::unique_ptr<nkreg_batch> b(new nkreg_batch);
+    b->owns_items = true;
+    b->items.reserve(count);
+    for (int i = 0; i < count; ++i) {
+      std::unique_ptr<nk::ProblemBase> impl(nk::make_problem(cfgs[i], (hipStream_t)hip_stream));
+      b->items.push_back(new nkreg_problem{impl.get()});
+      impl.release();
+    }
+    batch_init(b.get(), count);
+    *out = b.release();
+    return (int)NKREG_OK;
+  });
+}
+
+int nkreg_batch_wrap(int count, nkreg_problem* const* items, nkreg_batch** out) {
   NEED(out);
   *out = nullptr;
   if (count < 0 || (count > 0 && !items)) return fail(NKREG_EINVAL, "bad batch");
@@ -285,18 +358,17 @@ int nkreg_batch_create(int count, nkreg_problem* const* items, nkreg_batch** out
   return guarded([&]() {
     std::unique_ptr<nkreg_batch> b(new nkreg_batch);
     b->items.assign(items, items + count);
-    NK_HIP(hipStreamCreateWithFlags(&b->s, hipStreamNonBlocking));
-    NK_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
-    NK_HIP(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
-    b->joins.resize(count);
-    b->waits.resize(count);
-    for (int i = 0; i < count; ++i) {
-      NK_HIP(hipEventCreateWithFlags(&b->joins[i], hipEventDisableTiming));
-      NK_HIP(hipEventCreateWithFlags(&b->waits[i], hipEventDisableTiming));
-    }
+    batch_init(b.get(), count);
     *out = b.release();
     return (int)NKREG_OK;
   });
+}
+
+int nkreg_batch_item(nkreg_batch* b, int i, nkreg_problem** out) {
+  NEED(b); NEED(out);
+  if (i < 0 || i >= (int)b->items.size()) return fail(NKREG_EINVAL, "batch item index out of range");
+  *out = b->items[i];
+  return NKREG_OK;
 }
 
 int nkreg_batch_destroy(nkreg_batch* b) {
@@ -329,6 +401,8 @@ void launch_group(const nk::LaunchRec& r, int G, void* tab, hipStream_t st) {
     case nk::LaunchRec::FILL: args[0] = &cnt; args[1] = r.f64 ? (void*)&vd : (void*)&vf; args[2] = &tab; break;
     case nk::LaunchRec::CONV: args[0] = &cnt; args[1] = &tab; break;
     case nk::LaunchRec::SPEC: args[0] = &tab; args[1] = &iarg; break;
+    case nk::LaunchRec::RED: args[0] = &cnt; args[1] = &tab; break;
+    case nk::LaunchRec::REDF: args[0] = &iarg; args[1] = &tab; break;
     default: throw nk::HipError(NKREG_EHIP, "unexpected recorded launch");
   }
   NK_HIP(hipLaunchKernel(r.kernel, grid, r.block, args, 0, st));
@@ -433,6 +507,141 @@ float time_group(const GroupPlan& gp, hipStream_t st) {
   return ms / 2.f;
 }
 
+// Records an item's launch sequence for one batched operation (column pass variant
+// cv >= 0 overrides the item's own choice).
+using RecordFn = void (*)(nk::ProblemBase*, const void*, void*, nk::Recorder&, int);
+
+void record_matvec_fn(nk::ProblemBase* p, const void* in, void* out, nk::Recorder& r, int cv) {
+  p->record_matvec(in, out, r, cv);
+}
+void record_gradient_fn(nk::ProblemBase* p, const void* in, void* out, nk::Recorder& r, int cv) {
+  p->record_gradient(in, out, r, cv);
+}
+
+// One batched operation: (re)builds the batch graph bg of the operation when the
+// pointer sets or an item's configuration changed, then replays it, ordered after
+// every earlier call on the items' streams.
+void run_batch(nkreg_batch* b, BatchGraph& bg, RecordFn record, const void* const* vt, void* const* out) {
+  {
+    const size_t cnt = b->items.size();
+    if (cnt == 0) return;
+    // items on one caller stream: the graph replays on that stream, ordered like
+    // any other call; otherwise on the batch stream, joined to every caller stream
+    const hipStream_t cs = b->items[0]->impl->caller_stream();
+    bool one_stream = true;
+    for (size_t i = 1; i < cnt; ++i) one_stream = one_stream && b->items[i]->impl->caller_stream() == cs;
+    bool stale = !bg.exec || bg.key_in.size() != cnt;
+    for (size_t i = 0; i < cnt && !stale; ++i)
+      stale = bg.key_in[i] != vt[i] || bg.key_out[i] != out[i] || bg.key_gen[i] != b->items[i]->impl->generation;
+    if (stale || !one_stream) {
+      // the batch stream waits for every caller stream (and so for all earlier
+      // work on the items), also before a rebuild replays a group to time it
+      for (size_t i = 0; i < cnt; ++i) {
+        NK_HIP(hipEventRecord(b->waits[i], b->items[i]->impl->caller_stream()));
+        NK_HIP(hipStreamWaitEvent(b->s, b->waits[i], 0));
+      }
+    }
+    if (stale) {
+      NK_HIP(hipStreamSynchronize(b->s));
+      bg.reset();
+      // record every item's matvec and group equal-shaped sequences
+      std::vector<nk::Recorder> recs(cnt);
+      for (size_t i = 0; i < cnt; ++i) record(b->items[i]->impl, vt[i], out[i], recs[i], -1);
+      std::vector<GroupPlan> plans;
+      for (size_t i = 0; i < cnt; ++i) {
+        bool placed = false;
+        for (auto& gp : plans) {
+          if (same_sequence(gp.recs[0].recs, recs[i].recs)) {
+            gp.items.push_back(i);
+            gp.recs.push_back(std::move(recs[i]));
+            placed = true;
+            break;
+          }
+        }
+        if (!placed) {
+          plans.emplace_back();
+          plans.back().items.push_back(i);
+          plans.back().recs.push_back(std::move(recs[i]));
+        }
+      }
+      // a group's launches are G times larger than one item's: where the tiled
+      // column pass applies, time both column passes (identical values) at the
+      // group's scale and keep the faster
+      bg.variants.clear();
+      for (auto& gp : plans) {
+        nk::ProblemBase* first = b->items[gp.items[0]]->impl;
+        int chosen = first->col_variant();
+        if (gp.items.size() > 1 && first->tiled_pass_applies() && (chosen == 8 || chosen == 0)) {
+          float best = 0.f;
+          GroupPlan bestp;
+          for (int cv : {8, 0}) {
+            GroupPlan c;
+            c.items = gp.items;
+            c.recs.resize(gp.items.size());
+            for (size_t k = 0; k < gp.items.size(); ++k)
+              record(b->items[gp.items[k]]->impl, vt[gp.items[k]], out[gp.items[k]], c.recs[k], cv);
+            const float ms = time_group(c, b->s);
+            if (cv == 8 || ms < best) { best = ms; bestp = std::move(c); chosen = cv; }
+          }
+          gp = std::move(bestp);
+        }
+        bg.variants.push_back(chosen);
+      }
+      std::vector<unsigned char> host;
+      for (auto& gp : plans) add_tables(gp, host);
+      if (!host.empty()) {
+        NK_HIP(hipMalloc(&bg.tables, host.size()));
+        NK_HIP(hipMemcpy(bg.tables, host.data(), host.size(), hipMemcpyHostToDevice));
+      }
+      bg.group_sizes.clear();
+      for (auto& gp : plans) bg.group_sizes.push_back((int)gp.items.size());
+      // groups become parallel branches of the graph: each is captured on a
+      // stream of its own, forked from and joined back into the batch stream
+      while (b->branch.size() < plans.size()) {
+        hipStream_t st = nullptr;
+        NK_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));  // default priority
+        b->branch.push_back(st);
+      }
+      hipGraph_t graph = nullptr;
+      NK_HIP(hipStreamBeginCapture(b->s, hipStreamCaptureModeThreadLocal));
+      try {
+        NK_HIP(hipEventRecord(b->fork, b->s));
+        for (size_t gi = 0; gi < plans.size(); ++gi) {
+          hipStream_t st = b->branch[gi];
+          NK_HIP(hipStreamWaitEvent(st, b->fork, 0));
+          issue_group(plans[gi], bg.tables, st);
+          NK_HIP(hipEventRecord(b->joins[gi], st));
+          NK_HIP(hipStreamWaitEvent(b->s, b->joins[gi], 0));
+        }
+      } catch (...) {
+        (void)hipStreamEndCapture(b->s, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        throw;
+      }
+      NK_HIP(hipStreamEndCapture(b->s, &graph));
+      const hipError_t e = hipGraphInstantiate(&bg.exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) {
+        bg.exec = nullptr;
+        throw nk::HipError(NKREG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+      }
+      bg.key_in.assign(vt, vt + cnt);
+      bg.key_out.assign(out, out + cnt);
+      bg.key_gen.resize(cnt);
+      for (size_t i = 0; i < cnt; ++i) bg.key_gen[i] = b->items[i]->impl->generation;
+    }
+    if (one_stream) {
+      NK_HIP(hipGraphLaunch(bg.exec, cs));
+      return;
+    }
+    // every caller stream waits for the batch
+    NK_HIP(hipGraphLaunch(bg.exec, b->s));
+    NK_HIP(hipEventRecord(b->done, b->s));
+    for (size_t i = 0; i < cnt; ++i) NK_HIP(hipStreamWaitEvent(b->items[i]->impl->caller_stream(), b->done, 0));
+  }
+}
+
+
 // Columns of the dense Hessian assembled per graph replay: up to this many, and
 // fewer on large grids, where one matvec already fills the GPU.
 constexpr int kAssembleGroup = 32;
@@ -462,7 +671,7 @@ void assemble_grouped(nk::ProblemBase* src, double* H) {
     nk::ProblemBase* q = nk::make_problem(c, st);
     clones.emplace_back(q);
     q->set_hessian(src->hessian_mode());
-    q->set_images(mT, mR);
+    q->set_centred_images(mT, mR, src->image_shift());
     q->objective_gradient(src->velocity(), nullptr, nullptr, nullptr, nullptr);
     items.push_back(q);
   }
@@ -522,135 +731,45 @@ int nkreg_hessian_assemble(nkreg_problem* p, void* H) {
 int nkreg_batch_hessian_matvec(nkreg_batch* b, const void* const* vt, void* const* out) {
   NEED(b);
   if (!b->items.empty()) { NEED(vt); NEED(out); }
+  for (size_t i = 0; i < b->items.size(); ++i)
+    if (!vt[i] || !out[i] || vt[i] == out[i]) return fail(NKREG_EINVAL, "batch matvec: null or aliased item vectors");
   return guarded([&]() {
-    const size_t cnt = b->items.size();
-    if (cnt == 0) return (int)NKREG_OK;
-    // items on one caller stream: the graph replays on that stream, ordered like
-    // any other call; otherwise on the batch stream, joined to every caller stream
-    const hipStream_t cs = b->items[0]->impl->caller_stream();
-    bool one_stream = true;
-    for (size_t i = 1; i < cnt; ++i) one_stream = one_stream && b->items[i]->impl->caller_stream() == cs;
-    bool stale = !b->exec || b->key_in.size() != cnt;
-    for (size_t i = 0; i < cnt && !stale; ++i)
-      stale = b->key_in[i] != vt[i] || b->key_out[i] != out[i] || b->key_gen[i] != b->items[i]->impl->generation;
-    if (stale || !one_stream) {
-      // the batch stream waits for every caller stream (and so for all earlier
-      // work on the items), also before a rebuild replays a group to time it
-      for (size_t i = 0; i < cnt; ++i) {
-        NK_HIP(hipEventRecord(b->waits[i], b->items[i]->impl->caller_stream()));
-        NK_HIP(hipStreamWaitEvent(b->s, b->waits[i], 0));
-      }
-    }
-    if (stale) {
-      NK_HIP(hipStreamSynchronize(b->s));
-      if (b->exec) (void)hipGraphExecDestroy(b->exec);
-      b->exec = nullptr;
-      if (b->tables) (void)hipFree(b->tables);
-      b->tables = nullptr;
-      // record every item's matvec and group equal-shaped sequences
-      std::vector<nk::Recorder> recs(cnt);
-      for (size_t i = 0; i < cnt; ++i) b->items[i]->impl->record_matvec(vt[i], out[i], recs[i]);
-      std::vector<GroupPlan> plans;
-      for (size_t i = 0; i < cnt; ++i) {
-        bool placed = false;
-        for (auto& gp : plans) {
-          if (same_sequence(gp.recs[0].recs, recs[i].recs)) {
-            gp.items.push_back(i);
-            gp.recs.push_back(std::move(recs[i]));
-            placed = true;
-            break;
-          }
-        }
-        if (!placed) {
-          plans.emplace_back();
-          plans.back().items.push_back(i);
-          plans.back().recs.push_back(std::move(recs[i]));
-        }
-      }
-      // a group's launches are G times larger than one item's: where the tiled
-      // column pass applies, time both column passes (identical values) at the
-      // group's scale and keep the faster
-      b->variants.clear();
-      for (auto& gp : plans) {
-        nk::ProblemBase* first = b->items[gp.items[0]]->impl;
-        int chosen = first->col_variant();
-        if (gp.items.size() > 1 && first->tiled_pass_applies() && (chosen == 8 || chosen == 0)) {
-          float best = 0.f;
-          GroupPlan bestp;
-          for (int cv : {8, 0}) {
-            GroupPlan c;
-            c.items = gp.items;
-            c.recs.resize(gp.items.size());
-            for (size_t k = 0; k < gp.items.size(); ++k)
-              b->items[gp.items[k]]->impl->record_matvec(vt[gp.items[k]], out[gp.items[k]], c.recs[k], cv);
-            const float ms = time_group(c, b->s);
-            if (cv == 8 || ms < best) { best = ms; bestp = std::move(c); chosen = cv; }
-          }
-          gp = std::move(bestp);
-        }
-        b->variants.push_back(chosen);
-      }
-      std::vector<unsigned char> host;
-      for (auto& gp : plans) add_tables(gp, host);
-      if (!host.empty()) {
-        NK_HIP(hipMalloc(&b->tables, host.size()));
-        NK_HIP(hipMemcpy(b->tables, host.data(), host.size(), hipMemcpyHostToDevice));
-      }
-      b->group_sizes.clear();
-      for (auto& gp : plans) b->group_sizes.push_back((int)gp.items.size());
-      // groups become parallel branches of the graph: each is captured on a
-      // stream of its own, forked from and joined back into the batch stream
-      while (b->branch.size() < plans.size()) {
-        hipStream_t st = nullptr;
-        NK_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));  // default priority
-        b->branch.push_back(st);
-      }
-      hipGraph_t graph = nullptr;
-      NK_HIP(hipStreamBeginCapture(b->s, hipStreamCaptureModeThreadLocal));
-      try {
-        NK_HIP(hipEventRecord(b->fork, b->s));
-        for (size_t gi = 0; gi < plans.size(); ++gi) {
-          hipStream_t st = b->branch[gi];
-          NK_HIP(hipStreamWaitEvent(st, b->fork, 0));
-          issue_group(plans[gi], b->tables, st);
-          NK_HIP(hipEventRecord(b->joins[gi], st));
-          NK_HIP(hipStreamWaitEvent(b->s, b->joins[gi], 0));
-        }
-      } catch (...) {
-        (void)hipStreamEndCapture(b->s, &graph);
-        if (graph) (void)hipGraphDestroy(graph);
-        throw;
-      }
-      NK_HIP(hipStreamEndCapture(b->s, &graph));
-      const hipError_t e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
-      if (e != hipSuccess) {
-        b->exec = nullptr;
-        throw nk::HipError(NKREG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-      }
-      b->key_in.assign(vt, vt + cnt);
-      b->key_out.assign(out, out + cnt);
-      b->key_gen.resize(cnt);
-      for (size_t i = 0; i < cnt; ++i) b->key_gen[i] = b->items[i]->impl->generation;
-    }
-    if (one_stream) {
-      NK_HIP(hipGraphLaunch(b->exec, cs));
-      return (int)NKREG_OK;
-    }
-    // every caller stream waits for the batch
-    NK_HIP(hipGraphLaunch(b->exec, b->s));
-    NK_HIP(hipEventRecord(b->done, b->s));
-    for (size_t i = 0; i < cnt; ++i) NK_HIP(hipStreamWaitEvent(b->items[i]->impl->caller_stream(), b->done, 0));
+    run_batch(b, b->matvec, record_matvec_fn, vt, out);
     return (int)NKREG_OK;
   });
 }
 
+int nkreg_batch_objective_gradient(nkreg_batch* b, const void* const* v, double* J, double* J_dist, double* J_reg,
+                                   void* const* g) {
+  NEED(b);
+  if (!b->items.empty()) NEED(v);
+  for (size_t i = 0; i < b->items.size(); ++i)
+    if (!v[i]) return fail(NKREG_EINVAL, "batch gradient: null velocity");
+  return guarded([&]() {
+    const size_t cnt = b->items.size();
+    for (size_t i = 0; i < cnt; ++i) b->items[i]->impl->check_cfl(v[i]);
+    std::vector<void*> gout(cnt, nullptr);
+    if (g)
+      for (size_t i = 0; i < cnt; ++i) gout[i] = g[i];
+    run_batch(b, b->gradient, record_gradient_fn, v, gout.data());
+    for (size_t i = 0; i < cnt; ++i)
+      b->items[i]->impl->gradient_done(J ? J + i : nullptr, J_dist ? J_dist + i : nullptr,
+                                       J_reg ? J_reg + i : nullptr);
+    return (int)NKREG_OK;
+  });
+}
+
+int nkreg_batch_set_state(nkreg_batch* b, const void* const* v) {
+  return nkreg_batch_objective_gradient(b, v, nullptr, nullptr, nullptr, nullptr);
+}
+
 int nkreg_batch_groups(nkreg_batch* b, int* groups, int* sizes, int* tiled, int cap) {
   NEED(b); NEED(groups);
-  *groups = (int)b->group_sizes.size();
-  for (int i = 0; i < cap && i < (int)b->group_sizes.size(); ++i) {
-    if (sizes) sizes[i] = b->group_sizes[i];
-    if (tiled) tiled[i] = b->variants[i] == 0;
+  const BatchGraph& bg = b->matvec;
+  *groups = (int)bg.group_sizes.size();
+  for (int i = 0; i < cap && i < (int)bg.group_sizes.size(); ++i) {
+    if (sizes) sizes[i] = bg.group_sizes[i];
+    if (tiled) tiled[i] = bg.variants[i] == 0;
   }
   return NKREG_OK;
 }

@@ -81,9 +81,37 @@ class Reducer {
     if (host) (void)hipHostFree(host);
   }
 
+  // While set, reductions are recorded for a batch group instead of issued.
+  Recorder* rec = nullptr;
+
   template <typename R>
   void enqueue(int op, const R* x, const R* y, long long cnt, int slot) {
     const int nb = (int)std::max<long long>(1, std::min<long long>(kRedBlocks, (cnt + kRedThreads - 1) / kRedThreads));
+    if (rec) {
+      LaunchRec a;
+      a.kind = LaunchRec::RED;
+      switch (op) {
+        case RED_DOT: a.kernel = (const void*)k_reduce_t<R, RED_DOT>; break;
+        case RED_SUMSQ: a.kernel = (const void*)k_reduce_t<R, RED_SUMSQ>; break;
+        case RED_SUM: a.kernel = (const void*)k_reduce_t<R, RED_SUM>; break;
+        case RED_SUMSQDIFF: a.kernel = (const void*)k_reduce_t<R, RED_SUMSQDIFF>; break;
+        default: a.kernel = (const void*)k_reduce_t<R, RED_MAXABS>; break;
+      }
+      a.grid = dim3(nb);
+      a.block = dim3(kRedThreads);
+      a.cnt = cnt;
+      a.set_entry(RedPtrs<R>{x, y, partial.p});
+      rec->recs.push_back(a);
+      LaunchRec f;
+      f.kind = LaunchRec::REDF;
+      f.kernel = op == RED_MAXABS ? (const void*)k_reduce_final_t<true> : (const void*)k_reduce_final_t<false>;
+      f.grid = dim3(1);
+      f.block = dim3(kRedThreads);
+      f.iarg = nb;
+      f.set_entry(RedFinalPtrs{partial.p, result.p + slot});
+      rec->recs.push_back(f);
+      return;
+    }
     switch (op) {
       case RED_DOT: hipLaunchKernelGGL((k_reduce<R, RED_DOT>), dim3(nb), dim3(kRedThreads), 0, s, x, y, cnt, partial.p); break;
       case RED_SUMSQ: hipLaunchKernelGGL((k_reduce<R, RED_SUMSQ>), dim3(nb), dim3(kRedThreads), 0, s, x, y, cnt, partial.p); break;
@@ -146,6 +174,9 @@ class ProblemBase {
   virtual bool state_ready() const = 0;
   virtual const double* velocity() const = 0;
   virtual void images(const void** mT, const void** mR) const = 0;
+  // The template mean subtracted from the images, and setting already centred images.
+  virtual double image_shift() const = 0;
+  virtual void set_centred_images(const void* mT, const void* mR, double shift) = 0;
   virtual int lanczos(int steps, double* ritz, int* count) = 0;
   virtual int hessian_mode() const = 0;
   virtual void use_graph_capture(bool on) = 0;
@@ -154,6 +185,12 @@ class ProblemBase {
   // col_variant >= 0 records with that column pass (8 or 0 = tiled, which give
   // identical values) instead of the handle's own choice.
   virtual void record_matvec(const void* vt, void* out, Recorder& r, int col_variant = -1) = 0;
+  // Records one objective and gradient evaluation at v (g may be null: the handle's own
+  // buffer) the same way; gradient_done then reads J and marks the state valid once the
+  // recorded launches have run. check_cfl applies the CFL bound of the configuration.
+  virtual void record_gradient(const void* v, void* g, Recorder& r, int col_variant = -1) = 0;
+  virtual void gradient_done(double* J, double* Jd, double* Jr) = 0;
+  virtual void check_cfl(const void* v) = 0;
   virtual bool tiled_pass_applies() const = 0;
   virtual int col_variant() const = 0;
   virtual hipStream_t caller_stream() const = 0;
@@ -391,6 +428,25 @@ class ProblemT final : public ProblemBase {
     sp.colE = keep;
     sp64.colE = keep64;
   }
+  void record_gradient(const void* vin, void* gout, Recorder& r, int col_variant) override {
+    need_images();
+    state_valid = false;
+    const int keep = sp.colE, keep64 = sp64.colE;
+    if (col_variant >= 0) sp.colE = sp64.colE = col_variant;
+    rec = sp.rec = sp64.rec = red.rec = &r;
+    try {
+      gradient_body(vin, gout);
+    } catch (...) {
+      rec = sp.rec = sp64.rec = red.rec = nullptr;
+      sp.colE = keep;
+      sp64.colE = keep64;
+      held.assign(S, -1);
+      throw;
+    }
+    rec = sp.rec = sp64.rec = red.rec = nullptr;
+    sp.colE = keep;
+    sp64.colE = keep64;
+  }
   bool tiled_pass_applies() const override { return sp.any_tiled_pass(); }
   int col_variant() const override { return sp.colE; }
 
@@ -461,12 +517,36 @@ class ProblemT final : public ProblemBase {
     }
   }
 
+  // The images are kept centred: the template's mean c is subtracted from both.
+  // Transport carries a constant exactly and the objective, the adjoint, the
+  // gradient and the Hessian see only differences and gradients of the images, so
+  // nothing changes but the round-off: the transforms' rounding error scales with
+  // the field's norm, mean included, and in FP32 the spectral derivative amplifies
+  // it by the grid's wavenumbers. m_1 is returned with c added back.
+  double shift = 0.0;
   void set_images(const void* a, const void* b) override {
     copy(mT.p, a, n * sizeof(R));
     copy(mR.p, b, n * sizeof(R));
+    shift = red.one<R>(RED_SUM, mT.p, nullptr, n) / (double)n;
+    if (!std::isfinite(shift)) throw HipError(NKREG_ENONFINITE, "template image is not finite");
+    shift_images(-shift);
     have_images = true;
     state_valid = false;
   }
+  void shift_images(double c) {
+    hipLaunchKernelGGL((k_shift<R>), dim3(launch_blocks(n)), dim3(256), 0, s, n, (R)c, (const R*)mT.p, mT.p);
+    hipLaunchKernelGGL((k_shift<R>), dim3(launch_blocks(n)), dim3(256), 0, s, n, (R)c, (const R*)mR.p, mR.p);
+    NK_LAUNCHED();
+  }
+  // Images already centred by another handle (with their shift): copied as they are.
+  void set_centred_images(const void* a, const void* b, double c) override {
+    copy(mT.p, a, n * sizeof(R));
+    copy(mR.p, b, n * sizeof(R));
+    shift = c;
+    have_images = true;
+    state_valid = false;
+  }
+  double image_shift() const override { return shift; }
 
   // ---- state equation (Heun) ----
   struct SweepBufs {
@@ -648,20 +728,31 @@ class ProblemT final : public ProblemBase {
     copy(v.p, vin, nv * sizeof(double));
     const R* vl = to_transport(v.p, vR);
     forward_sweep(vl, true, m1.p);
-    if (m1out) copy(m1out, m1.p, n * sizeof(R));
+    if (m1out) {
+      hipLaunchKernelGGL((k_shift<R>), dim3(launch_blocks(n)), dim3(256), 0, s, n, (R)shift, (const R*)m1.p,
+                         (R*)m1out);
+      NK_LAUNCHED();
+    }
     state_valid = false;  // the adjoint solve of a gradient is still needed before matvecs
   }
 
-  // J_dist (FP64 reduction of the transport-precision mismatch) and J_reg (FP64).
-  void objective_terms(const double* vl, double* Jd, double* Jr, bool require_finite = true) {
+  // J_dist (FP64 reduction of the transport-precision mismatch) and J_reg (FP64):
+  // the reductions land in slots 0 and 1; objective_read waits for them.
+  void objective_enqueue(const double* vl) {
     sp64.vecop(OP_A, vl, nullptr, tmpv.p, nc, cfg.reg, 0, cfg.beta, Xs.p, Ys.p);
     red.enqueue<R>(RED_SUMSQDIFF, mR.p, m1.p, n, 0);
     red.enqueue<double>(RED_DOT, vl, tmpv.p, nv, 1);
+  }
+  void objective_read(double* Jd, double* Jr, bool require_finite = true) {
     red.fetch(2);
     *Jd = 0.5 * g.hd * red.host[0];
     *Jr = 0.5 * cfg.beta * g.hd * red.host[1];
     if (require_finite && (!std::isfinite(*Jd) || !std::isfinite(*Jr)))
       throw HipError(NKREG_ENONFINITE, "objective is not finite");
+  }
+  void objective_terms(const double* vl, double* Jd, double* Jr, bool require_finite = true) {
+    objective_enqueue(vl);
+    objective_read(Jd, Jr, require_finite);
   }
 
   // J at a line-search trial point; +inf if the trial's transport overflowed,
@@ -687,21 +778,39 @@ class ProblemT final : public ProblemBase {
     if (Jr) *Jr = jr;
   }
 
-  void objective_gradient(const void* vin, double* J, double* Jd, double* Jr, void* gout) override {
-    need_images();
-    check_velocity_cfl((const double*)vin);
+  // One objective and gradient evaluation as a sequence of launches: forward sweep
+  // (keeping the trajectory), the objective's reductions, adjoint sweep with the
+  // body force, and the spectral finalize g = beta A v + K[f]. Nothing waits.
+  void gradient_body(const void* vin, void* gout) {
     copy(v.p, vin, nv * sizeof(double));
     const R* vl = to_transport(v.p, vR);
     forward_sweep(vl, true, m1.p);
-    double jd, jr;
-    objective_terms(v.p, &jd, &jr);
+    objective_enqueue(v.p);
     adjoint_sweep_k<false>(vl, nullptr, R(1), mR.p, R(-1), m1.p, F.p, full_newton);
     double* gdst = gout ? (double*)gout : gbuf.p;
     sp64.vecop(OP_HESS, v.p, force64(), gdst, nc, cfg.reg, cfg.incompressible, cfg.beta, Xs.p, Ys.p);
+  }
+
+  void objective_gradient(const void* vin, double* J, double* Jd, double* Jr, void* gout) override {
+    need_images();
+    check_velocity_cfl((const double*)vin);
+    state_valid = false;
+    gradient_body(vin, gout);
+    gradient_done(J, Jd, Jr);
+  }
+
+  // After a gradient's launches: reads J (waits), checks it, marks the state valid.
+  void gradient_done(double* J, double* Jd, double* Jr) override {
+    double jd, jr;
+    objective_read(&jd, &jr);
     state_valid = true;
     if (J) *J = jd + jr;
     if (Jd) *Jd = jd;
     if (Jr) *Jr = jr;
+  }
+  void check_cfl(const void* vin) override {
+    need_images();
+    check_velocity_cfl((const double*)vin);
   }
 
   void hessian_matvec(const void* vtin, void* out) override {

@@ -16,6 +16,9 @@
 
 namespace nk {
 
+// Sets the text nkreg_last_error returns on this thread.
+void set_last_error(const std::string& msg);
+
 struct HipError : std::runtime_error {
   int code;
   HipError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
@@ -119,18 +122,18 @@ struct KernelTimer {
 // arguments every item of a group shares. A batch replays each position of
 // equal-shaped recordings as one launch over all items of the group.
 struct LaunchRec {
-  enum Kind { ROW, COL, FILL, CONV, SPEC, COPY };
+  enum Kind { ROW, COL, FILL, CONV, SPEC, COPY, RED, REDF };
   int kind = ROW;
   const void* kernel = nullptr;      // group form of the kernel
   dim3 grid, block;
   std::vector<unsigned char> entry;  // this item's table entry
   const void* tw = nullptr;          // ROW, COL: twiddle table (equal across a group)
-  int iarg = 0;                      // ROW: lmax; COL: twb; SPEC: op
+  int iarg = 0;                      // ROW: lmax; COL: twb; SPEC: op; REDF: partials
   int nfz = 1;                       // COL: fields per item
   ColArgs ca{};
   double scale = 0.0, fval = 0.0;    // COL scale, FILL value
   bool f64 = false;                  // precision of scale and fval
-  long long cnt = 0;                 // FILL, CONV element counts
+  long long cnt = 0;                 // FILL, CONV, RED element counts
   void* dst = nullptr;               // COPY (issued per item)
   const void* src = nullptr;
   size_t bytes = 0;
@@ -185,25 +188,37 @@ class Spectral {
     NK_LAUNCHED();
   }
 
+  // Twiddle table exp(-2 pi i m / lmax), m < lmax, computed in FP64 on the host.
+  static void twiddles(int lmax, cplx<R>* h) {
+    for (int m = 0; m < lmax; ++m) {
+      const double a = -2.0 * M_PI * (double)m / (double)lmax;
+      h[m] = {(R)std::cos(a), (R)std::sin(a)};
+    }
+  }
+
   Spectral() = default;
   Spectral(const Grid& grid, hipStream_t stream) : g(grid), s(stream) {
+    read_col_env();
+    std::vector<cplx<R>> h(g.lmax);
+    twiddles(g.lmax, h.data());
+    NK_HIP(hipMalloc(&tw, sizeof(cplx<R>) * g.lmax));
+    owns_tw = true;
+    NK_HIP(hipMemcpy(tw, h.data(), sizeof(cplx<R>) * g.lmax, hipMemcpyHostToDevice));
+  }
+  // Launchers over a twiddle table the caller provides (and keeps filled); allocates nothing.
+  Spectral(const Grid& grid, hipStream_t stream, cplx<R>* table) : g(grid), s(stream), tw(table) { read_col_env(); }
+  Spectral(const Spectral&) = delete;
+  Spectral& operator=(const Spectral&) = delete;
+  ~Spectral() {
+    if (tw && owns_tw) (void)hipFree(tw);
+  }
+  void read_col_env() {
     if (const char* ce = std::getenv("NKREG_COL_E")) {
       const int v = std::atoi(ce);
       colE = (std::string(ce) == "tiled" || v == 0) ? 0 : (v == 4 ? 4 : 8);
     }
-    std::vector<cplx<R>> h(g.lmax);
-    for (int m = 0; m < g.lmax; ++m) {
-      const double a = -2.0 * M_PI * (double)m / (double)g.lmax;
-      h[m] = {(R)std::cos(a), (R)std::sin(a)};
-    }
-    NK_HIP(hipMalloc(&tw, sizeof(cplx<R>) * g.lmax));
-    NK_HIP(hipMemcpy(tw, h.data(), sizeof(cplx<R>) * g.lmax, hipMemcpyHostToDevice));
   }
-  Spectral(const Spectral&) = delete;
-  Spectral& operator=(const Spectral&) = delete;
-  ~Spectral() {
-    if (tw) (void)hipFree(tw);
-  }
+  bool owns_tw = false;
 
   // ---- column passes ----
   // axis 0 = x1 for any d; axis 1 = x2 for d = 3.

@@ -86,7 +86,20 @@ def test_null_arguments_are_rejected():
     assert lib.nkreg_create(None, None, ctypes.byref(h)) == _lib.EINVAL
     assert lib.nkreg_destroy(None) == _lib.OK
     assert lib.nkreg_hessian_matvec(None, None, None) == _lib.EINVAL
-    assert lib.nkreg_batch_create(-1, None, ctypes.byref(h)) == _lib.EINVAL
+    assert lib.nkreg_batch_create(-1, None, None, ctypes.byref(h)) == _lib.EINVAL
+    assert lib.nkreg_batch_wrap(-1, None, ctypes.byref(h)) == _lib.EINVAL
+    assert lib.nkreg_batch_item(None, 0, ctypes.byref(h)) == _lib.EINVAL
+    assert lib.nkreg_batch_set_state(None, None) == _lib.EINVAL
+
+
+def test_batch_create_validates_every_configuration_before_any_device_work():
+    lib = _lib.load()
+    cfgs = (_lib.Config * 2)(make_cfg(), make_cfg(n=(48, 64, 1)))
+    h = ctypes.c_void_p()
+    assert lib.nkreg_batch_create(2, cfgs, None, ctypes.byref(h)) == _lib.ESHAPE
+    assert not h.value
+    cfgs = (_lib.Config * 2)(make_cfg(), make_cfg(beta=-1.0))
+    assert lib.nkreg_batch_create(2, cfgs, None, ctypes.byref(h)) == _lib.EINVAL
 
 
 def test_check_raises_with_message():

@@ -58,3 +58,61 @@ def test_counter_traffic_matches_the_algorithmic_bytes():
         t = bench.measured_traffic(sym)
         alg = fields * field_bytes
         assert abs(t - alg) <= 0.02 * alg, (sym, t, alg)
+
+
+def test_counter_pass_pins_the_column_pass_and_never_uses_graphs(monkeypatch):
+    """bench.py --counter-pass fixes the column variant before the first handle exists (so
+    the autotuner, which captures and times graphs, never runs) and launches every kernel
+    eagerly. Checked with stand-ins for the library and torch that record the calls."""
+    import types
+    events = []
+    monkeypatch.delenv("NKREG_COL_E", raising=False)
+    monkeypatch.delenv("NKREG_NO_GRAPHS", raising=False)
+
+    class FakeProblem:
+        def __init__(self, *a, **kw):
+            events.append(("create", os.environ.get("NKREG_COL_E"), os.environ.get("NKREG_NO_GRAPHS")))
+
+        def use_graphs(self, on):
+            events.append(("graphs", on))
+
+        def set_images(self, *a):
+            pass
+
+        def forward(self, v):
+            return "mR"
+
+        def objective_gradient(self, v):
+            events.append(("gradient",))
+
+        def zeros_v(self):
+            return None
+
+        def empty_v(self):
+            return None
+
+        def hessian_matvec(self, w, out):
+            events.append(("matvec",))
+
+        def describe(self):
+            return {}
+
+        def close(self):
+            pass
+
+    class FakeTensor:
+        def to(self, *a):
+            return self
+
+    fake_torch = types.SimpleNamespace(device=lambda *a: None, from_numpy=lambda a: FakeTensor(), float32=None,
+                                       cuda=types.SimpleNamespace(synchronize=lambda: None))
+    import synth
+    for name, variant in (("c2lit", "8"), ("c4", "tiled")):
+        events.clear()
+        monkeypatch.setattr(synth, "make_inputs", lambda spec: (0, 0))
+        monkeypatch.setattr(synth, "bandlimited_velocity", lambda *a, **kw: 0)
+        assert bench.counter_pass(types.SimpleNamespace(Problem=FakeProblem), synth, fake_torch, name) == 0
+        assert events[0] == ("create", variant, "1"), events
+        assert events[1] == ("graphs", False), events
+        assert events.count(("matvec",)) == 3
+        monkeypatch.delenv("NKREG_COL_E", raising=False)
