@@ -306,6 +306,20 @@ int nkreg_divergence(nkreg_problem* p, const void* d_w, void* d_s);
 /* d_out = A d_x (nc*d*n values, A = -Lap or Lap^2 per component). */
 int nkreg_apply_reg(nkreg_problem* p, const void* d_x, void* d_out);
 
+/* nkreg_gradient without a handle and without any device allocation, for callers
+ * that cannot allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc). d_g (dim * n values) = spectral gradient of the scalar field
+ * d_u (n values) on the grid dim, n[0..dim) (powers of two in [8, 512]) in the given
+ * precision (32: float, 64: double), on hip_stream (NULL = the null stream); the
+ * result is the same bits as nkreg_gradient's. The row spectra and twiddles live in a
+ * fixed device array of the library, 8 MiB + 16 KiB on each GPU that runs the call
+ * (held until the process ends): the grid's 2 (d = 2) or 3 (d = 3) spectra of
+ * n * sizeof(element) bytes must fit in 8 MiB (every 2D grid; 3D up to 64^3 in FP64),
+ * else ESHAPE. Every call on one GPU uses that GPU's one array, so calls that overlap
+ * on one GPU (concurrent streams or threads) race; calls ordered on a stream do not.
+ * Asynchronous. Errors: EINVAL, ESHAPE, EHIP. */
+int nkreg_gradient_noalloc(int dim, const int* n, int precision, const void* d_u, void* d_g, void* hip_stream);
+
 /* FP64 inner product sum(a*b) of two double arrays of cnt elements. Synchronises. */
 int nkreg_dot(nkreg_problem* p, const void* d_a, const void* d_b, long long cnt, double* h_out);
 
