@@ -128,6 +128,17 @@ def roofline(kernel: str, symbol: str, rec: dict, traffic=None) -> dict:
             "traffic": traffic}
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (as lscpu reports it), from /proc/cpuinfo."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -424,6 +435,236 @@ def analysis_section(nk, synth, torch, spec, mT_h, mR_h):
     return out
 
 
+def reference_image(nk, torch, spec, mT, vstar, precision=64):
+    """m_R = m_T transported by v* with the library's FP64 forward solve (input synthesis)."""
+    dev = torch.device("cuda:0")
+    G = nk.Problem(spec.shape, spec.nt, spec.nc, spec.reg, bool(spec.gamma), spec.beta, precision=64,
+                   checkpoint_every=spec.checkpoint_every)
+    G.set_images(torch.from_numpy(mT).to(dev), torch.zeros(spec.shape, dtype=torch.float64, device=dev))
+    mR = G.forward(torch.from_numpy(vstar).to(dev))
+    torch.cuda.synchronize()
+    G.close()
+    return mR
+
+
+def timed_solve(G, torch, **kw):
+    """Newton solve from v = 0; returns (seconds, report, v)."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    v, rep = G.newton_solve(G.zeros_v(), **kw)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, rep, v
+
+
+def solve_record(secs, rep, mis=None):
+    r = {"seconds": secs, "outer_iterations": rep.iterations, "matvecs": rep.cg_iterations, "n_pde": rep.n_pde,
+         "converged": rep.converged, "stop": rep.stop_reason,
+         "grad_rel": rep.gnorm_inf / rep.gnorm0_inf if rep.gnorm0_inf else 0.0}
+    if mis is not None:
+        r["relative_mismatch"] = mis
+    return r
+
+
+def c0_section(nk, synth, torch, reps=20):
+    """64^2 FP64, H1, beta 1e-2, nt = 16 (the paper's smooth test case at its size): GN-PCG
+    time-to-solution to a relative gradient of 1e-3, and the graph-replayed matvec rate."""
+    dev = torch.device("cuda:0")
+    spec = synth.CONFIGS["c0"]
+    mT, vstar = synth.make_inputs(spec)
+    mR = reference_image(nk, torch, spec, mT, vstar)
+    G = nk.Problem(spec.shape, spec.nt, 1, spec.reg, False, spec.beta, precision=64)
+    G.set_images(torch.from_numpy(mT).to(dev), mR)
+    secs, rep, v = timed_solve(G, torch, gtol=1e-3, max_outer=50)
+    mis = 2.0 * rep.J_dist / (G.hd * float(np.sum((mR.cpu().numpy() - mT) ** 2)))
+    out = {"grid": list(spec.shape), "nt": spec.nt, "precision": 64, "solve": solve_record(secs, rep, mis)}
+    G.objective_gradient(G.zeros_v())
+    w = torch.from_numpy(synth.bandlimited_velocity(spec.shape, 31, 4, 0.3)).to(dev)
+    ms = time_matvecs(G, w, reps, torch)
+    out["matvec_ms"] = ms
+    out["matvecs_per_s"] = 1e3 / ms
+    out["matvec_roofline"] = matvec_roofline(G, w, ms)
+    log(f"c0 64^2 FP64: solve {secs:.3f} s ({rep.iterations} outer / {rep.cg_iterations} matvecs), "
+        f"matvec {ms:.3f} ms")
+    G.close()
+    return out
+
+
+def c1_section(nk, synth, torch, precisions=(32, 64), reps=3):
+    """256^2, three Chebyshev coefficients per component, H2 + Stokes, beta 1e-3, nt = 408
+    (the CFL-adapted steps of the 32-step configuration): FP32 against FP64 matvec time and
+    time-to-solution (relative gradient 1e-3), and det F_1 of each solution (FP64)."""
+    dev = torch.device("cuda:0")
+    spec = synth.CONFIGS["c1"]
+    mT, vstar = synth.make_inputs(spec)
+    mR = reference_image(nk, torch, spec, mT, vstar)
+    out = {"grid": list(spec.shape), "nt": spec.nt, "nc": spec.nc, "reg": "H2", "incompressible": True,
+           "beta": spec.beta}
+    _, st = nk.Problem(spec.shape, spec.nt, spec.nc, spec.reg, True, spec.beta, precision=64).det_grad_y(
+        torch.from_numpy(vstar).to(dev))
+    out["det_F1_true_velocity"] = {"min": st[0], "max": st[1]}
+    w = torch.from_numpy(synth.bandlimited_velocity(spec.shape, 30, 8, 0.1, divfree=True, nc=3)).to(dev)
+    mis0 = float(np.sum((mR.cpu().numpy() - mT) ** 2))
+    for prec in precisions:
+        dt = torch.float32 if prec == 32 else torch.float64
+        G = nk.Problem(spec.shape, spec.nt, spec.nc, spec.reg, True, spec.beta, precision=prec)
+        G.set_images(torch.from_numpy(mT).to(dev).to(dt), mR.to(dt))
+        G.objective_gradient(G.zeros_v())
+        ms = time_matvecs(G, w, reps, torch)
+        r = {"matvec_ms": ms, "matvecs_per_s": 1e3 / ms, "matvec_roofline": matvec_roofline(G, w, ms)}
+        secs, rep, v = timed_solve(G, torch, gtol=1e-3, max_outer=50)
+        r["solve"] = solve_record(secs, rep, 2.0 * rep.J_dist / (G.hd * mis0))
+        _, st = G.det_grad_y(v)
+        r["det_F1"] = {"min": st[0], "max": st[1], "mean": st[2], "std": st[3]}
+        out[f"fp{prec}"] = r
+        log(f"c1 256^2 nt=408 FP{prec}: matvec {ms:.2f} ms, solve {secs:.2f} s ({rep.iterations} outer / "
+            f"{rep.cg_iterations} matvecs), det F_1 in [{st[0]:.4f}, {st[1]:.4f}]")
+        G.close()
+    if 32 in precisions and 64 in precisions:
+        out["fp32_matvec_speedup"] = out["fp64"]["matvec_ms"] / out["fp32"]["matvec_ms"]
+        out["fp32_solve_speedup"] = out["fp64"]["solve"]["seconds"] / out["fp32"]["solve"]["seconds"]
+    return out
+
+
+def c2_full_section(nk, synth, torch, precisions=(32, 64), reps=3, max_outer=20):
+    """512^2, H2, nt = 1224 (the CFL-adapted steps at max|v*| = 1.5), beta continuation
+    1e-1 -> 1e-4 with the paper's termination rule of its 512^2 continuation runs
+    ((C1 and C2 and C3) or C4 or C5, tau_J = 1e-3; at most max_outer + 1 iterations per
+    level): time-to-solution and matvec time. (The relative-gradient rule at 1e-3 is not
+    reached within 50 iterations here: at 1224 FP32 steps the gradient's round-off floor
+    lies above it.)"""
+    dev = torch.device("cuda:0")
+    spec = synth.CONFIGS["c2"]
+    mT, vstar = synth.make_inputs(spec)
+    mR = reference_image(nk, torch, spec, mT, vstar)
+    mis0 = float(np.sum((mR.cpu().numpy() - mT) ** 2))
+    out = {"grid": list(spec.shape), "nt": spec.nt, "beta_levels": list(spec.beta_levels)}
+    for prec in precisions:
+        dt = torch.float32 if prec == 32 else torch.float64
+        G = nk.Problem(spec.shape, spec.nt, 1, spec.reg, False, spec.beta_levels[0], precision=prec)
+        G.set_images(torch.from_numpy(mT).to(dev).to(dt), mR.to(dt))
+        # the continuation level by level (as nkreg_continuation runs it: every level's
+        # relative-gradient rule against the first level's gradient), one line per level
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        v, levels = G.zeros_v(), []
+        for b in spec.beta_levels:
+            G.beta = b
+            v, rep = G.newton_solve(v, gtol=0.0, tau_J=1e-3, max_outer=max_outer)
+            levels.append(rep)
+            log(f"c2 FP{prec} beta={b:g}: {rep.iterations} outer / {rep.cg_iterations} matvecs, stop "
+                f"{rep.stop_reason}, {time.perf_counter() - t0:.1f} s so far")
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        G.beta = spec.beta
+        G.objective_gradient(G.zeros_v())
+        w = torch.from_numpy(synth.bandlimited_velocity(spec.shape, 20, 16, 0.05)).to(dev)
+        ms = time_matvecs(G, w, reps, torch)
+        r = {"seconds": secs, "rule": "C1-C5, tau_J = 1e-3", "stops": [x.stop_reason for x in levels],
+             "outer_iterations": sum(x.iterations for x in levels),
+             "matvecs": sum(x.cg_iterations for x in levels), "n_pde": sum(x.n_pde for x in levels),
+             "converged": all(x.converged for x in levels),
+             "relative_mismatch": 2.0 * levels[-1].J_dist / (G.hd * mis0),
+             "matvec_ms": ms, "matvecs_per_s": 1e3 / ms, "matvec_roofline": matvec_roofline(G, w, ms)}
+        out[f"fp{prec}"] = r
+        log(f"c2 512^2 nt=1224 FP{prec}: continuation {secs:.2f} s ({r['outer_iterations']} outer / "
+            f"{r['matvecs']} matvecs), matvec {ms:.1f} ms")
+        G.close()
+    if 32 in precisions and 64 in precisions:
+        out["fp32_solve_speedup"] = out["fp64"]["seconds"] / out["fp32"]["seconds"]
+    return out
+
+
+def c4_full_section(nk, synth, torch, precisions=(32, 64)):
+    """256^3, H2 + Stokes, nt = 408 (the CFL-adapted steps at max|v*| = 1), checkpoint
+    every 8 steps (51 segments): gradient and matvec time, det F_1 of the true velocity."""
+    dev = torch.device("cuda:0")
+    base = synth.CONFIGS["c4"]
+    shape = base.shape
+    nt = synth.cfl_steps(1.0, shape[0], 0.1, 8)
+    vstar = synth.bandlimited_velocity(shape, base.vel_seed, base.vel_kmax, 1.0, divfree=True)
+    mT = synth.smooth_image(shape, base.image_seed, base.image_width)
+    out = {"grid": list(shape), "nt": nt, "checkpoint_every": base.checkpoint_every,
+           "segments": -(-nt // base.checkpoint_every)}
+    G64 = nk.Problem(shape, nt, 1, base.reg, True, base.beta, precision=64, checkpoint_every=base.checkpoint_every)
+    G64.set_images(torch.from_numpy(mT).to(dev), torch.zeros(shape, dtype=torch.float64, device=dev))
+    mR = G64.forward(torch.from_numpy(vstar).to(dev))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = G64.det_grad_y(torch.from_numpy(vstar).to(dev))
+    out["det_F1_true_velocity"] = {"min": st[0], "max": st[1], "mean": st[2], "std": st[3],
+                                   "seconds": time.perf_counter() - t0}
+    G64.close()
+    w = torch.from_numpy(synth.bandlimited_velocity(shape, 52, 6, 0.05, divfree=True)).to(dev)
+    for prec in precisions:
+        dt = torch.float32 if prec == 32 else torch.float64
+        G = nk.Problem(shape, nt, 1, base.reg, True, base.beta, precision=prec, checkpoint_every=base.checkpoint_every)
+        G.set_images(torch.from_numpy(mT).to(dev).to(dt), mR.to(dt))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        G.objective_gradient(G.zeros_v())
+        torch.cuda.synchronize()
+        tg = time.perf_counter() - t0
+        ms = time_matvecs(G, w, 1, torch)
+        out[f"fp{prec}"] = {"gradient_s": tg, "matvec_ms": ms, "matvec_roofline": matvec_roofline(G, w, ms)}
+        log(f"c4 256^3 nt={nt} FP{prec}: gradient {tg:.2f} s, matvec {ms:.0f} ms")
+        G.close()
+    if 32 in precisions and 64 in precisions:
+        out["fp32_matvec_speedup"] = out["fp64"]["matvec_ms"] / out["fp32"]["matvec_ms"]
+    return out
+
+
+def batch_nteff_section(nk, synth, torch, reps=2):
+    """The 64-pair batch at its own amplitudes: each item with the steps its CFL bound needs
+    (rounded up to a multiple of 64, 64..640): one batched matvec against the items one after
+    another, FP32."""
+    dev = torch.device("cuda:0")
+    specs = synth.batch_specs_nteff()
+    probs, ws, outs = [], [], []
+    for i, sp in enumerate(specs):
+        mT, vstar = synth.make_inputs(sp)
+        mR = reference_image(nk, torch, sp, mT, vstar)
+        G = nk.Problem(sp.shape, sp.nt, 1, sp.reg, False, sp.beta, precision=32)
+        G.set_images(torch.from_numpy(mT).to(dev).float(), mR.float())
+        G.objective_gradient(G.zeros_v())
+        probs.append(G)
+        ws.append(torch.from_numpy(synth.bandlimited_velocity(sp.shape, 500 + i, 6, 0.05)).to(dev))
+        outs.append(G.empty_v())
+    steps = sorted({(sp.shape[0], sp.nt) for sp in specs})
+    out = {"items": len(specs), "nt_range": [min(sp.nt for sp in specs), max(sp.nt for sp in specs)],
+           "grid_steps_pairs": len(steps)}
+    B = nk.Batch(probs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.hessian_matvec(ws, outs)
+    torch.cuda.synchronize()
+    out["build_and_first_s"] = time.perf_counter() - t0
+    out["groups"] = len(B.groups())
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        B.hessian_matvec(ws, outs)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / reps
+    for G, w, o in zip(probs, ws, outs):
+        G.hessian_matvec(w, o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for G, w, o in zip(probs, ws, outs):
+        G.hessian_matvec(w, o)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    nbytes = sum(G.matvec_bytes(w)[0] for G, w in zip(probs, ws))
+    ach = nbytes / tb / 1e9
+    out.update({"batched_ms": 1e3 * tb, "sequential_ms": 1e3 * ts, "batched_speedup_vs_sequential": ts / tb,
+                "roofline": {"bound": "hbm", "bytes_per_batched_matvec": nbytes, "achieved": ach,
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}})
+    log(f"batch at CFL steps ({out['nt_range'][0]}..{out['nt_range'][1]}, {out['groups']} groups): batched "
+        f"{1e3 * tb:.1f} ms, sequential {1e3 * ts:.1f} ms, {ach / 1e3:.2f} TB/s")
+    B.close()
+    for G in probs:
+        G.close()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -441,6 +682,11 @@ def main() -> int:
     ap.add_argument("--no-3d", action="store_true", help="skip the 256^3 workload")
     ap.add_argument("--no-beta-search", action="store_true", help="skip the det F_1-bounded beta search")
     ap.add_argument("--no-analysis", action="store_true", help="skip the Hessian assembly and Lanczos estimate")
+    ap.add_argument("--c2-fp64", action="store_true",
+                    help="also time the FP64 transport on the 512^2 nt = 1224 continuation (minutes)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other configurations (64^2 solve, 256^2 n_c = 3 Stokes at nt = 408, 512^2 at "
+                         "nt = 1224, 256^3 at nt = 408, the batch at its CFL steps)")
     ap.add_argument("--counter-pass", choices=("c2lit", "c4"), default=None,
                     help="only run three eager FP32 Hessian matvecs of the workload (no graphs, no timers; for "
                          "HBM counters) and exit")
@@ -589,10 +835,24 @@ def main() -> int:
     if not args.no_3d:
         out["cube_256"] = cube_section(nk, synth, torch, reps=4, kernel=args.kernel,
                                        precisions=(32,) if args.no_fp64 else (32, 64))
+    if not args.no_configs:
+        configs = {}
+        precs = (32,) if args.no_fp64 else (32, 64)
+        configs["c0_64sq_fp64"] = c0_section(nk, synth, torch)
+        configs["c1_256sq_nc3_stokes_nt408"] = c1_section(nk, synth, torch, precs)
+        configs["c2_512sq_nt1224"] = c2_full_section(nk, synth, torch, (32, 64) if args.c2_fp64 else (32,))
+        if not args.no_3d:
+            configs["c4_256cube_nt408"] = c4_full_section(nk, synth, torch, precs)
+        if not args.no_batch:
+            configs["batch_cfl_steps"] = batch_nteff_section(nk, synth, torch)
+        out["configs"] = configs
     if not args.no_cpu:
         from oracle import reduced as ord_
         from oracle import spectral as osp
-        P = ord_.Problem(mT_h, mR_h, nt, 1, spec.reg, 0, spec.beta)
+        from oracle import transport as otr
+        # the oracle's own reference image (its FP64 forward solve of the same velocity)
+        mR_o = otr.forward_only(mT_h, vstar_h, nt)
+        P = ord_.Problem(mT_h, mR_o, nt, 1, spec.reg, 0, spec.beta)
         S = ord_.objective_gradient(P, np.zeros(P.vshape()))
         w = -S.g
         n = max(1, args.cpu_matvecs)
@@ -602,9 +862,15 @@ def main() -> int:
             z = ord_.precond(P, hw)
         tc = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": n / tc, "unit": "matvecs/s", "cores": osp.WORKERS, "kind": "oracle",
+                               "cpu_model": cpu_model(),
                                "sample": f"{n} oracle GN Hessian matvecs + preconditioner applications "
-                                         f"(FP64 NumPy/SciPy) at the same 512^2 nt=32 state, {tc:.1f} s"}
-        log(f"CPU oracle: {n / tc:.3f} matvecs/s on {osp.WORKERS} threads")
+                                         f"(FP64 NumPy/SciPy) at the 512^2 nt=32 state, {tc:.1f} s"}
+        c2 = out.get("configs", {}).get("c2_512sq_nt1224", {}).get("fp32")
+        if c2:
+            # a matvec is two transport solves of nt steps; the oracle's cost grows linearly in nt
+            per_pde = tc / n / 2.0 * (synth.CONFIGS["c2"].nt / nt)
+            out["cpu_baseline"]["c2_512sq_nt1224_solve_extrapolated_s"] = c2["n_pde"] * per_pde
+        log(f"CPU oracle: {n / tc:.3f} matvecs/s on {osp.WORKERS} threads ({cpu_model()})")
     print(json.dumps(out), flush=True)
     return 0
 

@@ -56,8 +56,20 @@ __device__ __forceinline__ cplx<R> comb2(const R* __restrict__ f, const R* w, in
   return s;
 }
 
+// LDS scratch of one wavefront's row stage: SPW rows of KMAX padded sequences.
+template <typename R, int L, int E, int KIND0, int D>
+struct RowLds {
+  static constexpr int M = L / 2;
+  static constexpr int SPW = 64 / WavePlan<M, E>::LS;   // rows per wavefront
+  static constexpr int PADM = padded_e<E>(M);
+  static constexpr int SIZE = SPW * StageShape<KIND0, D>::KMAX * PADM;   // complex elements
+};
+
+// One wavefront's share of a row stage: row group rgroup (rows rgroup * SPW ..), field
+// fy of a batched launch, scratch lds (RowLds::SIZE elements), lane 0..63.
 template <typename R, int L, int E, int KIND0, int D, bool NC1>
-__device__ __forceinline__ void row_body(const StageArgs<R>& a, const cplx<R>* __restrict__ tw, int lmax) {
+__device__ __forceinline__ void row_body_at(const StageArgs<R>& a, const cplx<R>* __restrict__ tw, int lmax,
+                                            long long rgroup, int fy, cplx<R>* lds, int lane) {
   constexpr int KIND = base_kind(KIND0);    // full-Newton kinds run their adjoint kind's code ...
   constexpr bool NEWT = newton_kind(KIND0);  // ... plus the lambda terms
   constexpr int M = L / 2;
@@ -71,12 +83,10 @@ __device__ __forceinline__ void row_body(const StageArgs<R>& a, const cplx<R>* _
   constexpr bool FWDK = (KIND == ST_FWD1 || KIND == ST_FWD2);
   constexpr bool INCK = (KIND == ST_INC1 || KIND == ST_INC2);
   constexpr bool ADJOUT = (KIND == ST_ADJINIT || KIND == ST_ADJ1 || KIND == ST_ADJ2);
-  __shared__ cplx<R> lds[SPW * KMAX * PADM];
 
-  const int lane = threadIdx.x;
   const int sr = lane / LS, j = lane - sr * LS;
   const long long rows = a.n / L;
-  const long long rowr = (long long)blockIdx.x * SPW + sr;
+  const long long rowr = rgroup * SPW + sr;
   const bool live = rowr < rows;
   const long long row = live ? rowr : rows - 1;
   const long long n = a.n;
@@ -113,7 +123,7 @@ __device__ __forceinline__ void row_body(const StageArgs<R>& a, const cplx<R>* _
   cplx<R> XA[KA][H], XB[KA][H];
   if constexpr (KIN > 0) {
     if (!zero_in) {
-      const long long fin = (long long)blockIdx.y * a.fstride_in;
+      const long long fin = (long long)fy * a.fstride_in;
 #pragma unroll
       for (int k = 0; k < KIN; ++k) {
         const cplx<R>* src;
@@ -192,7 +202,7 @@ __device__ __forceinline__ void row_body(const StageArgs<R>& a, const cplx<R>* _
       X1[e] = ld2(a.src_a, e);
       X2[e] = a.src_b ? ld2(a.src_b, e) : cplx<R>{R(0), R(0)};
     }
-    if constexpr (KIND == ST_R2C) X1[e] = ld2(a.src_a + (long long)blockIdx.y * a.fstride_in, e);
+    if constexpr (KIND == ST_R2C) X1[e] = ld2(a.src_a + (long long)fy * a.fstride_in, e);
   }
 
   // ---- input row spectra: C2R packing -> natural layout -> inverse FFT ----
@@ -329,11 +339,11 @@ __device__ __forceinline__ void row_body(const StageArgs<R>& a, const cplx<R>* _
     } else if constexpr (KIND == ST_R2C) {
       O[0][e] = X1[e];
     } else if constexpr (KIND == ST_C2R || KIND == ST_DIV) {
-      st2(a.out_real + (long long)blockIdx.y * a.fstride_out, e, cscale(A[0][e], invL * a.scale));
+      st2(a.out_real + (long long)fy * a.fstride_out, e, cscale(A[0][e], invL * a.scale));
     } else if constexpr (KIND == ST_GRAD) {
 #pragma unroll
       for (int c = 0; c < D; ++c)
-        st2(a.out_real + (long long)blockIdx.y * a.fstride_out + (long long)c * n, e,
+        st2(a.out_real + (long long)fy * a.fstride_out + (long long)c * n, e,
             cscale(A[c][e], invL * a.scale));
     }
   }
@@ -347,7 +357,7 @@ __device__ __forceinline__ void row_body(const StageArgs<R>& a, const cplx<R>* _
 #pragma unroll
       for (int e = 0; e < E; ++e) S[k * PADM + pad_e<E>(j + LS * e)] = O[k][e];
     wave_lds_sync();
-    const long long fo = (long long)blockIdx.y * a.fstride_out;
+    const long long fo = (long long)fy * a.fstride_out;
 #pragma unroll
     for (int k = 0; k < KOUT; ++k) {
       cplx<R>* dst;
@@ -380,6 +390,13 @@ __device__ __forceinline__ void row_body(const StageArgs<R>& a, const cplx<R>* _
   }
 }
 
+// A row stage with one wavefront per workgroup: row group blockIdx.x, field blockIdx.y.
+template <typename R, int L, int E, int KIND0, int D, bool NC1>
+__device__ __forceinline__ void row_body(const StageArgs<R>& a, const cplx<R>* __restrict__ tw, int lmax) {
+  __shared__ cplx<R> lds[RowLds<R, L, E, KIND0, D>::SIZE];
+  row_body_at<R, L, E, KIND0, D, NC1>(a, tw, lmax, (long long)blockIdx.x, (int)blockIdx.y, lds, (int)threadIdx.x);
+}
+
 template <typename R, int L, int E, int KIND, int D, bool NC1>
 __global__ __launch_bounds__(64) void k_row_w(StageArgs<R> a, const cplx<R>* __restrict__ tw, int lmax) {
   row_body<R, L, E, KIND, D, NC1>(a, tw, lmax);
@@ -407,23 +424,22 @@ struct ColShape {
   static constexpr bool BLOCK = LS > 64;              // a column spans several waves
 };
 
+// One workgroup's column group of a column pass: columns bx * SPW .., outer slice by,
+// field fz; scratch lds (SPW padded columns), lane 0..NT-1.
 template <typename R, int N, int E, int MODE>
-__device__ __forceinline__ void col_w_body(const cplx<R>* in, const cplx<R>* add, cplx<R>* out, const ColArgs& a,
-                                           R scale, const cplx<R>* __restrict__ tw, int twb, int fz) {
+__device__ __forceinline__ void col_w_at(const cplx<R>* in, const cplx<R>* add, cplx<R>* out, const ColArgs& a,
+                                         R scale, const cplx<R>* __restrict__ tw, int twb, int fz, int bx, int by,
+                                         cplx<R>* lds, int lane) {
   using CS = ColShape<N, E>;
   constexpr int LS = CS::LS;
   constexpr int SPW = CS::SPW;
   constexpr bool BLK = CS::BLOCK;
   constexpr int PADN = padded_e<E>(N);
-  __shared__ cplx<R> lds[SPW * PADN];
-  const int lane = threadIdx.x;
   const int c = lane % SPW, j = lane / SPW;
-  const int nbx = gridDim.x;
-  const int bx = (nbx % 8 == 0) ? (int)(blockIdx.x % 8) * (nbx / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
   const long long colr = (long long)bx * SPW + c;
   const bool live = colr < a.inner;
   const long long col = live ? colr : a.inner - 1;
-  const long long base = (long long)fz * a.field + (long long)blockIdx.y * N * a.inner + col;
+  const long long base = (long long)fz * a.field + (long long)by * N * a.inner + col;
   cplx<R> v[E], ad[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = in[base + (long long)(j + LS * e) * a.inner];
@@ -455,6 +471,18 @@ __device__ __forceinline__ void col_w_body(const cplx<R>* in, const cplx<R>* add
 #pragma unroll
     for (int e = 0; e < E; ++e) out[base + (long long)(j + LS * e) * a.inner] = v[e];
   }
+}
+
+// A column pass with one column group per workgroup; consecutive column groups are
+// renumbered onto one XCD (the dispatcher deals workgroups to the 8 XCDs in turn).
+template <typename R, int N, int E, int MODE>
+__device__ __forceinline__ void col_w_body(const cplx<R>* in, const cplx<R>* add, cplx<R>* out, const ColArgs& a,
+                                           R scale, const cplx<R>* __restrict__ tw, int twb, int fz) {
+  using CS = ColShape<N, E>;
+  __shared__ cplx<R> lds[CS::SPW * padded_e<E>(N)];
+  const int nbx = gridDim.x;
+  const int bx = (nbx % 8 == 0) ? (int)(blockIdx.x % 8) * (nbx / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
+  col_w_at<R, N, E, MODE>(in, add, out, a, scale, tw, twb, fz, bx, (int)blockIdx.y, lds, (int)threadIdx.x);
 }
 
 template <typename R, int N, int E, int MODE>

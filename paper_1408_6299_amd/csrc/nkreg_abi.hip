@@ -4,6 +4,7 @@
 #include <memory>
 #include <string>
 
+#include "group.hpp"
 #include "problem.hpp"
 
 struct nkreg_problem {
@@ -380,132 +381,12 @@ int nkreg_batch_destroy(nkreg_batch* b) {
 
 namespace {
 
-// Issues one recorded launch position for a whole group (tab = its table).
-void launch_group(const nk::LaunchRec& r, int G, void* tab, hipStream_t st) {
-  dim3 grid = r.grid;
-  const unsigned z = grid.z;
-  grid.z = z * (unsigned)G;
-  const void* tw = r.tw;
-  int iarg = r.iarg, nfz = r.nfz;
-  long long cnt = r.cnt;
-  nk::ColArgs ca = r.ca;
-  float sf = (float)r.scale, vf = (float)r.fval;
-  double sd = r.scale, vd = r.fval;
-  void* args[6];
-  switch (r.kind) {
-    case nk::LaunchRec::ROW: args[0] = &tab; args[1] = &tw; args[2] = &iarg; break;
-    case nk::LaunchRec::COL:
-      args[0] = &tab; args[1] = &ca; args[2] = r.f64 ? (void*)&sd : (void*)&sf; args[3] = &tw; args[4] = &iarg;
-      args[5] = &nfz;
-      break;
-    case nk::LaunchRec::FILL: args[0] = &cnt; args[1] = r.f64 ? (void*)&vd : (void*)&vf; args[2] = &tab; break;
-    case nk::LaunchRec::CONV: args[0] = &cnt; args[1] = &tab; break;
-    case nk::LaunchRec::SPEC: args[0] = &tab; args[1] = &iarg; break;
-    case nk::LaunchRec::RED: args[0] = &cnt; args[1] = &tab; break;
-    case nk::LaunchRec::REDF: args[0] = &iarg; args[1] = &tab; break;
-    default: throw nk::HipError(NKREG_EHIP, "unexpected recorded launch");
-  }
-  NK_HIP(hipLaunchKernel(r.kernel, grid, r.block, args, 0, st));
-}
-
-bool same_sequence(const std::vector<nk::LaunchRec>& a, const std::vector<nk::LaunchRec>& b) {
-  if (a.size() != b.size()) return false;
-  for (size_t i = 0; i < a.size(); ++i)
-    if (!a[i].same_shape(b[i])) return false;
-  return true;
-}
-
-// The recorded launches of one group of items and where their tables live.
-struct GroupPlan {
-  std::vector<size_t> items;
-  std::vector<nk::Recorder> recs;  // one per item, equal-shaped
-  std::vector<size_t> offs;        // per launch position: table offset
-};
-
-// Appends the group's argument tables (items' entries side by side per position).
-void add_tables(GroupPlan& gp, std::vector<unsigned char>& host) {
-  const auto& seq = gp.recs[0].recs;
-  gp.offs.assign(seq.size(), 0);
-  for (size_t p = 0; p < seq.size(); ++p) {
-    if (seq[p].kind == nk::LaunchRec::COPY) continue;
-    host.resize((host.size() + 255) / 256 * 256);
-    gp.offs[p] = host.size();
-    for (const auto& r : gp.recs) host.insert(host.end(), r.recs[p].entry.begin(), r.recs[p].entry.end());
-  }
-}
-
-// Issues the group's launches on st (tables at base).
-void issue_group(const GroupPlan& gp, void* base, hipStream_t st) {
-  const auto& seq = gp.recs[0].recs;
-  for (size_t p = 0; p < seq.size(); ++p) {
-    if (seq[p].kind == nk::LaunchRec::COPY) {
-      for (const auto& r : gp.recs) {
-        const auto& c = r.recs[p];
-        NK_HIP(hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyDeviceToDevice, st));
-      }
-    } else {
-      launch_group(seq[p], (int)gp.recs.size(), (unsigned char*)base + gp.offs[p], st);
-    }
-  }
-}
-
-// Captures issue_group into a graph on st (which must not be capturing).
-hipGraphExec_t capture_group(const GroupPlan& gp, void* base, hipStream_t st) {
-  hipGraph_t graph = nullptr;
-  NK_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-  try {
-    issue_group(gp, base, st);
-  } catch (...) {
-    (void)hipStreamEndCapture(st, &graph);
-    if (graph) (void)hipGraphDestroy(graph);
-    throw;
-  }
-  NK_HIP(hipStreamEndCapture(st, &graph));
-  hipGraphExec_t ex = nullptr;
-  const hipError_t e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(graph);
-  if (e != hipSuccess) throw nk::HipError(NKREG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-  return ex;
-}
-
-// Milliseconds per replay of the group's launches (one warm-up, then two timed).
-float time_group(const GroupPlan& gp, hipStream_t st) {
-  std::vector<unsigned char> host;
-  GroupPlan g = gp;
-  add_tables(g, host);
-  void* dev = nullptr;
-  if (!host.empty()) {
-    NK_HIP(hipMalloc(&dev, host.size()));
-    NK_HIP(hipMemcpy(dev, host.data(), host.size(), hipMemcpyHostToDevice));
-  }
-  hipGraphExec_t ex = nullptr;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  float ms = 0.f;
-  try {
-    ex = capture_group(g, dev, st);
-    NK_HIP(hipEventCreate(&e0));
-    NK_HIP(hipEventCreate(&e1));
-    NK_HIP(hipGraphLaunch(ex, st));
-    NK_HIP(hipEventRecord(e0, st));
-    NK_HIP(hipGraphLaunch(ex, st));
-    NK_HIP(hipGraphLaunch(ex, st));
-    NK_HIP(hipEventRecord(e1, st));
-    NK_HIP(hipEventSynchronize(e1));
-    NK_HIP(hipEventElapsedTime(&ms, e0, e1));
-  } catch (...) {
-    (void)hipStreamSynchronize(st);
-    if (ex) (void)hipGraphExecDestroy(ex);
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    if (dev) (void)hipFree(dev);
-    throw;
-  }
-  (void)hipGraphExecDestroy(ex);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (dev) (void)hipFree(dev);
-  return ms / 2.f;
-}
+using nk::add_tables;
+using nk::capture_group;
+using nk::GroupPlan;
+using nk::issue_group;
+using nk::same_sequence;
+using nk::time_group;
 
 // Records an item's launch sequence for one batched operation (column pass variant
 // cv >= 0 overrides the item's own choice).
@@ -564,13 +445,28 @@ void run_batch(nkreg_batch* b, BatchGraph& bg, RecordFn record, const void* cons
           plans.back().recs.push_back(std::move(recs[i]));
         }
       }
-      // a group's launches are G times larger than one item's: where the tiled
-      // column pass applies, time both column passes (identical values) at the
-      // group's scale and keep the faster
+      // Small square grids run their sweeps in the persistent kernel (recorded with the
+      // 8-per-lane column pass it runs; the values are those of any column pass).
+      // Otherwise a group's launches are G times larger than one item's: where the
+      // tiled column pass applies, time both column passes (identical values) at the
+      // group's scale and keep the faster.
       bg.variants.clear();
       for (auto& gp : plans) {
         nk::ProblemBase* first = b->items[gp.items[0]]->impl;
         int chosen = first->col_variant();
+        if (nk::small_config(first->cfg)) {
+          GroupPlan c;
+          c.items = gp.items;
+          c.recs.resize(gp.items.size());
+          for (size_t k = 0; k < gp.items.size(); ++k)
+            record(b->items[gp.items[k]]->impl, vt[gp.items[k]], out[gp.items[k]], c.recs[k], 8);
+          c.small_ops = nk::small_prefix(c.recs[0].recs);
+          if (c.small_ops) {
+            gp = std::move(c);
+            bg.variants.push_back(8);
+            continue;
+          }
+        }
         if (gp.items.size() > 1 && first->tiled_pass_applies() && (chosen == 8 || chosen == 0)) {
           float best = 0.f;
           GroupPlan bestp;
@@ -656,7 +552,9 @@ void assemble_grouped(nk::ProblemBase* src, double* H) {
   const nkreg_config c = src->cfg;
   const long long npts = (long long)c.n[0] * c.n[1] * (c.dim == 3 ? c.n[2] : 1);
   const long long nv = (long long)c.nc * c.dim * npts;
-  const int G = (int)std::min<long long>(std::min<long long>(kAssembleGroup, nv),
+  // small grids run each matvec's sweeps in one workgroup: many items fill the GPU
+  const int gcap = nk::small_config(c) ? 256 : kAssembleGroup;
+  const int G = (int)std::min<long long>(std::min<long long>(gcap, nv),
                                          std::max<long long>(1, (1LL << 20) / npts));
   if (G <= 1) {
     src->assemble_hessian(H);
@@ -678,12 +576,14 @@ void assemble_grouped(nk::ProblemBase* src, double* H) {
   nk::DevBuf<double> E((size_t)G * nv), C((size_t)G * nv);
   GroupPlan gp;
   gp.recs.resize(G);
+  const int cv = nk::small_config(c) ? 8 : -1;
   for (int i = 0; i < G; ++i) {
     gp.items.push_back((size_t)i);
-    items[i]->record_matvec(E.p + (size_t)i * nv, C.p + (size_t)i * nv, gp.recs[i]);
+    items[i]->record_matvec(E.p + (size_t)i * nv, C.p + (size_t)i * nv, gp.recs[i], cv);
     if (!same_sequence(gp.recs[0].recs, gp.recs[i].recs))
       throw nk::HipError(NKREG_EHIP, "clone's matvec differs from the handle's");
   }
+  gp.small_ops = cv == 8 ? nk::small_prefix(gp.recs[0].recs) : 0;
   std::vector<unsigned char> host;
   add_tables(gp, host);
   nk::DevBuf<unsigned char> tab(host.size());

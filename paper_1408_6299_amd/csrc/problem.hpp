@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "../../include/nkreg.h"
+#include "group.hpp"
 #include "kernels_analysis.hpp"
 #include "spectral.hpp"
 
@@ -471,6 +472,7 @@ class ProblemT final : public ProblemBase {
       r.grid = dim3(launch_blocks(cnt));
       r.block = dim3(256);
       r.cnt = cnt;
+      r.conv = (sizeof(RS) == 8 && sizeof(RD) == 4) ? 1 : ((sizeof(RS) == 4 && sizeof(RD) == 8) ? 2 : 0);
       r.set_entry(ConvPtrs<RS, RD>{x, y});
       rec->recs.push_back(r);
       return;
@@ -831,7 +833,28 @@ class ProblemT final : public ProblemBase {
   }
 
   // Captures one matvec on the capture stream; nothing runs until the graph is launched.
+  // On small square grids the transport sweeps run in the persistent kernel (from the
+  // recorded launch sequence and its argument table, kept in mv_tab while the graph lives).
+  DevBuf<unsigned char> mv_tab;
+  bool small_sweeps = false;
   hipGraphExec_t capture_matvec(const void* vtin, void* out) {
+    small_sweeps = false;
+    if (small_config(cfg)) {
+      GroupPlan gp;
+      gp.items = {0};
+      gp.recs.resize(1);
+      record_matvec(vtin, out, gp.recs[0], 8);
+      gp.small_ops = small_prefix(gp.recs[0].recs);
+      if (gp.small_ops) {
+        std::vector<unsigned char> host;
+        add_tables(gp, host);
+        NK_HIP(hipStreamSynchronize(s));   // an earlier graph may still read the old table
+        mv_tab.alloc(host.size());
+        NK_HIP(hipMemcpy(mv_tab.p, host.data(), host.size(), hipMemcpyHostToDevice));
+        small_sweeps = true;
+        return capture_group(gp, mv_tab.p, cap_s);
+      }
+    }
     hipGraph_t graph = nullptr;
     OnCaptureStream on(*this);
     NK_HIP(hipStreamBeginCapture(cap_s, hipStreamCaptureModeThreadLocal));
@@ -933,7 +956,8 @@ class ProblemT final : public ProblemBase {
   }
   std::string describe() override {
     return std::string("{\"transport_precision\": ") + (kF64 ? "64" : "32") + ", \"graphs\": " +
-           (use_graphs ? "true" : "false") + ", \"row_E\": " + std::to_string(kRowE) + ", \"col_E\": " +
+           (use_graphs ? "true" : "false") + ", \"persistent_sweeps\": " + (small_sweeps ? "true" : "false") +
+           ", \"row_E\": " + std::to_string(kRowE) + ", \"col_E\": " +
            std::to_string(sp.colE) + ", \"col_deriv_symbols\": [" + col_symbols() + "], \"autotune\": \"" + tuning +
            "\"}";
   }

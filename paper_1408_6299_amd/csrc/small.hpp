@@ -1,0 +1,98 @@
+// Persistent form of a small problem's transport sweeps: one workgroup runs every
+// launch of an item's recorded sequence (row stages, column passes, fills and
+// conversions) one after another, with a workgroup barrier where the launch path
+// has a kernel boundary. Its wavefronts share each launch's row or column groups
+// and run the same device code on the same values as the launches, so the results
+// are the same bits. The items of a batch group run as concurrent workgroups.
+#pragma once
+
+#include "spectral.hpp"
+
+namespace nk {
+
+enum SmallOpKind { SOP_ROW = 0, SOP_COL = 1, SOP_FILL = 2, SOP_CONV = 3 };
+
+// One recorded launch as the persistent kernel runs it. Per-item arguments are the
+// launch's table entries: item i's entry at tab + off + i * esize.
+struct SmallOp {
+  int kind;        // SmallOpKind
+  int sub;         // ROW: stage kind; COL: column mode
+  long long off;   // table offset of the first item's entry
+  int esize;       // bytes per item entry
+  int gx, gy, gz;  // ROW: row groups, fields; COL: column groups, outer slices, fields
+  ColArgs ca;      // COL
+  double scale;    // COL: multiplier scale; FILL: value
+  int twb;         // COL: twiddle stride
+  long long cnt;   // FILL, CONV: elements
+};
+
+constexpr int kSmallWaves = 8;                  // wavefronts per workgroup
+constexpr int kSmallThreads = 64 * kSmallWaves;
+
+// Per-wavefront LDS scratch: the largest row-stage or column-pass need of the grid.
+template <typename R, int N1, int L>
+struct SmallShape {
+  static constexpr int E = kRowE;
+  static constexpr int ROW = RowLds<R, L, E, ST_ADJ1, 2>::SIZE > RowLds<R, L, E, ST_INC1, 2>::SIZE
+                                 ? RowLds<R, L, E, ST_ADJ1, 2>::SIZE
+                                 : RowLds<R, L, E, ST_INC1, 2>::SIZE;
+  static constexpr int COL = ColShape<N1, 8>::SPW * padded_e<8>(N1);
+  static constexpr int SLOT = ROW > COL ? ROW : COL;
+};
+
+template <typename R, int L, int KIND, bool NC1>
+__device__ __forceinline__ void small_rows(const SmallOp& op, const StageArgs<R>& a, const cplx<R>* tw, int lmax,
+                                           cplx<R>* lds, int wave, int lane) {
+  for (int fy = 0; fy < op.gy; ++fy)
+    for (int g = wave; g < op.gx; g += kSmallWaves)
+      row_body_at<R, L, kRowE, KIND, 2, NC1>(a, tw, lmax, g, fy, lds, lane);
+}
+
+template <typename R, int N1, int L, bool NC1>
+__global__ __launch_bounds__(kSmallThreads) void k_small(const SmallOp* __restrict__ prog, int nops,
+                                                         const unsigned char* __restrict__ tab,
+                                                         const cplx<R>* __restrict__ tw, int lmax) {
+  using SS = SmallShape<R, N1, L>;
+  __shared__ cplx<R> lds[kSmallWaves * SS::SLOT];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  cplx<R>* my = lds + wave * SS::SLOT;
+  const long long item = blockIdx.x;
+  for (int o = 0; o < nops; ++o) {
+    const SmallOp op = prog[o];
+    const unsigned char* e = tab + op.off + item * op.esize;
+    if (op.kind == SOP_ROW) {
+      const StageArgs<R>& a = *reinterpret_cast<const StageArgs<R>*>(e);
+      switch (op.sub) {
+        case ST_INC1: small_rows<R, L, ST_INC1, NC1>(op, a, tw, lmax, my, wave, lane); break;
+        case ST_INC2: small_rows<R, L, ST_INC2, NC1>(op, a, tw, lmax, my, wave, lane); break;
+        case ST_ADJINIT: small_rows<R, L, ST_ADJINIT, NC1>(op, a, tw, lmax, my, wave, lane); break;
+        case ST_ADJ1: small_rows<R, L, ST_ADJ1, NC1>(op, a, tw, lmax, my, wave, lane); break;
+        default: small_rows<R, L, ST_ADJ2, NC1>(op, a, tw, lmax, my, wave, lane); break;
+      }
+    } else if (op.kind == SOP_COL) {
+      const ColPtrs<R> p = *reinterpret_cast<const ColPtrs<R>*>(e);
+      for (int fz = 0; fz < op.gz; ++fz)
+        for (int by = 0; by < op.gy; ++by)
+          for (int bx = wave; bx < op.gx; bx += kSmallWaves)
+            col_w_at<R, N1, 8, COL_DERIV>(p.in, p.add, p.out, op.ca, (R)op.scale, tw, op.twb, fz, bx, by, my, lane);
+    } else if (op.kind == SOP_FILL) {
+      R* y = *reinterpret_cast<R* const*>(e);
+      const R v = (R)op.scale;
+      for (long long i = threadIdx.x; i < op.cnt; i += kSmallThreads) y[i] = v;
+    } else {
+      const ConvPtrs<double, R> p = *reinterpret_cast<const ConvPtrs<double, R>*>(e);
+      for (long long i = threadIdx.x; i < op.cnt; i += kSmallThreads) p.y[i] = (R)p.x[i];
+    }
+    __syncthreads();
+  }
+}
+
+// Square 2D grids up to this size run their sweeps in the persistent kernel.
+constexpr int kSmallMaxN = 64;
+
+// Launches k_small for `items` items over a program at prog (device) with nops
+// launches; defined for N1 = L in {8, 16, 32, 64}. Returns false if no instance fits.
+bool launch_small(bool f64, int n1, int l, bool nc1, int items, const SmallOp* prog, int nops,
+                  const unsigned char* tab, const void* tw, int lmax, hipStream_t st);
+
+}  // namespace nk

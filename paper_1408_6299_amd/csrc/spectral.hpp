@@ -137,6 +137,11 @@ struct LaunchRec {
   void* dst = nullptr;               // COPY (issued per item)
   const void* src = nullptr;
   size_t bytes = 0;
+  // What the launch computes, for running it inside a persistent kernel instead:
+  // ROW: stage kind, row length, dimension, stationary velocity; COL: mode, axis
+  // length, elements per lane (0 = tiled); CONV: 1 = FP64 to FP32, 2 = FP32 to FP64.
+  int stage = -1, len = 0, dim = 0, elems = 0, conv = 0;
+  bool nc1 = false;
   template <typename T>
   void set_entry(const T& v) {
     entry.resize(sizeof(T));
@@ -146,7 +151,8 @@ struct LaunchRec {
     return kind == o.kind && kernel == o.kernel && grid.x == o.grid.x && grid.y == o.grid.y &&
            grid.z == o.grid.z && block.x == o.block.x && iarg == o.iarg && nfz == o.nfz &&
            std::memcmp(&ca, &o.ca, sizeof(ColArgs)) == 0 && scale == o.scale && fval == o.fval && f64 == o.f64 &&
-           cnt == o.cnt && entry.size() == o.entry.size() && bytes == o.bytes;
+           cnt == o.cnt && entry.size() == o.entry.size() && bytes == o.bytes && stage == o.stage && len == o.len &&
+           dim == o.dim && elems == o.elems && conv == o.conv && nc1 == o.nc1;
   }
 };
 struct Recorder {
@@ -439,6 +445,9 @@ class Spectral {
                       : mode == COL_INV ? (const void*)k_col_tt<R, N, CT, COL_INV>
                                         : (const void*)k_col_tt<R, N, CT, COL_DERIV>;
       record_col(k, grid, dim3(TileShape<R, N, CT>::NT), nf, a, scale, twb, in, add, out);
+      rec->recs.back().stage = mode;
+      rec->recs.back().len = N;
+      rec->recs.back().elems = 0;
       return;
     }
     const bool timed = timer && timer->want(kColIdBase + mode);
@@ -467,6 +476,9 @@ class Spectral {
                       : mode == COL_INV ? (const void*)k_col_wt<R, N, E, COL_INV>
                                         : (const void*)k_col_wt<R, N, E, COL_DERIV>;
       record_col(k, grid, dim3(CS::NT), nf, a, scale, twb, in, add, out);
+      rec->recs.back().stage = mode;
+      rec->recs.back().len = N;
+      rec->recs.back().elems = E;
       return;
     }
     const bool timed = timer && timer->want(kColIdBase + mode);
@@ -517,6 +529,11 @@ class Spectral {
       r.block = dim3(64);
       r.tw = tw;
       r.iarg = g.lmax;
+      r.f64 = sizeof(R) == 8;
+      r.stage = KIND;
+      r.len = L;
+      r.dim = D;
+      r.nc1 = !uses_nc || a.nc <= 1;
       r.set_entry(a);
       rec->recs.push_back(r);
       return;

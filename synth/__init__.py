@@ -23,7 +23,8 @@ import numpy as np
 
 __all__ = [
     "grid_coords", "integer_wavenumbers", "smooth_image", "bandlimited_velocity",
-    "c0_velocity", "chebyshev_sample_max", "ProblemSpec", "CONFIGS", "make_inputs",
+    "c0_velocity", "chebyshev_sample_max", "ProblemSpec", "CONFIGS", "make_inputs", "cfl_steps",
+    "batch_specs_nteff",
     "batch_specs", "cfl_literal_linf",
 ]
 
@@ -258,4 +259,31 @@ def batch_specs(count: int = 64, seed: int = 3, nt: int = 16,
         s_n = cfl_literal_linf(n, nt) / (0.5 * 1.5)
         out.append(ProblemSpec(f"batch item {i}: {n}x{n}", (n, n), nt, 1, 1, 0, 1e-2, 32,
                                1000 + i, 36.0, "c0", vel_amplitude=float(amps[i] * s_n)))
+    return out
+
+
+def cfl_steps(vmax_linf: float, n: int, cfl: float = 0.1, multiple: int = 8, nt_min: int = 16) -> int:
+    """Time steps that keep h_t * max|v^i| / h_x at or below ``cfl`` on an n-point axis,
+    at least ``nt_min`` and rounded up to a multiple of ``multiple``."""
+    nt = int(np.ceil(vmax_linf * n / (2.0 * np.pi * cfl)))
+    nt = max(nt_min, nt)
+    return -(-nt // multiple) * multiple
+
+
+def batch_specs_nteff(count: int = 64, seed: int = 3, cfl: float = 0.1, multiple: int = 64,
+                      sizes: Sequence[int] = (64, 128, 256, 512)) -> List[ProblemSpec]:
+    """The batched workload at its own amplitudes: the grid sizes and amplitudes of
+    batch_specs (same draws), each item's velocity the 64^2 configuration's scaled by a_i
+    (max|v^i| = a_i / 2), and each item's steps set by the CFL bound at ``cfl`` (rounded up
+    to a multiple of ``multiple``, so items of one grid share a few step counts)."""
+    rng = np.random.default_rng(seed)
+    ns = rng.choice(np.asarray(sizes), size=count)
+    amps = rng.uniform(0.5, 1.5, size=count)
+    out = []
+    for i in range(count):
+        n = int(ns[i])
+        a = float(amps[i])
+        nt = cfl_steps(0.5 * a, n, cfl, multiple)
+        out.append(ProblemSpec(f"batch item {i}: {n}x{n}, nt {nt}", (n, n), nt, 1, 1, 0, 1e-2, 32,
+                               1000 + i, 36.0, "c0", vel_amplitude=a))
     return out

@@ -430,6 +430,37 @@ def test_c4_64cube_oracle_parity(nk):
         G.close()
 
 
+@pytest.mark.parametrize("prec", [32, 64])
+def test_c4_256cube_full_grid_against_the_oracle(nk, prec):
+    """The 256^3 grid itself against the oracle, over a short horizon the oracle finishes
+    in about a minute: H2 + Stokes, beta 1e-3, nt = 2 with the C4 generators (velocity at
+    CFL 0.1 for two steps), FP32 with the trajectory checkpointed every step (two segments,
+    one slot, so every sweep recomputes one). Gradient and GN matvec at v = 0.5 v*, and the
+    first PCG solve of the Newton step at two fixed iterations. FP64: 1e-10 (PCG 1e-9);
+    FP32: the GN matvec at 1e-5, the gradient at the kappa-scaled bound, PCG at 1e-4."""
+    spec = synth.CONFIGS["c4"]
+    shape, nt = spec.shape, 2
+    mT = synth.smooth_image(shape, spec.image_seed, spec.image_width)
+    vstar = synth.bandlimited_velocity(shape, spec.vel_seed, spec.vel_kmax, synth.cfl_literal_linf(256, nt),
+                                       divfree=True, norm="linf")
+    mR = otr.forward_only(mT, vstar, nt)
+    if prec == 32:
+        mT, mR = f32(mT), f32(mR)
+    P = ord_.Problem(mT, mR, nt, 1, spec.reg, 1, spec.beta)
+    v = 0.5 * vstar
+    w = synth.bandlimited_velocity(shape, 41, 6, 0.05, divfree=True)
+    G = nk.Problem(shape, nt, 1, spec.reg, True, spec.beta, precision=prec, checkpoint_every=1 if prec == 32 else 0)
+    G.set_images(dev_t(mT, prec), dev_t(mR, prec))
+    check_gradient_and_matvec_away_from_zero(G, P, v, w, prec)
+    S = ord_.objective_gradient(P, v)
+    x_ref, it_ref, _, _ = okr.pcg(lambda q: ord_.hessian_matvec(P, S, q), lambda r: ord_.precond(P, r), -S.g, 0.0, 2)
+    _, _, _, g = G.objective_gradient(dev_v(v))
+    x, it, _, _ = G.pcg((-g).contiguous(), 0.0, 2)
+    assert it == it_ref == 2
+    assert rel_inf(host(x), x_ref) < (1e-9 if prec == 64 else 1e-4)
+    G.close()
+
+
 def test_c4_256cube_properties(nk):
     """256^3 FP32, H2 + Stokes, beta = 1e-3, nt = 32, checkpoint every 8: the oracle cannot run
     here, so check what holds at any size: a constant image stays constant, checkpointing is
