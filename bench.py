@@ -483,8 +483,10 @@ def c0_section(nk, synth, torch, reps=20):
     out["matvec_ms"] = ms
     out["matvecs_per_s"] = 1e3 / ms
     out["matvec_roofline"] = matvec_roofline(G, w, ms)
+    d = G.describe()
+    out["sweeps"] = {"persistent": d.get("persistent_sweeps"), "timing": d.get("sweep_timing")}
     log(f"c0 64^2 FP64: solve {secs:.3f} s ({rep.iterations} outer / {rep.cg_iterations} matvecs), "
-        f"matvec {ms:.3f} ms")
+        f"matvec {ms:.3f} ms; sweeps: {out['sweeps']}")
     G.close()
     return out
 
@@ -525,7 +527,7 @@ def c1_section(nk, synth, torch, precisions=(32, 64), reps=3):
     return out
 
 
-def c2_full_section(nk, synth, torch, precisions=(32, 64), reps=3, max_outer=20):
+def c2_full_section(nk, synth, torch, precisions=(32, 64), reps=3, max_outer=5):
     """512^2, H2, nt = 1224 (the CFL-adapted steps at max|v*| = 1.5), beta continuation
     1e-1 -> 1e-4 with the paper's termination rule of its 512^2 continuation runs
     ((C1 and C2 and C3) or C4 or C5, tau_J = 1e-3; at most max_outer + 1 iterations per
@@ -629,6 +631,8 @@ def batch_nteff_section(nk, synth, torch, reps=2):
         probs.append(G)
         ws.append(torch.from_numpy(synth.bandlimited_velocity(sp.shape, 500 + i, 6, 0.05)).to(dev))
         outs.append(G.empty_v())
+        if i % 16 == 15:
+            log(f"batch at CFL steps: {i + 1} items set up")
     steps = sorted({(sp.shape[0], sp.nt) for sp in specs})
     out = {"items": len(specs), "nt_range": [min(sp.nt for sp in specs), max(sp.nt for sp in specs)],
            "grid_steps_pairs": len(steps)}
@@ -639,6 +643,7 @@ def batch_nteff_section(nk, synth, torch, reps=2):
     torch.cuda.synchronize()
     out["build_and_first_s"] = time.perf_counter() - t0
     out["groups"] = len(B.groups())
+    log(f"batch at CFL steps: graph of {out['groups']} groups built and run in {out['build_and_first_s']:.1f} s")
     t0 = time.perf_counter()
     for _ in range(reps):
         B.hessian_matvec(ws, outs)

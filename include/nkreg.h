@@ -320,6 +320,20 @@ int nkreg_apply_reg(nkreg_problem* p, const void* d_x, void* d_out);
  * Asynchronous. Errors: EINVAL, ESHAPE, EHIP. */
 int nkreg_gradient_noalloc(int dim, const int* n, int precision, const void* d_u, void* d_g, void* hip_stream);
 
+/* Exchange canary of the register FFTs (test instrumentation, Section "Numerical
+ * Discretization" transforms): count complex sequences of length m (interleaved re, im
+ * in the given precision, m contiguous values each) transformed forward then inverse
+ * (unnormalised, so out = m * in up to rounding) with the library's wavefront FFT at
+ * `elems` complex values per lane, `lockstep` sequences per lane group (1, or 2 as the
+ * row stages transform several sequences together). poison != 0 overwrites the LDS
+ * scratch with NaN around every exchange: if a wavefront's exchange read were served
+ * before its earlier writes, or a later write overtook a read, NaN would reach d_out;
+ * with correct ordering the output equals the unpoisoned run's bit for bit. Forms:
+ * (m, elems, lockstep) in {32, 128, 256} x {4} x {1, 2} and {64, 256, 512} x {8} x {1};
+ * others return ENOTIMPL. Allocates and frees a twiddle table. Synchronises. */
+int nkreg_exchange_canary(int precision, int m, int elems, int lockstep, int poison, const void* d_in, void* d_out,
+                          int count, void* hip_stream);
+
 /* FP64 inner product sum(a*b) of two double arrays of cnt elements. Synchronises. */
 int nkreg_dot(nkreg_problem* p, const void* d_a, const void* d_b, long long cnt, double* h_out);
 

@@ -12,10 +12,15 @@
 
 namespace nk {
 
-// Whether the persistent small-grid kernel is in use (NKREG_SMALL=0 turns it off).
+// Whether the persistent small-grid kernel may be used: NKREG_SMALL=0 turns it off,
+// NKREG_SMALL=1 forces it wherever it applies (no timing against plain launches).
 inline bool small_enabled() {
   const char* e = std::getenv("NKREG_SMALL");
   return !(e && e[0] == '0');
+}
+inline bool small_forced() {
+  const char* e = std::getenv("NKREG_SMALL");
+  return e && e[0] == '1';
 }
 
 // Configurations whose matvec may run its sweeps in the persistent kernel: square 2D
@@ -236,5 +241,27 @@ inline float time_group(const GroupPlan& gp, hipStream_t st) {
   return ms / 2.f;
 }
 
+
+// The faster of a set of candidate plans for one group (every candidate gives the same
+// values): each is replayed at the group's scale and timed; ms[i] receives the times.
+inline size_t fastest_plan(const std::vector<GroupPlan>& cands, hipStream_t st, std::vector<float>* ms = nullptr) {
+  size_t best = 0;
+  float tbest = 0.f;
+  if (ms) ms->clear();
+  if (small_forced()) {
+    if (ms) ms->assign(cands.size(), 0.f);
+    for (size_t i = 0; i < cands.size(); ++i)
+      if (cands[i].small_ops) return i;
+  }
+  for (size_t i = 0; i < cands.size(); ++i) {
+    const float t = time_group(cands[i], st);
+    if (ms) ms->push_back(t);
+    if (i == 0 || t < tbest) {
+      tbest = t;
+      best = i;
+    }
+  }
+  return best;
+}
 
 }  // namespace nk

@@ -462,7 +462,11 @@ void run_batch(nkreg_batch* b, BatchGraph& bg, RecordFn record, const void* cons
             record(b->items[gp.items[k]]->impl, vt[gp.items[k]], out[gp.items[k]], c.recs[k], 8);
           c.small_ops = nk::small_prefix(c.recs[0].recs);
           if (c.small_ops) {
-            gp = std::move(c);
+            // the persistent form against plain launches, timed at the group's scale
+            std::vector<GroupPlan> cands(2, c);
+            cands[1].small_ops = 0;
+            const size_t pick = nk::fastest_plan(cands, b->s);
+            gp = std::move(cands[pick]);
             bg.variants.push_back(8);
             continue;
           }
@@ -552,9 +556,7 @@ void assemble_grouped(nk::ProblemBase* src, double* H) {
   const nkreg_config c = src->cfg;
   const long long npts = (long long)c.n[0] * c.n[1] * (c.dim == 3 ? c.n[2] : 1);
   const long long nv = (long long)c.nc * c.dim * npts;
-  // small grids run each matvec's sweeps in one workgroup: many items fill the GPU
-  const int gcap = nk::small_config(c) ? 256 : kAssembleGroup;
-  const int G = (int)std::min<long long>(std::min<long long>(gcap, nv),
+  const int G = (int)std::min<long long>(std::min<long long>(kAssembleGroup, nv),
                                          std::max<long long>(1, (1LL << 20) / npts));
   if (G <= 1) {
     src->assemble_hessian(H);
@@ -584,6 +586,23 @@ void assemble_grouped(nk::ProblemBase* src, double* H) {
       throw nk::HipError(NKREG_EHIP, "clone's matvec differs from the handle's");
   }
   gp.small_ops = cv == 8 ? nk::small_prefix(gp.recs[0].recs) : 0;
+  if (gp.small_ops) {
+    // the persistent form against plain launches, timed at the group's scale
+    std::vector<GroupPlan> cands(2, gp);
+    cands[1].small_ops = 0;
+    NK_HIP(hipStreamSynchronize(st));
+    hipStream_t tst = nullptr;
+    NK_HIP(hipStreamCreateWithFlags(&tst, hipStreamNonBlocking));  // default priority
+    size_t pick = 0;
+    try {
+      pick = nk::fastest_plan(cands, tst);
+    } catch (...) {
+      (void)hipStreamDestroy(tst);
+      throw;
+    }
+    (void)hipStreamDestroy(tst);
+    gp = std::move(cands[pick]);
+  }
   std::vector<unsigned char> host;
   add_tables(gp, host);
   nk::DevBuf<unsigned char> tab(host.size());

@@ -835,8 +835,11 @@ class ProblemT final : public ProblemBase {
   // Captures one matvec on the capture stream; nothing runs until the graph is launched.
   // On small square grids the transport sweeps run in the persistent kernel (from the
   // recorded launch sequence and its argument table, kept in mv_tab while the graph lives).
+  // Where the persistent form applies, both forms are captured from the recorded sequence
+  // and timed (once per pointer pair; the values are the same), and the faster is kept.
   DevBuf<unsigned char> mv_tab;
   bool small_sweeps = false;
+  std::string sweep_timing;
   hipGraphExec_t capture_matvec(const void* vtin, void* out) {
     small_sweeps = false;
     if (small_config(cfg)) {
@@ -846,13 +849,20 @@ class ProblemT final : public ProblemBase {
       record_matvec(vtin, out, gp.recs[0], 8);
       gp.small_ops = small_prefix(gp.recs[0].recs);
       if (gp.small_ops) {
+        std::vector<GroupPlan> cands(2, gp);
+        cands[1].small_ops = 0;
+        NK_HIP(hipStreamSynchronize(user_s));   // the timing replays run on the capture stream
+        std::vector<float> ms;
+        const size_t pick = fastest_plan(cands, cap_s, &ms);
+        sweep_timing = "persistent " + std::to_string(1e3f * ms[0]) + " us, launches " + std::to_string(1e3f * ms[1]) +
+                       " us per matvec";
         std::vector<unsigned char> host;
-        add_tables(gp, host);
+        add_tables(cands[pick], host);
         NK_HIP(hipStreamSynchronize(s));   // an earlier graph may still read the old table
         mv_tab.alloc(host.size());
         NK_HIP(hipMemcpy(mv_tab.p, host.data(), host.size(), hipMemcpyHostToDevice));
-        small_sweeps = true;
-        return capture_group(gp, mv_tab.p, cap_s);
+        small_sweeps = cands[pick].small_ops > 0;
+        return capture_group(cands[pick], mv_tab.p, cap_s);
       }
     }
     hipGraph_t graph = nullptr;
@@ -956,7 +966,7 @@ class ProblemT final : public ProblemBase {
   }
   std::string describe() override {
     return std::string("{\"transport_precision\": ") + (kF64 ? "64" : "32") + ", \"graphs\": " +
-           (use_graphs ? "true" : "false") + ", \"persistent_sweeps\": " + (small_sweeps ? "true" : "false") +
+           (use_graphs ? "true" : "false") + ", \"persistent_sweeps\": " + (small_sweeps ? "true" : "false") + ", \"sweep_timing\": \"" + sweep_timing + "\"" +
            ", \"row_E\": " + std::to_string(kRowE) + ", \"col_E\": " +
            std::to_string(sp.colE) + ", \"col_deriv_symbols\": [" + col_symbols() + "], \"autotune\": \"" + tuning +
            "\"}";

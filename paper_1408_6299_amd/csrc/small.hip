@@ -8,7 +8,7 @@ namespace {
 template <typename R, int N, bool NC1>
 void launch_n(int items, const SmallOp* prog, int nops, const unsigned char* tab, const void* tw, int lmax,
               hipStream_t st) {
-  hipLaunchKernelGGL((k_small<R, N, N, NC1>), dim3(items), dim3(kSmallThreads), 0, st, prog, nops, tab,
+  hipLaunchKernelGGL((k_small<R, N, N, NC1>), dim3(items), dim3(SmallWaves<R>::NT), 0, st, prog, nops, tab,
                      (const cplx<R>*)tw, lmax);
 }
 

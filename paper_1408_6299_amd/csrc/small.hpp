@@ -26,8 +26,13 @@ struct SmallOp {
   long long cnt;   // FILL, CONV: elements
 };
 
-constexpr int kSmallWaves = 8;                  // wavefronts per workgroup
-constexpr int kSmallThreads = 64 * kSmallWaves;
+// Wavefronts per workgroup: eight in FP32; four in FP64, whose row stages need more than
+// the 256 registers per lane that eight wavefronts per CU leave (more would spill).
+template <typename R>
+struct SmallWaves {
+  static constexpr int W = sizeof(R) == 8 ? 4 : 8;
+  static constexpr int NT = 64 * W;
+};
 
 // Per-wavefront LDS scratch: the largest row-stage or column-pass need of the grid.
 template <typename R, int N1, int L>
@@ -44,22 +49,46 @@ template <typename R, int L, int KIND, bool NC1>
 __device__ __forceinline__ void small_rows(const SmallOp& op, const StageArgs<R>& a, const cplx<R>* tw, int lmax,
                                            cplx<R>* lds, int wave, int lane) {
   for (int fy = 0; fy < op.gy; ++fy)
-    for (int g = wave; g < op.gx; g += kSmallWaves)
+    for (int g = wave; g < op.gx; g += SmallWaves<R>::W)
       row_body_at<R, L, kRowE, KIND, 2, NC1>(a, tw, lmax, g, fy, lds, lane);
 }
 
+// Bytes of one launch's staged table entry (the largest is StageArgs<double>).
+constexpr int kSmallArgBytes = 1024;
+
 template <typename R, int N1, int L, bool NC1>
-__global__ __launch_bounds__(kSmallThreads) void k_small(const SmallOp* __restrict__ prog, int nops,
+__global__ __launch_bounds__(SmallWaves<R>::NT) void k_small(const SmallOp* __restrict__ prog, int nops,
                                                          const unsigned char* __restrict__ tab,
                                                          const cplx<R>* __restrict__ tw, int lmax) {
+  static_assert(sizeof(StageArgs<R>) <= kSmallArgBytes, "staged entry");
   using SS = SmallShape<R, N1, L>;
-  __shared__ cplx<R> lds[kSmallWaves * SS::SLOT];
+  constexpr int W = SmallWaves<R>::W, NT = SmallWaves<R>::NT;
+  __shared__ cplx<R> lds[W * SS::SLOT];
+  // The current launch's table entry and the next one's: the first wavefront copies the
+  // next entry while the current launch runs, so no launch waits for its arguments.
+  __shared__ __align__(16) unsigned long long args[2][kSmallArgBytes / 8];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   cplx<R>* my = lds + wave * SS::SLOT;
   const long long item = blockIdx.x;
+  auto entry_word = [&](const SmallOp& op, int w) -> unsigned long long {
+    const unsigned long long* e =
+        reinterpret_cast<const unsigned long long*>(tab + op.off + item * op.esize);
+    return w * 8 < op.esize ? e[w] : 0ull;
+  };
+  if (wave == 0) {
+    args[0][lane] = entry_word(prog[0], lane);
+    args[0][lane + 64] = entry_word(prog[0], lane + 64);
+  }
+  __syncthreads();
   for (int o = 0; o < nops; ++o) {
-    const SmallOp op = prog[o];
-    const unsigned char* e = tab + op.off + item * op.esize;
+    const SmallOp& op = prog[o];   // uniform: read in place by scalar loads
+    const bool more = o + 1 < nops;
+    unsigned long long w0 = 0, w1 = 0;
+    if (wave == 0 && more) {
+      w0 = entry_word(prog[o + 1], lane);
+      w1 = entry_word(prog[o + 1], lane + 64);
+    }
+    const unsigned char* e = reinterpret_cast<const unsigned char*>(args[o & 1]);
     if (op.kind == SOP_ROW) {
       const StageArgs<R>& a = *reinterpret_cast<const StageArgs<R>*>(e);
       switch (op.sub) {
@@ -73,15 +102,19 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(const SmallOp* __restri
       const ColPtrs<R> p = *reinterpret_cast<const ColPtrs<R>*>(e);
       for (int fz = 0; fz < op.gz; ++fz)
         for (int by = 0; by < op.gy; ++by)
-          for (int bx = wave; bx < op.gx; bx += kSmallWaves)
+          for (int bx = wave; bx < op.gx; bx += W)
             col_w_at<R, N1, 8, COL_DERIV>(p.in, p.add, p.out, op.ca, (R)op.scale, tw, op.twb, fz, bx, by, my, lane);
     } else if (op.kind == SOP_FILL) {
       R* y = *reinterpret_cast<R* const*>(e);
       const R v = (R)op.scale;
-      for (long long i = threadIdx.x; i < op.cnt; i += kSmallThreads) y[i] = v;
+      for (long long i = threadIdx.x; i < op.cnt; i += NT) y[i] = v;
     } else {
       const ConvPtrs<double, R> p = *reinterpret_cast<const ConvPtrs<double, R>*>(e);
-      for (long long i = threadIdx.x; i < op.cnt; i += kSmallThreads) p.y[i] = (R)p.x[i];
+      for (long long i = threadIdx.x; i < op.cnt; i += NT) p.y[i] = (R)p.x[i];
+    }
+    if (wave == 0 && more) {
+      args[(o + 1) & 1][lane] = w0;
+      args[(o + 1) & 1][lane + 64] = w1;
     }
     __syncthreads();
   }

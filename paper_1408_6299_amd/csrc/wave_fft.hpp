@@ -219,19 +219,39 @@ __device__ __forceinline__ void fft_gather(cplx<R> (&a)[E], int j, const cplx<R>
   for (int e = 0; e < E; ++e) a[e] = s[pad_e<E>(j + LS * e)];
 }
 
+// Exchange canary: the sequence's lanes overwrite its whole scratch with NaN. Issued
+// (and fenced) before a scatter, it checks that the gather after the scatter's fence
+// sees the scatter (a read served before the wavefront's earlier writes would return
+// NaN); issued after the gather's fence, it checks that no later write overtakes the
+// gather's reads. Each poison sits where the production code has a fence, so the
+// compiler cannot move it past the exchange it brackets.
+template <typename R, int M, int E>
+__device__ __forceinline__ void poison_scratch(int j, cplx<R>* s) {
+  constexpr int LS = WavePlan<M, E>::LS;
+  const R nan = __builtin_nan("");
+  for (int i = j; i < padded_e<E>(M); i += LS) s[i] = cplx<R>{nan, nan};
+}
+
 // BLOCK = true when a sequence spans several wavefronts of the workgroup
-// (M / E > 64 lanes): exchanges then synchronise the whole workgroup.
-template <typename R, int M, int E, bool INV, bool BLOCK = false>
+// (M / E > 64 lanes): exchanges then synchronise the whole workgroup. POISON runs the
+// exchange canary around every exchange (test builds only; same results when the
+// exchanges are ordered).
+template <typename R, int M, int E, bool INV, bool BLOCK = false, bool POISON = false>
 __device__ __forceinline__ void wave_fft(cplx<R> (&a)[E], int j, cplx<R>* s, const WaveTwiddles<R, M, E>& T) {
   using P = WavePlan<M, E>;
 #pragma unroll
   for (int p = 0; p < P::NP; ++p) {
     fft_pass<R, M, E, INV>(a, p, T);
     if (p != P::NP - 1) {
+      if (POISON) {
+        poison_scratch<R, M, E>(j, s);
+        wave_lds_sync();
+      }
       fft_scatter<R, M, E>(a, p, j, s);
       if (BLOCK) __syncthreads(); else wave_lds_sync();
       fft_gather<R, M, E>(a, j, s);
       if (BLOCK) __syncthreads(); else wave_lds_sync();
+      if (POISON) poison_scratch<R, M, E>(j, s);
     }
   }
 }
@@ -240,7 +260,7 @@ __device__ __forceinline__ void wave_fft(cplx<R> (&a)[E], int j, cplx<R>* s, con
 // transformed in lockstep: each pass runs on every sequence before the one
 // exchange wait, so the LDS round trips of the sequences overlap. Per sequence
 // the arithmetic is that of wave_fft.
-template <typename R, int M, int E, bool INV, int NK, int KA>
+template <typename R, int M, int E, bool INV, int NK, int KA, bool POISON = false>
 __device__ __forceinline__ void wave_fft_multi(cplx<R> (&a)[KA][E], int j, cplx<R>* s, int pitch,
                                                const WaveTwiddles<R, M, E>& T) {
   static_assert(NK >= 1 && NK <= KA, "sequence count");
@@ -251,12 +271,18 @@ __device__ __forceinline__ void wave_fft_multi(cplx<R> (&a)[KA][E], int j, cplx<
 #pragma unroll
     for (int k = 0; k < NK; ++k) fft_pass<R, M, E, INV>(a[k], p, T);
     if (p != P::NP - 1) {
+      if (POISON) {
+        for (int k = 0; k < NK; ++k) poison_scratch<R, M, E>(j, s + k * pitch);
+        wave_lds_sync();
+      }
 #pragma unroll
       for (int k = 0; k < NK; ++k) fft_scatter<R, M, E>(a[k], p, j, s + k * pitch);
       wave_lds_sync();
 #pragma unroll
       for (int k = 0; k < NK; ++k) fft_gather<R, M, E>(a[k], j, s + k * pitch);
       wave_lds_sync();
+      if (POISON)
+        for (int k = 0; k < NK; ++k) poison_scratch<R, M, E>(j, s + k * pitch);
     }
   }
 }

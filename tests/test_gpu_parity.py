@@ -366,6 +366,35 @@ def test_small_grid_batch_groups_run_persistent(nk, monkeypatch):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("prec", [32, 64])
+@pytest.mark.parametrize("m,elems,lockstep", [(32, 4, 1), (128, 4, 2), (256, 4, 1), (256, 4, 2), (64, 8, 1),
+                                              (256, 8, 1), (512, 8, 1)])
+def test_exchange_canary_poisoned_scratch_never_reaches_the_transform(nk, m, elems, lockstep, prec):
+    """The wavefront FFTs order their LDS exchanges by fences alone. With NaN written over
+    the scratch before every scatter and after every gather, the forward-inverse round trip
+    is NaN-free, equal to the unpoisoned run bit for bit, and m times the input."""
+    import ctypes
+    from paper_1408_6299_amd import _lib
+    lib = _lib.load()
+    count = 4099          # a ragged last wavefront
+    dt = torch.float32 if prec == 32 else torch.float64
+    x = torch.randn(count, m, 2, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(7))
+    x = x.to(dt).contiguous()
+    outs = []
+    for poison in (0, 1):
+        y = torch.full_like(x, float("nan"))
+        st = lib.nkreg_exchange_canary(prec, m, elems, lockstep, poison, ctypes.c_void_p(x.data_ptr()),
+                                       ctypes.c_void_p(y.data_ptr()), count,
+                                       ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        assert st == 0, lib.nkreg_last_error().decode()
+        torch.cuda.synchronize()
+        outs.append(y)
+    assert not torch.isnan(outs[1]).any()
+    assert torch.equal(outs[0], outs[1])
+    err = float(((outs[1].double() / m) - x.double()).abs().max())
+    assert err < (1e-13 if prec == 64 else 1e-5), err
+
+
 def test_handle_on_a_side_stream_matches_the_default_stream(nk):
     """A handle runs on the stream it was created with: work queued there (gradient,
     eager and replayed matvecs, PCG) gives the same bits as on the default stream."""
