@@ -26,7 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
-COUNTERS = os.path.join(ROOT, "profiles", "col_deriv_512sq_256cube_fp32_hbm_counters.md")
+COUNTERS = os.path.join(ROOT, "profiles", "col_deriv_512sq_256cube_fp32_fetch_write_counters.md")
 
 
 # The sources that define the kernels and their launch geometry; host-side sequencing
@@ -46,7 +46,8 @@ def source_digest() -> str:
 
 
 def measured_traffic(symbol: str):
-    """HBM bytes per launch of `symbol` from the committed counter summary, or None when the
+    """L2-to-fabric bytes (FETCH_SIZE + WRITE_SIZE, calibrated) per launch of `symbol` from the
+    committed counter summary, or None when the
     summary is missing, covers another kernel, or was taken on different sources."""
     try:
         text = open(COUNTERS).read()
@@ -225,7 +226,7 @@ def batch_section(nk, synth, torch, reps):
         for _ in range(2):
             B.hessian_matvec(ws, outs)
         torch.cuda.synchronize()
-        out["groups"] = [{"items": n, "tiled_columns": t} for n, t in B.group_plan()]
+        out["groups"] = [{"items": n, "form": f} for n, f in B.group_plan()]
         t0 = time.perf_counter()
         for _ in range(reps):
             B.hessian_matvec(ws, outs)
@@ -416,7 +417,8 @@ def analysis_section(nk, synth, torch, spec, mT_h, mR_h):
     t0 = time.perf_counter()
     H = G.hessian_matrix()
     torch.cuda.synchronize()
-    out["assemble_64sq"] = {"n": int(H.shape[0]), "seconds": time.perf_counter() - t0}
+    out["assemble_64sq"] = {"n": int(H.shape[0]), "seconds": time.perf_counter() - t0,
+                            "sweeps": G.describe().get("assembly_sweeps")}
     del H
     G.close()
     G = nk.Problem(spec.shape, spec.nt, 1, spec.reg, False, spec.beta, precision=32)
@@ -429,7 +431,7 @@ def analysis_section(nk, synth, torch, spec, mT_h, mR_h):
     out["lanczos_headline"] = {"steps": len(ritz), "seconds": secs, "ritz_min": ritz[0], "ritz_max": ritz[-1],
                                "condition_estimate": ritz[-1] / ritz[0] if ritz[0] > 0 else None}
     log(f"Hessian analysis: 64^2 assembly ({out['assemble_64sq']['n']} matvecs) "
-        f"{out['assemble_64sq']['seconds']:.2f} s; Lanczos(100) at 512^2 {secs:.2f} s, "
+        f"{out['assemble_64sq']['seconds']:.2f} s ({out['assemble_64sq']['sweeps']}); Lanczos(100) at 512^2 {secs:.2f} s, "
         f"Ritz values [{ritz[0]:.4g}, {ritz[-1]:.4g}]")
     G.close()
     return out
@@ -642,8 +644,11 @@ def batch_nteff_section(nk, synth, torch, reps=2):
     B.hessian_matvec(ws, outs)
     torch.cuda.synchronize()
     out["build_and_first_s"] = time.perf_counter() - t0
-    out["groups"] = len(B.groups())
-    log(f"batch at CFL steps: graph of {out['groups']} groups built and run in {out['build_and_first_s']:.1f} s")
+    plan = B.group_plan()
+    out["groups"] = len(plan)
+    out["group_forms"] = {f: sum(1 for _, g in plan if g == f) for f in nk.Batch.GROUP_FORMS}
+    log(f"batch at CFL steps: graph of {out['groups']} groups built and run in {out['build_and_first_s']:.1f} s; "
+        f"forms {out['group_forms']}")
     t0 = time.perf_counter()
     for _ in range(reps):
         B.hessian_matvec(ws, outs)

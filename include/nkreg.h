@@ -387,10 +387,12 @@ int nkreg_timer_read(nkreg_problem* p, int* launches, double* avg_ms, double* by
  * stream of the batch that waits for every item's stream, and every item's stream
  * waits for the batch. Where the LDS-tiled column pass applies, each group times it
  * against the per-column pass at the group's scale and keeps the faster (both give
- * the same values). nkreg_batch_groups reports the last built matvec graph: the
- * number of groups and, for up to cap groups, their sizes and whether they use the
- * tiled pass (sizes, tiled may be NULL). Errors: EINVAL, ESHAPE (a configuration),
- * ENOMEM, EHIP, ESTATE, ECFL, ENONFINITE. */
+ * the same values); groups of small square 2D grids time the persistent small-grid
+ * sweep kernel against the launches the same way. nkreg_batch_groups reports the
+ * last built matvec graph: the number of groups and, for up to cap groups, their
+ * sizes and forms (0 = per-column launches, 1 = tiled column launches, 2 = the
+ * persistent small-grid kernel; sizes, form may be NULL). Errors: EINVAL, ESHAPE (a
+ * configuration), ENOMEM, EHIP, ESTATE, ECFL, ENONFINITE. */
 typedef struct nkreg_batch nkreg_batch;
 int nkreg_batch_create(int count, const nkreg_config* cfgs, void* hip_stream, nkreg_batch** out);
 int nkreg_batch_wrap(int count, nkreg_problem* const* items, nkreg_batch** out);
@@ -399,7 +401,7 @@ int nkreg_batch_objective_gradient(nkreg_batch* b, const void* const* d_v, doubl
                                    double* h_J_reg, void* const* d_g);
 int nkreg_batch_set_state(nkreg_batch* b, const void* const* d_v);
 int nkreg_batch_hessian_matvec(nkreg_batch* b, const void* const* d_vt, void* const* d_Hvt);
-int nkreg_batch_groups(nkreg_batch* b, int* groups, int* sizes, int* tiled, int cap);
+int nkreg_batch_groups(nkreg_batch* b, int* groups, int* sizes, int* form, int cap);
 int nkreg_batch_destroy(nkreg_batch* b);
 
 #ifdef __cplusplus

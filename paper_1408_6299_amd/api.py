@@ -203,8 +203,8 @@ class Problem:
     def describe(self) -> dict:
         """Launch configuration of the handle (tile choices, autotuner timings)."""
         import json
-        buf = ctypes.create_string_buffer(1024)
-        check(self.lib.nkreg_describe(self._h, buf, 1024), "nkreg_describe")
+        buf = ctypes.create_string_buffer(8192)
+        check(self.lib.nkreg_describe(self._h, buf, 8192), "nkreg_describe")
         return json.loads(buf.value.decode())
 
     def use_graphs(self, enable: bool) -> None:
@@ -524,13 +524,17 @@ class Batch:
         """Sizes of the item groups that share launches in the last built batch graph."""
         return [n for n, _ in self.group_plan()]
 
-    def group_plan(self) -> List[Tuple[int, bool]]:
-        """(items, uses the tiled column pass) per group of the last built batch graph."""
+    GROUP_FORMS = ("columns", "tiled", "persistent")
+
+    def group_plan(self) -> List[Tuple[int, str]]:
+        """(items, form) per group of the last built batch graph; form is "columns"
+        (per-column launches), "tiled" (tiled column launches) or "persistent" (the
+        persistent small-grid sweep kernel)."""
         n = c_int()
         cap = max(1, len(self.problems))
-        sizes, tiled = (c_int * cap)(), (c_int * cap)()
-        check(self.lib.nkreg_batch_groups(self._h, byref(n), sizes, tiled, cap), "nkreg_batch_groups")
-        return [(sizes[i], bool(tiled[i])) for i in range(n.value)]
+        sizes, form = (c_int * cap)(), (c_int * cap)()
+        check(self.lib.nkreg_batch_groups(self._h, byref(n), sizes, form, cap), "nkreg_batch_groups")
+        return [(sizes[i], self.GROUP_FORMS[form[i]]) for i in range(n.value)]
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -3,7 +3,9 @@
 // for small grids, with the leading transport launches run by one persistent kernel.
 #pragma once
 
+#include <algorithm>
 #include <cstdlib>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -131,11 +133,149 @@ inline bool same_sequence(const std::vector<LaunchRec>& a, const std::vector<Lau
   return true;
 }
 
+// ---- items with different step counts in one group ----
+// Items whose operations differ only in their number of time steps record the same
+// launches outside the time loops and the same launches in each loop iteration they
+// share. Such items form one group: an item whose loop has ended rides along with
+// the others' remaining iterations as an inactive table entry, which the group
+// kernels skip. Every item still runs exactly its own launches, so its results are
+// those of its own operation. NKREG_RAGGED=0 keeps one group per step count.
+inline bool ragged_enabled() {
+  const char* e = std::getenv("NKREG_RAGGED");
+  return !(e && e[0] == '0');
+}
+
+// A recorded sequence cut at its time-loop marks: runs outside every loop (loop 0,
+// one range) and time loops (one range per iteration). Ranges are [first, last).
+struct SeqBlock {
+  int loop = 0;
+  std::vector<std::pair<size_t, size_t>> ranges;
+};
+// Returns false (and no blocks) when the marks do not describe whole loops in order,
+// as in a checkpointed sweep, whose segment recomputations nest inside the adjoint loop.
+inline bool cut_sequence(const Recorder& r, std::vector<SeqBlock>& out) {
+  out.clear();
+  struct Piece { size_t a, b; int loop, step; };
+  std::vector<Piece> pieces;
+  size_t pos = 0;
+  int loop = 0, step = 0;
+  for (const auto& m : r.marks) {
+    if (m.pos > pos) pieces.push_back({pos, m.pos, loop, step});
+    pos = m.pos > pos ? m.pos : pos;
+    loop = m.loop;
+    step = m.step;
+  }
+  if (r.recs.size() > pos) pieces.push_back({pos, r.recs.size(), loop, step});
+  for (const auto& p : pieces) {
+    if (p.loop == 0) {
+      if (!out.empty() && out.back().loop == 0) out.back().ranges.back().second = p.b;
+      else out.push_back({0, {{p.a, p.b}}});
+    } else if (!out.empty() && out.back().loop == p.loop && p.step == (int)out.back().ranges.size()) {
+      out.back().ranges.push_back({p.a, p.b});
+    } else if (p.step == 0) {
+      out.push_back({p.loop, {{p.a, p.b}}});
+    } else {
+      out.clear();
+      return false;
+    }
+  }
+  return true;
+}
+
+inline bool same_range(const std::vector<LaunchRec>& a, std::pair<size_t, size_t> ra, const std::vector<LaunchRec>& b,
+                       std::pair<size_t, size_t> rb, bool loop) {
+  if (ra.second - ra.first != rb.second - rb.first) return false;
+  for (size_t k = 0; k < ra.second - ra.first; ++k) {
+    const LaunchRec& x = a[ra.first + k];
+    if (!x.same_shape(b[rb.first + k])) return false;
+    if (loop && x.kind != LaunchRec::ROW && x.kind != LaunchRec::COL) return false;
+  }
+  return true;
+}
+
+// True if two recorded sequences differ at most in their time loops' iteration counts
+// (and then only in launches the group kernels can skip).
+inline bool ragged_compatible(const Recorder& a, const Recorder& b) {
+  std::vector<SeqBlock> ca, cb;
+  if (!cut_sequence(a, ca) || !cut_sequence(b, cb) || ca.size() != cb.size()) return false;
+  for (size_t i = 0; i < ca.size(); ++i) {
+    if (ca[i].loop != cb[i].loop) return false;
+    if (ca[i].loop == 0) {
+      if (!same_range(a.recs, ca[i].ranges[0], b.recs, cb[i].ranges[0], false)) return false;
+      continue;
+    }
+    const size_t n = std::min(ca[i].ranges.size(), cb[i].ranges.size());
+    for (size_t s = 0; s < n; ++s)
+      if (!same_range(a.recs, ca[i].ranges[s], b.recs, cb[i].ranges[s], true)) return false;
+  }
+  return true;
+}
+
+// A copy of a recorded row stage or column pass whose table entry is marked inactive.
+inline LaunchRec inactive_copy(const LaunchRec& r) {
+  LaunchRec c = r;
+  auto flag = [&](auto proto) {
+    using T = decltype(proto);
+    T v;
+    std::memcpy(&v, c.entry.data(), sizeof(T));
+    v.inactive = 1;
+    std::memcpy(c.entry.data(), &v, sizeof(T));
+  };
+  if (r.kind == LaunchRec::ROW) {
+    if (r.f64) flag(StageArgs<double>{}); else flag(StageArgs<float>{});
+  } else if (r.kind == LaunchRec::COL) {
+    if (r.f64) flag(ColPtrs<double>{}); else flag(ColPtrs<float>{});
+  } else {
+    throw HipError(NKREG_EHIP, "only row stages and column passes can be inactive");
+  }
+  return c;
+}
+
+// Equal-shaped sequences for items whose recordings are pairwise ragged-compatible:
+// each time loop runs as many iterations as its longest item, and every item that
+// has no iteration s gets inactive copies of the longest item's iteration s.
+inline std::vector<Recorder> pad_ragged(const std::vector<Recorder>& recs) {
+  std::vector<std::vector<SeqBlock>> cuts(recs.size());
+  for (size_t i = 0; i < recs.size(); ++i)
+    if (!cut_sequence(recs[i], cuts[i]) || cuts[i].size() != cuts[0].size())
+      throw HipError(NKREG_EHIP, "sequences without matching time loops");
+  const size_t nb = cuts[0].size();
+  std::vector<Recorder> out(recs.size());
+  for (size_t b = 0; b < nb; ++b) {
+    if (cuts[0][b].loop == 0) {
+      for (size_t i = 0; i < recs.size(); ++i) {
+        const auto rg = cuts[i][b].ranges[0];
+        out[i].recs.insert(out[i].recs.end(), recs[i].recs.begin() + rg.first, recs[i].recs.begin() + rg.second);
+      }
+      continue;
+    }
+    size_t ref = 0;
+    for (size_t i = 1; i < recs.size(); ++i)
+      if (cuts[i][b].ranges.size() > cuts[ref][b].ranges.size()) ref = i;
+    const size_t iters = cuts[ref][b].ranges.size();
+    for (size_t i = 0; i < recs.size(); ++i) {
+      for (size_t s = 0; s < iters; ++s) {
+        out[i].mark(cuts[0][b].loop, (int)s);
+        if (s < cuts[i][b].ranges.size()) {
+          const auto rg = cuts[i][b].ranges[s];
+          out[i].recs.insert(out[i].recs.end(), recs[i].recs.begin() + rg.first, recs[i].recs.begin() + rg.second);
+        } else {
+          const auto rg = cuts[ref][b].ranges[s];
+          for (size_t k = rg.first; k < rg.second; ++k) out[i].recs.push_back(inactive_copy(recs[ref].recs[k]));
+        }
+      }
+      out[i].mark(LOOP_NONE, 0);
+    }
+  }
+  return out;
+}
+
 // The recorded launches of one group of items and where their tables live.
 struct GroupPlan {
   std::vector<size_t> items;
   std::vector<Recorder> recs;  // one per item, equal-shaped
   std::vector<size_t> offs;        // per launch position: table offset
+  bool ragged = false;             // items with different step counts (padded sequences)
   size_t small_ops = 0;            // leading launches run by the persistent kernel (0: none)
   size_t prog_off = 0;             // table offset of its program
 };

@@ -95,7 +95,7 @@ struct StageArgs {
   R scale;                   // C2R output scale (ST_C2R, ST_GRAD, ST_DIV multiply by scale/L)
   int nc;
   int zero_state;            // INC1 at j = 0: the incremental state is zero
-  int write_real;            // unused (stage 2 always stores the new state as a real field)
+  int inactive;              // batch groups: this item has no work in this launch (its time loop has ended)
   int skip_out;              // ADJ2 at j = 0: no further spectra needed
   long long n;               // points per scalar field
   long long fstride_in;      // batch stride (elements) of inputs (ST_R2C: reals, else complex)

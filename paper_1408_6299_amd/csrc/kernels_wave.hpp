@@ -405,6 +405,7 @@ __global__ __launch_bounds__(64) void k_row_w(StageArgs<R> a, const cplx<R>* __r
 template <typename R, int L, int E, int KIND, int D, bool NC1>
 __global__ __launch_bounds__(64) void k_row_wt(const StageArgs<R>* __restrict__ tab, const cplx<R>* __restrict__ tw,
                                                int lmax) {
+  if (tab[blockIdx.z].inactive) return;
   row_body<R, L, E, KIND, D, NC1>(tab[blockIdx.z], tw, lmax);
 }
 
@@ -414,6 +415,7 @@ struct ColPtrs {
   const cplx<R>* in;
   const cplx<R>* add;
   cplx<R>* out;
+  int inactive;   // batch groups: this item has no work in this launch
 };
 
 template <int N, int E>
@@ -496,6 +498,7 @@ template <typename R, int N, int E, int MODE>
 __global__ __launch_bounds__((ColShape<N, E>::NT)) void k_col_wt(const ColPtrs<R>* __restrict__ tab, ColArgs a, R scale,
                                                                const cplx<R>* __restrict__ tw, int twb, int nfz) {
   const ColPtrs<R> p = tab[blockIdx.z / nfz];
+  if (p.inactive) return;
   col_w_body<R, N, E, MODE>(p.in, p.add, p.out, a, scale, tw, twb, (int)(blockIdx.z % nfz));
 }
 
@@ -598,6 +601,7 @@ __global__ __launch_bounds__((TileShape<R, N, CT>::NT)) void k_col_tt(const ColP
                                                                       R scale, const cplx<R>* __restrict__ tw, int twb,
                                                                       int nfz) {
   const ColPtrs<R> p = tab[blockIdx.z / nfz];
+  if (p.inactive) return;
   col_t_body<R, N, CT, MODE>(p.in, p.add, p.out, a, scale, tw, twb, (int)(blockIdx.z % nfz));
 }
 

@@ -17,10 +17,13 @@ struct nkreg_problem {
 // becomes one launch over all its items, whose per-item arguments come from a device
 // table. Groups are independent branches of the graph, each captured on a branch
 // stream of the batch.
+// Group form value of a group that runs its sweeps in the persistent small-grid kernel.
+constexpr int kFormPersistent = -2;
+
 struct BatchGraph {
   hipGraphExec_t exec = nullptr;
   void* tables = nullptr;  // device argument tables of the captured graph
-  std::vector<int> group_sizes, variants;  // per group: items, column pass (8 or 0 = tiled)
+  std::vector<int> group_sizes, variants;  // per group: items, column pass (8, 0 = tiled, or kFormPersistent)
   std::vector<const void*> key_in;
   std::vector<void*> key_out;
   std::vector<unsigned> key_gen;
@@ -388,6 +391,49 @@ using nk::issue_group;
 using nk::same_sequence;
 using nk::time_group;
 
+// Joins groups whose sequences differ only in their time loops' iteration counts
+// (items with different step counts and no checkpointing) into one group each; the
+// joined group's sequences are padded with inactive launches (group.hpp).
+std::vector<GroupPlan> merge_ragged(nkreg_batch* b, std::vector<GroupPlan> plans) {
+  auto eligible = [&](const GroupPlan& gp) { return b->items[gp.items[0]]->impl->cfg.checkpoint_every == 0; };
+  std::vector<std::vector<size_t>> clusters;
+  for (size_t i = 0; i < plans.size(); ++i) {
+    bool placed = false;
+    if (eligible(plans[i])) {
+      for (auto& c : clusters) {
+        bool ok = eligible(plans[c[0]]);
+        for (size_t k = 0; ok && k < c.size(); ++k) ok = nk::ragged_compatible(plans[c[k]].recs[0], plans[i].recs[0]);
+        if (ok) {
+          c.push_back(i);
+          placed = true;
+          break;
+        }
+      }
+    }
+    if (!placed) clusters.push_back({i});
+  }
+  std::vector<GroupPlan> out;
+  for (const auto& c : clusters) {
+    if (c.size() == 1) {
+      out.push_back(std::move(plans[c[0]]));
+      continue;
+    }
+    GroupPlan m;
+    m.ragged = true;
+    std::vector<nk::Recorder> all;
+    for (size_t i : c)
+      for (size_t k = 0; k < plans[i].items.size(); ++k) {
+        m.items.push_back(plans[i].items[k]);
+        all.push_back(std::move(plans[i].recs[k]));
+      }
+    m.recs = nk::pad_ragged(all);
+    for (const auto& r : m.recs)
+      if (!same_sequence(m.recs[0].recs, r.recs)) throw nk::HipError(NKREG_EHIP, "padded group sequences differ");
+    out.push_back(std::move(m));
+  }
+  return out;
+}
+
 // Records an item's launch sequence for one batched operation (column pass variant
 // cv >= 0 overrides the item's own choice).
 using RecordFn = void (*)(nk::ProblemBase*, const void*, void*, nk::Recorder&, int);
@@ -445,6 +491,19 @@ void run_batch(nkreg_batch* b, BatchGraph& bg, RecordFn record, const void* cons
           plans.back().recs.push_back(std::move(recs[i]));
         }
       }
+      if (nk::ragged_enabled()) plans = merge_ragged(b, std::move(plans));
+      // an item group's sequences recorded with column variant cv (padded to the
+      // group's longest loops for a group of several step counts)
+      auto record_plan = [&](const GroupPlan& gp, int cv) {
+        GroupPlan c;
+        c.items = gp.items;
+        c.ragged = gp.ragged;
+        c.recs.resize(gp.items.size());
+        for (size_t k = 0; k < gp.items.size(); ++k)
+          record(b->items[gp.items[k]]->impl, vt[gp.items[k]], out[gp.items[k]], c.recs[k], cv);
+        if (c.ragged) c.recs = nk::pad_ragged(c.recs);
+        return c;
+      };
       // Small square grids run their sweeps in the persistent kernel (recorded with the
       // 8-per-lane column pass it runs; the values are those of any column pass).
       // Otherwise a group's launches are G times larger than one item's: where the
@@ -455,11 +514,7 @@ void run_batch(nkreg_batch* b, BatchGraph& bg, RecordFn record, const void* cons
         nk::ProblemBase* first = b->items[gp.items[0]]->impl;
         int chosen = first->col_variant();
         if (nk::small_config(first->cfg)) {
-          GroupPlan c;
-          c.items = gp.items;
-          c.recs.resize(gp.items.size());
-          for (size_t k = 0; k < gp.items.size(); ++k)
-            record(b->items[gp.items[k]]->impl, vt[gp.items[k]], out[gp.items[k]], c.recs[k], 8);
+          GroupPlan c = record_plan(gp, 8);
           c.small_ops = nk::small_prefix(c.recs[0].recs);
           if (c.small_ops) {
             // the persistent form against plain launches, timed at the group's scale
@@ -467,7 +522,7 @@ void run_batch(nkreg_batch* b, BatchGraph& bg, RecordFn record, const void* cons
             cands[1].small_ops = 0;
             const size_t pick = nk::fastest_plan(cands, b->s);
             gp = std::move(cands[pick]);
-            bg.variants.push_back(8);
+            bg.variants.push_back(gp.small_ops ? kFormPersistent : 8);
             continue;
           }
         }
@@ -475,11 +530,7 @@ void run_batch(nkreg_batch* b, BatchGraph& bg, RecordFn record, const void* cons
           float best = 0.f;
           GroupPlan bestp;
           for (int cv : {8, 0}) {
-            GroupPlan c;
-            c.items = gp.items;
-            c.recs.resize(gp.items.size());
-            for (size_t k = 0; k < gp.items.size(); ++k)
-              record(b->items[gp.items[k]]->impl, vt[gp.items[k]], out[gp.items[k]], c.recs[k], cv);
+            GroupPlan c = record_plan(gp, cv);
             const float ms = time_group(c, b->s);
             if (cv == 8 || ms < best) { best = ms; bestp = std::move(c); chosen = cv; }
           }
@@ -594,14 +645,18 @@ void assemble_grouped(nk::ProblemBase* src, double* H) {
     hipStream_t tst = nullptr;
     NK_HIP(hipStreamCreateWithFlags(&tst, hipStreamNonBlocking));  // default priority
     size_t pick = 0;
+    std::vector<float> ms;
     try {
-      pick = nk::fastest_plan(cands, tst);
+      pick = nk::fastest_plan(cands, tst, &ms);
     } catch (...) {
       (void)hipStreamDestroy(tst);
       throw;
     }
     (void)hipStreamDestroy(tst);
     gp = std::move(cands[pick]);
+    src->assembly_timing = std::to_string(G) + " columns per replay: persistent " + std::to_string(1e3f * ms[0]) +
+                           " us, launches " + std::to_string(1e3f * ms[1]) + " us; chose " +
+                           (gp.small_ops ? "persistent" : "launches");
   }
   std::vector<unsigned char> host;
   add_tables(gp, host);
@@ -682,13 +737,13 @@ int nkreg_batch_set_state(nkreg_batch* b, const void* const* v) {
   return nkreg_batch_objective_gradient(b, v, nullptr, nullptr, nullptr, nullptr);
 }
 
-int nkreg_batch_groups(nkreg_batch* b, int* groups, int* sizes, int* tiled, int cap) {
+int nkreg_batch_groups(nkreg_batch* b, int* groups, int* sizes, int* form, int cap) {
   NEED(b); NEED(groups);
   const BatchGraph& bg = b->matvec;
   *groups = (int)bg.group_sizes.size();
   for (int i = 0; i < cap && i < (int)bg.group_sizes.size(); ++i) {
     if (sizes) sizes[i] = bg.group_sizes[i];
-    if (tiled) tiled[i] = bg.variants[i] == 0;
+    if (form) form[i] = bg.variants[i] == kFormPersistent ? 2 : bg.variants[i] == 0 ? 1 : 0;
   }
   return NKREG_OK;
 }

@@ -147,6 +147,7 @@ inline int launch_blocks(long long cnt) {
 class ProblemBase {
  public:
   nkreg_config cfg{};
+  std::string assembly_timing;  // the last grouped Hessian assembly's sweep-form timing
   virtual ~ProblemBase() = default;
   virtual void set_images(const void* mT, const void* mR) = 0;
   virtual void forward(const void* v, void* m1) = 0;
@@ -412,6 +413,11 @@ class ProblemT final : public ProblemBase {
   // Recording for batch groups: while rec is set, the matvec's launches are
   // recorded (here and in both spectral engines) instead of issued.
   Recorder* rec = nullptr;
+  // Marks the start of a time-loop iteration (loop: LOOP_*) or the end of a loop in
+  // the recording, so that items with different step counts can share launches.
+  void mark(int loop, int step) {
+    if (rec) rec->mark(loop, step);
+  }
   void record_matvec(const void* vt, void* out, Recorder& r, int col_variant) override {
     if (!state_valid) throw HipError(NKREG_ESTATE, "no gradient computed at the current velocity");
     const int keep = sp.colE, keep64 = sp64.colE;
@@ -569,6 +575,7 @@ class ProblemT final : public ProblemBase {
     const R h = R(1.0 / nt);
     sp.r2c(m_start, B.T, 1);
     for (int j = j0; j < j1; ++j) {
+      mark(LOOP_STATE, j - j0);
       sp.deriv_cols(B.T, B.S1, B.S2);
       StageArgs<R> a{};
       a.spec = B.T; a.s1 = B.S1; a.s2 = B.S2; a.out0 = B.Ts;
@@ -587,6 +594,7 @@ class ProblemT final : public ProblemBase {
       sp.template row<ST_FWD2>(b, 1);
       if (store_ckpt && (j + 1) % K == 0 && j + 1 < nt) copy(ckpt.p + (size_t)((j + 1) / K) * n, m_state, n * sizeof(R));
     }
+    mark(LOOP_NONE, 0);
   }
 
   // Forward solve from m_T; m1out receives m_1. With record, the trajectory is
@@ -646,6 +654,7 @@ class ProblemT final : public ProblemBase {
     basis(1.0, a.bv);
     sp.template row<KI>(a, 1);
     for (int j = nt - 1; j >= 0; --j) {
+      mark(LOOP_ADJOINT, nt - 1 - j);
       if (K && (j == nt - 1 || (j + 1) % K == 0)) load_segment(vl, j / K);
       sp.div_cols(U0, U1, U2, S2.p, Dsp.p);
       StageArgs<R> b{};
@@ -669,6 +678,7 @@ class ProblemT final : public ProblemBase {
       c.out0 = U0; c.out1 = U1; c.out2 = U2;
       sp.template row<K2>(c, 1);
     }
+    mark(LOOP_NONE, 0);
   }
 
   // ---- incremental state (GN), m~(0) = 0; writes m~_1 to mt1 ----
@@ -679,6 +689,7 @@ class ProblemT final : public ProblemBase {
   void incremental_sweep(const R* vl, const R* vtl) {
     const R h = R(1.0 / nt);
     for (int j = 0; j < nt; ++j) {
+      mark(LOOP_INCREMENTAL, j);
       if (K && j % K == 0) load_segment(vl, j / K);
       if (j > 0) sp.deriv_cols(T.p, S1.p, S2.p);
       StageArgs<R> a{};
@@ -700,6 +711,7 @@ class ProblemT final : public ProblemBase {
       b.out_real = mt1.p;  // m~^{j+1}; m~_1 after the last step
       sp.template row<ST_INC2>(b, 1);
     }
+    mark(LOOP_NONE, 0);
   }
 
   // h_t max over i of (sum_l max|v_l^i|) / h_x^i; bounds the CFL number since
@@ -966,7 +978,7 @@ class ProblemT final : public ProblemBase {
   }
   std::string describe() override {
     return std::string("{\"transport_precision\": ") + (kF64 ? "64" : "32") + ", \"graphs\": " +
-           (use_graphs ? "true" : "false") + ", \"persistent_sweeps\": " + (small_sweeps ? "true" : "false") + ", \"sweep_timing\": \"" + sweep_timing + "\"" +
+           (use_graphs ? "true" : "false") + ", \"persistent_sweeps\": " + (small_sweeps ? "true" : "false") + ", \"sweep_timing\": \"" + sweep_timing + "\", \"assembly_sweeps\": \"" + assembly_timing + "\"" +
            ", \"row_E\": " + std::to_string(kRowE) + ", \"col_E\": " +
            std::to_string(sp.colE) + ", \"col_deriv_symbols\": [" + col_symbols() + "], \"autotune\": \"" + tuning +
            "\"}";

@@ -91,7 +91,7 @@ __global__ __launch_bounds__(SmallWaves<R>::NT) void k_small(const SmallOp* __re
     const unsigned char* e = reinterpret_cast<const unsigned char*>(args[o & 1]);
     if (op.kind == SOP_ROW) {
       const StageArgs<R>& a = *reinterpret_cast<const StageArgs<R>*>(e);
-      switch (op.sub) {
+      if (!a.inactive) switch (op.sub) {
         case ST_INC1: small_rows<R, L, ST_INC1, NC1>(op, a, tw, lmax, my, wave, lane); break;
         case ST_INC2: small_rows<R, L, ST_INC2, NC1>(op, a, tw, lmax, my, wave, lane); break;
         case ST_ADJINIT: small_rows<R, L, ST_ADJINIT, NC1>(op, a, tw, lmax, my, wave, lane); break;
@@ -100,6 +100,7 @@ __global__ __launch_bounds__(SmallWaves<R>::NT) void k_small(const SmallOp* __re
       }
     } else if (op.kind == SOP_COL) {
       const ColPtrs<R> p = *reinterpret_cast<const ColPtrs<R>*>(e);
+      if (!p.inactive)
       for (int fz = 0; fz < op.gz; ++fz)
         for (int by = 0; by < op.gy; ++by)
           for (int bx = wave; bx < op.gx; bx += W)

@@ -155,8 +155,19 @@ struct LaunchRec {
            dim == o.dim && elems == o.elems && conv == o.conv && nc1 == o.nc1;
   }
 };
+// Time loops of a recorded operation (Recorder::mark).
+enum TimeLoop { LOOP_NONE = 0, LOOP_STATE = 1, LOOP_INCREMENTAL = 2, LOOP_ADJOINT = 3 };
+
 struct Recorder {
   std::vector<LaunchRec> recs;
+  // Time-loop marks: the records from position pos on belong to iteration `step` of
+  // time loop `loop` (0: outside every time loop), until the next mark.
+  struct Mark {
+    size_t pos;
+    int loop, step;
+  };
+  std::vector<Mark> marks;
+  void mark(int loop, int step) { marks.push_back({recs.size(), loop, step}); }
 };
 
 // Algorithmic bytes (fields read plus fields written) of every launch while set.
@@ -412,7 +423,7 @@ class Spectral {
     r.f64 = sizeof(R) == 8;
     r.tw = tw;
     r.iarg = twb;
-    r.set_entry(ColPtrs<R>{in, add, out});
+    r.set_entry(ColPtrs<R>{in, add, out, 0});
     rec->recs.push_back(r);
   }
   template <int N>

@@ -26,7 +26,7 @@ def _counters_current():
 
 
 def test_counter_summary_covers_both_roofline_kernels_at_the_current_sources():
-    """The committed HBM counters cover the column pass that the roofline reports for each
+    """The committed FETCH_SIZE / WRITE_SIZE counters cover the column pass that the roofline reports for each
     workload (when they were taken on the kernel sources in the tree; otherwise bench.py
     reports null traffic, which the gate test covers)."""
     if not _counters_current():
@@ -50,7 +50,7 @@ def test_counter_traffic_matches_the_algorithmic_bytes():
     """No wasted re-reads. The adjoint stage 1 with the body force reads the divergence
     spectrum, lambda, grad m^j and grad m*_j (2d fields), v (nc d) and F (nc d), and writes
     the accumulator, d spectra and F (nc d): 3 + 3d + 3 nc d fields, i.e. 21 in 3D and 15 in
-    2D at nc = 1. Its measured HBM bytes per launch lie within 2% of that."""
+    2D at nc = 1. Its measured L2-to-fabric bytes per launch lie within 2% of that."""
     if not _counters_current():
         pytest.skip("counters were taken on other kernel sources")
     for sym, fields, field_bytes in (("k_row_w<float, 256, 4, 5, 3, true>", 21, 256 ** 3 * 4),

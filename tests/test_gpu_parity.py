@@ -203,8 +203,8 @@ def test_call_order_and_cfl_errors(nk):
 
 
 # (shape, nt, precision, beta, seed, checkpoint): items 0-2 share a group (beta and data
-# differ per item), 3-4 another, 5 differs only in nt, 6-7 are 3D Stokes with
-# checkpointing, 8 is FP64.
+# differ per item), 3-4 another, 5 differs only in nt (it joins items 0-2 with inactive
+# entries for the steps it does not take), 6-7 are 3D Stokes with checkpointing, 8 is FP64.
 BATCH_ITEMS = [((32, 32), 6, 32, 1e-2, 1, 0), ((32, 32), 6, 32, 1e-3, 2, 0), ((32, 32), 6, 32, 3e-2, 3, 0),
                ((64, 32), 8, 32, 1e-2, 4, 0), ((64, 32), 8, 32, 1e-2, 5, 0), ((32, 32), 4, 32, 1e-2, 6, 0),
                ((16, 8, 16), 6, 32, 1e-3, 7, 4), ((16, 8, 16), 6, 32, 1e-3, 8, 4), ((32, 32), 6, 64, 1e-2, 9, 0)]
@@ -231,11 +231,12 @@ def test_batch_matches_single_items(nk):
         B.hessian_matvec(ws, outs)
         for o, r in zip(outs, refs):
             assert np.array_equal(host(o), r)
-    # five groups; the 64 x 32 pair may take the tiled column pass (timed at group scale),
+    # four groups; the 64 x 32 pair may take the tiled column pass (timed at group scale),
     # the others have no axis it applies to
     plan = B.group_plan()
-    assert sorted(n for n, _ in plan) == [1, 1, 2, 2, 3]
-    assert sum(t for _, t in plan) <= 1
+    assert sorted(n for n, _ in plan) == [1, 2, 2, 4]
+    assert sum(f == "tiled" for _, f in plan) <= 1
+    assert all(f in nk.Batch.GROUP_FORMS for _, f in plan)
     # a beta change invalidates the graph; the rebuilt batch uses the new beta for that item
     probs[1].beta = 5e-3
     ref1 = host(probs[1].hessian_matvec(ws[1]))
@@ -334,6 +335,55 @@ def test_small_grid_persistent_sweeps_equal_the_launch_path(nk, monkeypatch, sha
         assert rel_inf(outs[0][0], ref) < 1e-10
     else:
         assert rel_l2(outs[0][0], ref) < 1e-5
+
+
+@pytest.mark.parametrize("small", ["0", "1"])
+def test_batch_items_with_different_step_counts_share_launches(nk, monkeypatch, small):
+    """Items that differ only in nt form one group: each time loop runs as many iterations
+    as its longest item, and the others' entries are inactive for the iterations they do
+    not take. The batched gradient, the state it leaves and the batched matvec equal every
+    item's own calls bit for bit, with the groups joined and with one group per step count
+    (NKREG_RAGGED=0); 32^2 items also through the persistent small-grid kernel
+    (NKREG_SMALL=1). Checkpointed items keep groups of their own."""
+    monkeypatch.setenv("NKREG_SMALL", small)
+    items = [((64, 32), 4, 32, 1e-2, 1, 0), ((64, 32), 8, 32, 1e-3, 2, 0), ((64, 32), 12, 32, 1e-2, 3, 0),
+             ((32, 32), 6, 32, 1e-2, 4, 0), ((32, 32), 10, 32, 3e-2, 5, 0), ((64, 32), 8, 32, 1e-2, 6, 4),
+             ((32, 32), 6, 64, 1e-2, 7, 0), ((32, 32), 4, 64, 1e-3, 8, 0)]
+    cfgs, data = [], []
+    for shape, nt, prec, beta, seed, ck in items:
+        mT, mR, vstar, w = smooth_inputs(shape, nt, seed=seed)
+        cfgs.append(dict(shape=shape, nt=nt, reg=1, beta=beta, precision=prec, checkpoint_every=ck))
+        data.append((mT, mR, vstar, w, prec))
+    singles = []
+    for c, (mT, mR, vstar, w, prec) in zip(cfgs, data):
+        G = nk.Problem(**c)
+        G.set_images(dev_t(mT, prec), dev_t(mR, prec))
+        singles.append(G)
+    vs = [dev_v(0.5 * d[2]) for d in data]
+    ws = [dev_v(d[3]) for d in data]
+    ref_g, ref_h = [], []
+    for G, v, w in zip(singles, vs, ws):
+        J, Jd, Jr, g = G.objective_gradient(v)
+        ref_g.append((J, Jd, Jr, host(g)))
+        ref_h.append(host(G.hessian_matvec(w)))
+    for ragged, sizes in (("1", [1, 2, 2, 3]), ("0", [1, 1, 1, 1, 1, 1, 1, 1])):
+        monkeypatch.setenv("NKREG_RAGGED", ragged)
+        B = nk.Batch.create(cfgs)
+        for item, (mT, mR, vstar, w, prec) in zip(B.items, data):
+            item.set_images(dev_t(mT, prec), dev_t(mR, prec))
+        J, Jd, Jr, gs = B.objective_gradient(vs)
+        for i in range(len(items)):
+            assert (J[i], Jd[i], Jr[i]) == ref_g[i][:3], (ragged, i)
+            assert np.array_equal(host(gs[i]), ref_g[i][3]), (ragged, i)
+        B.set_state(vs)
+        for _ in range(2):
+            outs = B.hessian_matvec(ws)
+            for i in range(len(items)):
+                assert np.array_equal(host(outs[i]), ref_h[i]), (ragged, i)
+        assert sorted(n for n, _ in B.group_plan()) == sizes, B.group_plan()
+        B.close()
+    for G in singles:
+        G.close()
 
 
 def test_small_grid_batch_groups_run_persistent(nk, monkeypatch):
