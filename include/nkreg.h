@@ -97,7 +97,19 @@ typedef struct {
   int verbose;          /* 1: print one line per outer iteration to stderr */
   double gref_inf;      /* > 0: ||g_0||_inf of the relative gradient rule (continuation passes the
                            first level's value); <= 0: the gradient at the solve's starting point */
+  double* h_history;    /* optional host array of history_cap rows of NKREG_HISTORY_COLS doubles, one
+                           row per iterate v_k from k = 0: k, J, J_dist, ||g_k||_inf, PCG iterations
+                           of the step that produced v_k, its step length alpha, the CFL number of
+                           v_k, min and max of det F_1 at v_k (NaN unless history_detf). Rows past
+                           history_cap are dropped. nkreg_continuation appends every level's rows;
+                           nkreg_beta_search ignores it. NULL: no history */
+  int history_cap;
+  int history_detf;     /* 1: also solve for det F_1 at every iterate (one FP64 deformation-gradient
+                           solve per row, e:def-grad as nkreg_det_grad_y); with verbose, the line
+                           printed per iteration carries the CFL number and, with this, det F_1 */
 } nkreg_solve_opts;
+
+#define NKREG_HISTORY_COLS 9
 
 /* What the outer iteration did (quantities of interest, Table t:quantities-of-interest). */
 typedef struct {
@@ -113,6 +125,7 @@ typedef struct {
   int stop_reason;      /* 1 relative gradient rule, 2 (C1 and C2 and C3), 3 C4, 4 iteration limit
                            (relative rule: max_outer iterations; C1-C5 rule: C5, k > max_outer),
                            5 line search failed, 6 objective stagnation (Picard) */
+  int history_rows;     /* rows this solve wrote to opts.h_history */
 } nkreg_solve_report;
 
 /* Library version string, e.g. "nkreg 1.0 gfx950". */

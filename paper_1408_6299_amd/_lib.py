@@ -19,16 +19,20 @@ class Config(Structure):
                 ("trajectory_slots", c_int)]
 
 
+HISTORY_COLS = 9     # NKREG_HISTORY_COLS
+
+
 class SolveOpts(Structure):
     _fields_ = [("max_outer", c_int), ("gtol", c_double), ("tau_J", c_double), ("pcg_maxit", c_int),
-                ("cfl_guard", c_int), ("verbose", c_int), ("gref_inf", c_double)]
+                ("cfl_guard", c_int), ("verbose", c_int), ("gref_inf", c_double),
+                ("h_history", POINTER(c_double)), ("history_cap", c_int), ("history_detf", c_int)]
 
 
 class SolveReport(Structure):
     _fields_ = [("iterations", c_int), ("cg_iterations", c_int), ("n_pde", c_int),
                 ("line_search_failed", c_int), ("converged", c_int), ("J0", c_double), ("J", c_double),
                 ("J_dist", c_double), ("J_reg", c_double), ("gnorm0_inf", c_double),
-                ("gnorm_inf", c_double), ("seconds", c_double), ("stop_reason", c_int)]
+                ("gnorm_inf", c_double), ("seconds", c_double), ("stop_reason", c_int), ("history_rows", c_int)]
 
 
 class PicardOpts(Structure):

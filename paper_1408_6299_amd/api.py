@@ -39,7 +39,13 @@ class SolveResult:
     seconds: float
     status: int
     stop_reason: str = ""
+    # one row per iterate v_k (k = 0, 1, ...): k, J, J_dist, |g_k|_inf, PCG iterations, alpha,
+    # CFL number, min det F_1, max det F_1 (NaN unless det F was asked for), as a float64 host
+    # tensor; None unless asked for
+    history: Optional[torch.Tensor] = None
 
+
+HISTORY_COLUMNS = ("k", "J", "J_dist", "gnorm_inf", "cg_iterations", "alpha", "cfl", "detF_min", "detF_max")
 
 STOP_REASONS = {1: "relative gradient", 2: "C1-C3", 3: "C4", 4: "iteration limit", 5: "line search failed",
                 6: "objective stagnation"}
@@ -304,35 +310,54 @@ class Problem:
 
     def newton_solve(self, v: Optional[torch.Tensor] = None, gtol: float = 1e-3, max_outer: int = 50,
                      tau_J: float = 1e-3, pcg_maxit: int = 0, cfl_guard: bool = False,
-                     verbose: bool = False, gref_inf: float = 0.0) -> Tuple[torch.Tensor, SolveResult]:
+                     verbose: bool = False, gref_inf: float = 0.0, history: bool = False,
+                     history_detf: bool = False) -> Tuple[torch.Tensor, SolveResult]:
         """Gauss-Newton-Krylov solve from v (zero if None); returns (v, report).
 
         ``gref_inf`` > 0 replaces ||g_0||_inf in the relative gradient rule (used by
         beta continuation to measure every level against the first level's gradient).
+        ``history`` returns one row per iterate (HISTORY_COLUMNS) in the report;
+        ``history_detf`` adds det F_1's extremes at every iterate (one FP64 solve each).
         """
         v = self.zeros_v() if v is None else v.clone()
         self._check(v, self.vshape, "v")
-        o = self._solve_opts(gtol, max_outer, tau_J, pcg_maxit, cfl_guard, verbose, gref_inf)
+        o = self._solve_opts(gtol, max_outer, tau_J, pcg_maxit, cfl_guard, verbose, gref_inf,
+                             history_rows=max_outer + 2 if history else 0, history_detf=history_detf)
         rep = SolveReport()
         st = self.lib.nkreg_newton_solve(self._h, _ptr(v), byref(o), byref(rep))
         if st not in (_lib.OK, _lib.ENOCONV):
             check(st, "nkreg_newton_solve")
-        return v, self._result(rep, st)
+        return v, self._result(rep, st, o)
 
     @staticmethod
     def _solve_opts(gtol=1e-3, max_outer=50, tau_J=1e-3, pcg_maxit=0, cfl_guard=False, verbose=False,
-                    gref_inf=0.0) -> SolveOpts:
+                    gref_inf=0.0, history_rows=0, history_detf=False) -> SolveOpts:
         o = SolveOpts()
         o.max_outer, o.gtol, o.tau_J = int(max_outer), float(gtol), float(tau_J)
         o.pcg_maxit, o.cfl_guard, o.verbose = int(pcg_maxit), int(cfl_guard), int(verbose)
         o.gref_inf = float(gref_inf)
+        o.history_detf = int(history_detf)
+        if history_rows > 0:
+            buf = (c_double * (history_rows * _lib.HISTORY_COLS))()
+            o.h_history = ctypes.cast(buf, ctypes.POINTER(c_double))
+            o.history_cap = int(history_rows)
+            o._history_buf = buf          # keeps the array alive with the options
         return o
 
     @staticmethod
-    def _result(rep: SolveReport, st: int) -> "SolveResult":
+    def _history(o: SolveOpts, first: int, rows: int) -> Optional[torch.Tensor]:
+        buf = getattr(o, "_history_buf", None)
+        if buf is None:
+            return None
+        c = _lib.HISTORY_COLS
+        return torch.tensor(buf[first * c:(first + rows) * c], dtype=torch.float64).view(rows, c)
+
+    @staticmethod
+    def _result(rep: SolveReport, st: int, o: Optional[SolveOpts] = None, first: int = 0) -> "SolveResult":
+        hist = None if o is None else Problem._history(o, first, rep.history_rows)
         return SolveResult(rep.iterations, rep.cg_iterations, rep.n_pde, bool(rep.line_search_failed),
                            bool(rep.converged), rep.J0, rep.J, rep.J_dist, rep.J_reg, rep.gnorm0_inf,
-                           rep.gnorm_inf, rep.seconds, st, STOP_REASONS.get(rep.stop_reason, ""))
+                           rep.gnorm_inf, rep.seconds, st, STOP_REASONS.get(rep.stop_reason, ""), hist)
 
     def picard_solve(self, v: Optional[torch.Tensor] = None, gtol: float = 1e-3, max_outer: int = 500,
                      memory: bool = True, stagnation: Tuple[int, float] = (10, 1e-6), **kw
@@ -342,14 +367,15 @@ class Problem:
         count <= 0 disables the objective-stagnation stop."""
         v = self.zeros_v() if v is None else v.clone()
         self._check(v, self.vshape, "v")
-        o = self._solve_opts(gtol=gtol, max_outer=max_outer, **kw)
+        history = kw.pop("history", False)
+        o = self._solve_opts(gtol=gtol, max_outer=max_outer, history_rows=max_outer + 2 if history else 0, **kw)
         po = _lib.PicardOpts()
         po.memory, po.stagnation_count, po.stagnation_tol = int(memory), int(stagnation[0]), float(stagnation[1])
         rep = SolveReport()
         st = self.lib.nkreg_picard_solve(self._h, _ptr(v), byref(o), byref(po), byref(rep))
         if st not in (_lib.OK, _lib.ENOCONV):
             check(st, "nkreg_picard_solve")
-        return v, self._result(rep, st)
+        return v, self._result(rep, st, o)
 
     def continuation(self, betas: Sequence[float], v: Optional[torch.Tensor] = None, gtol: float = 1e-3,
                      max_outer: int = 50, **kw) -> Tuple[torch.Tensor, list]:
@@ -361,13 +387,19 @@ class Problem:
         n = len(betas)
         bs = (c_double * max(1, n))(*[float(b) for b in betas])
         reps = (SolveReport * max(1, n))()
-        o = self._solve_opts(gtol=gtol, max_outer=max_outer, **kw)
+        history = kw.pop("history", False)
+        o = self._solve_opts(gtol=gtol, max_outer=max_outer,
+                             history_rows=n * (max_outer + 2) if history else 0, **kw)
         st = self.lib.nkreg_continuation(self._h, _ptr(v), bs, n, byref(o), reps)
         if st not in (_lib.OK, _lib.ENOCONV):
             check(st, "nkreg_continuation")
         if n:
             self._beta = float(betas[-1])
-        return v, [self._result(reps[i], st) for i in range(n)]
+        out, first = [], 0
+        for i in range(n):
+            out.append(self._result(reps[i], st, o, first))
+            first += reps[i].history_rows
+        return v, out
 
     def beta_search(self, eps_F: float, v: Optional[torch.Tensor] = None, beta_start: float = 1.0,
                     beta_min: float = 1e-6, dbeta_rel: float = 0.05, l2_rel_min: float = 1e-2,

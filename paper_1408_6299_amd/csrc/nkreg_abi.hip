@@ -5,6 +5,7 @@
 #include <string>
 
 #include "group.hpp"
+#include "trace.hpp"
 #include "problem.hpp"
 
 struct nkreg_problem {
@@ -199,28 +200,48 @@ int nkreg_set_images(nkreg_problem* p, const void* mT, const void* mR) {
 
 int nkreg_forward(nkreg_problem* p, const void* v, void* m1) {
   NEED(p); NEED(v);
-  return guarded([&]() { p->impl->forward(v, m1); return (int)NKREG_OK; });
+  return guarded([&]() {
+    const nk::Range range("nkreg_forward");
+    p->impl->forward(v, m1);
+    return (int)NKREG_OK;
+  });
 }
 
 int nkreg_objective(nkreg_problem* p, const void* v, double* J, double* Jd, double* Jr) {
   NEED(p); NEED(v);
-  return guarded([&]() { p->impl->objective(v, J, Jd, Jr); return (int)NKREG_OK; });
+  return guarded([&]() {
+    const nk::Range range("nkreg_objective");
+    p->impl->objective(v, J, Jd, Jr);
+    return (int)NKREG_OK;
+  });
 }
 
 int nkreg_objective_gradient(nkreg_problem* p, const void* v, double* J, double* Jd, double* Jr, void* g) {
   NEED(p); NEED(v);
-  return guarded([&]() { p->impl->objective_gradient(v, J, Jd, Jr, g); return (int)NKREG_OK; });
+  return guarded([&]() {
+    const nk::Range range("nkreg_objective_gradient");
+    p->impl->objective_gradient(v, J, Jd, Jr, g);
+    return (int)NKREG_OK;
+  });
 }
 
 int nkreg_hessian_matvec(nkreg_problem* p, const void* vt, void* out) {
   NEED(p); NEED(vt); NEED(out);
   if (vt == out) return fail(NKREG_EINVAL, "input and output may not alias");
-  return guarded([&]() { p->impl->hessian_matvec(vt, out); return (int)NKREG_OK; });
+  return guarded([&]() {
+    const nk::Range range("nkreg_hessian_matvec");
+    p->impl->hessian_matvec(vt, out);
+    return (int)NKREG_OK;
+  });
 }
 
 int nkreg_precond_apply(nkreg_problem* p, const void* r, void* z) {
   NEED(p); NEED(r); NEED(z);
-  return guarded([&]() { p->impl->precond(r, z); return (int)NKREG_OK; });
+  return guarded([&]() {
+    const nk::Range range("nkreg_precond_apply");
+    p->impl->precond(r, z);
+    return (int)NKREG_OK;
+  });
 }
 
 int nkreg_project(nkreg_problem* p, const void* f, void* out) {
@@ -231,28 +252,44 @@ int nkreg_project(nkreg_problem* p, const void* f, void* out) {
 int nkreg_pcg(nkreg_problem* p, const void* rhs, void* s, double rtol, int maxit, int* iters, double* relres) {
   NEED(p); NEED(rhs); NEED(s);
   if (!(rtol >= 0.0)) return fail(NKREG_EINVAL, "rtol must be >= 0");
-  return guarded([&]() { return p->impl->pcg(rhs, s, rtol, maxit, iters, relres); });
+  return guarded([&]() {
+    const nk::Range range("nkreg_pcg");
+    return p->impl->pcg(rhs, s, rtol, maxit, iters, relres);
+  });
 }
 
 int nkreg_det_grad_y(nkreg_problem* p, const void* v, void* detF, double* stats) {
   NEED(p); NEED(v);
-  return guarded([&]() { p->impl->det_grad_y(v, detF, stats); return (int)NKREG_OK; });
+  return guarded([&]() {
+    const nk::Range range("nkreg_det_grad_y");
+    p->impl->det_grad_y(v, detF, stats);
+    return (int)NKREG_OK;
+  });
 }
 
 int nkreg_newton_solve(nkreg_problem* p, void* v, const nkreg_solve_opts* opts, nkreg_solve_report* rep) {
   NEED(p); NEED(v);
-  return guarded([&]() { return p->impl->newton(v, opts, rep); });
+  return guarded([&]() {
+    const nk::Range range("nkreg_newton_solve");
+    return p->impl->newton(v, opts, rep);
+  });
 }
 
 int nkreg_picard_solve(nkreg_problem* p, void* v, const nkreg_solve_opts* opts, const nkreg_picard_opts* popts,
                        nkreg_solve_report* rep) {
   NEED(p); NEED(v);
-  return guarded([&]() { return p->impl->picard(v, opts, popts, rep); });
+  return guarded([&]() {
+    const nk::Range range("nkreg_picard_solve");
+    return p->impl->picard(v, opts, popts, rep);
+  });
 }
 
 int nkreg_hessian_lanczos(nkreg_problem* p, int steps, double* ritz, int* count) {
   NEED(p); NEED(ritz);
-  return guarded([&]() { return p->impl->lanczos(steps, ritz, count); });
+  return guarded([&]() {
+    const nk::Range range("nkreg_hessian_lanczos");
+    return p->impl->lanczos(steps, ritz, count);
+  });
 }
 
 int nkreg_set_hessian(nkreg_problem* p, int mode) {
@@ -264,12 +301,18 @@ int nkreg_continuation(nkreg_problem* p, void* v, const double* betas, int level
                        nkreg_solve_report* reports) {
   NEED(p); NEED(v);
   if (levels < 0 || (levels > 0 && !betas)) return fail(NKREG_EINVAL, "bad beta levels");
-  return guarded([&]() { return p->impl->continuation(v, betas, levels, opts, reports); });
+  return guarded([&]() {
+    const nk::Range range("nkreg_continuation");
+    return p->impl->continuation(v, betas, levels, opts, reports);
+  });
 }
 
 int nkreg_beta_search(nkreg_problem* p, void* v, const nkreg_beta_search_opts* opts, nkreg_beta_search_report* rep) {
   NEED(p); NEED(v); NEED(opts);
-  return guarded([&]() { return p->impl->beta_search(v, opts, rep); });
+  return guarded([&]() {
+    const nk::Range range("nkreg_beta_search");
+    return p->impl->beta_search(v, opts, rep);
+  });
 }
 
 int nkreg_gradient(nkreg_problem* p, const void* u, void* g) {
@@ -699,7 +742,10 @@ extern "C" {
 
 int nkreg_hessian_assemble(nkreg_problem* p, void* H) {
   NEED(p); NEED(H);
-  return guarded([&]() { assemble_grouped(p->impl, (double*)H); return (int)NKREG_OK; });
+  return guarded([&]() {
+    const nk::Range range("nkreg_hessian_assemble");
+    assemble_grouped(p->impl, (double*)H); return (int)NKREG_OK;
+  });
 }
 
 int nkreg_batch_hessian_matvec(nkreg_batch* b, const void* const* vt, void* const* out) {
@@ -708,6 +754,7 @@ int nkreg_batch_hessian_matvec(nkreg_batch* b, const void* const* vt, void* cons
   for (size_t i = 0; i < b->items.size(); ++i)
     if (!vt[i] || !out[i] || vt[i] == out[i]) return fail(NKREG_EINVAL, "batch matvec: null or aliased item vectors");
   return guarded([&]() {
+    const nk::Range range("nkreg_batch_hessian_matvec");
     run_batch(b, b->matvec, record_matvec_fn, vt, out);
     return (int)NKREG_OK;
   });
@@ -720,6 +767,7 @@ int nkreg_batch_objective_gradient(nkreg_batch* b, const void* const* v, double*
   for (size_t i = 0; i < b->items.size(); ++i)
     if (!v[i]) return fail(NKREG_EINVAL, "batch gradient: null velocity");
   return guarded([&]() {
+    const nk::Range range("nkreg_batch_objective_gradient");
     const size_t cnt = b->items.size();
     for (size_t i = 0; i < cnt; ++i) b->items[i]->impl->check_cfl(v[i]);
     std::vector<void*> gout(cnt, nullptr);

@@ -16,6 +16,7 @@
 
 #include "../../include/nkreg.h"
 #include "group.hpp"
+#include "trace.hpp"
 #include "kernels_analysis.hpp"
 #include "spectral.hpp"
 
@@ -603,6 +604,7 @@ class ProblemT final : public ProblemBase {
   // restarts from its checkpoint exactly as a recomputation does, so the
   // buffer holds the same values either way.
   void forward_sweep(const R* vl, bool record, R* m1out) {
+    const Range range("state sweep");
     if (!K) {
       state_steps(vl, 0, nt, mT.p, m1out, main_bufs(), record, false);
     } else if (!record) {
@@ -637,6 +639,7 @@ class ProblemT final : public ProblemBase {
   template <bool NEWT>
   void adjoint_sweep_k(const R* vl, const R* vtl, R ca, const R* src_a, R cb, const R* src_b, R* Fout,
                        bool record_lam) {
+    const Range range("adjoint sweep");
     constexpr int KI = NEWT ? ST_NADJINIT : ST_ADJINIT;
     constexpr int K1 = NEWT ? ST_NADJ1 : ST_ADJ1;
     constexpr int K2 = NEWT ? ST_NADJ2 : ST_ADJ2;
@@ -687,6 +690,7 @@ class ProblemT final : public ProblemBase {
   // are not recomputed; nothing else writes the trajectory buffer while the
   // gradient state is valid.
   void incremental_sweep(const R* vl, const R* vtl) {
+    const Range range("incremental state sweep");
     const R h = R(1.0 / nt);
     for (int j = 0; j < nt; ++j) {
       mark(LOOP_INCREMENTAL, j);
@@ -903,13 +907,14 @@ class ProblemT final : public ProblemBase {
   // passes over zeroed spectra is captured on the capture stream and replayed
   // under HIP events; the fastest is kept and shared by every handle of the same
   // grid and precision in the process. NKREG_COL_E in the environment fixes the
-  // choice (8, 4 or tiled; 4 elements per lane rounds differently).
+  // choice (8, 4 or tiled; 4 elements per lane rounds differently), for every grid
+  // or per grid (col_env_variant).
   static constexpr int kTuneReps = 16;
   static std::string col_variant_name(int ce) { return ce == 0 ? "col=tiled" : "col_E=" + std::to_string(ce); }
   std::string tuning;
   std::array<int, 4> tune_key() const { return {g.n[0], g.n[1], g.n[2], kF64 ? 64 : 32}; }
   void tune_columns() {
-    if (std::getenv("NKREG_COL_E")) {
+    if (col_env_variant(g) >= 0) {
       tuning = col_variant_name(sp.colE) + " (fixed)";
       return;
     }
@@ -1058,6 +1063,7 @@ class ProblemT final : public ProblemBase {
     // One host read per iteration: the step length is formed on the device from
     // p.Hp and r.z, and p.Hp is checked when the new residual is read.
     while (!ok && it < maxit) {
+      const Range iter("pcg iteration", it);
       hessian_matvec(kp.p, kq.p);
       red.enqueue<double>(RED_DOT, kp.p, kq.p, nv, 2);
       hipLaunchKernelGGL(k_pcg_step, dim3(launch_blocks(nv)), dim3(256), 0, s, nv, (const double*)red.result.p + 1,
@@ -1112,6 +1118,32 @@ class ProblemT final : public ProblemBase {
     }
   }
 
+  // One row of the per-iterate history (nkreg_solve_opts::h_history) and, with verbose,
+  // one line on stderr: k, J, J_dist, ||g||_inf, PCG iterations, alpha, the CFL number of
+  // v_k and, when asked for, det F_1's extremes at v_k (an extra FP64 solve, which uses
+  // buffers of its own and leaves the cached state alone).
+  void log_iterate(const nkreg_solve_opts& opt, int& rows, const char* tag, int k, const double* vk, double J,
+                   double Jd, double ginf, double rel, int its, double alpha) {
+    if (!opt.verbose && !(opt.h_history && rows < opt.history_cap)) return;
+    const double cfl = cfl_number(vk);
+    double st[4] = {NAN, NAN, NAN, NAN};
+    if (opt.history_detf) det_grad_y(vk, nullptr, st);
+    if (opt.h_history && rows < opt.history_cap) {
+      double* row = opt.h_history + (size_t)rows * NKREG_HISTORY_COLS;
+      const double vals[NKREG_HISTORY_COLS] = {(double)k, J, Jd, ginf, (double)its, alpha, cfl, st[0], st[1]};
+      std::copy(vals, vals + NKREG_HISTORY_COLS, row);
+      ++rows;
+    }
+    if (opt.verbose) {
+      if (opt.history_detf)
+        fprintf(stderr, "[nkreg] %s k=%d J=%.6e Jd=%.6e |g|inf=%.3e rel=%.3e cg=%d alpha=%g cfl=%.3f detF=[%.4f, %.4f]\n",
+                tag, k, J, Jd, ginf, rel, its, alpha, cfl, st[0], st[1]);
+      else
+        fprintf(stderr, "[nkreg] %s k=%d J=%.6e Jd=%.6e |g|inf=%.3e rel=%.3e cg=%d alpha=%g cfl=%.3f\n", tag, k, J,
+                Jd, ginf, rel, its, alpha, cfl);
+    }
+  }
+
   // ---- globalised Picard iteration (preconditioned gradient descent, e:picard) ----
   // s_k = -alpha~ P^-1 g_k (the Picard iterate minus v_k), Armijo from alpha = 1;
   // alpha~ shrinks by alpha after backtracking and doubles after alpha = 1.
@@ -1137,10 +1169,12 @@ class ProblemT final : public ProblemBase {
     double at = 1.0;
     int flat = 0, k = 0;
     bool conv = false;
+    log_iterate(opt, r.history_rows, "picard", 0, vk, J, Jd, ginf, ginf / g0inf, 0, 0.0);
     while (true) {
       if (ginf <= opt.gtol * g0inf || g0inf == 0.0) { conv = true; r.stop_reason = 1; break; }
       if (pop.stagnation_count > 0 && flat >= pop.stagnation_count) { conv = true; r.stop_reason = 6; break; }
       if (k >= opt.max_outer) { r.stop_reason = 4; break; }
+      const Range outer("picard iteration", k);
       precond(gbuf.p, sbuf.p);
       axpby(nv, 0.0, sbuf.p, pop.memory ? -at : -1.0, sbuf.p);
       if (cfg.incompressible) project(sbuf.p, sbuf.p);
@@ -1155,9 +1189,7 @@ class ProblemT final : public ProblemBase {
       flat = std::fabs(Jprev - J) <= pop.stagnation_tol * (1.0 + r.J0) ? flat + 1 : 0;
       ginf = red.one<double>(RED_MAXABS, gbuf.p, nullptr, nv);
       ++k;
-      if (opt.verbose)
-        fprintf(stderr, "[nkreg] picard k=%d J=%.6e |g|inf=%.3e rel=%.3e alpha=%g scale=%g\n", k, J, ginf,
-                ginf / g0inf, alpha, at);
+      log_iterate(opt, r.history_rows, "picard", k, vk, J, Jd, ginf, ginf / g0inf, 0, alpha);
     }
     NK_HIP(hipStreamSynchronize(s));
     r.iterations = k;
@@ -1190,6 +1222,7 @@ class ProblemT final : public ProblemBase {
     double Jprev = J;
     int k = 0;
     bool conv = false;
+    log_iterate(opt, r.history_rows, "newton", 0, vk, J, Jd, ginf, ginf / g0inf, 0, 0.0);
     const double eps = 2.220446049250313e-16;  // FP64 machine precision in C4 for both transports
     while (true) {
       if (opt.gtol > 0) {
@@ -1213,6 +1246,7 @@ class ProblemT final : public ProblemBase {
         if (c123 || c4) { conv = true; r.stop_reason = c123 ? 2 : 3; break; }
         if (c5) { r.stop_reason = 4; break; }
       }
+      const Range outer("newton outer iteration", k);
       const double eta = std::min(0.5, std::sqrt(gtwo / g0two));
       lincomb(nv, -1.0, gbuf.p, 0.0, gbuf.p, rhsbuf.p);
       int its = 0;
@@ -1232,9 +1266,7 @@ class ProblemT final : public ProblemBase {
       ginf = red.one<double>(RED_MAXABS, gbuf.p, nullptr, nv);
       gtwo = std::sqrt(red.one<double>(RED_SUMSQ, gbuf.p, nullptr, nv));
       ++k;
-      if (opt.verbose)
-        fprintf(stderr, "[nkreg] k=%d J=%.6e Jd=%.6e |g|inf=%.3e rel=%.3e cg=%d alpha=%g\n", k, J, Jd, ginf,
-                ginf / g0inf, its, alpha);
+      log_iterate(opt, r.history_rows, "newton", k, vk, J, Jd, ginf, ginf / g0inf, its, alpha);
     }
     NK_HIP(hipStreamSynchronize(s));
     r.iterations = k;
@@ -1364,6 +1396,10 @@ class ProblemT final : public ProblemBase {
       so.gref_inf = gref;
       nkreg_solve_report r{};
       if (newton(vio, &so, &r) != NKREG_OK) status = NKREG_ENOCONV;
+      if (so.h_history) {  // the next level appends its rows
+        so.h_history += (size_t)r.history_rows * NKREG_HISTORY_COLS;
+        so.history_cap -= r.history_rows;
+      }
       if (gref <= 0) gref = r.gnorm0_inf;
       if (reps) reps[i] = r;
     }
@@ -1399,6 +1435,7 @@ class ProblemT final : public ProblemBase {
       set_beta(beta);
       copy(v, have_ok ? vok.p : vstart.p, nv * sizeof(double));
       nkreg_solve_opts so = o.solve;
+      so.h_history = nullptr;  // the search reports its trials instead
       so.gref_inf = gref;
       nkreg_solve_report nr{};
       newton(v, &so, &nr);

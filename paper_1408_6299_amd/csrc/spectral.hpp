@@ -48,6 +48,29 @@ struct Grid {
   double hd = 0.0;       // cell volume prod(2 pi / N_i)
 };
 
+// The column-pass variant NKREG_COL_E fixes for a grid: "8", "4" or "tiled" for every
+// grid, or comma-separated grid=variant entries ("512x512=8,256x256x256=tiled") for
+// the grids they name. -1 when nothing fixes it (the autotuner chooses).
+inline int col_env_variant(const Grid& g) {
+  const char* ce = std::getenv("NKREG_COL_E");
+  if (!ce || !*ce) return -1;
+  auto parse = [](const std::string& v) { return (v == "tiled" || v == "0") ? 0 : (v == "4" ? 4 : 8); };
+  const std::string s(ce);
+  if (s.find('=') == std::string::npos) return parse(s);
+  std::string key = std::to_string(g.n[0]) + "x" + std::to_string(g.n[1]);
+  if (g.d == 3) key += "x" + std::to_string(g.n[2]);
+  size_t p = 0;
+  while (p < s.size()) {
+    size_t q = s.find(',', p);
+    if (q == std::string::npos) q = s.size();
+    const std::string e = s.substr(p, q - p);
+    const size_t eq = e.find('=');
+    if (eq != std::string::npos && e.substr(0, eq) == key) return parse(e.substr(eq + 1));
+    p = q + 1;
+  }
+  return -1;
+}
+
 inline Grid make_grid(int d, const int* n) {
   Grid g;
   g.d = d;
@@ -230,10 +253,8 @@ class Spectral {
     if (tw && owns_tw) (void)hipFree(tw);
   }
   void read_col_env() {
-    if (const char* ce = std::getenv("NKREG_COL_E")) {
-      const int v = std::atoi(ce);
-      colE = (std::string(ce) == "tiled" || v == 0) ? 0 : (v == 4 ? 4 : 8);
-    }
+    const int v = col_env_variant(g);
+    if (v >= 0) colE = v;
   }
   bool owns_tw = false;
 

@@ -445,6 +445,29 @@ def test_exchange_canary_poisoned_scratch_never_reaches_the_transform(nk, m, ele
     assert err < (1e-13 if prec == 64 else 1e-5), err
 
 
+def test_column_variant_pinned_per_grid(nk, monkeypatch):
+    """NKREG_COL_E as grid=variant entries fixes the column pass of the grids it names and
+    leaves the others to the autotuner; both variants give the same matvec bits."""
+    shape, nt = (64, 64), 4
+    mT, mR, vstar, w = smooth_inputs(shape, nt)
+    outs = []
+    for pin in ("64x64=tiled,32x32=8", "64x64=8"):
+        monkeypatch.setenv("NKREG_COL_E", pin)
+        G = nk.Problem(shape, nt, reg=1, beta=1e-2, precision=32)
+        G.set_images(dev_t(mT, 32), dev_t(mR, 32))
+        G.objective_gradient(dev_v(0.5 * vstar))
+        outs.append(host(G.hessian_matvec(dev_v(w))))
+        d = G.describe()
+        assert d["col_E"] == (0 if "64x64=tiled" in pin else 8), d
+        assert "fixed" in d["autotune"], d
+        G.close()
+    assert np.array_equal(outs[0], outs[1])
+    monkeypatch.setenv("NKREG_COL_E", "128x128=tiled")
+    G = nk.Problem((64, 32), nt, reg=1, beta=1e-2, precision=32)
+    assert "fixed" not in G.describe()["autotune"]
+    G.close()
+
+
 def test_handle_on_a_side_stream_matches_the_default_stream(nk):
     """A handle runs on the stream it was created with: work queued there (gradient,
     eager and replayed matvecs, PCG) gives the same bits as on the default stream."""
@@ -517,6 +540,39 @@ def test_newton_solve_matches_oracle(nk, prec):
     else:
         assert abs(rep.iterations - rep_ref.iterations) <= 1
         assert rel_l2(host(v), v_ref) < 1e-3
+
+
+def test_newton_history_matches_oracle_iterates(nk):
+    """The per-iterate history of an FP64 solve (nkreg_solve_opts::h_history): J, ||g||_inf,
+    PCG iterations and step lengths equal the oracle's at every iterate; the last row's CFL
+    number and det F_1 extremes equal the oracle's at the final iterate; continuation
+    appends each level's rows; the history changes no result."""
+    shape, nt, reg, beta = (32, 32), 8, 2, 1e-2
+    P, G, _, _ = make_pair(nk, shape, nt, 1, reg, 0, beta, 64)
+    v_ref, rep_ref, _ = okr.gauss_newton(P, gtol=1e-3, max_outer=20)
+    v0, rep0 = G.newton_solve(gtol=1e-3, max_outer=20)
+    v, rep = G.newton_solve(gtol=1e-3, max_outer=20, history=True, history_detf=True)
+    assert np.array_equal(host(v), host(v0)) and rep.iterations == rep0.iterations
+    H = rep.history.numpy()
+    assert H.shape == (rep.iterations + 1, 9)
+    assert np.array_equal(H[:, 0], np.arange(rep.iterations + 1))
+    assert rep.iterations == rep_ref.iterations
+    np.testing.assert_allclose(H[:, 1], rep_ref.J, rtol=1e-9)
+    np.testing.assert_allclose(H[:, 3], rep_ref.gnorm_inf, rtol=1e-8)
+    assert list(H[1:, 4].astype(int)) == list(rep_ref.cg_iterations)
+    np.testing.assert_allclose(H[1:, 5], rep_ref.alphas, rtol=0, atol=0)
+    assert H[-1, 1] == rep.J and H[-1, 3] == rep.gnorm_inf
+    # the final iterates agree to 1e-8 relative; CFL and det F_1 are Lipschitz in v
+    assert abs(H[-1, 6] - okr.cfl_number(v_ref, nt)) <= 1e-7 * okr.cfl_number(v_ref, nt)
+    _, st_ref = odg.det_stats(v_ref, nt)
+    assert abs(H[-1, 7] - st_ref[0]) <= 1e-7 and abs(H[-1, 8] - st_ref[1]) <= 1e-7
+    assert H[0, 6] == 0.0 and abs(H[0, 7] - 1.0) < 1e-12 and abs(H[0, 8] - 1.0) < 1e-12
+    _, rep_nd = G.newton_solve(gtol=1e-3, max_outer=20, history=True)
+    assert np.isnan(rep_nd.history.numpy()[:, 7:]).all()
+    v2, reps = G.continuation([1e-1, 1e-2], gtol=1e-3, max_outer=20, history=True)
+    for r in reps:
+        assert tuple(r.history.shape) == (r.iterations + 1, 9) and float(r.history[-1, 1]) == r.J
+    G.close()
 
 
 @pytest.mark.parametrize("prec", [64])
