@@ -76,6 +76,12 @@ bool dispatch(int m, int e, int nk, bool poison, const void* in, void* out, int 
     if (m == 32) { run<R, 32, 4, 2>(poison, in, out, count, st); return true; }
     if (m == 128) { run<R, 128, 4, 2>(poison, in, out, count, st); return true; }
     if (m == 256) { run<R, 256, 4, 2>(poison, in, out, count, st); return true; }
+  } else if (e == 2 && nk == 1) {
+    if (m == 64) { run<R, 64, 2, 1>(poison, in, out, count, st); return true; }
+    if (m == 128) { run<R, 128, 2, 1>(poison, in, out, count, st); return true; }
+  } else if (e == 2 && nk == 2) {
+    if (m == 64) { run<R, 64, 2, 2>(poison, in, out, count, st); return true; }
+    if (m == 128) { run<R, 128, 2, 2>(poison, in, out, count, st); return true; }
   } else if (e == 8 && nk == 1) {
     if (m == 64) { run<R, 64, 8, 1>(poison, in, out, count, st); return true; }
     if (m == 256) { run<R, 256, 8, 1>(poison, in, out, count, st); return true; }

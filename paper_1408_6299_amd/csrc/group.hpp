@@ -216,6 +216,7 @@ inline LaunchRec inactive_copy(const LaunchRec& r) {
   LaunchRec c = r;
   auto flag = [&](auto proto) {
     using T = decltype(proto);
+    if (c.entry.size() != sizeof(T)) throw HipError(NKREG_EHIP, "unexpected table entry size");
     T v;
     std::memcpy(&v, c.entry.data(), sizeof(T));
     v.inactive = 1;

@@ -37,7 +37,7 @@ struct SmallWaves {
 // Per-wavefront LDS scratch: the largest row-stage or column-pass need of the grid.
 template <typename R, int N1, int L>
 struct SmallShape {
-  static constexpr int E = kRowE;
+  static constexpr int E = row_e<L>();
   static constexpr int ROW = RowLds<R, L, E, ST_ADJ1, 2>::SIZE > RowLds<R, L, E, ST_INC1, 2>::SIZE
                                  ? RowLds<R, L, E, ST_ADJ1, 2>::SIZE
                                  : RowLds<R, L, E, ST_INC1, 2>::SIZE;
@@ -50,7 +50,7 @@ __device__ __forceinline__ void small_rows(const SmallOp& op, const StageArgs<R>
                                            cplx<R>* lds, int wave, int lane) {
   for (int fy = 0; fy < op.gy; ++fy)
     for (int g = wave; g < op.gx; g += SmallWaves<R>::W)
-      row_body_at<R, L, kRowE, KIND, 2, NC1>(a, tw, lmax, g, fy, lds, lane);
+      row_body_at<R, L, row_e<L>(), KIND, 2, NC1>(a, tw, lmax, g, fy, lds, lane);
 }
 
 // Bytes of one launch's staged table entry (the largest is StageArgs<double>).

@@ -91,6 +91,18 @@ inline Grid make_grid(int d, const int* n) {
 
 // Complex elements per lane of the row-stage and column transforms.
 constexpr int kRowE = 4;
+// Complex elements per lane of an L-point real row transform (L / 2 complex points):
+// kRowE, except 2 on 128- and 256-point rows. With 2, one wavefront holds one 256-point
+// row (one 128-point row per half-wavefront) instead of two, which doubles the
+// wavefronts in flight where rows are few (a 256 x 256 grid has 256 rows for 256 CUs)
+// and shortens each wavefront's chain of loads and butterflies; the extra radix-2
+// exchange passes cost less than that. row_e4 is the layout with kRowE everywhere.
+constexpr int row_e4_n(int L) { return (L / 2 >= kRowE) ? kRowE : (L / 2 >= 4 ? 4 : 2); }
+constexpr int row_e_n(int L) { return (L == 128 || L == 256) ? 2 : row_e4_n(L); }
+template <int L>
+constexpr int row_e4() { return row_e4_n(L); }
+template <int L>
+constexpr int row_e() { return row_e_n(L); }
 
 // Kernel identifiers for launch timing: row-stage kinds are 0..10 (StageKind),
 // column passes are 20 + ColMode.
@@ -239,6 +251,7 @@ class Spectral {
   Spectral() = default;
   Spectral(const Grid& grid, hipStream_t stream) : g(grid), s(stream) {
     read_col_env();
+    read_row_env();
     std::vector<cplx<R>> h(g.lmax);
     twiddles(g.lmax, h.data());
     NK_HIP(hipMalloc(&tw, sizeof(cplx<R>) * g.lmax));
@@ -246,7 +259,17 @@ class Spectral {
     NK_HIP(hipMemcpy(tw, h.data(), sizeof(cplx<R>) * g.lmax, hipMemcpyHostToDevice));
   }
   // Launchers over a twiddle table the caller provides (and keeps filled); allocates nothing.
-  Spectral(const Grid& grid, hipStream_t stream, cplx<R>* table) : g(grid), s(stream), tw(table) { read_col_env(); }
+  Spectral(const Grid& grid, hipStream_t stream, cplx<R>* table) : g(grid), s(stream), tw(table) {
+    read_col_env();
+    read_row_env();
+  }
+  // Complex elements per lane of this grid's row transforms (row_e); NKREG_ROW_E=4 keeps
+  // four on every row length (the layout before 2 became the default on 128 and 256 points).
+  int rowE = 0;
+  void read_row_env() {
+    const char* e = std::getenv("NKREG_ROW_E");
+    rowE = (e && e[0] == '4') ? row_e4_n(g.L) : row_e_n(g.L);
+  }
   Spectral(const Spectral&) = delete;
   Spectral& operator=(const Spectral&) = delete;
   ~Spectral() {
@@ -546,7 +569,19 @@ class Spectral {
 
   template <int KIND, int D, int L>
   void row_l(StageArgs<R>& a, int nf) {
-    constexpr int E = (L / 2 >= kRowE) ? kRowE : (L / 2 >= 4 ? 4 : 2);
+    constexpr int E = row_e<L>();
+    constexpr int E4 = row_e4<L>();
+    if constexpr (E != E4) {
+      if (rowE == E4) {
+        row_le<KIND, D, L, E4>(a, nf);
+        return;
+      }
+    }
+    row_le<KIND, D, L, E>(a, nf);
+  }
+
+  template <int KIND, int D, int L, int E>
+  void row_le(StageArgs<R>& a, int nf) {
     constexpr int SPW = 64 / WavePlan<L / 2, E>::LS;
     dim3 grid((unsigned)((g.rows + SPW - 1) / SPW), (unsigned)nf);
     constexpr int BK = base_kind(KIND);

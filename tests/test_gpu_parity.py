@@ -417,8 +417,9 @@ def test_small_grid_batch_groups_run_persistent(nk, monkeypatch):
 
 
 @pytest.mark.parametrize("prec", [32, 64])
-@pytest.mark.parametrize("m,elems,lockstep", [(32, 4, 1), (128, 4, 2), (256, 4, 1), (256, 4, 2), (64, 8, 1),
-                                              (256, 8, 1), (512, 8, 1)])
+@pytest.mark.parametrize("m,elems,lockstep", [(32, 4, 1), (128, 4, 2), (256, 4, 1), (256, 4, 2), (64, 2, 1),
+                                              (64, 2, 2), (128, 2, 1), (128, 2, 2), (64, 8, 1), (256, 8, 1),
+                                              (512, 8, 1)])
 def test_exchange_canary_poisoned_scratch_never_reaches_the_transform(nk, m, elems, lockstep, prec):
     """The wavefront FFTs order their LDS exchanges by fences alone. With NaN written over
     the scratch before every scatter and after every gather, the forward-inverse round trip
