@@ -53,7 +53,7 @@ def test_counter_traffic_matches_the_algorithmic_bytes():
     2D at nc = 1. Its measured L2-to-fabric bytes per launch lie within 2% of that."""
     if not _counters_current():
         pytest.skip("counters were taken on other kernel sources")
-    for sym, fields, field_bytes in (("k_row_w<float, 256, 4, 5, 3, true>", 21, 256 ** 3 * 4),
+    for sym, fields, field_bytes in (("k_row_w<float, 256, 2, 5, 3, true>", 21, 256 ** 3 * 4),
                                      ("k_row_w<float, 512, 4, 5, 2, true>", 15, 512 ** 2 * 4)):
         t = bench.measured_traffic(sym)
         alg = fields * field_bytes
