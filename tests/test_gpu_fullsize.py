@@ -382,6 +382,46 @@ def test_c3_batch_subset(nk):
         assert rel_l2(refs[k], ord_.hessian_matvec(P, S0, w)) < 1e-5, sp.shape
 
 
+def test_c3_cfl_step_items_share_launches_and_match_the_oracle(nk):
+    """Items of the CFL-step batch (each with the steps its own CFL bound needs): 64^2 and
+    128^2 items of two step counts each join one group per grid size, equal their own
+    matvecs bit for bit at v = 0.5 v*, and one item of every (grid, nt) pair matches the
+    oracle there (FP32-rounded inputs, the FP32 bound)."""
+    specs = synth.batch_specs_nteff()
+    picks = {}
+    for i, sp in enumerate(specs):
+        key = (sp.shape[0], sp.nt)
+        if sp.shape[0] in (64, 128) and key not in picks and sum(k[0] == sp.shape[0] for k in picks) < 2:
+            picks[key] = i
+    assert sorted({k[0] for k in picks}) == [64, 128] and len(picks) == 4, picks
+    probs, ws, vs, refs, data = [], [], [], [], []
+    for (n, nt), i in sorted(picks.items()):
+        sp = specs[i]
+        mT, vstar = synth.make_inputs(sp)
+        mR = otr.forward_only(mT, vstar, sp.nt)
+        G = nk.Problem(sp.shape, sp.nt, 1, sp.reg, False, sp.beta, precision=32)
+        G.set_images(dev_t(mT, 32), dev_t(mR, 32))
+        v = 0.5 * vstar
+        G.objective_gradient(dev_v(v))
+        w = synth.bandlimited_velocity(sp.shape, 500 + i, 6, 0.05)
+        probs.append(G)
+        ws.append(dev_v(w))
+        refs.append(host(G.hessian_matvec(ws[-1])))
+        data.append((mT, mR, v, w, sp))
+    B = nk.Batch(probs)
+    for _ in range(2):
+        outs = B.hessian_matvec(ws)
+        for o, r in zip(outs, refs):
+            assert np.array_equal(host(o), r)
+    assert sorted(n for n, _ in B.group_plan()) == [2, 2], B.group_plan()
+    B.close()
+    for (mT, mR, v, w, sp), ref, G in zip(data, refs, probs):
+        P = ord_.Problem(f32(mT), f32(mR), sp.nt, 1, sp.reg, 0, sp.beta)
+        S = ord_.objective_gradient(P, v)
+        assert rel_l2(ref, ord_.hessian_matvec(P, S, f32(w).astype(np.float64))) < 1e-5, (sp.shape, sp.nt)
+        G.close()
+
+
 def test_c3_512_batch_item_away_from_zero(nk):
     """The first 512^2 item of the 64-pair batch (FP32, H1, nt = 16): gradient and GN
     matvec at v = 0.5 v* against the oracle, alone and through a batch of itself and a
