@@ -250,9 +250,25 @@ def batch_section(nk, synth, torch, reps):
             ts = (time.perf_counter() - t0) / reps
             r["sequential_ms"] = 1e3 * ts
             r["batched_speedup_vs_sequential"] = ts / tb
+        # every item's objective and gradient (state and adjoint sweeps) as one graph launch
+        vz = [G.zeros_v() for G in probs]
+        gs = [G.empty_v() for G in probs]
+        B.objective_gradient(vz, gs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            B.objective_gradient(vz, gs)
+        torch.cuda.synchronize()
+        r["batched_gradient_ms"] = 1e3 * (time.perf_counter() - t0) / reps
+        t0 = time.perf_counter()
+        for G, v, g in zip(probs, vz, gs):
+            G.objective_gradient(v, g)
+        torch.cuda.synchronize()
+        r["sequential_gradient_ms"] = 1e3 * (time.perf_counter() - t0)
         out[f"fp{prec}"] = r
         log(f"batch FP{prec}: {r['batched_ms']:.3f} ms per batched matvec ({r['item_matvecs_per_s']:.0f} item-matvecs/s, "
-            f"{ach / 1e3:.2f} TB/s)" + (f", sequential {r['sequential_ms']:.3f} ms" if prec == 32 else ""))
+            f"{ach / 1e3:.2f} TB/s)" + (f", sequential {r['sequential_ms']:.3f} ms" if prec == 32 else "")
+            + f"; gradient {r['batched_gradient_ms']:.3f} ms batched, {r['sequential_gradient_ms']:.3f} ms one after another")
         B.close()
         for G in probs:
             G.close()
