@@ -98,18 +98,19 @@ typedef struct {
   double gref_inf;      /* > 0: ||g_0||_inf of the relative gradient rule (continuation passes the
                            first level's value); <= 0: the gradient at the solve's starting point */
   double* h_history;    /* optional host array of history_cap rows of NKREG_HISTORY_COLS doubles, one
-                           row per iterate v_k from k = 0: k, J, J_dist, ||g_k||_inf, PCG iterations
-                           of the step that produced v_k, its step length alpha, the CFL number of
-                           v_k, min and max of det F_1 at v_k (NaN unless history_detf). Rows past
-                           history_cap are dropped. nkreg_continuation appends every level's rows;
-                           nkreg_beta_search ignores it. NULL: no history */
+                           row per iterate v_k from k = 0: k, J, J_dist, J_reg, ||g_k||_inf, PCG
+                           iterations of the step that produced v_k, its step length alpha, PDE
+                           solves so far (n_PDE), the CFL number of v_k, min and max of det F_1 at
+                           v_k (NaN unless history_detf). Rows past history_cap are dropped.
+                           nkreg_continuation appends every level's rows; nkreg_beta_search
+                           ignores it. NULL: no history */
   int history_cap;
   int history_detf;     /* 1: also solve for det F_1 at every iterate (one FP64 deformation-gradient
                            solve per row, e:def-grad as nkreg_det_grad_y); with verbose, the line
                            printed per iteration carries the CFL number and, with this, det F_1 */
 } nkreg_solve_opts;
 
-#define NKREG_HISTORY_COLS 9
+#define NKREG_HISTORY_COLS 11
 
 /* What the outer iteration did (quantities of interest, Table t:quantities-of-interest). */
 typedef struct {

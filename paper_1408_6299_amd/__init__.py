@@ -10,6 +10,7 @@ _load()
 
 from .api import Batch, BetaSearchResult, BetaTrial, Problem, SolveResult  # noqa: E402
 from .autograd import RegistrationObjective, objective  # noqa: E402
+from .checkpoint import load_continuation, resume_continuation, save_continuation  # noqa: E402
 
 __all__ = ["Problem", "Batch", "SolveResult", "BetaSearchResult", "BetaTrial", "NkregError", "RegistrationObjective",
-           "objective"]
+           "objective", "save_continuation", "load_continuation", "resume_continuation"]

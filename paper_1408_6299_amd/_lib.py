@@ -19,7 +19,7 @@ class Config(Structure):
                 ("trajectory_slots", c_int)]
 
 
-HISTORY_COLS = 9     # NKREG_HISTORY_COLS
+HISTORY_COLS = 11    # NKREG_HISTORY_COLS
 
 
 class SolveOpts(Structure):

@@ -39,13 +39,13 @@ class SolveResult:
     seconds: float
     status: int
     stop_reason: str = ""
-    # one row per iterate v_k (k = 0, 1, ...): k, J, J_dist, |g_k|_inf, PCG iterations, alpha,
-    # CFL number, min det F_1, max det F_1 (NaN unless det F was asked for), as a float64 host
-    # tensor; None unless asked for
+    # one row per iterate v_k (k = 0, 1, ...), columns HISTORY_COLUMNS (min and max det F_1
+    # are NaN unless det F was asked for), as a float64 host tensor; None unless asked for
     history: Optional[torch.Tensor] = None
 
 
-HISTORY_COLUMNS = ("k", "J", "J_dist", "gnorm_inf", "cg_iterations", "alpha", "cfl", "detF_min", "detF_max")
+HISTORY_COLUMNS = ("k", "J", "J_dist", "J_reg", "gnorm_inf", "cg_iterations", "alpha", "n_pde", "cfl", "detF_min",
+                   "detF_max")
 
 STOP_REASONS = {1: "relative gradient", 2: "C1-C3", 3: "C4", 4: "iteration limit", 5: "line search failed",
                 6: "objective stagnation"}

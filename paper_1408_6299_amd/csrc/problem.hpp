@@ -1133,24 +1133,27 @@ class ProblemT final : public ProblemBase {
   // v_k and, when asked for, det F_1's extremes at v_k (an extra FP64 solve, which uses
   // buffers of its own and leaves the cached state alone).
   void log_iterate(const nkreg_solve_opts& opt, int& rows, const char* tag, int k, const double* vk, double J,
-                   double Jd, double ginf, double rel, int its, double alpha) {
+                   double Jd, double Jr, double ginf, double rel, int its, double alpha, int n_pde) {
     if (!opt.verbose && !(opt.h_history && rows < opt.history_cap)) return;
     const double cfl = cfl_number(vk);
     double st[4] = {NAN, NAN, NAN, NAN};
     if (opt.history_detf) det_grad_y(vk, nullptr, st);
     if (opt.h_history && rows < opt.history_cap) {
       double* row = opt.h_history + (size_t)rows * NKREG_HISTORY_COLS;
-      const double vals[NKREG_HISTORY_COLS] = {(double)k, J, Jd, ginf, (double)its, alpha, cfl, st[0], st[1]};
+      const double vals[NKREG_HISTORY_COLS] = {(double)k, J,     Jd,  Jr,    ginf, (double)its,
+                                               alpha,     (double)n_pde, cfl, st[0], st[1]};
       std::copy(vals, vals + NKREG_HISTORY_COLS, row);
       ++rows;
     }
     if (opt.verbose) {
       if (opt.history_detf)
-        fprintf(stderr, "[nkreg] %s k=%d J=%.6e Jd=%.6e |g|inf=%.3e rel=%.3e cg=%d alpha=%g cfl=%.3f detF=[%.4f, %.4f]\n",
-                tag, k, J, Jd, ginf, rel, its, alpha, cfl, st[0], st[1]);
+        fprintf(stderr,
+                "[nkreg] %s k=%d J=%.6e Jd=%.6e Jr=%.6e |g|inf=%.3e rel=%.3e cg=%d alpha=%g n_pde=%d cfl=%.3f "
+                "detF=[%.4f, %.4f]\n",
+                tag, k, J, Jd, Jr, ginf, rel, its, alpha, n_pde, cfl, st[0], st[1]);
       else
-        fprintf(stderr, "[nkreg] %s k=%d J=%.6e Jd=%.6e |g|inf=%.3e rel=%.3e cg=%d alpha=%g cfl=%.3f\n", tag, k, J,
-                Jd, ginf, rel, its, alpha, cfl);
+        fprintf(stderr, "[nkreg] %s k=%d J=%.6e Jd=%.6e Jr=%.6e |g|inf=%.3e rel=%.3e cg=%d alpha=%g n_pde=%d cfl=%.3f\n",
+                tag, k, J, Jd, Jr, ginf, rel, its, alpha, n_pde, cfl);
     }
   }
 
@@ -1179,7 +1182,7 @@ class ProblemT final : public ProblemBase {
     double at = 1.0;
     int flat = 0, k = 0;
     bool conv = false;
-    log_iterate(opt, r.history_rows, "picard", 0, vk, J, Jd, ginf, ginf / g0inf, 0, 0.0);
+    log_iterate(opt, r.history_rows, "picard", 0, vk, J, Jd, Jr, ginf, ginf / g0inf, 0, 0.0, r.n_pde);
     while (true) {
       if (ginf <= opt.gtol * g0inf || g0inf == 0.0) { conv = true; r.stop_reason = 1; break; }
       if (pop.stagnation_count > 0 && flat >= pop.stagnation_count) { conv = true; r.stop_reason = 6; break; }
@@ -1199,7 +1202,7 @@ class ProblemT final : public ProblemBase {
       flat = std::fabs(Jprev - J) <= pop.stagnation_tol * (1.0 + r.J0) ? flat + 1 : 0;
       ginf = red.one<double>(RED_MAXABS, gbuf.p, nullptr, nv);
       ++k;
-      log_iterate(opt, r.history_rows, "picard", k, vk, J, Jd, ginf, ginf / g0inf, 0, alpha);
+      log_iterate(opt, r.history_rows, "picard", k, vk, J, Jd, Jr, ginf, ginf / g0inf, 0, alpha, r.n_pde);
     }
     NK_HIP(hipStreamSynchronize(s));
     r.iterations = k;
@@ -1232,7 +1235,7 @@ class ProblemT final : public ProblemBase {
     double Jprev = J;
     int k = 0;
     bool conv = false;
-    log_iterate(opt, r.history_rows, "newton", 0, vk, J, Jd, ginf, ginf / g0inf, 0, 0.0);
+    log_iterate(opt, r.history_rows, "newton", 0, vk, J, Jd, Jr, ginf, ginf / g0inf, 0, 0.0, r.n_pde);
     const double eps = 2.220446049250313e-16;  // FP64 machine precision in C4 for both transports
     while (true) {
       if (opt.gtol > 0) {
@@ -1276,7 +1279,7 @@ class ProblemT final : public ProblemBase {
       ginf = red.one<double>(RED_MAXABS, gbuf.p, nullptr, nv);
       gtwo = std::sqrt(red.one<double>(RED_SUMSQ, gbuf.p, nullptr, nv));
       ++k;
-      log_iterate(opt, r.history_rows, "newton", k, vk, J, Jd, ginf, ginf / g0inf, its, alpha);
+      log_iterate(opt, r.history_rows, "newton", k, vk, J, Jd, Jr, ginf, ginf / g0inf, its, alpha, r.n_pde);
     }
     NK_HIP(hipStreamSynchronize(s));
     r.iterations = k;

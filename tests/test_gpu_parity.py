@@ -555,25 +555,57 @@ def test_newton_history_matches_oracle_iterates(nk):
     v, rep = G.newton_solve(gtol=1e-3, max_outer=20, history=True, history_detf=True)
     assert np.array_equal(host(v), host(v0)) and rep.iterations == rep0.iterations
     H = rep.history.numpy()
-    assert H.shape == (rep.iterations + 1, 9)
-    assert np.array_equal(H[:, 0], np.arange(rep.iterations + 1))
+    c = {name: i for i, name in enumerate(nk.api.HISTORY_COLUMNS)}
+    assert H.shape == (rep.iterations + 1, len(c))
+    assert np.array_equal(H[:, c["k"]], np.arange(rep.iterations + 1))
     assert rep.iterations == rep_ref.iterations
-    np.testing.assert_allclose(H[:, 1], rep_ref.J, rtol=1e-9)
-    np.testing.assert_allclose(H[:, 3], rep_ref.gnorm_inf, rtol=1e-8)
-    assert list(H[1:, 4].astype(int)) == list(rep_ref.cg_iterations)
-    np.testing.assert_allclose(H[1:, 5], rep_ref.alphas, rtol=0, atol=0)
-    assert H[-1, 1] == rep.J and H[-1, 3] == rep.gnorm_inf
+    np.testing.assert_allclose(H[:, c["J"]], rep_ref.J, rtol=1e-9)
+    np.testing.assert_allclose(H[:, c["J"]], H[:, c["J_dist"]] + H[:, c["J_reg"]], rtol=1e-14)
+    np.testing.assert_allclose(H[:, c["gnorm_inf"]], rep_ref.gnorm_inf, rtol=1e-8)
+    assert list(H[1:, c["cg_iterations"]].astype(int)) == list(rep_ref.cg_iterations)
+    np.testing.assert_allclose(H[1:, c["alpha"]], rep_ref.alphas, rtol=0, atol=0)
+    assert H[0, c["n_pde"]] == 2 and H[-1, c["n_pde"]] == rep.n_pde and np.all(np.diff(H[:, c["n_pde"]]) > 0)
+    assert H[-1, c["J"]] == rep.J and H[-1, c["gnorm_inf"]] == rep.gnorm_inf
     # the final iterates agree to 1e-8 relative; CFL and det F_1 are Lipschitz in v
-    assert abs(H[-1, 6] - okr.cfl_number(v_ref, nt)) <= 1e-7 * okr.cfl_number(v_ref, nt)
+    assert abs(H[-1, c["cfl"]] - okr.cfl_number(v_ref, nt)) <= 1e-7 * okr.cfl_number(v_ref, nt)
     _, st_ref = odg.det_stats(v_ref, nt)
-    assert abs(H[-1, 7] - st_ref[0]) <= 1e-7 and abs(H[-1, 8] - st_ref[1]) <= 1e-7
-    assert H[0, 6] == 0.0 and abs(H[0, 7] - 1.0) < 1e-12 and abs(H[0, 8] - 1.0) < 1e-12
+    assert abs(H[-1, c["detF_min"]] - st_ref[0]) <= 1e-7 and abs(H[-1, c["detF_max"]] - st_ref[1]) <= 1e-7
+    assert H[0, c["cfl"]] == 0.0 and abs(H[0, c["detF_min"]] - 1.0) < 1e-12 and abs(H[0, c["detF_max"]] - 1.0) < 1e-12
     _, rep_nd = G.newton_solve(gtol=1e-3, max_outer=20, history=True)
-    assert np.isnan(rep_nd.history.numpy()[:, 7:]).all()
+    assert np.isnan(rep_nd.history.numpy()[:, 9:]).all()
     v2, reps = G.continuation([1e-1, 1e-2], gtol=1e-3, max_outer=20, history=True)
     for r in reps:
-        assert tuple(r.history.shape) == (r.iterations + 1, 9) and float(r.history[-1, 1]) == r.J
+        assert tuple(r.history.shape) == (r.iterations + 1, 11) and float(r.history[-1, 1]) == r.J
     G.close()
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_continuation_resumes_from_a_checkpoint(nk, prec, tmp_path):
+    """A continuation interrupted after two of three levels, saved, loaded and resumed on a
+    fresh handle, ends at the uninterrupted solve's velocity bit for bit, with the same
+    iterations on the last level."""
+    shape, nt, betas = (32, 32), 8, [1e-1, 1e-2, 1e-3]
+    mT, mR, vstar, _ = smooth_inputs(shape, nt)
+
+    def handle():
+        G = nk.Problem(shape, nt, reg=2, beta=betas[0], precision=prec)
+        G.set_images(dev_t(mT, prec), dev_t(mR, prec))
+        return G
+
+    G = handle()
+    v_full, reps_full = G.continuation(betas, gtol=1e-3, max_outer=20)
+    G.close()
+    G = handle()
+    v2, reps2 = G.continuation(betas[:2], gtol=1e-3, max_outer=20)
+    G.close()
+    path = str(tmp_path / "cont.pt")
+    nk.save_continuation(path, v2, betas, 2, reps2[0].gnorm0_inf, reps2)
+    G = handle()
+    v3, reps3 = nk.resume_continuation(G, path, gtol=1e-3, max_outer=20)
+    G.close()
+    assert len(reps3) == 1 and reps3[0].iterations == reps_full[2].iterations
+    assert reps3[0].cg_iterations == reps_full[2].cg_iterations
+    assert np.array_equal(host(v3), host(v_full))
 
 
 @pytest.mark.parametrize("prec", [64])
