@@ -925,16 +925,6 @@ class ProblemT final : public ProblemBase {
       tuning = col_variant_name(sp.colE) + " (chosen earlier in this process for this grid)";
       return;
     }
-    if (g.d == 2 && (g.n[0] == 128 || g.n[0] == 256)) {
-      // 128- and 256-point columns of a 2D grid: 4 per lane, one column per wavefront (two
-      // at 128 points), twice the wavefronts of 8 per lane; the tiled pass is slower there
-      // (about 1.3x per matvec at 128^2, 1.7x at 256^2) and rounds like 8 per lane, so
-      // neither is timed against it
-      sp.colE = 4;
-      tt.col_e[tune_key()] = 4;
-      tuning = "col_E=4 (2D grid with 128- or 256-point columns)";
-      return;
-    }
     const long long ns = g.nspec;
     std::vector<int> cands = {8};
     if (sp.any_tiled_pass()) cands.push_back(0);
