@@ -126,7 +126,10 @@ def roofline(kernel: str, symbol: str, rec: dict, traffic=None) -> dict:
             "timing": "HIP events stamped by each dispatch (hipExtLaunchKernelGGL) over eager matvecs of the "
                       "same workload, each queued behind a device spin so its launches run back to back",
             "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-            "traffic": traffic}
+            "traffic": traffic,
+            "traffic_counts": "bytes per launch between the L2 caches and the memory fabric (rocprofv3 FETCH_SIZE + "
+                              "WRITE_SIZE, scaled by a plain device copy); the Infinity Cache is on the fabric side, "
+                              "so this bounds the HBM bytes from above"}
 
 
 def cpu_model() -> str:
