@@ -841,6 +841,18 @@ def main() -> int:
         "launch": results[32]["launch"],
     }
     out["matvec_roofline"] = results[32]["matvec_roofline"]
+    # the launch-latency floor of the same number of dependent launches (plain copies of the
+    # row spectrum, row and column patterns alternating), against which the matvec is bound
+    fl = {k: nk.launch_floor(k, shape[0], shape[1] // 2, 200) for k in ("empty", "row_column_alternating")}
+    mv = out["matvec_roofline"]
+    floor_ms = mv["launches"] * fl["row_column_alternating"] * 1e-3
+    out["latency_floor"] = {"empty_node_us": fl["empty"], "copy_node_us": fl["row_column_alternating"],
+                            "launches_per_matvec": mv["launches"], "floor_ms": floor_ms, "matvec_ms": mv["matvec_ms"],
+                            "frac": floor_ms / mv["matvec_ms"],
+                            "note": "graph of dependent launches, each copying the spectrum the previous one wrote"}
+    log(f"latency floor: empty node {fl['empty']:.2f} us, copy node {fl['row_column_alternating']:.2f} us; "
+        f"{mv['launches']} launches -> {floor_ms:.3f} ms against the {mv['matvec_ms']:.3f} ms matvec "
+        f"({100 * floor_ms / mv['matvec_ms']:.0f}%)")
     if 64 in results:
         out["fp64"] = {"matvecs_per_s": results[64]["matvecs_per_s"], "ms_per_step": results[64]["ms_per_step"],
                        "fp32_speedup": results[32]["matvecs_per_s"] / results[64]["matvecs_per_s"],

@@ -343,10 +343,22 @@ int nkreg_gradient_noalloc(int dim, const int* n, int precision, const void* d_u
  * scratch with NaN around every exchange: if a wavefront's exchange read were served
  * before its earlier writes, or a later write overtook a read, NaN would reach d_out;
  * with correct ordering the output equals the unpoisoned run's bit for bit. Forms:
- * (m, elems, lockstep) in {32, 128, 256} x {4} x {1, 2} and {64, 256, 512} x {8} x {1};
- * others return ENOTIMPL. Allocates and frees a twiddle table. Synchronises. */
+ * (m, elems, lockstep) in {32, 128, 256} x {4} x {1, 2}, {64, 128} x {2} x {1, 2} and
+ * {64, 256, 512} x {8} x {1}; others return ENOTIMPL. Allocates and frees a twiddle
+ * table. Synchronises. */
 int nkreg_exchange_canary(int precision, int m, int elems, int lockstep, int poison, const void* d_in, void* d_out,
                           int count, void* hip_stream);
+
+/* Latency floor of a chain of dependent launches (measurement instrumentation for the
+ * launch-bound grids): *h_us_per_node receives the microseconds per node of a HIP graph of
+ * `nodes` launches replayed on hip_stream, each reading the FP32 complex rows x cols array
+ * the previous one wrote (two arrays allocated and freed here). kind 0: an empty kernel;
+ * 1: a row-pattern copy (one wavefront per row, contiguous); 2: a column-pattern copy (one
+ * wavefront per column, rows/64 elements per lane, the column pass's workgroup order);
+ * 3: row and column copies alternating, as the transport stages and column passes of a
+ * matvec do. rows and cols are multiples of 64 in [64, 4096], nodes in [2, 4096]; EINVAL
+ * otherwise. Synchronises. */
+int nkreg_launch_floor(int kind, int rows, int cols, int nodes, void* hip_stream, double* h_us_per_node);
 
 /* FP64 inner product sum(a*b) of two double arrays of cnt elements. Synchronises. */
 int nkreg_dot(nkreg_problem* p, const void* d_a, const void* d_b, long long cnt, double* h_out);

@@ -8,9 +8,9 @@ from ._lib import NkregError, load as _load
 
 _load()
 
-from .api import Batch, BetaSearchResult, BetaTrial, Problem, SolveResult  # noqa: E402
+from .api import Batch, BetaSearchResult, BetaTrial, Problem, SolveResult, launch_floor  # noqa: E402
 from .autograd import RegistrationObjective, objective  # noqa: E402
 from .checkpoint import load_continuation, resume_continuation, save_continuation  # noqa: E402
 
 __all__ = ["Problem", "Batch", "SolveResult", "BetaSearchResult", "BetaTrial", "NkregError", "RegistrationObjective",
-           "objective", "save_continuation", "load_continuation", "resume_continuation"]
+           "objective", "save_continuation", "load_continuation", "resume_continuation", "launch_floor"]

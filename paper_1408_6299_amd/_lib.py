@@ -94,6 +94,7 @@ SIGNATURES = {
     "nkreg_matvec_bytes": (c_int, [c_void_p, c_void_p, c_void_p, POINTER(c_double), POINTER(c_int)]),
     "nkreg_timer_read": (c_int, [c_void_p, POINTER(c_int), POINTER(c_double), POINTER(c_double)]),
     "nkreg_exchange_canary": (c_int, [c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, c_int, c_void_p]),
+    "nkreg_launch_floor": (c_int, [c_int, c_int, c_int, c_int, c_void_p, ctypes.POINTER(c_double)]),
     "nkreg_gradient_noalloc": (c_int, [c_int, POINTER(c_int), c_int, c_void_p, c_void_p, c_void_p]),
     "nkreg_batch_create": (c_int, [c_int, POINTER(Config), c_void_p, POINTER(c_void_p)]),
     "nkreg_batch_wrap": (c_int, [c_int, POINTER(c_void_p), POINTER(c_void_p)]),

@@ -470,6 +470,20 @@ class Problem:
         return out.value
 
 
+LAUNCH_FLOOR_KINDS = {"empty": 0, "row_copy": 1, "column_copy": 2, "row_column_alternating": 3}
+
+
+def launch_floor(kind: str, rows: int = 512, cols: int = 256, nodes: int = 200) -> float:
+    """Microseconds per node of a graph of dependent launches over a rows x cols complex
+    FP32 array (nkreg_launch_floor): "empty", "row_copy", "column_copy" or
+    "row_column_alternating"; runs on torch's current stream."""
+    lib = _lib.load()
+    us = c_double()
+    check(lib.nkreg_launch_floor(LAUNCH_FLOOR_KINDS[kind], int(rows), int(cols), int(nodes),
+                                 c_void_p(torch.cuda.current_stream().cuda_stream), byref(us)), "nkreg_launch_floor")
+    return us.value
+
+
 class Batch:
     """Several independent problems whose gradients and Hessian matvecs are applied in one
     call each (one HIP-graph launch over all items; items of one configuration share every

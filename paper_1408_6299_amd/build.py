@@ -18,7 +18,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnkreg.so")
 ARCH = os.environ.get("NKREG_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["nkreg_abi.hip", "problem_f32.hip", "problem_f64.hip", "noalloc.hip", "small.hip", "canary.hip"]
+SOURCES = ["nkreg_abi.hip", "problem_f32.hip", "problem_f64.hip", "noalloc.hip", "small.hip", "canary.hip",
+           "floor.hip"]
 
 # The target-feature flag turns off packed FP32 instruction generation in every kernel.
 HIPFLAGS = [

@@ -92,6 +92,15 @@ def test_null_arguments_are_rejected():
     assert lib.nkreg_batch_set_state(None, None) == _lib.EINVAL
 
 
+def test_launch_floor_validates_its_arguments_before_any_device_work():
+    lib = _lib.load()
+    us = ctypes.c_double()
+    for args in ((0, 512, 256, 200, None, None), (4, 512, 256, 200, None, ctypes.byref(us)),
+                 (1, 100, 256, 200, None, ctypes.byref(us)), (2, 512, 8192, 200, None, ctypes.byref(us)),
+                 (3, 512, 256, 1, None, ctypes.byref(us))):
+        assert lib.nkreg_launch_floor(*args) == _lib.EINVAL, args
+
+
 def test_batch_create_validates_every_configuration_before_any_device_work():
     lib = _lib.load()
     cfgs = (_lib.Config * 2)(make_cfg(), make_cfg(n=(48, 64, 1)))

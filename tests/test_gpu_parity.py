@@ -446,6 +446,14 @@ def test_exchange_canary_poisoned_scratch_never_reaches_the_transform(nk, m, ele
     assert err < (1e-13 if prec == 64 else 1e-5), err
 
 
+def test_launch_floor_chains(nk):
+    """nkreg_launch_floor: graphs of dependent launches time to positive per-node costs, and
+    a copy of a 512 x 256 complex spectrum costs more per node than an empty kernel."""
+    t = {k: nk.launch_floor(k, 512, 256, 100) for k in nk.api.LAUNCH_FLOOR_KINDS}
+    assert all(v > 0 for v in t.values()), t
+    assert t["column_copy"] > t["empty"] and t["row_copy"] > t["empty"], t
+
+
 def test_column_variant_pinned_per_grid(nk, monkeypatch):
     """NKREG_COL_E as grid=variant entries fixes the column pass of the grids it names and
     leaves the others to the autotuner; both variants give the same matvec bits."""
