@@ -343,6 +343,31 @@ inline hipGraphExec_t capture_group(const GroupPlan& gp, void* base, hipStream_t
   return ex;
 }
 
+// Milliseconds per replay of an instantiated graph on st (one warm-up, then two timed).
+inline float time_exec(hipGraphExec_t ex, hipStream_t st) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  float ms = 0.f;
+  try {
+    NK_HIP(hipEventCreate(&e0));
+    NK_HIP(hipEventCreate(&e1));
+    NK_HIP(hipGraphLaunch(ex, st));
+    NK_HIP(hipEventRecord(e0, st));
+    NK_HIP(hipGraphLaunch(ex, st));
+    NK_HIP(hipGraphLaunch(ex, st));
+    NK_HIP(hipEventRecord(e1, st));
+    NK_HIP(hipEventSynchronize(e1));
+    NK_HIP(hipEventElapsedTime(&ms, e0, e1));
+  } catch (...) {
+    (void)hipStreamSynchronize(st);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms / 2.f;
+}
+
 // Milliseconds per replay of the group's launches (one warm-up, then two timed).
 inline float time_group(const GroupPlan& gp, hipStream_t st) {
   std::vector<unsigned char> host;

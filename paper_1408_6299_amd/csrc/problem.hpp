@@ -856,31 +856,9 @@ class ProblemT final : public ProblemBase {
   DevBuf<unsigned char> mv_tab;
   bool small_sweeps = false;
   std::string sweep_timing;
-  hipGraphExec_t capture_matvec(const void* vtin, void* out) {
-    small_sweeps = false;
-    if (small_config(cfg)) {
-      GroupPlan gp;
-      gp.items = {0};
-      gp.recs.resize(1);
-      record_matvec(vtin, out, gp.recs[0], 8);
-      gp.small_ops = small_prefix(gp.recs[0].recs);
-      if (gp.small_ops) {
-        std::vector<GroupPlan> cands(2, gp);
-        cands[1].small_ops = 0;
-        NK_HIP(hipStreamSynchronize(user_s));   // the timing replays run on the capture stream
-        std::vector<float> ms;
-        const size_t pick = fastest_plan(cands, cap_s, &ms);
-        sweep_timing = "persistent " + std::to_string(1e3f * ms[0]) + " us, launches " + std::to_string(1e3f * ms[1]) +
-                       " us per matvec";
-        std::vector<unsigned char> host;
-        add_tables(cands[pick], host);
-        NK_HIP(hipStreamSynchronize(s));   // an earlier graph may still read the old table
-        mv_tab.alloc(host.size());
-        NK_HIP(hipMemcpy(mv_tab.p, host.data(), host.size(), hipMemcpyHostToDevice));
-        small_sweeps = cands[pick].small_ops > 0;
-        return capture_group(cands[pick], mv_tab.p, cap_s);
-      }
-    }
+  // The matvec's launches captured as they are issued (kernels take their arguments
+  // directly).
+  hipGraphExec_t capture_direct(const void* vtin, void* out) {
     hipGraph_t graph = nullptr;
     OnCaptureStream on(*this);
     NK_HIP(hipStreamBeginCapture(cap_s, hipStreamCaptureModeThreadLocal));
@@ -897,6 +875,46 @@ class ProblemT final : public ProblemBase {
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) throw HipError(NKREG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     return exec;
+  }
+
+  // The matvec graph. On small square grids the persistent form of its sweeps
+  // (group.hpp, small.hpp) is timed against the direct launches and the faster kept;
+  // NKREG_SMALL=1 forces the persistent form.
+  hipGraphExec_t capture_matvec(const void* vtin, void* out) {
+    small_sweeps = false;
+    hipGraphExec_t direct = capture_direct(vtin, out);
+    if (!small_config(cfg)) return direct;
+    try {
+      GroupPlan gp;
+      gp.items = {0};
+      gp.recs.resize(1);
+      record_matvec(vtin, out, gp.recs[0], 8);
+      gp.small_ops = small_prefix(gp.recs[0].recs);
+      if (!gp.small_ops) return direct;
+      NK_HIP(hipStreamSynchronize(user_s));   // the timing replays run on the capture stream
+      bool persistent = small_forced();
+      if (!persistent) {
+        const float t_pers = time_group(gp, cap_s);
+        const float t_dir = time_exec(direct, cap_s);
+        sweep_timing = "persistent " + std::to_string(1e3f * t_pers) + " us, launches " +
+                       std::to_string(1e3f * t_dir) + " us per matvec";
+        persistent = t_pers < t_dir;
+      }
+      if (!persistent) return direct;
+      std::vector<unsigned char> host;
+      add_tables(gp, host);
+      NK_HIP(hipStreamSynchronize(s));   // an earlier graph may still read the old table
+      mv_tab.alloc(host.size());
+      NK_HIP(hipMemcpy(mv_tab.p, host.data(), host.size(), hipMemcpyHostToDevice));
+      hipGraphExec_t ex = capture_group(gp, mv_tab.p, cap_s);
+      (void)hipGraphExecDestroy(direct);
+      small_sweeps = true;
+      return ex;
+    } catch (...) {
+      (void)hipStreamSynchronize(cap_s);
+      (void)hipGraphExecDestroy(direct);
+      throw;
+    }
   }
 
   // Column-pass autotuner, run once per handle at creation: the candidates are
