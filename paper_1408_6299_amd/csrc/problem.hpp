@@ -849,10 +849,10 @@ class ProblemT final : public ProblemBase {
   }
 
   // Captures one matvec on the capture stream; nothing runs until the graph is launched.
-  // On small square grids the transport sweeps run in the persistent kernel (from the
-  // recorded launch sequence and its argument table, kept in mv_tab while the graph lives).
-  // Where the persistent form applies, both forms are captured from the recorded sequence
-  // and timed (once per pointer pair; the values are the same), and the faster is kept.
+  // On small square grids the transport sweeps may run in the persistent kernel (from the
+  // recorded launch sequence and its argument table, kept in mv_tab while the graph lives):
+  // it is timed against the direct launches (once per pointer pair; the values are the
+  // same), and the faster is kept.
   DevBuf<unsigned char> mv_tab;
   bool small_sweeps = false;
   std::string sweep_timing;
