@@ -268,10 +268,27 @@ def batch_section(nk, synth, torch, reps):
             G.objective_gradient(v, g)
         torch.cuda.synchronize()
         r["sequential_gradient_ms"] = 1e3 * (time.perf_counter() - t0)
+        # PCG on every item (rhs = -g at v = 0, relative tolerance 1e-2) in lockstep, one
+        # batched matvec per iteration, against each item's own PCG one after another
+        rhs = [-g for g in gs]
+        xs = [G.empty_v() for G in probs]
+        B.pcg(rhs, 1e-2, 0, xs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, its, _, _ = B.pcg(rhs, 1e-2, 0, xs)
+        r["batched_pcg_ms"] = 1e3 * (time.perf_counter() - t0)
+        r["pcg_iterations"] = [min(its), max(its), int(sum(its))]
+        t0 = time.perf_counter()
+        for G, b, x in zip(probs, rhs, xs):
+            G.pcg(b, 1e-2, 0, x)
+        torch.cuda.synchronize()
+        r["sequential_pcg_ms"] = 1e3 * (time.perf_counter() - t0)
         out[f"fp{prec}"] = r
         log(f"batch FP{prec}: {r['batched_ms']:.3f} ms per batched matvec ({r['item_matvecs_per_s']:.0f} item-matvecs/s, "
             f"{ach / 1e3:.2f} TB/s)" + (f", sequential {r['sequential_ms']:.3f} ms" if prec == 32 else "")
-            + f"; gradient {r['batched_gradient_ms']:.3f} ms batched, {r['sequential_gradient_ms']:.3f} ms one after another")
+            + f"; gradient {r['batched_gradient_ms']:.3f} ms batched, {r['sequential_gradient_ms']:.3f} ms one after another"
+            + f"; PCG to 1e-2 ({r['pcg_iterations'][0]}-{r['pcg_iterations'][1]} iterations) "
+              f"{r['batched_pcg_ms']:.1f} ms batched, {r['sequential_pcg_ms']:.1f} ms one after another")
         B.close()
         for G in probs:
             G.close()

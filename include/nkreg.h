@@ -426,6 +426,15 @@ int nkreg_batch_item(nkreg_batch* b, int i, nkreg_problem** out);
 int nkreg_batch_objective_gradient(nkreg_batch* b, const void* const* d_v, double* h_J, double* h_J_dist,
                                    double* h_J_reg, void* const* d_g);
 int nkreg_batch_set_state(nkreg_batch* b, const void* const* d_v);
+/* PCG on every item (e:termination-criterion-ksm, as nkreg_pcg: x0 = 0, stop when
+ * ||r_i||_2 <= rtol ||rhs_i||_2, at most maxit iterations, <= 0: n) at each item's cached
+ * state (ESTATE if an item has none). The items iterate in lockstep: each iteration is
+ * one batched matvec graph launch for all items, then every unfinished item's own vector
+ * work, then one wait. Each item's x_i, iteration count and relative residual equal those
+ * of its own nkreg_pcg bit for bit. iters and relres (count entries each) may be NULL.
+ * Returns ENOCONV (outputs written) if any item reached maxit. Synchronises. */
+int nkreg_batch_pcg(nkreg_batch* b, const void* const* d_rhs, void* const* d_x, double rtol, int maxit, int* h_iters,
+                    double* h_relres);
 int nkreg_batch_hessian_matvec(nkreg_batch* b, const void* const* d_vt, void* const* d_Hvt);
 int nkreg_batch_groups(nkreg_batch* b, int* groups, int* sizes, int* form, int cap);
 int nkreg_batch_destroy(nkreg_batch* b);

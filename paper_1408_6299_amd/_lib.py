@@ -102,6 +102,8 @@ SIGNATURES = {
     "nkreg_batch_objective_gradient": (c_int, [c_void_p, POINTER(c_void_p), POINTER(c_double), POINTER(c_double),
                                                POINTER(c_double), POINTER(c_void_p)]),
     "nkreg_batch_set_state": (c_int, [c_void_p, POINTER(c_void_p)]),
+    "nkreg_batch_pcg": (c_int, [c_void_p, POINTER(c_void_p), POINTER(c_void_p), c_double, c_int, POINTER(c_int),
+                                POINTER(c_double)]),
     "nkreg_batch_groups": (c_int, [c_void_p, POINTER(c_int), POINTER(c_int), POINTER(c_int), c_int]),
     "nkreg_batch_destroy": (c_int, [c_void_p]),
     "nkreg_batch_hessian_matvec": (c_int, [c_void_p, POINTER(c_void_p), POINTER(c_void_p)]),

@@ -546,6 +546,24 @@ class Batch:
         check(self.lib.nkreg_batch_objective_gradient(self._h, ins, J, Jd, Jr, os_), "nkreg_batch_objective_gradient")
         return list(J), list(Jd), list(Jr), gs
 
+    def pcg(self, rhs: Sequence[torch.Tensor], rtol: float, maxit: int = 0,
+            outs: Optional[Sequence[torch.Tensor]] = None):
+        """PCG on every item at its cached state, all items iterating in lockstep with one
+        batched matvec per iteration (nkreg_batch_pcg). Returns (xs, iterations, relative
+        residuals, all converged); each item's results equal its own Problem.pcg's."""
+        n = len(self.problems)
+        outs = [p.empty_v() for p in self.problems] if outs is None else list(outs)
+        for p, a, b in zip(self.problems, rhs, outs):
+            p._check(a, p.vshape, "rhs")
+            p._check(b, p.vshape, "x")
+        ins = (c_void_p * n)(*[t.data_ptr() for t in rhs])
+        os_ = (c_void_p * n)(*[t.data_ptr() for t in outs])
+        its, rel = (c_int * n)(), (c_double * n)()
+        st = self.lib.nkreg_batch_pcg(self._h, ins, os_, c_double(rtol), c_int(maxit), its, rel)
+        if st not in (_lib.OK, _lib.ENOCONV):
+            check(st, "nkreg_batch_pcg")
+        return outs, list(its), list(rel), st == _lib.OK
+
     def set_state(self, vs: Sequence[torch.Tensor]) -> None:
         """Every item's forward and adjoint sweeps at vs[i] (the state its matvecs use)."""
         n = len(self.problems)

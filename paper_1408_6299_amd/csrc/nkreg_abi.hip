@@ -781,6 +781,54 @@ int nkreg_batch_objective_gradient(nkreg_batch* b, const void* const* v, double*
   });
 }
 
+int nkreg_batch_pcg(nkreg_batch* b, const void* const* rhs, void* const* x, double rtol, int maxit, int* iters,
+                    double* relres) {
+  NEED(b);
+  if (!b->items.empty()) { NEED(rhs); NEED(x); }
+  if (!(rtol >= 0.0)) return fail(NKREG_EINVAL, "rtol must be >= 0");
+  for (size_t i = 0; i < b->items.size(); ++i)
+    if (!rhs[i] || !x[i]) return fail(NKREG_EINVAL, "batch PCG: null item vectors");
+  return guarded([&]() {
+    const nk::Range range("nkreg_batch_pcg");
+    const size_t cnt = b->items.size();
+    for (size_t i = 0; i < cnt; ++i)
+      if (!b->items[i]->impl->state_ready()) throw nk::HipError(NKREG_ESTATE, "batch PCG: an item has no state");
+    std::vector<const void*> ps(cnt);
+    std::vector<void*> qs(cnt);
+    bool any = false;
+    for (size_t i = 0; i < cnt; ++i) {
+      nk::ProblemBase* p = b->items[i]->impl;
+      any = p->pcg_begin(rhs[i], x[i], rtol, maxit) || any;
+      ps[i] = p->pcg_p();
+      qs[i] = p->pcg_q();
+    }
+    // Every iteration: one batched matvec for all items (an item that has stopped keeps its
+    // direction, so its product is recomputed unchanged and unused), then each active
+    // item's step and one wait for all of them.
+    int round = 0;
+    while (any) {
+      const nk::Range iter("batch pcg iteration", round++);
+      run_batch(b, b->matvec, record_matvec_fn, ps.data(), qs.data());
+      for (size_t i = 0; i < cnt; ++i)
+        if (b->items[i]->impl->pcg_active()) b->items[i]->impl->pcg_step();
+      for (size_t i = 0; i < cnt; ++i)
+        if (b->items[i]->impl->pcg_active()) NK_HIP(hipStreamSynchronize(b->items[i]->impl->stream()));
+      any = false;
+      for (size_t i = 0; i < cnt; ++i) {
+        nk::ProblemBase* p = b->items[i]->impl;
+        if (!p->pcg_active()) continue;
+        p->pcg_finish();
+        any = p->pcg_active() || any;
+      }
+    }
+    int status = NKREG_OK;
+    for (size_t i = 0; i < cnt; ++i)
+      if (b->items[i]->impl->pcg_result(iters ? iters + i : nullptr, relres ? relres + i : nullptr) != NKREG_OK)
+        status = NKREG_ENOCONV;
+    return status;
+  });
+}
+
 int nkreg_batch_set_state(nkreg_batch* b, const void* const* v) {
   return nkreg_batch_objective_gradient(b, v, nullptr, nullptr, nullptr, nullptr);
 }

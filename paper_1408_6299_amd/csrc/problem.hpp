@@ -158,6 +158,18 @@ class ProblemBase {
   virtual void precond(const void* r, void* z) = 0;
   virtual void project(const void* f, void* out) = 0;
   virtual int pcg(const void* rhs, void* s, double rtol, int maxit, int* iters, double* relres) = 0;
+  // The same PCG in steps, so that a batch can run many at once with one batched matvec
+  // per iteration: pcg_begin starts it (false: nothing to iterate); while pcg_active(),
+  // the caller computes q = H p into pcg_q() from pcg_p(), pcg_step enqueues the rest of
+  // the iteration and the read-back of its scalars, and once the handle's stream has
+  // been synchronised pcg_finish takes the iteration's decisions. pcg_result reports.
+  virtual bool pcg_begin(const void* rhs, void* s, double rtol, int maxit) = 0;
+  virtual bool pcg_active() const = 0;
+  virtual const void* pcg_p() const = 0;
+  virtual void* pcg_q() = 0;
+  virtual void pcg_step() = 0;
+  virtual void pcg_finish() = 0;
+  virtual int pcg_result(int* iters, double* relres) const = 0;
   virtual void det_grad_y(const void* v, void* detF, double* stats) = 0;
   virtual int newton(void* v, const nkreg_solve_opts* o, nkreg_solve_report* rep) = 0;
   virtual int picard(void* v, const nkreg_solve_opts* o, const nkreg_picard_opts* po, nkreg_solve_report* rep) = 0;
@@ -1053,60 +1065,89 @@ class ProblemT final : public ProblemBase {
   }
 
   // ---- PCG (textbook preconditioned CG, x0 = 0) ----
-  int pcg(const void* rhsin, void* sout, double rtol, int maxit, int* iters, double* relres) override {
+  // ---- PCG (x0 = 0; stop when |r| <= rtol |rhs|; non-positive curvature ends it) ----
+  // Reduction slots: 0 = |r|^2, 1 = r.z (read by the next step), 2 = p.Hp. One host read
+  // per iteration: the step length is formed on the device from p.Hp and r.z, and p.Hp
+  // is checked when the new residual is read.
+  struct PcgRun {
+    double* x = nullptr;
+    double nb = 0.0, tol = 0.0, rz = 0.0, rn = 0.0;
+    int it = 0, maxit = 0;
+    bool ok = false, active = false;
+  } pr;
+  bool pcg_begin(const void* rhsin, void* sout, double rtol, int maxit) override {
     if (!state_valid) throw HipError(NKREG_ESTATE, "no gradient computed at the current velocity");
-    const double* rhs = (const double*)rhsin;
-    double* x = (double*)sout;
-    if (maxit <= 0) maxit = (int)std::min<long long>(nv, 1 << 30);
-    hipLaunchKernelGGL((k_fill<double>), dim3(launch_blocks(nv)), dim3(256), 0, s, nv, 0.0, x);
+    pr = PcgRun{};
+    pr.x = (double*)sout;
+    pr.maxit = maxit <= 0 ? (int)std::min<long long>(nv, 1 << 30) : maxit;
+    hipLaunchKernelGGL((k_fill<double>), dim3(launch_blocks(nv)), dim3(256), 0, s, nv, 0.0, pr.x);
     NK_LAUNCHED();
-    copy(kr.p, rhs, nv * sizeof(double));
-    const double nb = std::sqrt(red.one<double>(RED_SUMSQ, kr.p, nullptr, nv));
-    if (!std::isfinite(nb)) throw HipError(NKREG_ENONFINITE, "right-hand side is not finite");
-    if (nb == 0.0) {
-      if (iters) *iters = 0;
-      if (relres) *relres = 0.0;
-      return NKREG_OK;
+    copy(kr.p, rhsin, nv * sizeof(double));
+    pr.nb = std::sqrt(red.one<double>(RED_SUMSQ, kr.p, nullptr, nv));
+    if (!std::isfinite(pr.nb)) throw HipError(NKREG_ENONFINITE, "right-hand side is not finite");
+    if (pr.nb == 0.0) {
+      pr.ok = true;
+      return false;
     }
-    const double tol = rtol * nb;
+    pr.tol = rtol * pr.nb;
     precond(kr.p, kz.p);
     copy(kp.p, kz.p, nv * sizeof(double));
-    // reduction slots: 0 = |r|^2, 1 = r.z (read by the next step), 2 = p.Hp
     red.enqueue<double>(RED_DOT, kr.p, kz.p, nv, 1);
     red.fetch(2);
-    double rz = red.host[1];
-    double rn = nb;
-    int it = 0;
-    bool ok = rn <= tol;
-    // One host read per iteration: the step length is formed on the device from
-    // p.Hp and r.z, and p.Hp is checked when the new residual is read.
-    while (!ok && it < maxit) {
-      const Range iter("pcg iteration", it);
-      hessian_matvec(kp.p, kq.p);
-      red.enqueue<double>(RED_DOT, kp.p, kq.p, nv, 2);
-      hipLaunchKernelGGL(k_pcg_step, dim3(launch_blocks(nv)), dim3(256), 0, s, nv, (const double*)red.result.p + 1,
-                         (const double*)red.result.p + 2, (const double*)kp.p, (const double*)kq.p, x, kr.p);
-      NK_LAUNCHED();
-      precond(kr.p, kz.p);
-      red.enqueue<double>(RED_SUMSQ, kr.p, nullptr, nv, 0);
-      red.enqueue<double>(RED_DOT, kr.p, kz.p, nv, 1);
-      red.fetch(3);
-      const double pq = red.host[2];
-      if (!std::isfinite(pq)) throw HipError(NKREG_ENONFINITE, "p.Hp is not finite");
-      if (pq <= 0.0) {  // non-positive curvature ends the iteration (x and r were left unchanged)
-        if (it == 0) copy(x, kp.p, nv * sizeof(double));  // then x = P^-1 rhs, a descent direction
-        break;
-      }
-      ++it;
-      rn = std::sqrt(red.host[0]);
-      const double rz_new = red.host[1];
-      if (rn <= tol) { ok = true; break; }
-      lincomb(nv, 1.0, kz.p, rz_new / rz, kp.p, kp.p);
-      rz = rz_new;
+    pr.rz = red.host[1];
+    pr.rn = pr.nb;
+    pr.ok = pr.rn <= pr.tol;
+    pr.active = !pr.ok && pr.it < pr.maxit;
+    return pr.active;
+  }
+  bool pcg_active() const override { return pr.active; }
+  const void* pcg_p() const override { return kp.p; }
+  void* pcg_q() override { return kq.p; }
+  void pcg_step() override {
+    red.enqueue<double>(RED_DOT, kp.p, kq.p, nv, 2);
+    hipLaunchKernelGGL(k_pcg_step, dim3(launch_blocks(nv)), dim3(256), 0, s, nv, (const double*)red.result.p + 1,
+                       (const double*)red.result.p + 2, (const double*)kp.p, (const double*)kq.p, pr.x, kr.p);
+    NK_LAUNCHED();
+    precond(kr.p, kz.p);
+    red.enqueue<double>(RED_SUMSQ, kr.p, nullptr, nv, 0);
+    red.enqueue<double>(RED_DOT, kr.p, kz.p, nv, 1);
+    NK_HIP(hipMemcpyAsync(red.host, red.result.p, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  void pcg_finish() override {
+    const double pq = red.host[2];
+    if (!std::isfinite(pq)) throw HipError(NKREG_ENONFINITE, "p.Hp is not finite");
+    if (pq <= 0.0) {  // non-positive curvature ends the iteration (x and r were left unchanged)
+      if (pr.it == 0) copy(pr.x, kp.p, nv * sizeof(double));  // then x = P^-1 rhs, a descent direction
+      pr.active = false;
+      return;
     }
-    if (iters) *iters = it;
-    if (relres) *relres = rn / nb;
-    return ok ? NKREG_OK : NKREG_ENOCONV;
+    ++pr.it;
+    pr.rn = std::sqrt(red.host[0]);
+    const double rz_new = red.host[1];
+    if (pr.rn <= pr.tol) {
+      pr.ok = true;
+      pr.active = false;
+      return;
+    }
+    lincomb(nv, 1.0, kz.p, rz_new / pr.rz, kp.p, kp.p);
+    pr.rz = rz_new;
+    pr.active = pr.it < pr.maxit;
+  }
+  int pcg_result(int* iters, double* relres) const override {
+    if (iters) *iters = pr.it;
+    if (relres) *relres = pr.nb == 0.0 ? 0.0 : pr.rn / pr.nb;
+    return pr.ok ? NKREG_OK : NKREG_ENOCONV;
+  }
+  int pcg(const void* rhsin, void* sout, double rtol, int maxit, int* iters, double* relres) override {
+    pcg_begin(rhsin, sout, rtol, maxit);
+    while (pr.active) {
+      const Range iter("pcg iteration", pr.it);
+      hessian_matvec(kp.p, kq.p);
+      pcg_step();
+      NK_HIP(hipStreamSynchronize(s));
+      pcg_finish();
+    }
+    return pcg_result(iters, relres);
   }
   // Armijo backtracking along sbuf from alpha = 1 (c1 = 1e-4, at most 20
   // halvings; Section "Numerical Optimization"); gbuf holds the gradient at vk.

@@ -90,6 +90,7 @@ def test_null_arguments_are_rejected():
     assert lib.nkreg_batch_wrap(-1, None, ctypes.byref(h)) == _lib.EINVAL
     assert lib.nkreg_batch_item(None, 0, ctypes.byref(h)) == _lib.EINVAL
     assert lib.nkreg_batch_set_state(None, None) == _lib.EINVAL
+    assert lib.nkreg_batch_pcg(None, None, None, 1e-3, 10, None, None) == _lib.EINVAL
 
 
 def test_launch_floor_validates_its_arguments_before_any_device_work():

@@ -337,6 +337,37 @@ def test_small_grid_persistent_sweeps_equal_the_launch_path(nk, monkeypatch, sha
         assert rel_l2(outs[0][0], ref) < 1e-5
 
 
+def test_batch_pcg_equals_each_items_own_pcg(nk):
+    """nkreg_batch_pcg: the items (mixed grids, step counts, precisions, a checkpointed 3D
+    pair) iterate in lockstep with one batched matvec per iteration; every item's x, its
+    iteration count and relative residual equal its own nkreg_pcg's bit for bit, also when
+    maxit stops some of them and for a zero right-hand side."""
+    probs, rhs = [], []
+    for shape, nt, prec, beta, seed, ck in BATCH_ITEMS:
+        gamma = len(shape) == 3
+        mT, mR, vstar, w = smooth_inputs(shape, nt, divfree=gamma, seed=seed)
+        G = nk.Problem(shape, nt, reg=2 if gamma else 1, incompressible=gamma, beta=beta, precision=prec,
+                       checkpoint_every=ck)
+        G.set_images(dev_t(mT, prec), dev_t(mR, prec))
+        _, _, _, g = G.objective_gradient(dev_v(0.5 * vstar))
+        probs.append(G)
+        rhs.append(-g)
+    rhs[3] = torch.zeros_like(rhs[3])
+    B = nk.Batch(probs)
+    for rtol, maxit in ((1e-6, 0), (1e-10, 3)):
+        xs, its, rel, conv = B.pcg(rhs, rtol, maxit)
+        for i, G in enumerate(probs):
+            x, it, rr, ok = G.pcg(rhs[i], rtol, maxit)
+            assert np.array_equal(host(xs[i]), host(x)), (rtol, i)
+            assert its[i] == it and rel[i] == rr, (rtol, i, its[i], it, rel[i], rr)
+        assert its[3] == 0 and rel[3] == 0.0
+        if maxit == 3:
+            assert not conv and max(its) == 3
+    B.close()
+    for G in probs:
+        G.close()
+
+
 @pytest.mark.parametrize("small", ["0", "1"])
 def test_batch_items_with_different_step_counts_share_launches(nk, monkeypatch, small):
     """Items that differ only in nt form one group: each time loop runs as many iterations
