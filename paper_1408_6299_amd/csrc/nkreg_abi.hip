@@ -4,6 +4,8 @@
 #include <memory>
 #include <string>
 
+#include <algorithm>
+
 #include "group.hpp"
 #include "trace.hpp"
 #include "problem.hpp"
@@ -45,8 +47,17 @@ struct nkreg_batch {
   hipEvent_t fork = nullptr, done = nullptr;
   std::vector<hipEvent_t> joins, waits;
   BatchGraph matvec, gradient;
+  std::vector<hipStream_t> lanes;       // batched PCG: streams for the items' vector work
+  std::vector<hipEvent_t> lane_done;
+  hipEvent_t mv_done = nullptr;
   ~nkreg_batch() {
     if (s) (void)hipStreamSynchronize(s);
+    for (hipStream_t st : lanes) {
+      (void)hipStreamSynchronize(st);
+      (void)hipStreamDestroy(st);
+    }
+    for (hipEvent_t e : lane_done) (void)hipEventDestroy(e);
+    if (mv_done) (void)hipEventDestroy(mv_done);
     matvec.reset();
     gradient.reset();
     for (hipEvent_t e : joins) (void)hipEventDestroy(e);
@@ -804,21 +815,59 @@ int nkreg_batch_pcg(nkreg_batch* b, const void* const* rhs, void* const* x, doub
     }
     // Every iteration: one batched matvec for all items (an item that has stopped keeps its
     // direction, so its product is recomputed unchanged and unused), then each active
-    // item's step and one wait for all of them.
+    // item's own vector work, spread over a few streams so that the items' small launches
+    // overlap, and one wait for all of them. The streams only reorder independent items'
+    // work: every item runs the kernels of its own PCG in its own order.
+    const size_t nl = std::min<size_t>(cnt, 8);
+    while (b->lanes.size() < nl) {
+      hipStream_t st = nullptr;
+      NK_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));  // default priority
+      b->lanes.push_back(st);
+      hipEvent_t e = nullptr;
+      NK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      b->lane_done.push_back(e);
+    }
+    if (!b->mv_done) NK_HIP(hipEventCreateWithFlags(&b->mv_done, hipEventDisableTiming));
+    std::vector<hipStream_t> callers;
+    for (size_t i = 0; i < cnt; ++i) {
+      const hipStream_t cs = b->items[i]->impl->caller_stream();
+      if (std::find(callers.begin(), callers.end(), cs) == callers.end()) callers.push_back(cs);
+    }
+    struct Unroute {
+      nkreg_batch* b;
+      ~Unroute() {
+        for (nkreg_problem* p : b->items) p->impl->route_launches(nullptr);
+      }
+    } unroute{b};
     int round = 0;
     while (any) {
       const nk::Range iter("batch pcg iteration", round++);
+      for (nkreg_problem* p : b->items) p->impl->route_launches(nullptr);
       run_batch(b, b->matvec, record_matvec_fn, ps.data(), qs.data());
-      for (size_t i = 0; i < cnt; ++i)
-        if (b->items[i]->impl->pcg_active()) b->items[i]->impl->pcg_step();
-      for (size_t i = 0; i < cnt; ++i)
-        if (b->items[i]->impl->pcg_active()) NK_HIP(hipStreamSynchronize(b->items[i]->impl->stream()));
+      // the streams take up the items' work after the batched matvec and after all
+      // earlier work on the callers' streams
+      for (hipStream_t cs : callers) {
+        NK_HIP(hipEventRecord(b->mv_done, cs));
+        for (size_t k = 0; k < nl; ++k) NK_HIP(hipStreamWaitEvent(b->lanes[k], b->mv_done, 0));
+      }
+      for (size_t i = 0; i < cnt; ++i) {
+        nk::ProblemBase* p = b->items[i]->impl;
+        if (!p->pcg_active()) continue;
+        p->route_launches(b->lanes[i % nl]);
+        p->pcg_step();
+      }
+      for (size_t k = 0; k < nl; ++k) NK_HIP(hipStreamSynchronize(b->lanes[k]));
       any = false;
       for (size_t i = 0; i < cnt; ++i) {
         nk::ProblemBase* p = b->items[i]->impl;
         if (!p->pcg_active()) continue;
         p->pcg_finish();
         any = p->pcg_active() || any;
+      }
+      // the next batched matvec (and anything after the call) waits for the items' updates
+      for (size_t k = 0; k < nl; ++k) {
+        NK_HIP(hipEventRecord(b->lane_done[k], b->lanes[k]));
+        for (hipStream_t cs : callers) NK_HIP(hipStreamWaitEvent(cs, b->lane_done[k], 0));
       }
     }
     int status = NKREG_OK;

@@ -170,6 +170,8 @@ class ProblemBase {
   virtual void pcg_step() = 0;
   virtual void pcg_finish() = 0;
   virtual int pcg_result(int* iters, double* relres) const = 0;
+  // Sends the handle's launches to st (nullptr: back to the handle's own stream).
+  virtual void route_launches(hipStream_t st) = 0;
   virtual void det_grad_y(const void* v, void* detF, double* stats) = 0;
   virtual int newton(void* v, const nkreg_solve_opts* o, nkreg_solve_report* rep) = 0;
   virtual int picard(void* v, const nkreg_solve_opts* o, const nkreg_picard_opts* po, nkreg_solve_report* rep) = 0;
@@ -1101,6 +1103,7 @@ class ProblemT final : public ProblemBase {
     return pr.active;
   }
   bool pcg_active() const override { return pr.active; }
+  void route_launches(hipStream_t st) override { route(st ? st : user_s); }
   const void* pcg_p() const override { return kp.p; }
   void* pcg_q() override { return kq.p; }
   void pcg_step() override {
