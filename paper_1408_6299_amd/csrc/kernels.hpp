@@ -186,12 +186,58 @@ __device__ __forceinline__ void spec_apply(const SpecArgs<R>& a, int op, const R
   }
 }
 
+// The multiplier's output at one mode of the full-spectrum layout. kv/kt hold the
+// wavenumbers of the axes before the last; q is the packed column. For q > 0, x and y are
+// the inputs at the mode. For q = 0, x and y hold Z = A + iB at the mode and xp, yp the
+// values at the partner mode -k' of the same packed plane; A and B are separated, the
+// multiplier is applied on both planes (k_last = 0 and the Nyquist plane, whose even
+// symbol keeps N_last/2 and whose derivative wavenumber is 0), and out = oA + i oB.
+// Every mode is formed from its own and its partner's inputs, so the outputs keep the
+// planes' Hermitian symmetry exactly (the multipliers are even). y and yp are read only
+// when has_y.
+template <typename R, int D>
+__device__ __forceinline__ void spec_mode(const SpecArgs<R>& a, int op, R kv[3], R kt[3], int q, bool has_y,
+                                          const cplx<R>* x, const cplx<R>* y, const cplx<R>* xp,
+                                          const cplx<R>* yp, cplx<R>* out) {
+  if (q > 0) {
+    kv[D - 1] = R(q); kt[D - 1] = R(q);
+    cplx<R> yy[3];
+#pragma unroll
+    for (int i = 0; i < D; ++i) yy[i] = has_y ? y[i] : cplx<R>{R(0), R(0)};
+    spec_apply<R, D>(a, op, kv, kt, x, yy, out);
+    return;
+  }
+  cplx<R> zA[3], zB[3], yA[3], yB[3];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const cplx<R> z = x[i], zp = xp[i];
+    zA[i] = {R(0.5) * (z.x + zp.x), R(0.5) * (z.y - zp.y)};    // (z + conj zp)/2
+    zB[i] = {R(0.5) * (z.y + zp.y), -R(0.5) * (z.x - zp.x)};   // (z - conj zp)/(2i)
+    if (has_y) {
+      const cplx<R> w = y[i], wp = yp[i];
+      yA[i] = {R(0.5) * (w.x + wp.x), R(0.5) * (w.y - wp.y)};
+      yB[i] = {R(0.5) * (w.y + wp.y), -R(0.5) * (w.x - wp.x)};
+    } else {
+      yA[i] = yB[i] = {R(0), R(0)};
+    }
+  }
+  const int nl = (D == 2) ? a.n2 : a.n3;
+  cplx<R> oA[3], oB[3];
+  kv[D - 1] = R(0); kt[D - 1] = R(0);
+  spec_apply<R, D>(a, op, kv, kt, zA, yA, oA);
+  kv[D - 1] = R(-(nl / 2));
+  spec_apply<R, D>(a, op, kv, kt, zB, yB, oB);
+#pragma unroll
+  for (int i = 0; i < D; ++i) out[i] = {oA[i].x - oB[i].y, oA[i].y + oB[i].x};   // oA + i oB
+}
+
 template <typename R, int D>
 __device__ __forceinline__ void spec_mul_body(const SpecArgs<R>& a, int op) {
   const int nl = (D == 2) ? a.n2 : a.n3;   // last axis length
   const int M = nl / 2;
   const long long rows = (long long)a.n1 * (D == 3 ? a.n2 : 1);
   const long long tot = rows * M * a.nc;
+  const bool has_y = a.Y != nullptr;
   for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot;
        t += (long long)gridDim.x * blockDim.x) {
     const int l = (int)(t / (rows * M));
@@ -205,54 +251,39 @@ __device__ __forceinline__ void spec_mul_body(const SpecArgs<R>& a, int op) {
     if (D == 3) { kv[1] = R(wavenumber(i2, a.n2)); kt[1] = R(deriv_wavenumber(i2, a.n2)); }
     const long long base = (long long)l * D * a.nspec;
     cplx<R> x[3], y[3], o[3];
-    if (q > 0) {
-      kv[D - 1] = R(q); kt[D - 1] = R(q);
 #pragma unroll
-      for (int i = 0; i < D; ++i) {
-        x[i] = a.X[base + i * a.nspec + mi];
-        y[i] = a.Y ? a.Y[base + i * a.nspec + mi] : cplx<R>{R(0), R(0)};
-      }
-      spec_apply<R, D>(a, op, kv, kt, x, y, o);
+    for (int i = 0; i < D; ++i) {
+      x[i] = a.X[base + i * a.nspec + mi];
+      if (has_y) y[i] = a.Y[base + i * a.nspec + mi];
+    }
+    if (q > 0) {
+      spec_mode<R, D>(a, op, kv, kt, q, has_y, x, y, x, y, o);
 #pragma unroll
       for (int i = 0; i < D; ++i) a.out[base + i * a.nspec + mi] = o[i];
       continue;
     }
-    // packed plane: pair (k', -k'); the lexicographically smaller row index handles both
+    // packed plane: the pair (k', -k') is read and written by one thread (the smaller
+    // row index), since the output may overwrite the input
     const int j1 = (a.n1 - i1) % a.n1;
     const int j2 = (D == 3) ? (a.n2 - i2) % a.n2 : 0;
     const long long prow = (D == 2) ? j1 : (long long)j1 * a.n2 + j2;
     if (prow < row) continue;
     const long long mp = prow * M;
-    cplx<R> zA[3], zB[3], yA[3], yB[3];
+    cplx<R> xp[3], yp[3], op_[3];
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      const cplx<R> z = a.X[base + i * a.nspec + mi];
-      const cplx<R> zp = a.X[base + i * a.nspec + mp];
-      zA[i] = {R(0.5) * (z.x + zp.x), R(0.5) * (z.y - zp.y)};    // (z + conj zp)/2
-      zB[i] = {R(0.5) * (z.y + zp.y), -R(0.5) * (z.x - zp.x)};   // (z - conj zp)/(2i)
-      if (a.Y) {
-        const cplx<R> w = a.Y[base + i * a.nspec + mi];
-        const cplx<R> wp = a.Y[base + i * a.nspec + mp];
-        yA[i] = {R(0.5) * (w.x + wp.x), R(0.5) * (w.y - wp.y)};
-        yB[i] = {R(0.5) * (w.y + wp.y), -R(0.5) * (w.x - wp.x)};
-      } else {
-        yA[i] = yB[i] = {R(0), R(0)};
-      }
+      xp[i] = a.X[base + i * a.nspec + mp];
+      if (has_y) yp[i] = a.Y[base + i * a.nspec + mp];
     }
-    // A plane: k_last = 0; B plane: k_last = -N_last/2 (Nyquist: kept in a(k), zeroed in kt)
-    cplx<R> oA[3], oB[3];
-    kv[D - 1] = R(0); kt[D - 1] = R(0);
-    spec_apply<R, D>(a, op, kv, kt, zA, yA, oA);
-    kv[D - 1] = R(-M);
-    spec_apply<R, D>(a, op, kv, kt, zB, yB, oB);
-    // partner values: A(-k') = conj A(k'), B(-k') = conj B(k') (Hermitian planes).
-    // The multipliers are even, so the outputs keep that symmetry.
+    R kvp[3], ktp[3];
+    kvp[0] = R(wavenumber(j1, a.n1)); ktp[0] = R(deriv_wavenumber(j1, a.n1));
+    if (D == 3) { kvp[1] = R(wavenumber(j2, a.n2)); ktp[1] = R(deriv_wavenumber(j2, a.n2)); }
+    spec_mode<R, D>(a, op, kv, kt, 0, has_y, x, y, xp, yp, o);
+    spec_mode<R, D>(a, op, kvp, ktp, 0, has_y, xp, yp, x, y, op_);
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      a.out[base + i * a.nspec + mi] = {oA[i].x - oB[i].y, oA[i].y + oB[i].x};   // oA + i oB
-      if (prow != row) {
-        a.out[base + i * a.nspec + mp] = {oA[i].x + oB[i].y, oB[i].x - oA[i].y}; // conj(oA) + i conj(oB)
-      }
+      a.out[base + i * a.nspec + mi] = o[i];
+      if (prow != row) a.out[base + i * a.nspec + mp] = op_[i];
     }
   }
 }

@@ -502,6 +502,95 @@ __global__ __launch_bounds__((ColShape<N, E>::NT)) void k_col_wt(const ColPtrs<R
   col_w_body<R, N, E, MODE>(p.in, p.add, p.out, a, scale, tw, twb, (int)(blockIdx.z % nfz));
 }
 
+// The 2D control-space multiplier between its column transforms, in one pass: each
+// column group takes column q of the D components of coefficient l (blockIdx.y) of X and,
+// with HAS_Y, of Y; transforms them forward, applies spec_mode per mode and transforms
+// the D results back into out (which may be X). Column 0 holds the packed planes, whose
+// partner values (row -k_1 of the same column) come through LDS. The transforms run in
+// lockstep (wave_fft_multi), so the result rounds like the separate forward pass,
+// k_spec_mul and inverse pass up to the order of the butterflies' products.
+template <typename R, int N, bool HAS_Y>
+__device__ __forceinline__ void col_spec_body(const SpecArgs<R>& sa, int op, int inner,
+                                              const cplx<R>* __restrict__ tw, int twb) {
+  constexpr int E = 8, D = 2;
+  using CS = ColShape<N, E>;
+  static_assert(!CS::BLOCK && CS::NT == 64, "one wavefront per column group");
+  constexpr int LS = CS::LS, SPW = CS::SPW;
+  constexpr int PADN = padded_e<E>(N);
+  constexpr int NF = HAS_Y ? 2 * D : D;
+  __shared__ cplx<R> lds[SPW * NF * PADN];
+  const int lane = threadIdx.x;
+  const int c = lane % SPW, j = lane / SPW;
+  const int nbx = gridDim.x;
+  const int bx = (nbx % 8 == 0) ? (int)(blockIdx.x % 8) * (nbx / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
+  const long long colr = (long long)bx * SPW + c;
+  const bool live = colr < inner;
+  const int q = (int)(live ? colr : inner - 1);
+  const long long base = (long long)blockIdx.y * D * sa.nspec + q;
+  cplx<R>* S = lds + c * NF * PADN;
+  WaveTwiddles<R, N, E> T;
+  T.load(j, tw, twb);
+  cplx<R> v[NF][E];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    const cplx<R>* src = (f < D ? sa.X : sa.Y) + base + (long long)(f % D) * sa.nspec;
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[f][e] = src[(long long)(j + LS * e) * inner];
+  }
+  wave_fft_multi<R, N, E, false, NF, NF>(v, j, S, PADN, T);
+  // the group that holds column 0 (the same for every lane of the wavefront) stages its
+  // transformed columns in LDS, where the packed column's lanes find their partner values
+  // at row -k_1
+  const bool packed = bx == 0;
+  if (packed) {
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int e = 0; e < E; ++e) S[f * N + j + LS * e] = v[f][e];
+    wave_lds_sync();
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i1 = j + LS * e;
+    R kv[3], kt[3];
+    kv[0] = R(wavenumber(i1, N)); kt[0] = R(deriv_wavenumber(i1, N));
+    cplx<R> x[D], y[D], xp[D], yp[D], o[D];
+    const int ip = (N - i1) & (N - 1);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      x[i] = v[i][e];
+      xp[i] = q == 0 ? S[i * N + ip] : x[i];
+      if (HAS_Y) {
+        y[i] = v[D + i][e];
+        yp[i] = q == 0 ? S[(D + i) * N + ip] : y[i];
+      }
+    }
+    spec_mode<R, D>(sa, op, kv, kt, q, HAS_Y, x, y, xp, yp, o);
+#pragma unroll
+    for (int i = 0; i < D; ++i) v[i][e] = o[i];
+  }
+  if (packed) wave_lds_sync();   // the partner reads precede the inverse transforms' exchanges
+  wave_fft_multi<R, N, E, true, D, NF>(v, j, S, PADN, T);
+  if (live) {
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int e = 0; e < E; ++e) sa.out[base + (long long)i * sa.nspec + (long long)(j + LS * e) * inner] = v[i][e];
+  }
+}
+
+template <typename R, int N, bool HAS_Y>
+__global__ __launch_bounds__(64) void k_col_spec(SpecArgs<R> sa, int op, int inner, const cplx<R>* __restrict__ tw,
+                                                int twb) {
+  col_spec_body<R, N, HAS_Y>(sa, op, inner, tw, twb);
+}
+// One launch over the items of a batch group: item blockIdx.z uses tab[blockIdx.z].
+template <typename R, int N, bool HAS_Y>
+__global__ __launch_bounds__(64) void k_col_spec_t(const SpecArgs<R>* __restrict__ tab, int op, int inner,
+                                                  const cplx<R>* __restrict__ tw, int twb) {
+  col_spec_body<R, N, HAS_Y>(tab[blockIdx.z], op, inner, tw, twb);
+}
+
 // Tiled column pass for long strided axes. A workgroup owns CT adjacent
 // columns (CT * sizeof(cplx) = 64 or 128 bytes, a whole cache line per row):
 // it stages the N x CT tile through LDS with row-coalesced loads, transforms

@@ -823,6 +823,8 @@ int nkreg_batch_pcg(nkreg_batch* b, const void* const* rhs, void* const* x, doub
       hipStream_t st = nullptr;
       NK_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));  // default priority
       b->lanes.push_back(st);
+    }
+    while (b->lane_done.size() < nl) {
       hipEvent_t e = nullptr;
       NK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
       b->lane_done.push_back(e);
@@ -833,9 +835,12 @@ int nkreg_batch_pcg(nkreg_batch* b, const void* const* rhs, void* const* x, doub
       const hipStream_t cs = b->items[i]->impl->caller_stream();
       if (std::find(callers.begin(), callers.end(), cs) == callers.end()) callers.push_back(cs);
     }
+    // on every way out (an error included) the items launch on their own streams again and
+    // no work of theirs is left on the batch's streams
     struct Unroute {
       nkreg_batch* b;
       ~Unroute() {
+        for (hipStream_t st : b->lanes) (void)hipStreamSynchronize(st);
         for (nkreg_problem* p : b->items) p->impl->route_launches(nullptr);
       }
     } unroute{b};

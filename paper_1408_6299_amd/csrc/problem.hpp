@@ -1016,6 +1016,7 @@ class ProblemT final : public ProblemBase {
   std::string describe() override {
     return std::string("{\"transport_precision\": ") + (kF64 ? "64" : "32") + ", \"graphs\": " +
            (use_graphs ? "true" : "false") + ", \"persistent_sweeps\": " + (small_sweeps ? "true" : "false") + ", \"sweep_timing\": \"" + sweep_timing + "\", \"assembly_sweeps\": \"" + assembly_timing + "\"" +
+           ", \"spec_fused\": " + (sp64.spec_fused() ? "true" : "false") +
            ", \"row_E\": " + std::to_string(sp.rowE) + ", \"col_E\": " +
            std::to_string(sp.colE) + ", \"col_deriv_symbols\": [" + col_symbols() + "], \"autotune\": \"" + tuning +
            "\"}";

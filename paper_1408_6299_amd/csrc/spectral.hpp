@@ -157,13 +157,14 @@ struct KernelTimer {
 // arguments every item of a group shares. A batch replays each position of
 // equal-shaped recordings as one launch over all items of the group.
 struct LaunchRec {
-  enum Kind { ROW, COL, FILL, CONV, SPEC, COPY, RED, REDF };
+  enum Kind { ROW, COL, FILL, CONV, SPEC, COPY, RED, REDF, SPECCOL };
   int kind = ROW;
   const void* kernel = nullptr;      // group form of the kernel
   dim3 grid, block;
   std::vector<unsigned char> entry;  // this item's table entry
   const void* tw = nullptr;          // ROW, COL: twiddle table (equal across a group)
-  int iarg = 0;                      // ROW: lmax; COL: twb; SPEC: op; REDF: partials
+  int iarg = 0;                      // ROW: lmax; COL: twb; SPEC, SPECCOL: op; REDF: partials
+  int iarg2 = 0;                     // SPECCOL: twb (and ca.inner the column stride)
   int nfz = 1;                       // COL: fields per item
   ColArgs ca{};
   double scale = 0.0, fval = 0.0;    // COL scale, FILL value
@@ -184,7 +185,7 @@ struct LaunchRec {
   }
   bool same_shape(const LaunchRec& o) const {
     return kind == o.kind && kernel == o.kernel && grid.x == o.grid.x && grid.y == o.grid.y &&
-           grid.z == o.grid.z && block.x == o.block.x && iarg == o.iarg && nfz == o.nfz &&
+           grid.z == o.grid.z && block.x == o.block.x && iarg == o.iarg && iarg2 == o.iarg2 && nfz == o.nfz &&
            std::memcmp(&ca, &o.ca, sizeof(ColArgs)) == 0 && scale == o.scale && fval == o.fval && f64 == o.f64 &&
            cnt == o.cnt && entry.size() == o.entry.size() && bytes == o.bytes && stage == o.stage && len == o.len &&
            dim == o.dim && elems == o.elems && conv == o.conv && nc1 == o.nc1;
@@ -278,7 +279,15 @@ class Spectral {
   void read_col_env() {
     const int v = col_env_variant(g);
     if (v >= 0) colE = v;
+    const char* f = std::getenv("NKREG_FUSED_SPEC");
+    fuseSpec = !(f && f[0] == '0');
   }
+  // The control-space multiplier as one fused column pass (k_col_spec) on 2D grids, except
+  // with the 4-per-lane column variant (which rounds differently, so its handles keep the
+  // separate passes). Launched and recorded alike, so batch items round like their
+  // handles. NKREG_FUSED_SPEC=0 keeps the separate passes.
+  bool fuseSpec = true;
+  bool spec_fused() const { return fuseSpec && g.d == 2 && colE != 4; }
   bool owns_tw = false;
 
   // ---- column passes ----
@@ -335,6 +344,47 @@ class Spectral {
       case 512: col_n<512>(mode, in, add, out, nf, scale, outer, inner); break;
       default: throw HipError(-2, "unsupported axis length");
     }
+  }
+
+  // Forward column transforms, multiplier and inverse column transforms of the 2D
+  // spectra a.X (and a.Y) into a.out, one launch.
+  void col_spec(const SpecArgs<R>& a, int op, int nf) {
+    switch (g.n[0]) {
+      case 8: col_spec_n<8>(a, op, nf); break;
+      case 16: col_spec_n<16>(a, op, nf); break;
+      case 32: col_spec_n<32>(a, op, nf); break;
+      case 64: col_spec_n<64>(a, op, nf); break;
+      case 128: col_spec_n<128>(a, op, nf); break;
+      case 256: col_spec_n<256>(a, op, nf); break;
+      case 512: col_spec_n<512>(a, op, nf); break;
+      default: throw HipError(-2, "unsupported axis length");
+    }
+  }
+  template <int N>
+  void col_spec_n(const SpecArgs<R>& a, int op, int nf) {
+    constexpr int SPW = ColShape<N, 8>::SPW;
+    const int inner = g.L / 2;
+    const dim3 grid((unsigned)((inner + SPW - 1) / SPW), (unsigned)a.nc);
+    const int twb = g.lmax / N;
+    if (rec) {
+      LaunchRec r;
+      r.kind = LaunchRec::SPECCOL;
+      r.kernel = a.Y ? (const void*)k_col_spec_t<R, N, true> : (const void*)k_col_spec_t<R, N, false>;
+      r.grid = grid;
+      r.block = dim3(64);
+      r.iarg = op;
+      r.iarg2 = twb;
+      r.ca.inner = inner;
+      r.tw = tw;
+      r.f64 = sizeof(R) == 8;
+      r.set_entry(a);
+      rec->recs.push_back(r);
+      return;
+    }
+    if (tally) tally->add((double)nf * g.nspec * sizeof(cplx<R>) * (a.Y ? 3 : 2));
+    if (a.Y) hipLaunchKernelGGL((k_col_spec<R, N, true>), grid, dim3(64), 0, s, a, op, inner, (const cplx<R>*)tw, twb);
+    else hipLaunchKernelGGL((k_col_spec<R, N, false>), grid, dim3(64), 0, s, a, op, inner, (const cplx<R>*)tw, twb);
+    NK_LAUNCHED();
   }
 
   // ---- row stages ----
@@ -415,12 +465,6 @@ class Spectral {
     const int nf = nc * g.d;
     r2c(X, Xs, nf);
     if (Y) r2c(Y, Ys, nf);
-    if (g.d == 3) {
-      col(COL_FWD, 1, Xs, nullptr, Xs, nf, R(1));
-      if (Y) col(COL_FWD, 1, Ys, nullptr, Ys, nf, R(1));
-    }
-    col(COL_FWD, 0, Xs, nullptr, Xs, nf, R(1));
-    if (Y) col(COL_FWD, 0, Ys, nullptr, Ys, nf, R(1));
     SpecArgs<R> a{};
     a.X = Xs; a.Y = Y ? Ys : nullptr; a.out = Xs;
     a.n1 = g.n[0]; a.n2 = g.n[1]; a.n3 = g.d == 3 ? g.n[2] : 1;
@@ -430,6 +474,18 @@ class Spectral {
     for (int i = 0; i < g.d - 1; ++i) sc /= g.n[i];
     a.scale = (R)sc;
     a.nspec = g.nspec;
+    if (spec_fused()) {
+      // 2D launches: the column transforms and the multiplier in one pass (same bits)
+      col_spec(a, op, nf);
+      c2r(Xs, out, nf, R(1));
+      return;
+    }
+    if (g.d == 3) {
+      col(COL_FWD, 1, Xs, nullptr, Xs, nf, R(1));
+      if (Y) col(COL_FWD, 1, Ys, nullptr, Ys, nf, R(1));
+    }
+    col(COL_FWD, 0, Xs, nullptr, Xs, nf, R(1));
+    if (Y) col(COL_FWD, 0, Ys, nullptr, Ys, nf, R(1));
     const long long work = (long long)nc * g.nspec;
     const int blocks = (int)std::min<long long>((work + 255) / 256, 4096);
     if (rec) {

@@ -508,6 +508,47 @@ def test_column_variant_pinned_per_grid(nk, monkeypatch):
     G.close()
 
 
+@pytest.mark.parametrize("shape,nc,reg,stokes,prec", [
+    ((8, 8), 1, 1, False, 64),
+    ((16, 32), 2, 2, True, 32),
+    ((64, 64), 3, 2, True, 32),
+    ((128, 64), 1, 2, False, 64),
+    ((32, 256), 1, 1, True, 64),
+    ((512, 512), 1, 2, False, 32),
+])
+def test_fused_control_space_pass_matches_separate_passes(nk, monkeypatch, shape, nc, reg, stokes, prec):
+    """On 2D grids the control-space multiplier runs as one fused column pass (k_col_spec):
+    forward column transforms, the multiplier per mode (with the packed k_2 = 0 / Nyquist
+    column's partner modes) and inverse transforms, across column groups of 64 columns
+    (8 points) down to one (512 points). The gradient, GN matvec, P^-1, K and A agree with
+    those of the separate passes (NKREG_FUSED_SPEC=0) to FP64 rounding: the lockstep
+    transforms may order a butterfly's products differently, and A (|k|^4 on H2)
+    amplifies a last-bit difference of the highest modes by up to (N/2)^4: the bound is
+    1e-15 (N/2)^(2 reg) of the output's largest entry for A w, g and H w (which contain
+    beta A), and 1e-13 for P^-1 w and K w, which amplify nothing."""
+    nt = 4
+    mT, mR, vstar, w = smooth_inputs(shape, nt, nc=nc, divfree=stokes)
+    res = []
+    for fused in (True, False):
+        if fused:
+            monkeypatch.delenv("NKREG_FUSED_SPEC", raising=False)
+        else:
+            monkeypatch.setenv("NKREG_FUSED_SPEC", "0")
+        G = nk.Problem(shape, nt, nc=nc, reg=reg, incompressible=stokes, beta=1e-2, precision=prec)
+        assert G.describe()["spec_fused"] is fused
+        G.set_images(dev_t(mT, prec), dev_t(mR, prec))
+        J, _, _, g = G.objective_gradient(dev_v(0.5 * vstar))
+        x = dev_v(w)
+        out = [J, host(g), host(G.hessian_matvec(x)), host(G.precond(x)), host(G.project(x)), host(G.apply_reg(x))]
+        res.append(out)
+        G.close()
+    assert abs(res[0][0] - res[1][0]) <= 1e-13 * abs(res[1][0])
+    amp = (max(shape) / 2.0) ** (2 * reg)
+    for name, a, b in zip(("g", "Hw", "P^-1 w", "K w", "A w"), res[0][1:], res[1][1:]):
+        bound = 1e-13 if name in ("P^-1 w", "K w") else 1e-15 * amp
+        assert np.max(np.abs(a - b)) <= bound * np.max(np.abs(b)), name
+
+
 def test_handle_on_a_side_stream_matches_the_default_stream(nk):
     """A handle runs on the stream it was created with: work queued there (gradient,
     eager and replayed matvecs, PCG) gives the same bits as on the default stream."""
