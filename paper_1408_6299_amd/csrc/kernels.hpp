@@ -91,10 +91,12 @@ struct StageArgs {
   const R* src_a;
   const R* src_b;
   R ca, cb;                  // lam = ca * src_a + cb * src_b (src_b may be null)
+  const float* src_bf;       // ST_R2C with a second source: src_b or, in FP32 (widened), src_bf
+  int split;                 // ST_R2C: fields fy >= split come from the second source at fy - split and go to out1
   R h;                       // time step
   R scale;                   // C2R output scale (ST_C2R, ST_GRAD, ST_DIV multiply by scale/L)
   int nc;
-  int zero_state;            // INC1 at j = 0: the incremental state is zero
+  int zero_state;            // INC1 at j = 0: the incremental state is zero; ADJ1 at j = nt - 1: F starts at zero
   int inactive;              // batch groups: this item has no work in this launch (its time loop has ended)
   int skip_out;              // ADJ2 at j = 0: no further spectra needed
   long long n;               // points per scalar field

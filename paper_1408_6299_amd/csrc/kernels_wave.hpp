@@ -150,6 +150,8 @@ __device__ __forceinline__ void row_body_at(const StageArgs<R>& a, const cplx<R>
   cplx<R> V[DV][E], W[DW][E], G0[DG][E], G1[DG][E], FV[DF][E], X1[E], X2[E];
   cplx<R> LT0[E], LT1[E], GT0[DT][E], GT1[DT][E];
   const R* wv = (KIND == ST_FWD1 || KIND == ST_INC1) ? a.b0 : ((KIND == ST_FWD2 || KIND == ST_INC2) ? a.b1 : a.bv);
+  // ST_R2C: this field comes from the second source (and goes to out1)
+  const bool r2c_second = KIND == ST_R2C && (a.src_b || a.src_bf) && fy >= a.split;
   const bool need_v = !(KIND == ST_ADJ2 && a.skip_out);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -202,7 +204,16 @@ __device__ __forceinline__ void row_body_at(const StageArgs<R>& a, const cplx<R>
       X1[e] = ld2(a.src_a, e);
       X2[e] = a.src_b ? ld2(a.src_b, e) : cplx<R>{R(0), R(0)};
     }
-    if constexpr (KIND == ST_R2C) X1[e] = ld2(a.src_a + (long long)fy * a.fstride_in, e);
+    if constexpr (KIND == ST_R2C) {
+      if (!r2c_second) {
+        X1[e] = ld2(a.src_a + (long long)fy * a.fstride_in, e);
+      } else if (a.src_bf) {
+        const float2 f = reinterpret_cast<const float2*>(a.src_bf + (long long)(fy - a.split) * a.fstride_in)[pidx(e)];
+        X1[e] = {R(f.x), R(f.y)};
+      } else {
+        X1[e] = ld2(a.src_b + (long long)(fy - a.split) * a.fstride_in, e);
+      }
+    }
   }
 
   // ---- input row spectra: C2R packing -> natural layout -> inverse FFT ----
@@ -312,13 +323,15 @@ __device__ __forceinline__ void row_body_at(const StageArgs<R>& a, const cplx<R>
           t0 = pfma(LT1[e], GT0[c][e], t0);   // lam*_j grad m~^j
           t1 = pfma(LT0[e], GT1[c][e], t1);   // lam^{j+1} grad m~*_j
         }
+        // the first adjoint step starts the accumulators at zero (their contents are ignored)
         if constexpr (NC1) {
-          const cplx<R> f = cadd(FV[c][e], cscale(cadd(cscale(t0, a.b0[0]), cscale(t1, a.b1[0])), hh));
+          const cplx<R> f0 = a.zero_state ? cplx<R>{R(0), R(0)} : FV[c][e];
+          const cplx<R> f = cadd(f0, cscale(cadd(cscale(t0, a.b0[0]), cscale(t1, a.b1[0])), hh));
           st2(a.F + (long long)c * n, e, f);
         } else {
           for (int l = 0; l < a.nc; ++l) {
             R* fp = a.F + ((long long)l * D + c) * n;
-            const cplx<R> f0 = ld2(fp, e);
+            const cplx<R> f0 = a.zero_state ? cplx<R>{R(0), R(0)} : ld2(fp, e);
             st2(fp, e, cadd(f0, cscale(cadd(cscale(t0, a.b0[l]), cscale(t1, a.b1[l])), hh)));
           }
         }
@@ -357,12 +370,12 @@ __device__ __forceinline__ void row_body_at(const StageArgs<R>& a, const cplx<R>
 #pragma unroll
       for (int e = 0; e < E; ++e) S[k * PADM + pad_e<E>(j + LS * e)] = O[k][e];
     wave_lds_sync();
-    const long long fo = (long long)fy * a.fstride_out;
+    const long long fo = (long long)(r2c_second ? fy - a.split : fy) * a.fstride_out;
 #pragma unroll
     for (int k = 0; k < KOUT; ++k) {
       cplx<R>* dst;
       if constexpr (ADJOUT) dst = (k == 0) ? a.out0 : (k == 1 ? a.out1 : a.out2);
-      else dst = a.out0;
+      else dst = r2c_second ? a.out1 : a.out0;
       dst += fo + c0;
       const bool ik = ADJOUT && D > 1 && k == D - 1;
 #pragma unroll

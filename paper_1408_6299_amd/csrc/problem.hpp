@@ -269,7 +269,7 @@ class ProblemT final : public ProblemBase {
   DevBuf<R> ckpt, accr, mr;
   DevBuf<cplx<R>> Tr, Tsr, S1r, S2r;
   // control space (FP64)
-  DevBuf<double> v, F64, tmpv, kx, kr, kz, kp, kq, gbuf, sbuf, vtrial, rhsbuf;
+  DevBuf<double> v, tmpv, kx, kr, kz, kp, kq, gbuf, sbuf, vtrial, rhsbuf;
   DevBuf<cplx<double>> Xs, Ys;
 
   static hipStream_t make_stream() {
@@ -304,7 +304,7 @@ class ProblemT final : public ProblemBase {
     }
     acc.alloc(n); lam.alloc(n); m1.alloc(n); mt1.alloc(n);
     F.alloc(nv);
-    if (!kF64) { vR.alloc(nv); vtR.alloc(nv); F64.alloc(nv); }
+    if (!kF64) { vR.alloc(nv); vtR.alloc(nv); }
     T.alloc(g.nspec); Ts.alloc(g.nspec); S1.alloc(g.nspec); S2.alloc(g.nspec);
     U.alloc((size_t)3 * g.nspec); Dsp.alloc(g.nspec);
     v.alloc(nv); tmpv.alloc(nv);
@@ -530,14 +530,14 @@ class ProblemT final : public ProblemBase {
       return dst.p;
     }
   }
-  // body force in transport precision -> FP64
-  const double* force64() {
-    if constexpr (kF64) {
-      return F.p;
-    } else {
-      convert<R, double>(nv, F.p, F64.p);
-      return F64.p;
-    }
+  // beta A x + K[F] for the body force F in the transport precision (read as FP32 and
+  // widened by the R2C when the transport runs in FP32)
+  void hess_vecop(const double* x, double* out) {
+    if constexpr (kF64)
+      sp64.vecop(OP_HESS, x, (const double*)F.p, out, nc, cfg.reg, cfg.incompressible, cfg.beta, Xs.p, Ys.p);
+    else
+      sp64.vecop(OP_HESS, x, nullptr, out, nc, cfg.reg, cfg.incompressible, cfg.beta, Xs.p, Ys.p,
+                 (const float*)F.p);
   }
 
   // The images are kept centred: the template's mean c is subtracted from both.
@@ -662,7 +662,6 @@ class ProblemT final : public ProblemBase {
     cplx<R>* U0 = U.p;
     cplx<R>* U1 = U.p + ns;
     cplx<R>* U2 = U.p + 2 * ns;
-    fill(nv, R(0), Fout);
     StageArgs<R> a{};
     a.vl = vl; a.nc = nc; a.h = h;
     a.src_a = src_a; a.src_b = src_b; a.ca = ca; a.cb = cb;
@@ -677,6 +676,7 @@ class ProblemT final : public ProblemBase {
       StageArgs<R> b{};
       b.spec = Dsp.p; b.vl = vl; b.nc = nc; b.h = h;
       b.lam = lam.p; b.acc = acc.p; b.F = Fout;
+      b.zero_state = (j == nt - 1);   // the first step overwrites the force accumulators
       b.g0 = trajp(j, 0); b.g1 = trajp(j, 1);
       if (record_lam) { b.lamw0 = ltp(j, 0); b.lamw1 = ltp(j, 1); }
       if (NEWT) { b.vtl = vtl; b.lt0 = ltp(j, 0); b.lt1 = ltp(j, 1); b.gt0 = mtp(j, 0); b.gt1 = mtp(j, 1); }
@@ -820,7 +820,7 @@ class ProblemT final : public ProblemBase {
     objective_enqueue(v.p);
     adjoint_sweep_k<false>(vl, nullptr, R(1), mR.p, R(-1), m1.p, F.p, full_newton);
     double* gdst = gout ? (double*)gout : gbuf.p;
-    sp64.vecop(OP_HESS, v.p, force64(), gdst, nc, cfg.reg, cfg.incompressible, cfg.beta, Xs.p, Ys.p);
+    hess_vecop(v.p, gdst);
   }
 
   void objective_gradient(const void* vin, double* J, double* Jd, double* Jr, void* gout) override {
@@ -1036,7 +1036,7 @@ class ProblemT final : public ProblemBase {
       held.assign(S, -1);
       throw;
     }
-    sp64.vecop(OP_HESS, vt, force64(), (double*)out, nc, cfg.reg, cfg.incompressible, cfg.beta, Xs.p, Ys.p);
+    hess_vecop(vt, (double*)out);
   }
 
   void precond(const void* r, void* z) override {

@@ -419,6 +419,19 @@ class Spectral {
     a.fstride_out = g.nspec;
     row<ST_R2C>(a, nf);
   }
+  // R2C of nf fields of X into Xs and nf fields of Y (or of Yf, FP32) into Ys, one launch.
+  void r2c2(const R* X, cplx<R>* Xs, const R* Y, const float* Yf, cplx<R>* Ys, int nf) {
+    StageArgs<R> a{};
+    a.src_a = X;
+    a.src_b = Yf ? nullptr : Y;
+    a.src_bf = Yf;
+    a.split = nf;
+    a.out0 = Xs;
+    a.out1 = Ys;
+    a.fstride_in = g.npts;
+    a.fstride_out = g.nspec;
+    row<ST_R2C>(a, 2 * nf);
+  }
   void c2r(const cplx<R>* in, R* out, int nf, R scale) {
     StageArgs<R> a{};
     a.spec = in;
@@ -460,13 +473,16 @@ class Spectral {
   void ik_last(cplx<R>* T);
 
   // out (nc x d fields) = op(X, Y); Xs, Ys workspace of nc*d spectra each.
+  // out = the op's multiplier applied to X (and Y: OP_HESS), all [nc][d] fields; Y may
+  // instead be given in FP32 (Yf), which the R2C widens as it reads.
   void vecop(int op, const R* X, const R* Y, R* out, int nc, int reg, int proj, R beta, cplx<R>* Xs,
-             cplx<R>* Ys) {
+             cplx<R>* Ys, const float* Yf = nullptr) {
     const int nf = nc * g.d;
-    r2c(X, Xs, nf);
-    if (Y) r2c(Y, Ys, nf);
+    const bool hasY = Y || Yf;
+    if (hasY) r2c2(X, Xs, Y, Yf, Ys, nf);
+    else r2c(X, Xs, nf);
     SpecArgs<R> a{};
-    a.X = Xs; a.Y = Y ? Ys : nullptr; a.out = Xs;
+    a.X = Xs; a.Y = hasY ? Ys : nullptr; a.out = Xs;
     a.n1 = g.n[0]; a.n2 = g.n[1]; a.n3 = g.d == 3 ? g.n[2] : 1;
     a.d = g.d; a.nc = nc; a.reg = reg; a.proj = proj;
     a.beta = beta;
@@ -482,10 +498,10 @@ class Spectral {
     }
     if (g.d == 3) {
       col(COL_FWD, 1, Xs, nullptr, Xs, nf, R(1));
-      if (Y) col(COL_FWD, 1, Ys, nullptr, Ys, nf, R(1));
+      if (hasY) col(COL_FWD, 1, Ys, nullptr, Ys, nf, R(1));
     }
     col(COL_FWD, 0, Xs, nullptr, Xs, nf, R(1));
-    if (Y) col(COL_FWD, 0, Ys, nullptr, Ys, nf, R(1));
+    if (hasY) col(COL_FWD, 0, Ys, nullptr, Ys, nf, R(1));
     const long long work = (long long)nc * g.nspec;
     const int blocks = (int)std::min<long long>((work + 255) / 256, 4096);
     if (rec) {
@@ -498,7 +514,7 @@ class Spectral {
       r.set_entry(a);
       rec->recs.push_back(r);
     } else {
-      if (tally) tally->add((double)nf * g.nspec * sizeof(cplx<R>) * (Y ? 3 : 2));
+      if (tally) tally->add((double)nf * g.nspec * sizeof(cplx<R>) * (hasY ? 3 : 2));
       if (g.d == 2) hipLaunchKernelGGL((k_spec_mul<R, 2>), dim3(blocks), dim3(256), 0, s, a, op);
       else hipLaunchKernelGGL((k_spec_mul<R, 3>), dim3(blocks), dim3(256), 0, s, a, op);
       NK_LAUNCHED();
@@ -662,7 +678,12 @@ class Spectral {
       return;
     }
     const bool timed = timer && timer->want(KIND);
-    if (tally) tally->add((double)nf * stage_fields<KIND>(a, D) * g.npts * sizeof(R));
+    if (tally) {
+      double b = (double)nf * stage_fields<KIND>(a, D) * g.npts * sizeof(R);
+      // fields read in FP32 by a two-source R2C
+      if (KIND == ST_R2C && a.src_bf) b -= (double)(nf - a.split) * g.npts * (sizeof(R) - sizeof(float));
+      tally->add(b);
+    }
     if (!uses_nc || a.nc <= 1)
       launch(k_row_w<R, L, E, KIND, D, true>, grid, dim3(64), timed, a, (const cplx<R>*)tw, g.lmax);
     else if constexpr (uses_nc)
