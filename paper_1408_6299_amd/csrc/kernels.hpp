@@ -369,6 +369,29 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_final(const double* __re
   reduce_final_body<MAX>(partial, np, out);
 }
 
+// |x|^2 and <x, y> in one pass over x and y: each block's two partial sums are formed in
+// the order of the single reductions (RED_SUMSQ, RED_DOT), so each result equals its own
+// reduction bit for bit. partial holds [2][gridDim.x].
+template <typename R>
+__global__ __launch_bounds__(kRedThreads) void k_reduce_sumsq_dot(const R* __restrict__ x, const R* __restrict__ y,
+                                                                  long long cnt, double* partial) {
+  double s2 = 0.0, sd = 0.0;
+  for (long long i = (long long)blockIdx.x * kRedThreads + threadIdx.x; i < cnt;
+       i += (long long)gridDim.x * kRedThreads) {
+    const double a = (double)x[i];
+    s2 += a * a;
+    sd += a * (double)y[i];
+  }
+  block_reduce_store<false>(s2, partial + blockIdx.x);
+  __syncthreads();
+  block_reduce_store<false>(sd, partial + gridDim.x + blockIdx.x);
+}
+// Final stage of np partial sums per reduction for gridDim.x reductions side by side.
+static __global__ __launch_bounds__(kRedThreads) void k_reduce_final_n(const double* __restrict__ partial,
+                                                                       int np, double* out) {
+  reduce_final_body<false>(partial + (long long)blockIdx.x * np, np, out + blockIdx.x);
+}
+
 // Batch-group forms of the two reduction stages: each item takes its pointers
 // from the table (blockIdx.z); the per-item grid and summation order are those of the
 // plain forms.

@@ -128,6 +128,17 @@ class Reducer {
       hipLaunchKernelGGL((k_reduce_final<false>), dim3(1), dim3(kRedThreads), 0, s, partial.p, nb, result.p + slot);
     NK_LAUNCHED();
   }
+  // |x|^2 into slot and <x, y> into slot + 1, each equal to its own enqueue (issued only)
+  template <typename R>
+  void enqueue_sumsq_dot(const R* x, const R* y, long long cnt, int slot) {
+    if (rec) throw HipError(NKREG_EHIP, "paired reduction is not recorded");
+    const int nb = (int)std::max<long long>(1, std::min<long long>(kRedBlocks, (cnt + kRedThreads - 1) / kRedThreads));
+    hipLaunchKernelGGL((k_reduce_sumsq_dot<R>), dim3(nb), dim3(kRedThreads), 0, s, x, y, cnt, partial.p);
+    NK_LAUNCHED();
+    hipLaunchKernelGGL(k_reduce_final_n, dim3(2), dim3(kRedThreads), 0, s, (const double*)partial.p, nb,
+                       result.p + slot);
+    NK_LAUNCHED();
+  }
   // copies slots [0, n) to the host and waits
   void fetch(int n) {
     NK_HIP(hipMemcpyAsync(host, result.p, n * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1113,8 +1124,7 @@ class ProblemT final : public ProblemBase {
                        (const double*)red.result.p + 2, (const double*)kp.p, (const double*)kq.p, pr.x, kr.p);
     NK_LAUNCHED();
     precond(kr.p, kz.p);
-    red.enqueue<double>(RED_SUMSQ, kr.p, nullptr, nv, 0);
-    red.enqueue<double>(RED_DOT, kr.p, kz.p, nv, 1);
+    red.enqueue_sumsq_dot<double>(kr.p, kz.p, nv, 0);   // |r|^2 and <r, z> in one pass
     NK_HIP(hipMemcpyAsync(red.host, red.result.p, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
   }
   void pcg_finish() override {
