@@ -104,7 +104,7 @@ inline void launch_group(const LaunchRec& r, int G, void* tab, hipStream_t st) {
   const unsigned z = grid.z;
   grid.z = z * (unsigned)G;
   const void* tw = r.tw;
-  int iarg = r.iarg, iarg2 = r.iarg2, nfz = r.nfz, inner = r.ca.inner;
+  int iarg = r.iarg, nfz = r.nfz, inner = r.ca.inner;
   long long cnt = r.cnt;
   ColArgs ca = r.ca;
   float sf = (float)r.scale, vf = (float)r.fval;
@@ -119,7 +119,7 @@ inline void launch_group(const LaunchRec& r, int G, void* tab, hipStream_t st) {
     case LaunchRec::FILL: args[0] = &cnt; args[1] = r.f64 ? (void*)&vd : (void*)&vf; args[2] = &tab; break;
     case LaunchRec::CONV: args[0] = &cnt; args[1] = &tab; break;
     case LaunchRec::SPEC: args[0] = &tab; args[1] = &iarg; break;
-    case LaunchRec::SPECCOL: args[0] = &tab; args[1] = &iarg; args[2] = &inner; args[3] = &tw; args[4] = &iarg2; break;
+    case LaunchRec::SPECCOL: args[0] = &tab; args[1] = &inner; args[2] = &tw; args[3] = &iarg; break;
     case LaunchRec::RED: args[0] = &cnt; args[1] = &tab; break;
     case LaunchRec::REDF: args[0] = &iarg; args[1] = &tab; break;
     default: throw HipError(NKREG_EHIP, "unexpected recorded launch");

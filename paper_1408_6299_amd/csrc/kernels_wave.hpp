@@ -516,21 +516,25 @@ __global__ __launch_bounds__((ColShape<N, E>::NT)) void k_col_wt(const ColPtrs<R
 }
 
 // The 2D control-space multiplier between its column transforms, in one pass: each
-// column group takes column q of the D components of coefficient l (blockIdx.y) of X and,
-// with HAS_Y, of Y; transforms them forward, applies spec_mode per mode and transforms
-// the D results back into out (which may be X). Column 0 holds the packed planes, whose
-// partner values (row -k_1 of the same column) come through LDS. The transforms run in
-// lockstep (wave_fft_multi), so the result rounds like the separate forward pass,
-// k_spec_mul and inverse pass up to the order of the butterflies' products.
-template <typename R, int N, bool HAS_Y>
-__device__ __forceinline__ void col_spec_body(const SpecArgs<R>& sa, int op, int inner,
-                                              const cplx<R>* __restrict__ tw, int twb) {
+// column group takes column q of DW components (all D when the op mixes them: K, or the
+// Hessian with the Stokes projection; else one, blockIdx.y = l * D + component) of
+// coefficient l of X and, with HAS_Y, of Y; transforms them forward, applies spec_mode per
+// mode (the other components held at zero, which a non-mixing op never reads into this
+// one's output) and transforms the results back into out (which may be X). Column 0 holds
+// the packed planes, whose partner values (row -k_1 of the same column) come through LDS.
+// The transforms run in lockstep (wave_fft_multi), so the result rounds like the separate
+// forward pass, k_spec_mul and inverse pass up to the order of the butterflies' products.
+// OP is a template argument so that each instance holds one multiplier's code.
+template <typename R, int N, bool HAS_Y, int DW, int OP>
+__device__ __forceinline__ void col_spec_body(const SpecArgs<R>& sa, int inner, const cplx<R>* __restrict__ tw,
+                                              int twb) {
   constexpr int E = 8, D = 2;
+  static_assert(DW == 1 || DW == D, "components per wavefront");
   using CS = ColShape<N, E>;
   static_assert(!CS::BLOCK && CS::NT == 64, "one wavefront per column group");
   constexpr int LS = CS::LS, SPW = CS::SPW;
   constexpr int PADN = padded_e<E>(N);
-  constexpr int NF = HAS_Y ? 2 * D : D;
+  constexpr int NF = HAS_Y ? 2 * DW : DW;
   __shared__ cplx<R> lds[SPW * NF * PADN];
   const int lane = threadIdx.x;
   const int c = lane % SPW, j = lane / SPW;
@@ -539,14 +543,16 @@ __device__ __forceinline__ void col_spec_body(const SpecArgs<R>& sa, int op, int
   const long long colr = (long long)bx * SPW + c;
   const bool live = colr < inner;
   const int q = (int)(live ? colr : inner - 1);
-  const long long base = (long long)blockIdx.y * D * sa.nspec + q;
+  const int l = (int)blockIdx.y / (D / DW);
+  const int c0 = ((int)blockIdx.y % (D / DW)) * DW;   // first component of this group
+  const long long base = (long long)l * D * sa.nspec + (long long)c0 * sa.nspec + q;
   cplx<R>* S = lds + c * NF * PADN;
   WaveTwiddles<R, N, E> T;
   T.load(j, tw, twb);
   cplx<R> v[NF][E];
 #pragma unroll
   for (int f = 0; f < NF; ++f) {
-    const cplx<R>* src = (f < D ? sa.X : sa.Y) + base + (long long)(f % D) * sa.nspec;
+    const cplx<R>* src = (f < DW ? sa.X : sa.Y) + base + (long long)(f % DW) * sa.nspec;
 #pragma unroll
     for (int e = 0; e < E; ++e) v[f][e] = src[(long long)(j + LS * e) * inner];
   }
@@ -562,6 +568,7 @@ __device__ __forceinline__ void col_spec_body(const SpecArgs<R>& sa, int op, int
       for (int e = 0; e < E; ++e) S[f * N + j + LS * e] = v[f][e];
     wave_lds_sync();
   }
+  const cplx<R> zero = {R(0), R(0)};
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int i1 = j + LS * e;
@@ -569,39 +576,46 @@ __device__ __forceinline__ void col_spec_body(const SpecArgs<R>& sa, int op, int
     kv[0] = R(wavenumber(i1, N)); kt[0] = R(deriv_wavenumber(i1, N));
     cplx<R> x[D], y[D], xp[D], yp[D], o[D];
     const int ip = (N - i1) & (N - 1);
+    // component i of the mode: sequence i - c0 of this group, or zero (selects, so that no
+    // array is indexed by a run-time value)
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      x[i] = v[i][e];
-      xp[i] = q == 0 ? S[i * N + ip] : x[i];
+      const int f = DW == D ? i : 0;
+      const bool mine = DW == D || i == c0;
+      x[i] = mine ? v[f][e] : zero;
+      xp[i] = mine ? (q == 0 ? S[f * N + ip] : v[f][e]) : zero;
       if (HAS_Y) {
-        y[i] = v[D + i][e];
-        yp[i] = q == 0 ? S[(D + i) * N + ip] : y[i];
+        y[i] = mine ? v[DW + f][e] : zero;
+        yp[i] = mine ? (q == 0 ? S[(DW + f) * N + ip] : v[DW + f][e]) : zero;
       }
     }
-    spec_mode<R, D>(sa, op, kv, kt, q, HAS_Y, x, y, xp, yp, o);
+    spec_mode<R, D>(sa, OP, kv, kt, q, HAS_Y, x, y, xp, yp, o);
+    if constexpr (DW == D) {
 #pragma unroll
-    for (int i = 0; i < D; ++i) v[i][e] = o[i];
+      for (int i = 0; i < D; ++i) v[i][e] = o[i];
+    } else {
+      v[0][e] = c0 == 0 ? o[0] : o[1];
+    }
   }
   if (packed) wave_lds_sync();   // the partner reads precede the inverse transforms' exchanges
-  wave_fft_multi<R, N, E, true, D, NF>(v, j, S, PADN, T);
+  wave_fft_multi<R, N, E, true, DW, NF>(v, j, S, PADN, T);
   if (live) {
 #pragma unroll
-    for (int i = 0; i < D; ++i)
+    for (int i = 0; i < DW; ++i)
 #pragma unroll
       for (int e = 0; e < E; ++e) sa.out[base + (long long)i * sa.nspec + (long long)(j + LS * e) * inner] = v[i][e];
   }
 }
 
-template <typename R, int N, bool HAS_Y>
-__global__ __launch_bounds__(64) void k_col_spec(SpecArgs<R> sa, int op, int inner, const cplx<R>* __restrict__ tw,
-                                                int twb) {
-  col_spec_body<R, N, HAS_Y>(sa, op, inner, tw, twb);
+template <typename R, int N, bool HAS_Y, int DW, int OP>
+__global__ __launch_bounds__(64) void k_col_spec(SpecArgs<R> sa, int inner, const cplx<R>* __restrict__ tw, int twb) {
+  col_spec_body<R, N, HAS_Y, DW, OP>(sa, inner, tw, twb);
 }
 // One launch over the items of a batch group: item blockIdx.z uses tab[blockIdx.z].
-template <typename R, int N, bool HAS_Y>
-__global__ __launch_bounds__(64) void k_col_spec_t(const SpecArgs<R>* __restrict__ tab, int op, int inner,
+template <typename R, int N, bool HAS_Y, int DW, int OP>
+__global__ __launch_bounds__(64) void k_col_spec_t(const SpecArgs<R>* __restrict__ tab, int inner,
                                                   const cplx<R>* __restrict__ tw, int twb) {
-  col_spec_body<R, N, HAS_Y>(tab[blockIdx.z], op, inner, tw, twb);
+  col_spec_body<R, N, HAS_Y, DW, OP>(tab[blockIdx.z], inner, tw, twb);
 }
 
 // Tiled column pass for long strided axes. A workgroup owns CT adjacent

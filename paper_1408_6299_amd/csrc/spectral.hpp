@@ -163,8 +163,7 @@ struct LaunchRec {
   dim3 grid, block;
   std::vector<unsigned char> entry;  // this item's table entry
   const void* tw = nullptr;          // ROW, COL: twiddle table (equal across a group)
-  int iarg = 0;                      // ROW: lmax; COL: twb; SPEC, SPECCOL: op; REDF: partials
-  int iarg2 = 0;                     // SPECCOL: twb (and ca.inner the column stride)
+  int iarg = 0;                      // ROW: lmax; COL, SPECCOL: twb; SPEC: op; REDF: partials
   int nfz = 1;                       // COL: fields per item
   ColArgs ca{};
   double scale = 0.0, fval = 0.0;    // COL scale, FILL value
@@ -185,7 +184,7 @@ struct LaunchRec {
   }
   bool same_shape(const LaunchRec& o) const {
     return kind == o.kind && kernel == o.kernel && grid.x == o.grid.x && grid.y == o.grid.y &&
-           grid.z == o.grid.z && block.x == o.block.x && iarg == o.iarg && iarg2 == o.iarg2 && nfz == o.nfz &&
+           grid.z == o.grid.z && block.x == o.block.x && iarg == o.iarg && nfz == o.nfz &&
            std::memcmp(&ca, &o.ca, sizeof(ColArgs)) == 0 && scale == o.scale && fval == o.fval && f64 == o.f64 &&
            cnt == o.cnt && entry.size() == o.entry.size() && bytes == o.bytes && stage == o.stage && len == o.len &&
            dim == o.dim && elems == o.elems && conv == o.conv && nc1 == o.nc1;
@@ -362,18 +361,32 @@ class Spectral {
   }
   template <int N>
   void col_spec_n(const SpecArgs<R>& a, int op, int nf) {
+    // one component per wavefront unless the op mixes them (K, the Stokes Hessian)
+    switch (op) {
+      case OP_HESS:
+        if (!a.Y) throw HipError(-1, "the Hessian multiplier needs the body force");
+        if (a.proj) col_spec_k<N, true, 2, OP_HESS>(a, nf);
+        else col_spec_k<N, true, 1, OP_HESS>(a, nf);
+        break;
+      case OP_PINV: col_spec_k<N, false, 1, OP_PINV>(a, nf); break;
+      case OP_A: col_spec_k<N, false, 1, OP_A>(a, nf); break;
+      case OP_K: col_spec_k<N, false, 2, OP_K>(a, nf); break;
+      default: throw HipError(-1, "unknown spectral multiplier");
+    }
+  }
+  template <int N, bool HAS_Y, int DW, int OP>
+  void col_spec_k(const SpecArgs<R>& a, int nf) {
     constexpr int SPW = ColShape<N, 8>::SPW;
     const int inner = g.L / 2;
-    const dim3 grid((unsigned)((inner + SPW - 1) / SPW), (unsigned)a.nc);
+    const dim3 grid((unsigned)((inner + SPW - 1) / SPW), (unsigned)(a.nc * (2 / DW)));
     const int twb = g.lmax / N;
     if (rec) {
       LaunchRec r;
       r.kind = LaunchRec::SPECCOL;
-      r.kernel = a.Y ? (const void*)k_col_spec_t<R, N, true> : (const void*)k_col_spec_t<R, N, false>;
+      r.kernel = (const void*)k_col_spec_t<R, N, HAS_Y, DW, OP>;
       r.grid = grid;
       r.block = dim3(64);
-      r.iarg = op;
-      r.iarg2 = twb;
+      r.iarg = twb;
       r.ca.inner = inner;
       r.tw = tw;
       r.f64 = sizeof(R) == 8;
@@ -381,9 +394,8 @@ class Spectral {
       rec->recs.push_back(r);
       return;
     }
-    if (tally) tally->add((double)nf * g.nspec * sizeof(cplx<R>) * (a.Y ? 3 : 2));
-    if (a.Y) hipLaunchKernelGGL((k_col_spec<R, N, true>), grid, dim3(64), 0, s, a, op, inner, (const cplx<R>*)tw, twb);
-    else hipLaunchKernelGGL((k_col_spec<R, N, false>), grid, dim3(64), 0, s, a, op, inner, (const cplx<R>*)tw, twb);
+    if (tally) tally->add((double)nf * g.nspec * sizeof(cplx<R>) * (HAS_Y ? 3 : 2));
+    hipLaunchKernelGGL((k_col_spec<R, N, HAS_Y, DW, OP>), grid, dim3(64), 0, s, a, inner, (const cplx<R>*)tw, twb);
     NK_LAUNCHED();
   }
 
