@@ -164,8 +164,9 @@ int nkreg_set_hessian(nkreg_problem* p, int mode);
 int nkreg_use_graphs(nkreg_problem* p, int enable);
 
 /* Writes a JSON object describing the handle's launch configuration (transport
- * precision, graph use, elements per lane of the row and column transforms and
- * the autotuner's timings, which it records at the first graph capture) into
+ * precision, graph use, elements per lane of the row and column transforms, whether
+ * the control-space multiplier runs fused with its column transforms, and the
+ * autotuner's timings, which it records at the first graph capture) into
  * buf (len bytes, NUL-terminated, truncated if needed). */
 int nkreg_describe(nkreg_problem* p, char* buf, int len);
 
