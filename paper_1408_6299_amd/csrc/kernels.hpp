@@ -189,26 +189,27 @@ __device__ __forceinline__ void spec_apply(const SpecArgs<R>& a, int op, const R
 }
 
 // The multiplier's output at one mode of the full-spectrum layout. kv/kt hold the
-// wavenumbers of the axes before the last; q is the packed column. For q > 0, x and y are
-// the inputs at the mode. For q = 0, x and y hold Z = A + iB at the mode and xp, yp the
-// values at the partner mode -k' of the same packed plane; A and B are separated, the
-// multiplier is applied on both planes (k_last = 0 and the Nyquist plane, whose even
-// symbol keeps N_last/2 and whose derivative wavenumber is 0), and out = oA + i oB.
-// Every mode is formed from its own and its partner's inputs, so the outputs keep the
-// planes' Hermitian symmetry exactly (the multipliers are even). y and yp are read only
-// when has_y.
+// wavenumbers of the axes before the last; q is the packed column.
+// spec_plain, q > 0: x and y are the inputs at the mode (y read only when has_y).
 template <typename R, int D>
-__device__ __forceinline__ void spec_mode(const SpecArgs<R>& a, int op, R kv[3], R kt[3], int q, bool has_y,
-                                          const cplx<R>* x, const cplx<R>* y, const cplx<R>* xp,
-                                          const cplx<R>* yp, cplx<R>* out) {
-  if (q > 0) {
-    kv[D - 1] = R(q); kt[D - 1] = R(q);
-    cplx<R> yy[3];
+__device__ __forceinline__ void spec_plain(const SpecArgs<R>& a, int op, R kv[3], R kt[3], int q, bool has_y,
+                                           const cplx<R>* x, const cplx<R>* y, cplx<R>* out) {
+  kv[D - 1] = R(q); kt[D - 1] = R(q);
+  cplx<R> yy[3];
 #pragma unroll
-    for (int i = 0; i < D; ++i) yy[i] = has_y ? y[i] : cplx<R>{R(0), R(0)};
-    spec_apply<R, D>(a, op, kv, kt, x, yy, out);
-    return;
-  }
+  for (int i = 0; i < D; ++i) yy[i] = has_y ? y[i] : cplx<R>{R(0), R(0)};
+  spec_apply<R, D>(a, op, kv, kt, x, yy, out);
+}
+// spec_packed, q = 0: x and y hold Z = A + iB at the mode and xp, yp the values at the
+// partner mode -k' of the same packed plane; A and B are separated, the multiplier is
+// applied on both planes (k_last = 0 and the Nyquist plane, whose even symbol keeps
+// N_last/2 and whose derivative wavenumber is 0), and out = oA + i oB. Every mode is
+// formed from its own and its partner's inputs, so the outputs keep the planes' Hermitian
+// symmetry exactly (the multipliers are even).
+template <typename R, int D>
+__device__ __forceinline__ void spec_packed(const SpecArgs<R>& a, int op, R kv[3], R kt[3], bool has_y,
+                                            const cplx<R>* x, const cplx<R>* y, const cplx<R>* xp,
+                                            const cplx<R>* yp, cplx<R>* out) {
   cplx<R> zA[3], zB[3], yA[3], yB[3];
 #pragma unroll
   for (int i = 0; i < D; ++i) {
@@ -231,6 +232,13 @@ __device__ __forceinline__ void spec_mode(const SpecArgs<R>& a, int op, R kv[3],
   spec_apply<R, D>(a, op, kv, kt, zB, yB, oB);
 #pragma unroll
   for (int i = 0; i < D; ++i) out[i] = {oA[i].x - oB[i].y, oA[i].y + oB[i].x};   // oA + i oB
+}
+template <typename R, int D>
+__device__ __forceinline__ void spec_mode(const SpecArgs<R>& a, int op, R kv[3], R kt[3], int q, bool has_y,
+                                          const cplx<R>* x, const cplx<R>* y, const cplx<R>* xp,
+                                          const cplx<R>* yp, cplx<R>* out) {
+  if (q > 0) spec_plain<R, D>(a, op, kv, kt, q, has_y, x, y, out);
+  else spec_packed<R, D>(a, op, kv, kt, has_y, x, y, xp, yp, out);
 }
 
 template <typename R, int D>

@@ -518,13 +518,13 @@ __global__ __launch_bounds__((ColShape<N, E>::NT)) void k_col_wt(const ColPtrs<R
 // The 2D control-space multiplier between its column transforms, in one pass: each
 // column group takes column q of DW components (all D when the op mixes them: K, or the
 // Hessian with the Stokes projection; else one, blockIdx.y = l * D + component) of
-// coefficient l of X and, with HAS_Y, of Y; transforms them forward, applies spec_mode per
-// mode (the other components held at zero, which a non-mixing op never reads into this
-// one's output) and transforms the results back into out (which may be X). Column 0 holds
-// the packed planes, whose partner values (row -k_1 of the same column) come through LDS.
-// The transforms run in lockstep (wave_fft_multi), so the result rounds like the separate
-// forward pass, k_spec_mul and inverse pass up to the order of the butterflies' products.
-// OP is a template argument so that each instance holds one multiplier's code.
+// coefficient l of X and, with HAS_Y, of Y; transforms them forward, applies the multiplier
+// per mode (spec_plain, spec_packed) and transforms the results back into out (which may
+// be X). Column 0 holds the packed planes, whose partner values (row -k_1 of the same
+// column) come through LDS. The transforms run in lockstep (wave_fft_multi), so the result
+// rounds like the separate forward pass, k_spec_mul and inverse pass up to the order of
+// the butterflies' products. OP is a template argument so that each instance holds one
+// multiplier's code.
 template <typename R, int N, bool HAS_Y, int DW, int OP>
 __device__ __forceinline__ void col_spec_body(const SpecArgs<R>& sa, int inner, const cplx<R>* __restrict__ tw,
                                               int twb) {
@@ -535,7 +535,10 @@ __device__ __forceinline__ void col_spec_body(const SpecArgs<R>& sa, int inner, 
   constexpr int LS = CS::LS, SPW = CS::SPW;
   constexpr int PADN = padded_e<E>(N);
   constexpr int NF = HAS_Y ? 2 * DW : DW;
-  __shared__ cplx<R> lds[SPW * NF * PADN];
+  // per column: NF sequences (FFT scratch, then the packed column's staged spectra), and
+  // the packed column's DW results
+  constexpr int SLOT = (NF + DW) * PADN;
+  __shared__ cplx<R> lds[SPW * SLOT];
   const int lane = threadIdx.x;
   const int c = lane % SPW, j = lane / SPW;
   const int nbx = gridDim.x;
@@ -546,7 +549,7 @@ __device__ __forceinline__ void col_spec_body(const SpecArgs<R>& sa, int inner, 
   const int l = (int)blockIdx.y / (D / DW);
   const int c0 = ((int)blockIdx.y % (D / DW)) * DW;   // first component of this group
   const long long base = (long long)l * D * sa.nspec + (long long)c0 * sa.nspec + q;
-  cplx<R>* S = lds + c * NF * PADN;
+  cplx<R>* S = lds + c * SLOT;
   WaveTwiddles<R, N, E> T;
   T.load(j, tw, twb);
   cplx<R> v[NF][E];
@@ -557,9 +560,20 @@ __device__ __forceinline__ void col_spec_body(const SpecArgs<R>& sa, int inner, 
     for (int e = 0; e < E; ++e) v[f][e] = src[(long long)(j + LS * e) * inner];
   }
   wave_fft_multi<R, N, E, false, NF, NF>(v, j, S, PADN, T);
-  // the group that holds column 0 (the same for every lane of the wavefront) stages its
-  // transformed columns in LDS, where the packed column's lanes find their partner values
-  // at row -k_1
+  // Column q > 0: each lane applies the multiplier to its E modes in registers. The packed
+  // column q = 0 (in the group that holds column 0, the same for every lane of the
+  // wavefront) stages its transformed sequences in LDS, where each mode finds its partner
+  // at row -k_1, and runs one loop over its modes there (kept out of the unrolled code, so
+  // the other columns' instruction stream stays short); its results return through LDS.
+  const cplx<R> zero = {R(0), R(0)};
+  // component i of the multiplier's input: sequence i; with one component per wavefront
+  // the group's component sits in slot 0 and slot 1 is zero (the op does not mix them, so
+  // slot 0's output is that component's, whichever it is)
+  auto gather = [&](int i, const cplx<R>* seq, cplx<R>& xi, cplx<R>& yi) {
+    const bool mine = DW == D || i == 0;
+    xi = mine ? seq[DW == D ? i : 0] : zero;
+    if (HAS_Y) yi = mine ? seq[DW + (DW == D ? i : 0)] : zero;
+  };
   const bool packed = bx == 0;
   if (packed) {
 #pragma unroll
@@ -567,37 +581,48 @@ __device__ __forceinline__ void col_spec_body(const SpecArgs<R>& sa, int inner, 
 #pragma unroll
       for (int e = 0; e < E; ++e) S[f * N + j + LS * e] = v[f][e];
     wave_lds_sync();
-  }
-  const cplx<R> zero = {R(0), R(0)};
+    if (q == 0) {
+      cplx<R>* Sout = S + NF * N;   // DW result sequences
+#pragma unroll 1
+      for (int e = 0; e < E; ++e) {
+        const int i1 = j + LS * e, ip = (N - i1) & (N - 1);
+        R kv[3], kt[3];
+        kv[0] = R(wavenumber(i1, N)); kt[0] = R(deriv_wavenumber(i1, N));
+        cplx<R> own[NF], par[NF], x[D], y[D], xp[D], yp[D], o[D];
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int i1 = j + LS * e;
-    R kv[3], kt[3];
-    kv[0] = R(wavenumber(i1, N)); kt[0] = R(deriv_wavenumber(i1, N));
-    cplx<R> x[D], y[D], xp[D], yp[D], o[D];
-    const int ip = (N - i1) & (N - 1);
-    // component i of the mode: sequence i - c0 of this group, or zero (selects, so that no
-    // array is indexed by a run-time value)
+        for (int f = 0; f < NF; ++f) { own[f] = S[f * N + i1]; par[f] = S[f * N + ip]; }
 #pragma unroll
-    for (int i = 0; i < D; ++i) {
-      const int f = DW == D ? i : 0;
-      const bool mine = DW == D || i == c0;
-      x[i] = mine ? v[f][e] : zero;
-      xp[i] = mine ? (q == 0 ? S[f * N + ip] : v[f][e]) : zero;
-      if (HAS_Y) {
-        y[i] = mine ? v[DW + f][e] : zero;
-        yp[i] = mine ? (q == 0 ? S[(DW + f) * N + ip] : v[DW + f][e]) : zero;
+        for (int i = 0; i < D; ++i) { gather(i, own, x[i], y[i]); gather(i, par, xp[i], yp[i]); }
+        spec_packed<R, D>(sa, OP, kv, kt, HAS_Y, x, y, xp, yp, o);
+#pragma unroll
+        for (int i = 0; i < DW; ++i) Sout[i * N + i1] = o[i];
       }
     }
-    spec_mode<R, D>(sa, OP, kv, kt, q, HAS_Y, x, y, xp, yp, o);
-    if constexpr (DW == D) {
+    wave_lds_sync();
+    if (q == 0) {
 #pragma unroll
-      for (int i = 0; i < D; ++i) v[i][e] = o[i];
-    } else {
-      v[0][e] = c0 == 0 ? o[0] : o[1];
+      for (int i = 0; i < DW; ++i)
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[i][e] = S[NF * N + i * N + j + LS * e];
+    }
+    wave_lds_sync();   // the result reads precede the inverse transforms' exchanges
+  }
+  if (q > 0) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int i1 = j + LS * e;
+      R kv[3], kt[3];
+      kv[0] = R(wavenumber(i1, N)); kt[0] = R(deriv_wavenumber(i1, N));
+      cplx<R> own[NF], x[D], y[D], o[D];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) own[f] = v[f][e];
+#pragma unroll
+      for (int i = 0; i < D; ++i) gather(i, own, x[i], y[i]);
+      spec_plain<R, D>(sa, OP, kv, kt, q, HAS_Y, x, y, o);
+#pragma unroll
+      for (int i = 0; i < DW; ++i) v[i][e] = o[i];
     }
   }
-  if (packed) wave_lds_sync();   // the partner reads precede the inverse transforms' exchanges
   wave_fft_multi<R, N, E, true, DW, NF>(v, j, S, PADN, T);
   if (live) {
 #pragma unroll
