@@ -431,8 +431,9 @@ int nkreg_batch_set_state(nkreg_batch* b, const void* const* d_v);
  * ||r_i||_2 <= rtol ||rhs_i||_2, at most maxit iterations, <= 0: n) at each item's cached
  * state (ESTATE if an item has none). The items iterate in lockstep: each iteration is
  * one batched matvec graph launch for all items, then every unfinished item's own vector
- * work on one of up to eight streams that the batch owns (ordered after the matvec and
- * after the items' streams, which wait for it in turn), then one wait. Each item's x_i, iteration count and relative residual equal those
+ * work (its step replayed as a graph while graphs are in use) on one of up to eight
+ * streams that the batch owns (ordered after the matvec and after the items' streams,
+ * which wait for it in turn), then one wait. Each item's x_i, iteration count and relative residual equal those
  * of its own nkreg_pcg bit for bit. iters and relres (count entries each) may be NULL.
  * Returns ENOCONV (outputs written) if any item reached maxit. Synchronises. */
 int nkreg_batch_pcg(nkreg_batch* b, const void* const* d_rhs, void* const* d_x, double rtol, int maxit, int* h_iters,

@@ -858,8 +858,8 @@ int nkreg_batch_pcg(nkreg_batch* b, const void* const* rhs, void* const* x, doub
       for (size_t i = 0; i < cnt; ++i) {
         nk::ProblemBase* p = b->items[i]->impl;
         if (!p->pcg_active()) continue;
-        p->route_launches(b->lanes[i % nl]);
-        p->pcg_step();
+        p->route_launches(b->lanes[i % nl]);   // pcg_finish's launches follow on the same stream
+        p->pcg_step_on(b->lanes[i % nl]);
       }
       for (size_t k = 0; k < nl; ++k) NK_HIP(hipStreamSynchronize(b->lanes[k]));
       any = false;

@@ -179,6 +179,9 @@ class ProblemBase {
   virtual const void* pcg_p() const = 0;
   virtual void* pcg_q() = 0;
   virtual void pcg_step() = 0;
+  // pcg_step issued on st: replays a graph of the step's launches (captured once per
+  // solution vector) while graphs are in use, else launches them directly on st.
+  virtual void pcg_step_on(hipStream_t st) = 0;
   virtual void pcg_finish() = 0;
   virtual int pcg_result(int* iters, double* relres) const = 0;
   // Sends the handle's launches to st (nullptr: back to the handle's own stream).
@@ -369,9 +372,16 @@ class ProblemT final : public ProblemBase {
     void* out = nullptr;
     hipGraphExec_t exec = nullptr;
   } mv_graph;
+  // the PCG step's launches (pcg_step_on), keyed by the solution vector it updates
+  struct StepGraph {
+    const double* x = nullptr;
+    hipGraphExec_t exec = nullptr;
+  } step_graph;
   void drop_graphs() {
     if (mv_graph.exec) (void)hipGraphExecDestroy(mv_graph.exec);
     mv_graph = GraphEntry{};
+    if (step_graph.exec) (void)hipGraphExecDestroy(step_graph.exec);
+    step_graph = StepGraph{};
     ++generation;
   }
   hipStream_t caller_stream() const override { return user_s; }
@@ -1126,6 +1136,42 @@ class ProblemT final : public ProblemBase {
     precond(kr.p, kz.p);
     red.enqueue_sumsq_dot<double>(kr.p, kz.p, nv, 0);   // |r|^2 and <r, z> in one pass
     NK_HIP(hipMemcpyAsync(red.host, red.result.p, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  void pcg_step_on(hipStream_t st) override {
+    if (!use_graphs) {
+      const hipStream_t prev = s;
+      route(st);
+      pcg_step();
+      route(prev);
+      return;
+    }
+    if (!step_graph.exec || step_graph.x != pr.x) {
+      if (step_graph.exec) (void)hipGraphExecDestroy(step_graph.exec);
+      step_graph = StepGraph{};
+      const hipStream_t prev = s;
+      hipGraph_t graph = nullptr;
+      {
+        OnCaptureStream on(*this);
+        NK_HIP(hipStreamBeginCapture(cap_s, hipStreamCaptureModeThreadLocal));
+        try {
+          pcg_step();
+        } catch (...) {
+          (void)hipStreamEndCapture(cap_s, &graph);
+          if (graph) (void)hipGraphDestroy(graph);
+          route(prev);
+          throw;
+        }
+        NK_HIP(hipStreamEndCapture(cap_s, &graph));
+      }
+      route(prev);
+      hipGraphExec_t exec = nullptr;
+      const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) throw HipError(NKREG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+      step_graph.exec = exec;
+      step_graph.x = pr.x;
+    }
+    NK_HIP(hipGraphLaunch(step_graph.exec, st));
   }
   void pcg_finish() override {
     const double pq = red.host[2];
