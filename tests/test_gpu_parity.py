@@ -337,17 +337,21 @@ def test_small_grid_persistent_sweeps_equal_the_launch_path(nk, monkeypatch, sha
         assert rel_l2(outs[0][0], ref) < 1e-5
 
 
-def test_batch_pcg_equals_each_items_own_pcg(nk):
+@pytest.mark.parametrize("graphs", [True, False])
+def test_batch_pcg_equals_each_items_own_pcg(nk, graphs):
     """nkreg_batch_pcg: the items (mixed grids, step counts, precisions, a checkpointed 3D
     pair) iterate in lockstep with one batched matvec per iteration; every item's x, its
     iteration count and relative residual equal its own nkreg_pcg's bit for bit, also when
-    maxit stops some of them and for a zero right-hand side."""
+    maxit stops some of them and for a zero right-hand side; with the items' graphs in use
+    (each step a replayed graph, captured again for each new solution vector) and with
+    direct launches."""
     probs, rhs = [], []
     for shape, nt, prec, beta, seed, ck in BATCH_ITEMS:
         gamma = len(shape) == 3
         mT, mR, vstar, w = smooth_inputs(shape, nt, divfree=gamma, seed=seed)
         G = nk.Problem(shape, nt, reg=2 if gamma else 1, incompressible=gamma, beta=beta, precision=prec,
                        checkpoint_every=ck)
+        G.use_graphs(graphs)
         G.set_images(dev_t(mT, prec), dev_t(mR, prec))
         _, _, _, g = G.objective_gradient(dev_v(0.5 * vstar))
         probs.append(G)
