@@ -157,7 +157,8 @@ int nkreg_set_beta(nkreg_problem* p, double beta);
 int nkreg_set_hessian(nkreg_problem* p, int mode);
 
 /* Hessian matvecs are captured into a HIP graph per (input, output) pointer
- * pair and replayed (the default); enable = 0 launches every kernel eagerly.
+ * pair and replayed (the default), and so is the PCG step of a batch item in
+ * nkreg_batch_pcg (per solution vector); enable = 0 launches every kernel eagerly.
  * All work runs on the caller's stream; graphs are captured on a stream of the
  * handle's own (capture is not possible on the null stream) and replayed on the
  * caller's. */

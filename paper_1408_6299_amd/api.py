@@ -214,7 +214,8 @@ class Problem:
         return json.loads(buf.value.decode())
 
     def use_graphs(self, enable: bool) -> None:
-        """Replay Hessian matvecs from a captured HIP graph (default) or launch eagerly."""
+        """Replay Hessian matvecs (and a batch item's PCG step) from captured HIP graphs
+        (default) or launch eagerly."""
         check(self.lib.nkreg_use_graphs(self._h, c_int(int(enable))), "nkreg_use_graphs")
 
     def _check(self, t: torch.Tensor, shape: Tuple[int, ...], name: str) -> torch.Tensor:
